@@ -1,0 +1,930 @@
+/*
+ * pond_oracle.c -- TEST INFRASTRUCTURE ONLY (oracle).
+ *
+ * A plain, slow, FP64 CPU implementation of the time step of the two-population
+ * Particles-on-Demand (PonD) kinetic model of Reyhanian, Dorschner & Karlin,
+ * "Thermokinetic model of compressible multiphase flows", arXiv:2002.09217.
+ *
+ * Only the test suite, the smoke check and the CPU-baseline leg of the benchmark
+ * load this library.  The product (HIP) path never loads or links it, and the two
+ * share no source, header, table or helper.
+ *
+ * Every operation follows the paper in the paper's own order:
+ *   - discrete velocities v_i = sqrt(theta) c_i + u, theta = p/(rho T_L)        (eq. 1; App. B)
+ *   - populations f (mass, momentum) and g (energy), moments                   (eq. 2)
+ *   - semi-Lagrangian streaming f_i(x,t) = f_i(x - v_i dt, t - dt)               (eqs. 3-4)
+ *   - each donor of the 4x4 stencil is first re-expressed in the receiver's
+ *     gauge with the transfer matrix G = M_{lambda'}^{-1} M_lambda             (App. C)
+ *     and then interpolated with cubic Lagrange polynomials                    (App. D)
+ *   - van der Waals EoS, e = C_v T - a rho, C_v = R/delta                       (main text; App. A)
+ *   - BGK collision of f with the forcing term S_i                             (eqs. 16-17)
+ *   - Korteweg stress K and force F = -div K                                   (eq. 18; App. F)
+ *   - BGK collision of g with the force-extended equilibrium, the heat-flux
+ *     correction g~ and the work source phi                                    (eqs. 9, 19-22)
+ *
+ * Points the paper leaves open are resolved as follows (each is also listed
+ * with its justification in the design notes of the repository):
+ *   R1  predictor-corrector: the receiver gauge starts from the node's gauge of
+ *       the previous step; a fixed number n_pass of streaming passes is made,
+ *       each pass re-deriving (u, theta) from the streamed populations.
+ *   R2  collision gauge: after the last pass the streamed populations are
+ *       re-expressed in the gauge (u, theta_final) (a moment-preserving map) and
+ *       collide there; theta_final uses the force of the current step.
+ *   R3  inside the passes the actual velocity uses the force of the previous
+ *       step: u_hat = u + F_prev dt / (2 rho).
+ *   R4  F = -div K (App. F); the energy source phi_i = (2 u_hat.F) Psi_i with the
+ *       same kernel Psi_i as g~ (whose first and second moments vanish).
+ *   R5  heat-flux correction with conductivity k = k_scale * mu * C_p^ig,
+ *       C_p^ig = R (1 + delta)/delta; M0 = 2 div(-mu grad h + k grad T) in flux
+ *       form with arithmetic means of mu and k across each link.
+ *   R6  gradient, Laplacian and divergence use the isotropic lattice stencils
+ *       grad phi = (1/T_L) sum_i W_i c_i phi(x + c_i),
+ *       lap phi  = (2/T_L) sum_i W_i (phi(x + c_i) - phi(x)).
+ *   R7  E := sum(g)/(2 rho) is the E-hat of App. F; H = E + p/rho.
+ *   R8  boundaries: periodic wrap; outflow takes every field (populations,
+ *       gauge, derived scalars) at the nearest interior node; inflow uses a
+ *       constant equilibrium ghost state with F = 0.
+ *   R9  initial state: given (rho, u_hat, T), F0 = -div K(rho), the gauge
+ *       velocity is u = u_hat - F0 dt/(2 rho), and the stored populations are
+ *       the collision of the equilibrium state (f = rho W, g = g^eq).
+ *   R10 the transfer matrix is taken from its definition M'^{-1} M; its printed
+ *       explicit form carries a sign error for a single axis (w(i) flips sign),
+ *       which cancels for the two-axis product.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no FMA contraction).
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define T_L (1.0 / 3.0) /* lattice reference temperature of C1 = {-1, 0, 1} (App. B) */
+
+/* one-dimensional weights W_c for c = -1, 0, +1 (App. B) */
+static const double W1[3] = {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0};
+
+enum { ORC_PERIODIC = 0, ORC_OUTFLOW = 1, ORC_INFLOW = 2 };
+enum {
+    ORC_OK = 0,
+    ORC_E_INVALID = -1,
+    ORC_E_NOMEM = -2,
+    ORC_E_PRESSURE = -4,
+    ORC_E_NONFINITE = -5
+};
+
+typedef struct {
+    int dim;                  /* 1: D1Q3, 2: D2Q9 */
+    int nx, ny;               /* ny = 1 for dim = 1 */
+    int bc[2][2];             /* [axis][0 = low face, 1 = high face] */
+    double inflow[2][2][4];   /* inflow state per face: rho, u_hat_x, u_hat_y, T */
+    double a, b, R, delta;    /* van der Waals constants, C_v = R / delta */
+    double omega;             /* BGK relaxation frequency */
+    double kappa;             /* Korteweg coefficient */
+    double k_scale;           /* conductivity k = k_scale mu C_p^ig; < 0 disables M0 */
+    double dt;                /* time step (lattice units) */
+    int n_pass;               /* streaming passes of the predictor-corrector */
+} orc_params;
+
+/* ------------------------------------------------------------------------- */
+/* thermodynamics (main text; App. A)                                         */
+/* ------------------------------------------------------------------------- */
+static double vdw_p(const orc_params *P, double rho, double T)
+{
+    return rho * P->R * T / (1.0 - P->b * rho) - P->a * rho * rho;
+}
+static double vdw_e(const orc_params *P, double rho, double T)
+{
+    return (P->R / P->delta) * T - P->a * rho;
+}
+static double vdw_T_of_e(const orc_params *P, double rho, double e)
+{
+    return P->delta * (e + P->a * rho) / P->R;
+}
+
+/* ------------------------------------------------------------------------- */
+/* lattice                                                                     */
+/* ------------------------------------------------------------------------- */
+static int nq(const orc_params *P) { return P->dim == 2 ? 9 : 3; }
+/* direction q <-> (cx, cy); the x factor is the outer index */
+static int q_cx(const orc_params *P, int q) { return P->dim == 2 ? q / 3 - 1 : q - 1; }
+static int q_cy(const orc_params *P, int q) { return P->dim == 2 ? q % 3 - 1 : 0; }
+static double q_w(const orc_params *P, int q)
+{
+    return P->dim == 2 ? W1[q / 3] * W1[q % 3] : W1[q];
+}
+
+/* ------------------------------------------------------------------------- */
+/* transfer matrix (App. C): G = M_to^{-1} M_from                              */
+/* One axis: the moment matrix is the Vandermonde V[m][i] = v_i^m, m = 0..2, of */
+/* the three velocities u + sqrt(theta) c_i.  For two axes the nine moments     */
+/* M_mn factor, so the 9x9 moment matrix is the Kronecker product of the two    */
+/* axis matrices and G = G_x (x) G_y.                                           */
+/* ------------------------------------------------------------------------- */
+static void vandermonde3(double u, double theta, double V[3][3])
+{
+    double s = sqrt(theta);
+    for (int i = 0; i < 3; ++i) {
+        double v = u + s * (double)(i - 1);
+        V[0][i] = 1.0;
+        V[1][i] = v;
+        V[2][i] = v * v;
+    }
+}
+
+/* Solve A X = B for 3x3 A and three right-hand sides: Gaussian elimination with
+ * partial pivoting, then back substitution. */
+static void solve3(const double Ain[3][3], const double Bin[3][3], double X[3][3])
+{
+    double A[3][3], B[3][3];
+    memcpy(A, Ain, sizeof A);
+    memcpy(B, Bin, sizeof B);
+    for (int c = 0; c < 3; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < 3; ++r)
+            if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+        if (piv != c) {
+            for (int j = 0; j < 3; ++j) {
+                double t = A[c][j]; A[c][j] = A[piv][j]; A[piv][j] = t;
+                t = B[c][j]; B[c][j] = B[piv][j]; B[piv][j] = t;
+            }
+        }
+        for (int r = c + 1; r < 3; ++r) {
+            double l = A[r][c] / A[c][c];
+            for (int j = c; j < 3; ++j) A[r][j] -= l * A[c][j];
+            for (int j = 0; j < 3; ++j) B[r][j] -= l * B[c][j];
+        }
+    }
+    for (int j = 0; j < 3; ++j) {
+        for (int r = 2; r >= 0; --r) {
+            double s = B[r][j];
+            for (int k = r + 1; k < 3; ++k) s -= A[r][k] * X[k][j];
+            X[r][j] = s / A[r][r];
+        }
+    }
+}
+
+/* G[k][i]: population k of the target gauge (u_to, theta_to) receives G[k][i] of
+ * population i of the source gauge (u_from, theta_from), for one axis. */
+void orc_transfer_1d(double u_from, double th_from, double u_to, double th_to, double G[3][3])
+{
+    double Vf[3][3], Vt[3][3];
+    vandermonde3(u_from, th_from, Vf);
+    vandermonde3(u_to, th_to, Vt);
+    solve3(Vt, Vf, G);
+}
+
+/* Re-express a full population vector (Q values) from gauge lf to gauge lt.
+ * A gauge is (u_x, u_y, theta); u_y is ignored for dim = 1. */
+void orc_transfer_pop(const orc_params *P, const double lf[3], const double lt[3],
+                      const double *fin, double *fout)
+{
+    double Gx[3][3], Gy[3][3];
+    orc_transfer_1d(lf[0], lf[2], lt[0], lt[2], Gx);
+    if (P->dim == 1) {
+        for (int k = 0; k < 3; ++k) {
+            double s = 0.0;
+            for (int i = 0; i < 3; ++i) s += Gx[k][i] * fin[i];
+            fout[k] = s;
+        }
+        return;
+    }
+    orc_transfer_1d(lf[1], lf[2], lt[1], lt[2], Gy);
+    for (int k = 0; k < 3; ++k)
+        for (int l = 0; l < 3; ++l) {
+            double s = 0.0;
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) s += Gx[k][i] * Gy[l][j] * fin[3 * i + j];
+            fout[3 * k + l] = s;
+        }
+}
+
+/* ------------------------------------------------------------------------- */
+/* reconstruction (App. D): cubic Lagrange weights on the nodes 0, 1, 2, 3 at   */
+/* local coordinate t = x - x0, x0 = floor(x) - 1.                              */
+/* ------------------------------------------------------------------------- */
+void orc_lagrange4(double t, double w[4])
+{
+    for (int n = 0; n < 4; ++n) {
+        double p = 1.0;
+        for (int k = 0; k < 4; ++k)
+            if (k != n) p *= (t - (double)k) / (double)(n - k);
+        w[n] = p;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* equilibria and sources (eqs. 7-9, 16-22; App. F)                            */
+/* ------------------------------------------------------------------------- */
+
+/* Force source S_i = G^{u}_{u+du}[rho W] - rho W (eq. 17): the equilibrium of
+ * the gauge (u + du, theta) re-expressed in the gauge (u, theta). */
+void orc_force_source(const orc_params *P, double rho, const double u[2], double theta,
+                      const double du[2], double *S)
+{
+    int Q = nq(P);
+    double feq[9], fs[9];
+    double lf[3] = {u[0] + du[0], P->dim == 2 ? u[1] + du[1] : 0.0, theta};
+    double lt[3] = {u[0], P->dim == 2 ? u[1] : 0.0, theta};
+    for (int q = 0; q < Q; ++q) feq[q] = rho * q_w(P, q);
+    orc_transfer_pop(P, lf, lt, feq, fs);
+    for (int q = 0; q < Q; ++q) S[q] = fs[q] - feq[q];
+}
+
+/* Force-extended energy equilibrium (eqs. 20-22) in the gauge (u, theta):
+ *   g_i = W_i [2 rho E + M.(v_i - u) + N:(v_i v_i - (p/rho) I - u u)]
+ *   M = dt/(p/rho) [F H - (uh F + F uh + dt F F E/(2p)) . u]
+ *   N = rho I + dt/(2 p/rho) [uh F + F uh + dt F F E/(2p)]
+ * with E = E-hat, H = E-hat + p/rho (R7), uh the actual velocity. */
+void orc_geq(const orc_params *P, double rho, const double u[2], double theta, double p,
+             double E, const double uh[2], const double F[2], double *g)
+{
+    int D = P->dim, Q = nq(P);
+    double Pr = p / rho;
+    double H = E + Pr;
+    double s = sqrt(theta);
+    double X[2][2]; /* uh F + F uh + dt F F E/(2p) */
+    double M[2], N[2][2];
+    for (int a = 0; a < D; ++a)
+        for (int b = 0; b < D; ++b)
+            X[a][b] = uh[a] * F[b] + F[a] * uh[b] + P->dt * F[a] * F[b] * E / (2.0 * p);
+    for (int a = 0; a < D; ++a) {
+        double xu = 0.0;
+        for (int b = 0; b < D; ++b) xu += X[a][b] * u[b];
+        M[a] = P->dt / Pr * (F[a] * H - xu);
+    }
+    for (int a = 0; a < D; ++a)
+        for (int b = 0; b < D; ++b)
+            N[a][b] = (a == b ? rho : 0.0) + P->dt / (2.0 * Pr) * X[a][b];
+    for (int q = 0; q < Q; ++q) {
+        double c[2] = {(double)q_cx(P, q), (double)q_cy(P, q)};
+        double v[2];
+        for (int a = 0; a < D; ++a) v[a] = u[a] + s * c[a];
+        double t1 = 0.0, t2 = 0.0;
+        for (int a = 0; a < D; ++a) t1 += M[a] * (v[a] - u[a]);
+        for (int a = 0; a < D; ++a)
+            for (int b = 0; b < D; ++b)
+                t2 += N[a][b] * (v[a] * v[b] - (a == b ? Pr : 0.0) - u[a] * u[b]);
+        g[q] = q_w(P, q) * (2.0 * rho * E + t1 + t2);
+    }
+}
+
+/* Kernel of the heat-flux correction (eq. 9): g~_i = M0 Psi_i with
+ *   Psi_i = W_i (1 + rho (u.c_i)^2/(2 p T_L) - rho v_i^2/(2 p) + D/2). */
+void orc_psi(const orc_params *P, double rho, const double u[2], double theta, double p,
+             double *psi)
+{
+    int D = P->dim, Q = nq(P);
+    double s = sqrt(theta);
+    for (int q = 0; q < Q; ++q) {
+        double c[2] = {(double)q_cx(P, q), (double)q_cy(P, q)};
+        double uc = 0.0, v2 = 0.0;
+        for (int a = 0; a < D; ++a) {
+            double v = u[a] + s * c[a];
+            uc += u[a] * c[a];
+            v2 += v * v;
+        }
+        psi[q] = q_w(P, q) *
+                 (1.0 + rho * uc * uc / (2.0 * p * T_L) - rho * v2 / (2.0 * p) + 0.5 * (double)D);
+    }
+}
+
+/* Thermodynamic closure of one node after streaming: from rho, the momentum j,
+ * E = sum(g)/(2 rho) and the force F, compute u, u_hat, T, p, theta (R2, R7). */
+typedef struct {
+    double rho, u[2], uh[2], E, e, T, p, theta, h, mu, kc;
+} node_thermo;
+
+static void close_node(const orc_params *P, double rho, const double j[2], double E,
+                       const double F[2], node_thermo *n)
+{
+    int D = P->dim;
+    n->rho = rho;
+    n->E = E;
+    double uh2 = 0.0;
+    for (int a = 0; a < 2; ++a) {
+        n->u[a] = a < D ? j[a] / rho : 0.0;
+        n->uh[a] = a < D ? n->u[a] + F[a] * P->dt / (2.0 * rho) : 0.0;
+        uh2 += n->uh[a] * n->uh[a];
+    }
+    n->e = E - 0.5 * uh2;
+    n->T = vdw_T_of_e(P, rho, n->e);
+    n->p = vdw_p(P, rho, n->T);
+    n->theta = n->p / (rho * T_L);
+    n->h = n->e + n->p / rho;
+    n->mu = (1.0 / P->omega - 0.5) * n->p * P->dt;
+    n->kc = P->k_scale * n->mu * P->R * (1.0 + P->delta) / P->delta;
+}
+
+static int thermo_bad(const orc_params *P, double rho, double p)
+{
+    if (!isfinite(rho) || !isfinite(p)) return ORC_E_NONFINITE;
+    if (p <= 0.0 || 1.0 - P->b * rho <= 0.0 || rho <= 0.0) return ORC_E_PRESSURE;
+    return ORC_OK;
+}
+
+/* Collision of one node (R2): the streamed populations fstr, gstr live in the gauge
+ * lam_str; F is the force of the step and M0 the heat-flux correction.  Output in
+ * the gauge (u, theta_final) which is also returned in lam_out. */
+int orc_collide(const orc_params *P, const double lam_str[3], const double *fstr,
+                const double *gstr, const double F[2], double M0, double *fout, double *gout,
+                double lam_out[3])
+{
+    int D = P->dim, Q = nq(P);
+    double s_str = sqrt(lam_str[2]);
+    double rho = 0.0, j[2] = {0.0, 0.0}, G2 = 0.0;
+    for (int q = 0; q < Q; ++q) {
+        double c[2] = {(double)q_cx(P, q), (double)q_cy(P, q)};
+        rho += fstr[q];
+        for (int a = 0; a < D; ++a) j[a] += fstr[q] * (lam_str[a] + s_str * c[a]);
+        G2 += gstr[q];
+    }
+    double E = G2 / (2.0 * rho);
+    node_thermo n;
+    double Fl[2] = {F[0], D == 2 ? F[1] : 0.0};
+    close_node(P, rho, j, E, Fl, &n);
+    int bad = thermo_bad(P, rho, n.p);
+    if (bad) return bad;
+
+    /* re-express the streamed populations in the collision gauge (u, theta_final) */
+    double lam_c[3] = {n.u[0], n.u[1], n.theta};
+    double f[9], g[9];
+    orc_transfer_pop(P, lam_str, lam_c, fstr, f);
+    orc_transfer_pop(P, lam_str, lam_c, gstr, g);
+
+    /* f: BGK towards rho W plus the force source (eqs. 16-17) */
+    double du[2] = {Fl[0] * P->dt / rho, Fl[1] * P->dt / rho};
+    double S[9];
+    orc_force_source(P, rho, n.u, n.theta, du, S);
+    for (int q = 0; q < Q; ++q) {
+        double feq = rho * q_w(P, q);
+        fout[q] = f[q] + P->omega * (feq - f[q]) + S[q];
+    }
+
+    /* g: BGK towards the force-extended equilibrium plus (g~ + phi) dt (eq. 19) */
+    double geq[9], psi[9];
+    orc_geq(P, rho, n.u, n.theta, n.p, E, n.uh, Fl, geq);
+    orc_psi(P, rho, n.u, n.theta, n.p, psi);
+    double work = 0.0;
+    for (int a = 0; a < D; ++a) work += 2.0 * n.uh[a] * Fl[a];
+    for (int q = 0; q < Q; ++q)
+        gout[q] = g[q] + P->omega * (geq[q] - g[q]) + (M0 + work) * psi[q] * P->dt;
+
+    lam_out[0] = n.u[0];
+    lam_out[1] = n.u[1];
+    lam_out[2] = n.theta;
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* boundaries (R8)                                                             */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int active;
+    double f[9], g[9], lam[3];
+    double rho, T, h, mu, kc;
+} ghost_state;
+
+static void make_ghost(const orc_params *P, const double st[4], ghost_state *gs)
+{
+    int Q = nq(P);
+    double rho = st[0], T = st[3];
+    double u[2] = {st[1], P->dim == 2 ? st[2] : 0.0};
+    double p = vdw_p(P, rho, T);
+    double e = vdw_e(P, rho, T);
+    double theta = p / (rho * T_L);
+    double E = e + 0.5 * (u[0] * u[0] + u[1] * u[1]);
+    double F0[2] = {0.0, 0.0};
+    gs->active = 1;
+    gs->lam[0] = u[0];
+    gs->lam[1] = u[1];
+    gs->lam[2] = theta;
+    for (int q = 0; q < Q; ++q) gs->f[q] = rho * q_w(P, q);
+    orc_geq(P, rho, u, theta, p, E, u, F0, gs->g);
+    gs->rho = rho;
+    gs->T = T;
+    gs->h = e + p / rho;
+    gs->mu = (1.0 / P->omega - 0.5) * p * P->dt;
+    gs->kc = P->k_scale * gs->mu * P->R * (1.0 + P->delta) / P->delta;
+}
+
+/* Map a lattice position to a node index (>= 0), or to an inflow ghost
+ * (returns -1 - face, face = 2 axis + side). */
+static int map_pos(const orc_params *P, int ix, int iy)
+{
+    int n[2] = {P->nx, P->ny};
+    int i[2] = {ix, iy};
+    for (int a = 0; a < P->dim; ++a) {
+        if (i[a] < 0 || i[a] >= n[a]) {
+            int side = i[a] < 0 ? 0 : 1;
+            int bc = P->bc[a][side];
+            if (bc == ORC_PERIODIC)
+                i[a] = ((i[a] % n[a]) + n[a]) % n[a];
+            else if (bc == ORC_OUTFLOW)
+                i[a] = i[a] < 0 ? 0 : n[a] - 1;
+            else
+                return -1 - (2 * a + side);
+        }
+    }
+    if (P->dim == 1) i[1] = 0;
+    return i[0] + n[0] * i[1];
+}
+
+/* ------------------------------------------------------------------------- */
+/* streaming of one receiver with the predictor-corrector (eqs. 1-4; R1, R3)   */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    const double *f, *g, *ux, *uy, *th, *Fx, *Fy;
+} cstate;
+
+static void donor(const orc_params *P, const cstate *S, const ghost_state *gh, int ix, int iy,
+                  double *f, double *g, double lam[3])
+{
+    int Q = nq(P), N = P->nx * P->ny;
+    int m = map_pos(P, ix, iy);
+    if (m < 0) {
+        const ghost_state *gs = &gh[-1 - m];
+        memcpy(f, gs->f, sizeof(double) * Q);
+        memcpy(g, gs->g, sizeof(double) * Q);
+        memcpy(lam, gs->lam, sizeof(double) * 3);
+        return;
+    }
+    for (int q = 0; q < Q; ++q) {
+        f[q] = S->f[(size_t)q * N + m];
+        g[q] = S->g[(size_t)q * N + m];
+    }
+    lam[0] = S->ux[m];
+    lam[1] = P->dim == 2 ? S->uy[m] : 0.0;
+    lam[2] = S->th[m];
+}
+
+static int stream_receiver(const orc_params *P, const cstate *S, const ghost_state *gh, int x,
+                           int y, double *fstr, double *gstr, double lam_str[3], double *rho_o,
+                           double j_o[2], double *E_o, double *resid)
+{
+    int D = P->dim, Q = nq(P), N = P->nx * P->ny;
+    int node = x + P->nx * y;
+    double lam[3] = {S->ux[node], D == 2 ? S->uy[node] : 0.0, S->th[node]};
+    double Fp[2] = {S->Fx[node], D == 2 ? S->Fy[node] : 0.0};
+    double rho = 0.0, j[2] = {0.0, 0.0}, E = 0.0;
+    (void)N;
+    *resid = 0.0;
+    for (int pass = 0; pass < P->n_pass; ++pass) {
+        double s = sqrt(lam[2]);
+        for (int q = 0; q < Q; ++q) {
+            int cx = q_cx(P, q), cy = q_cy(P, q);
+            double vx = lam[0] + s * (double)cx;
+            double vy = lam[1] + s * (double)cy;
+            double X = (double)x - vx * P->dt; /* departure point (eqs. 3-4) */
+            double Y = (double)y - vy * P->dt;
+            double x0 = floor(X) - 1.0;        /* App. D */
+            double y0 = floor(Y) - 1.0;
+            double wx[4], wy[4] = {1.0, 0.0, 0.0, 0.0};
+            orc_lagrange4(X - x0, wx);
+            int nmy = 1, iy0 = y;
+            if (D == 2) {
+                orc_lagrange4(Y - y0, wy);
+                nmy = 4;
+                iy0 = (int)y0;
+            }
+            double accf = 0.0, accg = 0.0;
+            for (int mm = 0; mm < nmy; ++mm) {
+                for (int nn = 0; nn < 4; ++nn) {
+                    double fd[9], gd[9], ld[3], fr[9], gr[9];
+                    donor(P, S, gh, (int)x0 + nn, iy0 + mm, fd, gd, ld);
+                    /* donor populations re-expressed in the receiver gauge (App. C) */
+                    orc_transfer_pop(P, ld, lam, fd, fr);
+                    orc_transfer_pop(P, ld, lam, gd, gr);
+                    double a_mn = wx[nn] * wy[mm];
+                    accf += a_mn * fr[q];
+                    accg += a_mn * gr[q];
+                }
+            }
+            fstr[q] = accf;
+            gstr[q] = accg;
+        }
+        /* moments (eq. 2) in the absolute frame */
+        rho = 0.0;
+        j[0] = j[1] = 0.0;
+        double G2 = 0.0;
+        for (int q = 0; q < Q; ++q) {
+            double c[2] = {(double)q_cx(P, q), (double)q_cy(P, q)};
+            rho += fstr[q];
+            for (int a = 0; a < D; ++a) j[a] += fstr[q] * (lam[a] + s * c[a]);
+            G2 += gstr[q];
+        }
+        E = G2 / (2.0 * rho);
+        node_thermo n;
+        close_node(P, rho, j, E, Fp, &n);
+        int bad = thermo_bad(P, rho, n.p);
+        if (bad) return bad;
+        lam_str[0] = lam[0];
+        lam_str[1] = lam[1];
+        lam_str[2] = lam[2];
+        double r = fabs(n.u[0] - lam[0]) + fabs(n.u[1] - lam[1]) + fabs(n.theta - lam[2]);
+        *resid = r;
+        lam[0] = n.u[0];
+        lam[1] = n.u[1];
+        lam[2] = n.theta;
+    }
+    *rho_o = rho;
+    j_o[0] = j[0];
+    j_o[1] = j[1];
+    *E_o = E;
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* non-local terms (eq. 18; R5, R6, R8)                                         */
+/* ------------------------------------------------------------------------- */
+/* value of a nodal scalar at lattice position (ix, iy), with boundary mapping */
+static double field_at(const orc_params *P, const double *fld, const double ghost_val[4],
+                       int ix, int iy)
+{
+    int m = map_pos(P, ix, iy);
+    if (m < 0) return ghost_val[-1 - m];
+    return fld[m];
+}
+
+/* Korteweg stress at every node from rho; K has components xx, xy, yy. */
+static void korteweg(const orc_params *P, const double *rho, const double ghost_rho[4],
+                     double *Kxx, double *Kxy, double *Kyy)
+{
+    int D = P->dim, Q = nq(P);
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < P->ny; ++y) {
+        for (int x = 0; x < P->nx; ++x) {
+            int node = x + P->nx * y;
+            double r0 = rho[node];
+            double gr[2] = {0.0, 0.0}, lap = 0.0;
+            for (int q = 0; q < Q; ++q) {
+                int cx = q_cx(P, q), cy = q_cy(P, q);
+                double rq = field_at(P, rho, ghost_rho, x + cx, y + cy);
+                gr[0] += q_w(P, q) * (double)cx * rq;
+                gr[1] += q_w(P, q) * (double)cy * rq;
+                lap += q_w(P, q) * (rq - r0);
+            }
+            gr[0] /= T_L;
+            gr[1] /= T_L;
+            lap *= 2.0 / T_L;
+            double iso = -P->kappa * (r0 * lap + 0.5 * (gr[0] * gr[0] + gr[1] * gr[1]));
+            Kxx[node] = iso + P->kappa * gr[0] * gr[0];
+            Kxy[node] = P->kappa * gr[0] * gr[1];
+            Kyy[node] = D == 2 ? iso + P->kappa * gr[1] * gr[1] : 0.0;
+        }
+    }
+}
+
+/* F = -div K at every node (App. F). */
+static void korteweg_force(const orc_params *P, const double *Kxx, const double *Kxy,
+                           const double *Kyy, double *Fx, double *Fy)
+{
+    int D = P->dim, Q = nq(P);
+    const double zero[4] = {0.0, 0.0, 0.0, 0.0}; /* uniform inflow state: K = 0 */
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < P->ny; ++y) {
+        for (int x = 0; x < P->nx; ++x) {
+            int node = x + P->nx * y;
+            double dv[2] = {0.0, 0.0};
+            for (int q = 0; q < Q; ++q) {
+                int cx = q_cx(P, q), cy = q_cy(P, q);
+                double kxx = field_at(P, Kxx, zero, x + cx, y + cy);
+                double kxy = field_at(P, Kxy, zero, x + cx, y + cy);
+                double kyy = field_at(P, Kyy, zero, x + cx, y + cy);
+                dv[0] += q_w(P, q) * (kxx * (double)cx + kxy * (double)cy);
+                dv[1] += q_w(P, q) * (kxy * (double)cx + kyy * (double)cy);
+            }
+            Fx[node] = -dv[0] / T_L;
+            Fy[node] = D == 2 ? -dv[1] / T_L : 0.0;
+        }
+    }
+}
+
+/* M0 = 2 div(-mu grad h + k grad T) in flux form (R5, R6). */
+static void heat_correction(const orc_params *P, const double *T, const double *h,
+                            const double *mu, const double *kc, const double gT[4],
+                            const double gh_[4], const double gmu[4], const double gkc[4],
+                            double *M0)
+{
+    int Q = nq(P);
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < P->ny; ++y) {
+        for (int x = 0; x < P->nx; ++x) {
+            int node = x + P->nx * y;
+            if (P->k_scale < 0.0) {
+                M0[node] = 0.0;
+                continue;
+            }
+            double acc = 0.0;
+            for (int q = 0; q < Q; ++q) {
+                int cx = q_cx(P, q), cy = q_cy(P, q);
+                double Tq = field_at(P, T, gT, x + cx, y + cy);
+                double hq = field_at(P, h, gh_, x + cx, y + cy);
+                double mq = field_at(P, mu, gmu, x + cx, y + cy);
+                double kq = field_at(P, kc, gkc, x + cx, y + cy);
+                double kmid = 0.5 * (kq + kc[node]);
+                double mmid = 0.5 * (mq + mu[node]);
+                acc += q_w(P, q) * (kmid * (Tq - T[node]) - mmid * (hq - h[node]));
+            }
+            M0[node] = 2.0 * (2.0 / T_L) * acc;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* public entry points                                                          */
+/* ------------------------------------------------------------------------- */
+static int valid(const orc_params *P)
+{
+    if (P->dim != 1 && P->dim != 2) return 0;
+    if (P->nx < 1 || P->ny < 1 || (P->dim == 1 && P->ny != 1)) return 0;
+    if (!(P->delta > 0.0 && P->delta <= 2.0 / 3.0)) return 0;
+    if (!(P->omega > 0.0 && P->omega < 2.0)) return 0;
+    if (P->n_pass < 1 || !(P->dt > 0.0)) return 0;
+    return 1;
+}
+
+static void build_ghosts(const orc_params *P, ghost_state gh[4])
+{
+    memset(gh, 0, sizeof(ghost_state) * 4);
+    for (int a = 0; a < P->dim; ++a)
+        for (int s = 0; s < 2; ++s)
+            if (P->bc[a][s] == ORC_INFLOW) make_ghost(P, P->inflow[a][s], &gh[2 * a + s]);
+}
+
+/* Non-local closure and collision of all nodes, shared by the step and by the
+ * initial state (R9).  Inputs per node: streamed populations in the gauge lam_str,
+ * and their moments rho, j, E. */
+static int close_and_collide(const orc_params *P, const ghost_state gh[4], const double *fstr,
+                             const double *gstr, const double *lsx, const double *lsy,
+                             const double *lst, const double *rho, const double *jx,
+                             const double *jy, const double *E, double *f, double *g,
+                             double *ux, double *uy, double *th, double *Fx, double *Fy)
+{
+    int Q = nq(P), N = P->nx * P->ny, D = P->dim;
+    int err = ORC_OK;
+    double *Kxx = malloc(sizeof(double) * N), *Kxy = malloc(sizeof(double) * N);
+    double *Kyy = malloc(sizeof(double) * N), *Fnx = malloc(sizeof(double) * N);
+    double *Fny = malloc(sizeof(double) * N), *T = malloc(sizeof(double) * N);
+    double *h = malloc(sizeof(double) * N), *mu = malloc(sizeof(double) * N);
+    double *kc = malloc(sizeof(double) * N), *M0 = malloc(sizeof(double) * N);
+    if (!Kxx || !Kxy || !Kyy || !Fnx || !Fny || !T || !h || !mu || !kc || !M0) {
+        err = ORC_E_NOMEM;
+        goto done;
+    }
+    double grho[4], gT[4], gh_[4], gmu[4], gkc[4];
+    for (int k = 0; k < 4; ++k) {
+        grho[k] = gh[k].rho;
+        gT[k] = gh[k].T;
+        gh_[k] = gh[k].h;
+        gmu[k] = gh[k].mu;
+        gkc[k] = gh[k].kc;
+    }
+    korteweg(P, rho, grho, Kxx, Kxy, Kyy);
+    korteweg_force(P, Kxx, Kxy, Kyy, Fnx, Fny);
+    for (int n = 0; n < N; ++n) {
+        double j[2] = {jx[n], D == 2 ? jy[n] : 0.0};
+        double F[2] = {Fnx[n], Fny[n]};
+        node_thermo t;
+        close_node(P, rho[n], j, E[n], F, &t);
+        int bad = thermo_bad(P, rho[n], t.p);
+        if (bad) {
+            err = bad;
+            goto done;
+        }
+        T[n] = t.T;
+        h[n] = t.h;
+        mu[n] = t.mu;
+        kc[n] = t.kc;
+    }
+    heat_correction(P, T, h, mu, kc, gT, gh_, gmu, gkc, M0);
+    for (int n = 0; n < N; ++n) {
+        double ls[3] = {lsx[n], D == 2 ? lsy[n] : 0.0, lst[n]};
+        double fs[9], gs[9], fo[9], go[9], lo[3];
+        for (int q = 0; q < Q; ++q) {
+            fs[q] = fstr[(size_t)q * N + n];
+            gs[q] = gstr[(size_t)q * N + n];
+        }
+        double F[2] = {Fnx[n], Fny[n]};
+        int bad = orc_collide(P, ls, fs, gs, F, M0[n], fo, go, lo);
+        if (bad) {
+            err = bad;
+            goto done;
+        }
+        for (int q = 0; q < Q; ++q) {
+            f[(size_t)q * N + n] = fo[q];
+            g[(size_t)q * N + n] = go[q];
+        }
+        ux[n] = lo[0];
+        if (D == 2) uy[n] = lo[1];
+        th[n] = lo[2];
+        Fx[n] = Fnx[n];
+        if (D == 2) Fy[n] = Fny[n];
+    }
+done:
+    free(Kxx); free(Kxy); free(Kyy); free(Fnx); free(Fny);
+    free(T); free(h); free(mu); free(kc); free(M0);
+    return err;
+}
+
+/* Initial state from (rho, u_hat, T) per node (R9).  uy, Fy may be NULL for dim 1. */
+int orc_init(const orc_params *P, const double *rho, const double *uhx, const double *uhy,
+             const double *Tin, double *f, double *g, double *ux, double *uy, double *th,
+             double *Fx, double *Fy)
+{
+    if (!valid(P)) return ORC_E_INVALID;
+    int Q = nq(P), N = P->nx * P->ny, D = P->dim;
+    ghost_state gh[4];
+    build_ghosts(P, gh);
+    double *Kxx = malloc(sizeof(double) * N), *Kxy = malloc(sizeof(double) * N);
+    double *Kyy = malloc(sizeof(double) * N), *F0x = malloc(sizeof(double) * N);
+    double *F0y = malloc(sizeof(double) * N), *fe = malloc(sizeof(double) * Q * N);
+    double *ge = malloc(sizeof(double) * Q * N), *lx = malloc(sizeof(double) * N);
+    double *ly = malloc(sizeof(double) * N), *lt = malloc(sizeof(double) * N);
+    double *jx = malloc(sizeof(double) * N), *jy = malloc(sizeof(double) * N);
+    double *Ev = malloc(sizeof(double) * N);
+    double dummy_y[1];
+    int err = ORC_OK;
+    if (!Kxx || !Kxy || !Kyy || !F0x || !F0y || !fe || !ge || !lx || !ly || !lt || !jx || !jy ||
+        !Ev) {
+        err = ORC_E_NOMEM;
+        goto done;
+    }
+    double grho[4];
+    for (int k = 0; k < 4; ++k) grho[k] = gh[k].rho;
+    korteweg(P, rho, grho, Kxx, Kxy, Kyy);
+    korteweg_force(P, Kxx, Kxy, Kyy, F0x, F0y);
+    for (int n = 0; n < N; ++n) {
+        double r = rho[n];
+        double uh[2] = {uhx[n], D == 2 ? uhy[n] : 0.0};
+        double F0[2] = {F0x[n], F0y[n]};
+        double u[2] = {uh[0] - F0[0] * P->dt / (2.0 * r), uh[1] - F0[1] * P->dt / (2.0 * r)};
+        if (D == 1) u[1] = 0.0;
+        double p = vdw_p(P, r, Tin[n]);
+        int bad = thermo_bad(P, r, p);
+        if (bad) {
+            err = bad;
+            goto done;
+        }
+        double e = vdw_e(P, r, Tin[n]);
+        double E = e + 0.5 * (uh[0] * uh[0] + uh[1] * uh[1]);
+        double theta = p / (r * T_L);
+        double geq[9];
+        orc_geq(P, r, u, theta, p, E, uh, F0, geq);
+        for (int q = 0; q < Q; ++q) {
+            fe[(size_t)q * N + n] = r * q_w(P, q);
+            ge[(size_t)q * N + n] = geq[q];
+        }
+        lx[n] = u[0];
+        ly[n] = u[1];
+        lt[n] = theta;
+        jx[n] = r * u[0];
+        jy[n] = r * u[1];
+        Ev[n] = E;
+    }
+    err = close_and_collide(P, gh, fe, ge, lx, ly, lt, rho, jx, jy, Ev, f, g, ux,
+                            D == 2 ? uy : dummy_y, th, Fx, D == 2 ? Fy : dummy_y);
+done:
+    free(Kxx); free(Kxy); free(Kyy); free(F0x); free(F0y); free(fe); free(ge);
+    free(lx); free(ly); free(lt); free(jx); free(jy); free(Ev);
+    return err;
+}
+
+/* Advance the state by nsteps time steps.  On error the state holds the last
+ * completed step and the number of completed steps is stored in *done_steps.
+ * max_resid (optional) receives the largest gauge residual |lambda^(N) -
+ * lambda^(N-1)| of the last step. */
+int orc_step(const orc_params *P, int nsteps, double *f, double *g, double *ux, double *uy,
+             double *th, double *Fx, double *Fy, int *done_steps, double *max_resid)
+{
+    if (!valid(P)) return ORC_E_INVALID;
+    int Q = nq(P), N = P->nx * P->ny, D = P->dim;
+    ghost_state gh[4];
+    build_ghosts(P, gh);
+    double *fstr = malloc(sizeof(double) * Q * N), *gstr = malloc(sizeof(double) * Q * N);
+    double *lsx = malloc(sizeof(double) * N), *lsy = malloc(sizeof(double) * N);
+    double *lst = malloc(sizeof(double) * N), *rho = malloc(sizeof(double) * N);
+    double *jx = malloc(sizeof(double) * N), *jy = malloc(sizeof(double) * N);
+    double *E = malloc(sizeof(double) * N), *res = malloc(sizeof(double) * N);
+    int *errs = malloc(sizeof(int) * N);
+    double *fn = malloc(sizeof(double) * Q * N), *gn = malloc(sizeof(double) * Q * N);
+    double *uxn = malloc(sizeof(double) * N), *uyn = malloc(sizeof(double) * N);
+    double *thn = malloc(sizeof(double) * N), *Fxn = malloc(sizeof(double) * N);
+    double *Fyn = malloc(sizeof(double) * N);
+    double zy[1] = {0.0};
+    int err = ORC_OK, step = 0;
+    if (done_steps) *done_steps = 0;
+    if (!fstr || !gstr || !lsx || !lsy || !lst || !rho || !jx || !jy || !E || !res || !errs ||
+        !fn || !gn || !uxn || !uyn || !thn || !Fxn || !Fyn) {
+        err = ORC_E_NOMEM;
+        goto done;
+    }
+    for (step = 0; step < nsteps; ++step) {
+        cstate S = {f, g, ux, D == 2 ? uy : zy, th, Fx, D == 2 ? Fy : zy};
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int y = 0; y < P->ny; ++y) {
+            for (int x = 0; x < P->nx; ++x) {
+                int n = x + P->nx * y;
+                double fs[9] = {0}, gs[9] = {0}, ls[3] = {0}, j[2] = {0}, r = 0.0, e_ = 0.0;
+                errs[n] = stream_receiver(P, &S, gh, x, y, fs, gs, ls, &r, j, &e_, &res[n]);
+                for (int q = 0; q < Q; ++q) {
+                    fstr[(size_t)q * N + n] = fs[q];
+                    gstr[(size_t)q * N + n] = gs[q];
+                }
+                lsx[n] = ls[0];
+                lsy[n] = ls[1];
+                lst[n] = ls[2];
+                rho[n] = r;
+                jx[n] = j[0];
+                jy[n] = j[1];
+                E[n] = e_;
+            }
+        }
+        for (int n = 0; n < N; ++n)
+            if (errs[n]) {
+                err = errs[n];
+                goto done;
+            }
+        err = close_and_collide(P, gh, fstr, gstr, lsx, lsy, lst, rho, jx, jy, E, fn, gn, uxn,
+                                uyn, thn, Fxn, Fyn);
+        if (err) goto done;
+        memcpy(f, fn, sizeof(double) * Q * N);
+        memcpy(g, gn, sizeof(double) * Q * N);
+        memcpy(ux, uxn, sizeof(double) * N);
+        memcpy(th, thn, sizeof(double) * N);
+        memcpy(Fx, Fxn, sizeof(double) * N);
+        if (D == 2) {
+            memcpy(uy, uyn, sizeof(double) * N);
+            memcpy(Fy, Fyn, sizeof(double) * N);
+        }
+        if (max_resid) {
+            double m = 0.0;
+            for (int n = 0; n < N; ++n)
+                if (res[n] > m) m = res[n];
+            *max_resid = m;
+        }
+        if (done_steps) *done_steps = step + 1;
+    }
+done:
+    free(fstr); free(gstr); free(lsx); free(lsy); free(lst); free(rho); free(jx); free(jy);
+    free(E); free(res); free(errs); free(fn); free(gn); free(uxn); free(uyn); free(thn);
+    free(Fxn); free(Fyn);
+    return err;
+}
+
+/* Macroscopic fields of a state: rho = sum f, u_hat = u + F dt/(2 rho),
+ * p = rho theta T_L, T from the EoS, E = e + u_hat^2/2. */
+void orc_moments(const orc_params *P, const double *f, const double *ux, const double *uy,
+                 const double *th, const double *Fx, const double *Fy, double *rho,
+                 double *uhx, double *uhy, double *T, double *p, double *E)
+{
+    int Q = nq(P), N = P->nx * P->ny, D = P->dim;
+    for (int n = 0; n < N; ++n) {
+        double r = 0.0;
+        for (int q = 0; q < Q; ++q) r += f[(size_t)q * N + n];
+        double hx = ux[n] + Fx[n] * P->dt / (2.0 * r);
+        double hy = D == 2 ? uy[n] + Fy[n] * P->dt / (2.0 * r) : 0.0;
+        double pr = r * th[n] * T_L;
+        double Tn = (pr + P->a * r * r) * (1.0 - P->b * r) / (r * P->R);
+        double e = vdw_e(P, r, Tn);
+        rho[n] = r;
+        uhx[n] = hx;
+        if (D == 2) uhy[n] = hy;
+        T[n] = Tn;
+        p[n] = pr;
+        E[n] = e + 0.5 * (hx * hx + hy * hy);
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* exported views of the non-local operators, for the tests of their          */
+/* telescoping sums                                                             */
+/* ------------------------------------------------------------------------- */
+void orc_korteweg_force(const orc_params *P, const double *rho, double *Fx, double *Fy)
+{
+    int N = P->nx * P->ny;
+    ghost_state gh[4];
+    build_ghosts(P, gh);
+    double grho[4];
+    for (int k = 0; k < 4; ++k) grho[k] = gh[k].rho;
+    double *Kxx = malloc(sizeof(double) * N), *Kxy = malloc(sizeof(double) * N);
+    double *Kyy = malloc(sizeof(double) * N);
+    if (Kxx && Kxy && Kyy) {
+        korteweg(P, rho, grho, Kxx, Kxy, Kyy);
+        korteweg_force(P, Kxx, Kxy, Kyy, Fx, Fy);
+    }
+    free(Kxx); free(Kxy); free(Kyy);
+}
+
+void orc_heat_correction(const orc_params *P, const double *T, const double *h,
+                         const double *mu, const double *kc, double *M0)
+{
+    ghost_state gh[4];
+    build_ghosts(P, gh);
+    double gT[4], gh_[4], gmu[4], gkc[4];
+    for (int k = 0; k < 4; ++k) {
+        gT[k] = gh[k].T;
+        gh_[k] = gh[k].h;
+        gmu[k] = gh[k].mu;
+        gkc[k] = gh[k].kc;
+    }
+    heat_correction(P, T, h, mu, kc, gT, gh_, gmu, gkc, M0);
+}

@@ -1,0 +1,189 @@
+"""TEST INFRASTRUCTURE ONLY -- van der Waals thermodynamics used by the oracle tests.
+
+Only the test suite, ``__graft_entry__.smoke()``, the CPU-baseline leg of
+``bench.py`` and ``oracle/write_constants.py`` may import this module.
+
+Everything follows Reyhanian, Dorschner & Karlin (arXiv:2002.09217):
+  * van der Waals EoS p = rho R T/(1 - b rho) - a rho^2 and critical values
+    rho_cr = 1/(3b), T_cr = 8a/(27 R b), p_cr = a/(27 b^2)          (main text)
+  * e = C_v T - a rho, C_v = R/delta                                   (main text; App. A)
+  * C_p, the speed of sound (general and van der Waals forms)          (App. A)
+  * the fundamental derivative Gamma(p, v) of the van der Waals fluid  (App. E, shock tube)
+  * Rankine-Hugoniot post-shock state                                  (App. E)
+  * Maxwell's equal-area rule for the coexistence densities            (main text, Fig. 2)
+All arithmetic is FP64.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+from scipy.optimize import brentq
+
+A_SIM, B_SIM, R_SIM = 2.0 / 49.0, 2.0 / 21.0, 1.0  # constants used in the paper's simulations
+
+
+@dataclass(frozen=True)
+class VdW:
+    a: float = A_SIM
+    b: float = B_SIM
+    R: float = R_SIM
+    delta: float = 1.0 / 3.0
+
+    # critical point (main text)
+    @property
+    def rho_cr(self) -> float:
+        return 1.0 / (3.0 * self.b)
+
+    @property
+    def T_cr(self) -> float:
+        return 8.0 * self.a / (27.0 * self.R * self.b)
+
+    @property
+    def p_cr(self) -> float:
+        return self.a / (27.0 * self.b * self.b)
+
+    @property
+    def Cv(self) -> float:
+        return self.R / self.delta
+
+    # EoS and caloric relation
+    def p(self, rho, T):
+        return rho * self.R * T / (1.0 - self.b * rho) - self.a * rho * rho
+
+    def e(self, rho, T):
+        return self.Cv * T - self.a * rho
+
+    def T_of_e(self, rho, e):
+        return (e + self.a * rho) / self.Cv
+
+    def T_of_p(self, rho, p):
+        return (p + self.a * rho * rho) * (1.0 - self.b * rho) / (rho * self.R)
+
+    # partial derivatives of p(rho, T)
+    def dp_drho_T(self, rho, T):
+        return self.R * T / (1.0 - self.b * rho) ** 2 - 2.0 * self.a * rho
+
+    def dp_dT_rho(self, rho, T):
+        return rho * self.R / (1.0 - self.b * rho)
+
+    # App. A: C_p = C_v + T (dp/dT)_v (dv/dT)_p, general form with the EoS derivatives
+    def Cp_general(self, rho, T):
+        v = 1.0 / rho
+        dp_dT_v = self.dp_dT_rho(rho, T)
+        dp_dv_T = -rho * rho * self.dp_drho_T(rho, T)
+        dv_dT_p = -dp_dT_v / dp_dv_T
+        return self.Cv + T * dp_dT_v * dv_dT_p + 0.0 * v
+
+    # App. A: closed form for the van der Waals fluid
+    def Cp_vdw(self, rho, T):
+        R = self.R
+        return self.Cv + R * R * T / (R * T - 2.0 * self.a * rho * (1.0 - self.b * rho) ** 2)
+
+    # App. A: sound speed, general relation and the van der Waals closed form
+    def sound_general(self, rho, T):
+        return math.sqrt(self.dp_drho_T(rho, T) + T / (rho * rho * self.Cv) * self.dp_dT_rho(rho, T) ** 2)
+
+    def sound_vdw(self, rho, T):
+        return math.sqrt(self.R * T / (1.0 - self.b * rho) ** 2 * (1.0 + self.delta) - 2.0 * self.a * rho)
+
+    # App. E: fundamental derivative of the van der Waals fluid
+    def gamma(self, p, v):
+        a, b, d = self.a, self.b, self.delta
+        num = (d + 1.0) * (d + 2.0) * (p + a / v**2) / (v - b) ** 2 - 6.0 * a / v**4
+        den = 2.0 * (d + 1.0) * (p + a / v**2) / (v * (v - b)) - 4.0 * a / v**4
+        return num / den
+
+    # ------------------------------------------------------------------
+    # Maxwell's equal-area rule (main text, Fig. 2)
+    # ------------------------------------------------------------------
+    def spinodal(self, T):
+        """Densities where (dp/drho)_T = 0 at T < T_cr (vapor-side, liquid-side)."""
+        rc = self.rho_cr
+        f = lambda r: self.dp_drho_T(r, T)
+        lo = brentq(f, 1e-12, rc, xtol=1e-15, rtol=1e-15, maxiter=500)
+        hi = brentq(f, rc, (1.0 - 1e-12) / self.b, xtol=1e-15, rtol=1e-15, maxiter=500)
+        return lo, hi
+
+    def _outer_roots(self, T, ps):
+        """Smallest and largest specific volume with p(v) = ps (roots of the cubic)."""
+        a, b, R = self.a, self.b, self.R
+        roots = np.roots([ps, -(ps * b + R * T), a, -a * b])
+        real = np.sort(roots[np.abs(roots.imag) < 1e-9 * np.abs(roots).max()].real)
+        real = real[real > b]
+        return real[0], real[-1]
+
+    def maxwell(self, T):
+        """(rho_vapor, rho_liquid, p_sat) at T < T_cr from the equal-area rule
+        int_{v_l}^{v_v} p dv = p_sat (v_v - v_l)."""
+        if not T < self.T_cr:
+            raise ValueError("Maxwell construction needs T < T_cr")
+        r_sv, r_sl = self.spinodal(T)
+        p_hi = self.p(r_sv, T)             # local maximum of the loop
+        p_lo = max(self.p(r_sl, T), 0.0)   # local minimum (clipped at 0)
+        R, a, b = self.R, self.a, self.b
+
+        def area(ps):
+            vl, vv = self._outer_roots(T, ps)
+            integral = R * T * math.log((vv - b) / (vl - b)) + a / vv - a / vl
+            return integral - ps * (vv - vl)
+
+        eps = 1e-13 * p_hi
+        ps = brentq(area, p_lo + eps, p_hi - eps, xtol=1e-16, rtol=1e-15, maxiter=500)
+        vl, vv = self._outer_roots(T, ps)
+        # polish the two densities on the exact EoS
+        rho_l = brentq(lambda r: self.p(r, T) - ps, r_sl, (1.0 - 1e-14) / b, xtol=1e-15, rtol=1e-15)
+        rho_v = brentq(lambda r: self.p(r, T) - ps, 1e-12, r_sv, xtol=1e-15, rtol=1e-15)
+        return rho_v, rho_l, ps
+
+    # ------------------------------------------------------------------
+    # Rankine-Hugoniot (App. E)
+    # ------------------------------------------------------------------
+    def e_pv(self, p, v):
+        """Internal energy as a function of (p, v): T from the EoS, then e = C_v T - a/v."""
+        T = (p + self.a / v**2) * (v - self.b) / self.R
+        return self.Cv * T - self.a / v
+
+    def hugoniot_direct(self, rho0, p0, p1):
+        """Post-shock state behind a shock into still fluid (u0 = 0) with pressure p1.
+        Solves e(p1, v1) - e(p0, v0) = (p1 + p0)(v0 - v1)/2 for v1, then mass and
+        momentum jumps give the shock speed s and the post-shock velocity u1."""
+        v0 = 1.0 / rho0
+        e0 = self.e_pv(p0, v0)
+        f = lambda v1: self.e_pv(p1, v1) - e0 - 0.5 * (p1 + p0) * (v0 - v1)
+        v1 = brentq(f, self.b * (1.0 + 1e-9), v0, xtol=1e-16, rtol=1e-15, maxiter=500)
+        rho1 = 1.0 / v1
+        m2 = (p1 - p0) / (v0 - v1)            # mass flux squared through the shock
+        m = math.sqrt(m2)
+        s = m * v0                            # shock speed (u0 = 0)
+        u1 = s - m * v1
+        T1 = self.T_of_p(rho1, p1)
+        return dict(rho1=rho1, u1=u1, p1=p1, s=s, T1=T1, Ms=s / self.sound_vdw(rho0, self.T_of_p(rho0, p0)))
+
+    def rh_closed_form(self, rho0, p0, rho1):
+        """The closed form of App. E in reduced variables (rho1 as the free parameter).
+        Returns (M0, u1, p1) in physical units.  The velocity line uses the pre-shock
+        sound speed (see the design notes for this reading)."""
+        rc, pc = self.rho_cr, self.p_cr
+        scale = math.sqrt(pc / rc)            # sqrt(p_cr v_cr)
+        r0, r1, P0, d = rho0 / rc, rho1 / rc, p0 / pc, self.delta
+        c0 = self.sound_vdw(rho0, self.T_of_p(rho0, p0)) / scale
+        M0 = (1.0 / c0) * math.sqrt(
+            6.0 * r1 * (P0 * (1.0 + d) + r0 * r1 * (r0 + r1 + 3.0 * d - 3.0))
+            / (r0 * (2.0 * r0 * (3.0 - r1) + 3.0 * d * (r0 - r1))))
+        u1 = c0 * M0 * (r1 - r0) / r1
+        P1 = P0 + c0 * c0 * M0 * M0 * r0 * (r1 - r0) / r1
+        return M0, u1 * scale, P1 * pc
+
+    def rh_jump_residual(self, rho0, p0, u0, rho1, p1, u1, s):
+        """Residual of -s <M> + <N> = 0 for M = (rho, rho u, rho E), N = (rho u, p + rho u^2,
+        rho u H), E = e + u^2/2, H = E + p/rho."""
+        def MN(r, p, u):
+            T = self.T_of_p(r, p)
+            E = self.e(r, T) + 0.5 * u * u
+            H = E + p / r
+            return np.array([r, r * u, r * E]), np.array([r * u, p + r * u * u, r * u * H])
+        M0_, N0_ = MN(rho0, p0, u0)
+        M1_, N1_ = MN(rho1, p1, u1)
+        return -s * (M1_ - M0_) + (N1_ - N0_)
