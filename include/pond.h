@@ -1,0 +1,126 @@
+/*
+ * pond.h -- C ABI of the MI355X (gfx950) library for the time step of the
+ * two-population Particles-on-Demand kinetic model of compressible multiphase
+ * flow: Reyhanian, Dorschner & Karlin, "Thermokinetic model of compressible
+ * multiphase flows", arXiv:2002.09217.
+ *
+ * One handle owns one lattice (D1Q3 or D2Q9) and its device state.  A time step
+ *   1. streams f (mass, momentum) and g (energy) semi-Lagrangianly at the shifted
+ *      velocities v_i = sqrt(p/(rho T_L)) c_i + u                     (eqs. 1, 3-4)
+ *      re-expressing every donor in the receiving node's gauge        (App. C)
+ *      with cubic Lagrange reconstruction                             (App. D)
+ *      inside a fixed-count predictor-corrector on (rho, u, E) through the van
+ *      der Waals equation of state                                    (main text; App. A)
+ *   2. evaluates the Korteweg stress and force F = -div K              (eq. 18; App. F)
+ *      and the heat-flux correction M0                                (eq. 9)
+ *   3. relaxes f and g to their equilibria with the force source S_i, the
+ *      force-extended g equilibrium and the sources g~ + phi          (eqs. 16-22)
+ *
+ * Conventions for every call below
+ *   - All functions return a pond_status (0 = POND_OK, negative = error).
+ *   - Host arrays are caller-owned, plain C doubles, copied synchronously.
+ *   - Node order: index = x + n[0] * y.  A vector field is `dim` consecutive planes
+ *     of n[0]*n[1] values (x component first).
+ *   - Device memory is owned by the library (allocated in pond_create, released in
+ *     pond_destroy).  Work is enqueued on cfg.stream (a hipStream_t, e.g. PyTorch's
+ *     current stream) or on a library-owned stream when cfg.stream is NULL.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *   - After an error in pond_step the state is that of the last completed step,
+ *     the handle refuses further steps (POND_E_STATE) until pond_init_fields is
+ *     called again, and pond_last_error() describes the failure.
+ */
+#ifndef POND_H
+#define POND_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pond_handle pond_handle; /* opaque, library-owned */
+
+typedef enum {
+    POND_OK = 0,
+    POND_E_INVALID = -1,   /* bad argument or configuration                          */
+    POND_E_NOMEM = -2,     /* device or host allocation failed                        */
+    POND_E_DEVICE = -3,    /* HIP runtime error                                       */
+    POND_E_PRESSURE = -4,  /* p <= 0, rho <= 0 or 1 - b rho <= 0 at some node         */
+    POND_E_NONFINITE = -5, /* NaN or Inf in the state                                 */
+    POND_E_HALO = -6,      /* a departure stencil leaves the +-2 node window:
+                              |u| + sqrt(theta) times dt reached 1                    */
+    POND_E_STATE = -7      /* handle not initialised, or in the error state           */
+} pond_status;
+
+enum { POND_BC_PERIODIC = 0, POND_BC_OUTFLOW = 1, POND_BC_INFLOW = 2 };
+enum { POND_FP64 = 0, POND_FP32_STORE = 1 };
+
+typedef struct {
+    int dim;                  /* 1 (D1Q3) or 2 (D2Q9), App. B                          */
+    int n[3];                 /* nodes per axis; unused axes = 1                        */
+    int bc[3][2];             /* per axis, [low face, high face]: POND_BC_*             */
+    double inflow[3][2][5];   /* state of an inflow face: rho, u_x, u_y, u_z, T (the
+                                 actual velocity); its ghost nodes hold the equilibrium
+                                 of that state with F = 0                              */
+    double a, b, R;           /* van der Waals p = rho R T/(1 - b rho) - a rho^2        */
+    double delta;             /* C_v = R/delta, 0 < delta <= 2/3 (main text)            */
+    double omega;             /* BGK relaxation, 0 < omega < 2; mu = (1/omega - 1/2) p dt */
+    double kappa;             /* Korteweg coefficient of eq. 18; 0 switches the force off */
+    double k_scale;           /* conductivity k = k_scale mu C_p^ig, C_p^ig = R(1+delta)/delta;
+                                 k_scale < 0 switches the heat-flux correction off     */
+    double dt;                /* time step in lattice units (dx = 1, App. D)            */
+    int n_pass;               /* streaming passes of the predictor-corrector, >= 1      */
+    int precision;            /* POND_FP64, or POND_FP32_STORE: populations stored and
+                                 interpolated in FP32; moments, EoS, gauge, forcing and
+                                 collision in FP64                                      */
+    void *stream;             /* hipStream_t or NULL                                    */
+} pond_config;
+
+/* Validate cfg and allocate the device state.  *out receives the handle (NULL on
+ * error).  Errors: POND_E_INVALID (dim, sizes, 0 < delta <= 2/3, 0 < omega < 2,
+ * n_pass >= 1, dt > 0, inflow state with p <= 0), POND_E_NOMEM, POND_E_DEVICE. */
+int pond_create(const pond_config *cfg, pond_handle **out);
+
+/* Set the state from the macroscopic fields rho (N), actual velocity u (dim planes
+ * of N) and temperature T (N), host arrays.  The force F0 = -div K(rho) follows from
+ * rho; the gauge velocity is u - F0 dt/(2 rho); the stored populations are the
+ * collision of the equilibrium populations f = rho W, g = g^eq (eqs. 7, 16-22).
+ * Errors: POND_E_INVALID (NULL pointer), POND_E_PRESSURE / POND_E_NONFINITE when a
+ * node is outside the EoS domain (state then undefined, handle not initialised). */
+int pond_init_fields(pond_handle *h, const double *rho, const double *u, const double *T);
+
+/* Advance nsteps >= 0 time steps, then synchronise the stream.  Returns the first
+ * error met; the state is then that of the last completed step. */
+int pond_step(pond_handle *h, int nsteps);
+
+/* Macroscopic fields of the current state into host arrays (any may be NULL):
+ * rho = sum_i f_i; u = u_gauge + F dt/(2 rho) (the actual velocity u-hat, eq. 17 and
+ * App. F); p = rho theta T_L; T from the EoS; E = e + |u|^2/2 (dim planes for u). */
+int pond_moments(pond_handle *h, double *rho, double *u, double *T, double *p, double *E);
+
+/* Conservation monitors of the current state (eq. 2 and App. F), FP64 sums in a
+ * fixed order: out[0] = sum rho, out[1..dim] = sum rho u-hat, out[dim+1] = sum rho E,
+ * out[dim+2] = sum (rho E + kappa |grad rho|^2/2), out[dim+3] = min p,
+ * out[dim+4] = max over nodes and directions of |v_i| dt.  out holds dim + 5 values. */
+int pond_monitors(pond_handle *h, double *out);
+
+/* Number of completed steps since the last pond_init_fields. */
+int pond_steps_done(const pond_handle *h, long long *out);
+
+/* Human-readable description of the last error of the handle (never NULL). */
+const char *pond_last_error(const pond_handle *h);
+
+/* Release everything owned by h.  NULL is accepted. */
+int pond_destroy(pond_handle *h);
+
+/* Measurement: launch kernel `which` (0 = streaming with the predictor-corrector,
+ * 1 = Korteweg stress, 2 = force and thermodynamic closure, 3 = collision) `reps`
+ * times on the handle's stream on the current state and return the mean duration
+ * per launch in microseconds, from HIP events recorded on that stream.  The
+ * launches read the current state and overwrite only scratch planes, so the state
+ * is unchanged.  Errors: POND_E_STATE (not initialised), POND_E_INVALID. */
+int pond_time_kernel(pond_handle *h, int which, int reps, double *avg_us);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POND_H */

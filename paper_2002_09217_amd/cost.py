@@ -1,0 +1,43 @@
+"""Algorithmic cost model of one time step (per lattice node), used to express measured
+throughput against the MI355X rooflines.
+
+Bytes: the compulsory HBM traffic of a step is reading and writing the post-collision
+populations f, g (2 Q values) and the five side fields (gauge u_x, u_y, theta and the
+force F_x, F_y); neighbour reuse through LDS or caches is not counted.
+
+FLOPs of the streaming kernel (the dominant one), per receiver and pass, for the
+moment-first reconstruction: every set (f, g) has NF moment fields; each field is
+interpolated at the departure points of all Q directions with separable cubic weights
+(x: 3 departure abscissae x 5 window rows x 4 taps; y: Q directions x 4 taps) and
+contracted into the Q populations (one multiply and one FMA each).  A FMA counts as
+two flops.  The weights, Lagrange coefficients, moments and EoS of a pass, the donor
+moments of the tile and the output moments are added as fixed terms.
+"""
+from __future__ import annotations
+
+# MI355X (gfx950) peaks
+HBM_PEAK_GBS = 8000.0
+# 256 CUs x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz; FP64 vector and non-packed FP32
+VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+def bytes_per_node_step(dim: int, fp32_store: bool) -> int:
+    q = 9 if dim == 2 else 3
+    pop = 4 if fp32_store else 8
+    return 2 * (2 * q * pop + 5 * 8)
+
+
+def stream_flops_per_node(dim: int, n_pass: int) -> int:
+    if dim == 2:
+        per_field = 2 * (3 * 5 * 4 + 9 * 4 + 9) + 9   # 2 x 105 FMA + 9 MUL = 219
+        fields = 18
+        fixed_pass = 6 * 16 + 2 * 20 + 54 + 20         # weights, Lagrange coeffs, moments, EoS
+        donor = 340                                     # tile moments incl. the 2-node halo
+        out = 200                                       # central moments of the result
+    else:
+        per_field = 2 * (3 * 4 + 3) + 3
+        fields = 6
+        fixed_pass = 3 * 16 + 20 + 18 + 20
+        donor = 60
+        out = 60
+    return n_pass * (fields * per_field + fixed_pass) + donor + out

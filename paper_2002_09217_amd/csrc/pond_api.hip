@@ -1,0 +1,425 @@
+// pond_api.hip -- C ABI of libpond (see include/pond.h): handle lifetime, device
+// memory, step scheduling with HIP graphs, error state, readback and timing.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "pond.h"
+#include "pond_internal.h"
+
+using namespace pond;
+
+struct pond_handle {
+    pond_config cfg;
+    LaunchCtx lc;
+    DevState ds;
+    hipStream_t stream = nullptr;       // where work runs (caller's or owned)
+    bool own_stream = false;
+    hipStream_t capture_stream = nullptr; // used only to record graphs
+    hipGraphExec_t pair_exec[2] = {nullptr, nullptr}; // two steps starting from state 0 / 1
+    bool graphs_ok = true;
+    int cur = 0;                        // state buffer holding the current state
+    long long steps = 0;
+    bool initialised = false;
+    bool failed = false;
+    double *mon_partials = nullptr;
+    double *mon_out = nullptr;
+    int mon_blocks = 0;
+    char msg[256] = "ok";
+};
+
+namespace {
+
+const double kW1h[3] = {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0};
+
+int fail(pond_handle *h, int code, const char *fmt, ...)
+{
+    if (h) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(h->msg, sizeof h->msg, fmt, ap);
+        va_end(ap);
+    }
+    return code;
+}
+
+#define HIP_TRY(h, expr)                                                                        \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return fail((h), POND_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));            \
+    } while (0)
+
+double host_p(const pond_config &c, double rho, double T)
+{
+    return rho * c.R * T / (1.0 - c.b * rho) - c.a * rho * rho;
+}
+
+// equilibrium populations of (rho, u, T) with F = 0 in their own gauge (eqs. 7-8)
+bool make_ghost(const pond_config &c, const double st[5], GhostFace &G)
+{
+    const double rho = st[0], T = st[4];
+    const double u[2] = {st[1], c.dim == 2 ? st[2] : 0.0};
+    const double p = host_p(c, rho, T);
+    if (!(rho > 0.0) || !(p > 0.0) || !(1.0 - c.b * rho > 0.0) || !std::isfinite(p)) return false;
+    const double e = (c.R / c.delta) * T - c.a * rho;
+    const double theta = p / (rho * (1.0 / 3.0));
+    const double s = std::sqrt(theta);
+    const int Q = c.dim == 2 ? 9 : 3;
+    std::memset(&G, 0, sizeof G);
+    for (int q = 0; q < Q; ++q) {
+        const int cx = c.dim == 2 ? q / 3 - 1 : q - 1;
+        const int cy = c.dim == 2 ? q % 3 - 1 : 0;
+        const double w = c.dim == 2 ? kW1h[q / 3] * kW1h[q % 3] : kW1h[q];
+        const double vx = u[0] + s * cx, vy = u[1] + s * cy;
+        G.f[q] = rho * w;
+        G.g[q] = rho * w * (2.0 * e - c.dim * p / rho + vx * vx + vy * vy);
+    }
+    G.ux = u[0];
+    G.uy = u[1];
+    G.theta = theta;
+    G.rho = rho;
+    G.T = T;
+    G.h = e + p / rho;
+    G.mu = (1.0 / c.omega - 0.5) * p * c.dt;
+    G.kc = c.k_scale * G.mu * c.R * (1.0 + c.delta) / c.delta;
+    return true;
+}
+
+int enqueue_step(pond_handle *h, hipStream_t st, int from)
+{
+    LaunchCtx c = h->lc;
+    c.st = st;
+    const DevState &s = h->ds;
+    HIP_TRY(h, launch_stream(c, s, from));
+    if (h->cfg.kappa != 0.0) HIP_TRY(h, launch_korteweg(c, s, s.mom));
+    HIP_TRY(h, launch_force_thermo(c, s));
+    HIP_TRY(h, launch_collide(c, s, 1 - from, 1));
+    return POND_OK;
+}
+
+// record two steps starting from state `from` into an executable graph
+int build_pair_graph(pond_handle *h, int from)
+{
+    if (h->pair_exec[from]) return POND_OK;
+    hipGraph_t g = nullptr;
+    HIP_TRY(h, hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue_step(h, h->capture_stream, from);
+    if (rc == POND_OK) rc = enqueue_step(h, h->capture_stream, 1 - from);
+    hipError_t e = hipStreamEndCapture(h->capture_stream, &g);
+    if (rc != POND_OK) return rc;
+    if (e != hipSuccess) return fail(h, POND_E_DEVICE, "graph capture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&h->pair_exec[from], g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        h->pair_exec[from] = nullptr;
+        return fail(h, POND_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
+    }
+    return POND_OK;
+}
+
+int read_flags(pond_handle *h, int out[kFlagWords])
+{
+    HIP_TRY(h, hipMemcpyAsync(out, h->ds.flags, sizeof(int) * kFlagWords, hipMemcpyDeviceToHost,
+                              h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return POND_OK;
+}
+
+int err_code(int bits)
+{
+    if (bits & kErrNonfinite) return POND_E_NONFINITE;
+    if (bits & kErrPressure) return POND_E_PRESSURE;
+    if (bits & kErrHalo) return POND_E_HALO;
+    return POND_E_DEVICE;
+}
+
+const char *err_name(int bits)
+{
+    if (bits & kErrNonfinite) return "non-finite state";
+    if (bits & kErrPressure) return "state outside the EoS domain (p <= 0, rho <= 0 or 1 - b rho <= 0)";
+    if (bits & kErrHalo) return "departure stencil outside the +-2 window (|v| dt >= 1)";
+    return "unknown";
+}
+
+void free_all(pond_handle *h)
+{
+    for (int i = 0; i < 2; ++i) {
+        if (h->pair_exec[i]) hipGraphExecDestroy(h->pair_exec[i]);
+        if (h->ds.pop[i]) hipFree(h->ds.pop[i]);
+        if (h->ds.side[i]) hipFree(h->ds.side[i]);
+    }
+    if (h->ds.mom) hipFree(h->ds.mom);
+    if (h->ds.kor) hipFree(h->ds.kor);
+    if (h->ds.aux) hipFree(h->ds.aux);
+    if (h->ds.flags) hipFree(h->ds.flags);
+    if (h->ds.params) hipFree(h->ds.params);
+    if (h->mon_partials) hipFree(h->mon_partials);
+    if (h->mon_out) hipFree(h->mon_out);
+    if (h->capture_stream) hipStreamDestroy(h->capture_stream);
+    if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
+}
+
+} // namespace
+
+extern "C" {
+
+int pond_create(const pond_config *cfg, pond_handle **out)
+{
+    if (!out) return POND_E_INVALID;
+    *out = nullptr;
+    if (!cfg) return POND_E_INVALID;
+    const pond_config &c = *cfg;
+    if (c.dim != 1 && c.dim != 2) return POND_E_INVALID;
+    const int nx = c.n[0], ny = c.dim == 2 ? c.n[1] : 1;
+    if (nx < 1 || ny < 1 || (long long)nx * ny > (1LL << 30)) return POND_E_INVALID;
+    if (!(c.delta > 0.0 && c.delta <= 2.0 / 3.0)) return POND_E_INVALID;
+    if (!(c.omega > 0.0 && c.omega < 2.0)) return POND_E_INVALID;
+    if (c.n_pass < 1 || c.n_pass > 64 || !(c.dt > 0.0) || !(c.R > 0.0)) return POND_E_INVALID;
+    if (c.precision != POND_FP64 && c.precision != POND_FP32_STORE) return POND_E_INVALID;
+    for (int a = 0; a < c.dim; ++a)
+        for (int s = 0; s < 2; ++s)
+            if (c.bc[a][s] < 0 || c.bc[a][s] > 2) return POND_E_INVALID;
+
+    pond_handle *h = new (std::nothrow) pond_handle();
+    if (!h) return POND_E_NOMEM;
+    h->cfg = c;
+    if (c.dim == 1) {
+        h->cfg.n[1] = 1;
+        h->cfg.n[2] = 1;
+    }
+    const int N = nx * ny;
+    const int Q = c.dim == 2 ? 9 : 3;
+    h->lc = LaunchCtx{c.dim, nx, ny, N, c.precision == POND_FP32_STORE ? 1 : 0, nullptr};
+
+    DevParams P;
+    std::memset(&P, 0, sizeof P);
+    P.dim = c.dim;
+    P.nx = nx;
+    P.ny = ny;
+    P.N = N;
+    for (int a = 0; a < 2; ++a)
+        for (int s = 0; s < 2; ++s) P.bc[a][s] = a < c.dim ? c.bc[a][s] : kPeriodic;
+    P.n_pass = c.n_pass;
+    P.a = c.a;
+    P.b = c.b;
+    P.R = c.R;
+    P.delta = c.delta;
+    P.omega = c.omega;
+    P.kappa = c.kappa;
+    P.k_scale = c.k_scale;
+    P.dt = c.dt;
+    P.Cv = c.R / c.delta;
+    P.Cp_ig = c.R * (1.0 + c.delta) / c.delta;
+    for (int a = 0; a < c.dim; ++a)
+        for (int s = 0; s < 2; ++s)
+            if (c.bc[a][s] == kInflow && !make_ghost(c, c.inflow[a][s], P.ghost[2 * a + s])) {
+                delete h;
+                return POND_E_INVALID;
+            }
+
+    int rc = POND_OK;
+    const size_t popb = (size_t)2 * Q * N * (h->lc.fp32 ? sizeof(float) : sizeof(double));
+    const int momPlanes = c.dim == 2 ? Layout<2>::kMomPlanes : Layout<1>::kMomPlanes;
+    auto alloc = [&](void **p, size_t bytes) {
+        if (rc != POND_OK) return;
+        if (hipMalloc(p, bytes) != hipSuccess) {
+            *p = nullptr;
+            rc = fail(h, POND_E_NOMEM, "hipMalloc of %zu bytes failed", bytes);
+        }
+    };
+    for (int i = 0; i < 2; ++i) {
+        alloc(&h->ds.pop[i], popb);
+        alloc((void **)&h->ds.side[i], sizeof(double) * kSidePlanes * N);
+    }
+    alloc((void **)&h->ds.mom, sizeof(double) * momPlanes * N);
+    alloc((void **)&h->ds.kor, sizeof(double) * kKorPlanes * N);
+    alloc((void **)&h->ds.aux, sizeof(double) * kAuxPlanes * N);
+    alloc((void **)&h->ds.flags, sizeof(int) * kFlagWords);
+    alloc((void **)&h->ds.params, sizeof(DevParams));
+    h->mon_blocks = monitor_blocks(h->lc);
+    alloc((void **)&h->mon_partials, sizeof(double) * 8 * h->mon_blocks);
+    alloc((void **)&h->mon_out, sizeof(double) * 8);
+    if (rc == POND_OK) {
+        if (c.stream) {
+            h->stream = (hipStream_t)c.stream;
+        } else if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) == hipSuccess) {
+            h->own_stream = true;
+        } else {
+            rc = POND_E_DEVICE;
+        }
+    }
+    if (rc == POND_OK && hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking) != hipSuccess)
+        rc = POND_E_DEVICE;
+    if (rc == POND_OK) {
+        h->lc.st = h->stream;
+        if (hipMemcpy(h->ds.params, &P, sizeof P, hipMemcpyHostToDevice) != hipSuccess)
+            rc = POND_E_DEVICE;
+    }
+    if (rc != POND_OK) {
+        free_all(h);
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return POND_OK;
+}
+
+int pond_init_fields(pond_handle *h, const double *rho, const double *u, const double *T)
+{
+    if (!h) return POND_E_INVALID;
+    if (!rho || !u || !T) return fail(h, POND_E_INVALID, "NULL field");
+    const int N = h->lc.N, dim = h->lc.dim;
+    h->initialised = false;
+    h->failed = false;
+    // stage the inputs in the aux planes: rho | u (dim planes) | T
+    double *d_rho = h->ds.aux, *d_u = h->ds.aux + N, *d_T = h->ds.aux + (size_t)(1 + dim) * N;
+    HIP_TRY(h, hipMemcpyAsync(d_rho, rho, sizeof(double) * N, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(d_u, u, sizeof(double) * N * dim, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(d_T, T, sizeof(double) * N, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, launch_reset_flags(h->lc, h->ds.flags));
+    if (h->cfg.kappa != 0.0) HIP_TRY(h, launch_korteweg(h->lc, h->ds, d_rho));
+    HIP_TRY(h, launch_init_equilibrium(h->lc, h->ds, d_rho, d_u, d_T));
+    if (h->cfg.kappa != 0.0) HIP_TRY(h, launch_korteweg(h->lc, h->ds, h->ds.mom));
+    HIP_TRY(h, launch_force_thermo(h->lc, h->ds));
+    HIP_TRY(h, launch_collide(h->lc, h->ds, 0, 0));
+    int fl[kFlagWords];
+    int rc = read_flags(h, fl);
+    if (rc != POND_OK) return rc;
+    if (fl[kFlagErr]) return fail(h, err_code(fl[kFlagErr]), "init: %s", err_name(fl[kFlagErr]));
+    h->cur = 0;
+    h->steps = 0;
+    h->initialised = true;
+    std::snprintf(h->msg, sizeof h->msg, "ok");
+    return POND_OK;
+}
+
+int pond_step(pond_handle *h, int nsteps)
+{
+    if (!h || nsteps < 0) return POND_E_INVALID;
+    if (!h->initialised || h->failed) return fail(h, POND_E_STATE, h->failed ? "handle in error state" : "not initialised");
+    if (nsteps == 0) return POND_OK;
+    HIP_TRY(h, launch_reset_flags(h->lc, h->ds.flags));
+    int parity = h->cur;
+    int left = nsteps;
+    if (h->graphs_ok && nsteps >= 2) {
+        if (build_pair_graph(h, parity) != POND_OK) h->graphs_ok = false;
+    }
+    if (h->graphs_ok && nsteps >= 2) {
+        // a pair returns to the same buffer parity
+        for (; left >= 2; left -= 2) HIP_TRY(h, hipGraphLaunch(h->pair_exec[parity], h->stream));
+    }
+    for (; left > 0; --left) {
+        int rc = enqueue_step(h, h->stream, parity);
+        if (rc != POND_OK) return rc;
+        parity = 1 - parity;
+    }
+    int fl[kFlagWords];
+    int rc = read_flags(h, fl);
+    if (rc != POND_OK) return rc;
+    const int done = fl[kFlagSteps];
+    h->cur = (h->cur + done) % 2;
+    h->steps += done;
+    if (fl[kFlagErr]) {
+        h->failed = true;
+        return fail(h, err_code(fl[kFlagErr]), "step %lld: %s", h->steps + 1, err_name(fl[kFlagErr]));
+    }
+    return POND_OK;
+}
+
+int pond_moments(pond_handle *h, double *rho, double *u, double *T, double *p, double *E)
+{
+    if (!h) return POND_E_INVALID;
+    if (!h->initialised) return fail(h, POND_E_STATE, "not initialised");
+    const size_t N = h->lc.N;
+    const int dim = h->lc.dim;
+    HIP_TRY(h, launch_macro(h->lc, h->ds, h->cur, h->ds.aux));
+    const double *base = h->ds.aux;
+    struct {
+        double *dst;
+        size_t off, count;
+    } parts[] = {{rho, 0, N}, {u, N, N * dim}, {T, (1 + dim) * N, N}, {p, (2 + dim) * N, N},
+                 {E, (3 + dim) * N, N}};
+    for (auto &pt : parts)
+        if (pt.dst)
+            HIP_TRY(h, hipMemcpyAsync(pt.dst, base + pt.off, sizeof(double) * pt.count,
+                                      hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return POND_OK;
+}
+
+int pond_monitors(pond_handle *h, double *out)
+{
+    if (!h || !out) return POND_E_INVALID;
+    if (!h->initialised) return fail(h, POND_E_STATE, "not initialised");
+    HIP_TRY(h, launch_monitors(h->lc, h->ds, h->cur, h->mon_partials, h->mon_blocks, h->mon_out));
+    double tmp[8];
+    HIP_TRY(h, hipMemcpyAsync(tmp, h->mon_out, sizeof tmp, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    std::memcpy(out, tmp, sizeof(double) * (h->lc.dim + 5));
+    return POND_OK;
+}
+
+int pond_steps_done(const pond_handle *h, long long *out)
+{
+    if (!h || !out) return POND_E_INVALID;
+    *out = h->steps;
+    return POND_OK;
+}
+
+const char *pond_last_error(const pond_handle *h) { return h ? h->msg : "NULL handle"; }
+
+int pond_destroy(pond_handle *h)
+{
+    if (!h) return POND_OK;
+    if (h->stream) hipStreamSynchronize(h->stream);
+    free_all(h);
+    delete h;
+    return POND_OK;
+}
+
+int pond_time_kernel(pond_handle *h, int which, int reps, double *avg_us)
+{
+    if (!h || !avg_us || reps < 1 || which < 0 || which > 3) return POND_E_INVALID;
+    if (!h->initialised || h->failed) return fail(h, POND_E_STATE, "not initialised");
+    const DevState &s = h->ds;
+    const LaunchCtx &c = h->lc;
+    HIP_TRY(h, launch_reset_flags(c, s.flags));
+    // bring the scratch planes to the current step's values first
+    HIP_TRY(h, launch_stream(c, s, h->cur));
+    if (h->cfg.kappa != 0.0) HIP_TRY(h, launch_korteweg(c, s, s.mom));
+    HIP_TRY(h, launch_force_thermo(c, s));
+    hipEvent_t e0, e1;
+    HIP_TRY(h, hipEventCreate(&e0));
+    HIP_TRY(h, hipEventCreate(&e1));
+    HIP_TRY(h, hipEventRecord(e0, h->stream));
+    for (int r = 0; r < reps; ++r) {
+        hipError_t e = hipSuccess;
+        switch (which) {
+        case 0: e = launch_stream(c, s, h->cur); break;
+        case 1: e = launch_korteweg(c, s, s.mom); break;
+        case 2: e = launch_force_thermo(c, s); break;
+        case 3: e = launch_collide(c, s, 1 - h->cur, 0); break;
+        }
+        if (e != hipSuccess) return fail(h, POND_E_DEVICE, "timing launch: %s", hipGetErrorString(e));
+    }
+    HIP_TRY(h, hipEventRecord(e1, h->stream));
+    HIP_TRY(h, hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIP_TRY(h, hipEventElapsedTime(&ms, e0, e1));
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    *avg_us = 1000.0 * (double)ms / reps;
+    int fl[kFlagWords];
+    int rc = read_flags(h, fl);
+    if (rc != POND_OK) return rc;
+    if (fl[kFlagErr]) return fail(h, err_code(fl[kFlagErr]), "timing: %s", err_name(fl[kFlagErr]));
+    return POND_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,190 @@
+// pond_device.h -- device-side algebra of the two-population Particles-on-Demand step
+// (Reyhanian, Dorschner & Karlin, arXiv:2002.09217) for gfx950.
+//
+// Everything here is per node and FP64 unless the caller instantiates it with float.
+// The lattice is D1Q3 or D2Q9 = C1 x C1 with C1 = {-1, 0, 1}, W = (1/6, 2/3, 1/6),
+// T_L = 1/3 (App. B).  Population index q = 3 (cx + 1) + (cy + 1) in 2D (x factor
+// outer), q = cx + 1 in 1D.  Moment index mn = 3 m + n for sum_i f_i wx^m wy^n.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "pond_internal.h"
+
+namespace pond {
+
+constexpr double kTL = 1.0 / 3.0;
+constexpr double kW1[3] = {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0};
+
+// ---------------------------------------------------------------------------
+// van der Waals thermodynamics (main text; App. A)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double vdw_p(const DevParams &P, double rho, double T)
+{
+    return rho * P.R * T / (1.0 - P.b * rho) - P.a * rho * rho;
+}
+__device__ __forceinline__ double vdw_T_of_e(const DevParams &P, double rho, double e)
+{
+    return P.delta * (e + P.a * rho) / P.R;
+}
+// bit set of the admissibility violations of a state (pressure domain, finiteness)
+__device__ __forceinline__ int vdw_bad(const DevParams &P, double rho, double p)
+{
+    if (!isfinite(rho) || !isfinite(p)) return kErrNonfinite;
+    if (!(p > 0.0) || !(1.0 - P.b * rho > 0.0) || !(rho > 0.0)) return kErrPressure;
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// boundary mapping: node index >= 0, or -(1 + face) for an inflow ghost,
+// face = 2 axis + side.  Periodic faces wrap, outflow faces clamp.
+// ---------------------------------------------------------------------------
+template <int DIM>
+__device__ __forceinline__ int map_node(const DevParams &P, int x, int y)
+{
+    if (x < 0 || x >= P.nx) {
+        const int side = x < 0 ? 0 : 1;
+        const int bc = P.bc[0][side];
+        if (bc == kPeriodic)
+            x = ((x % P.nx) + P.nx) % P.nx;
+        else if (bc == kOutflow)
+            x = x < 0 ? 0 : P.nx - 1;
+        else
+            return -(1 + side);
+    }
+    if (DIM == 2) {
+        if (y < 0 || y >= P.ny) {
+            const int side = y < 0 ? 0 : 1;
+            const int bc = P.bc[1][side];
+            if (bc == kPeriodic)
+                y = ((y % P.ny) + P.ny) % P.ny;
+            else if (bc == kOutflow)
+                y = y < 0 ? 0 : P.ny - 1;
+            else
+                return -(1 + 2 + side);
+        }
+        return x + P.nx * y;
+    }
+    return x;
+}
+
+// ---------------------------------------------------------------------------
+// moments of one population set about a reference velocity (rx, ry):
+// out[3m+n] = sum_{a,b} f_ab (ux - rx + s (a-1))^m (uy - ry + s (b-1))^n  (2D)
+// out[m]    = sum_a f_a (ux - rx + s (a-1))^m                              (1D)
+// These are the moments of App. C taken about (rx, ry) instead of 0; the
+// shift keeps them well scaled for any flow speed.
+// ---------------------------------------------------------------------------
+template <int DIM, typename T>
+__device__ __forceinline__ void moments_about(const T *f, double dux, double duy, double s,
+                                              double *out)
+{
+    if (DIM == 2) {
+        double cy[3] = {duy - s, duy, duy + s};
+        double cx[3] = {dux - s, dux, dux + s};
+        double col[3][3]; // col[a][n] = sum_b f_ab cy_b^n
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const double fv = (double)f[3 * a + b];
+                s0 += fv;
+                s1 += fv * cy[b];
+                s2 += fv * cy[b] * cy[b];
+            }
+            col[a][0] = s0;
+            col[a][1] = s1;
+            col[a][2] = s2;
+        }
+#pragma unroll
+        for (int n = 0; n < 3; ++n) {
+            out[0 + n] = col[0][n] + col[1][n] + col[2][n];
+            out[3 + n] = col[0][n] * cx[0] + col[1][n] * cx[1] + col[2][n] * cx[2];
+            out[6 + n] = col[0][n] * cx[0] * cx[0] + col[1][n] * cx[1] * cx[1] +
+                         col[2][n] * cx[2] * cx[2];
+        }
+    } else {
+        double cx[3] = {dux - s, dux, dux + s};
+        out[0] = (double)f[0] + (double)f[1] + (double)f[2];
+        out[1] = (double)f[0] * cx[0] + (double)f[1] * cx[1] + (double)f[2] * cx[2];
+        out[2] = (double)f[0] * cx[0] * cx[0] + (double)f[1] * cx[1] * cx[1] +
+                 (double)f[2] * cx[2] * cx[2];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Coefficients of the quadratic Lagrange basis on the three velocities
+// du + s c, c = -1, 0, 1 (relative to the same reference as the moments):
+// L_k(w) = A[k][0] + A[k][1] w + A[k][2] w^2.  Re-expressing populations given
+// by their moments into this gauge is f_k = sum_m A[k][m] M_m per axis; this is
+// the transfer matrix M'^{-1} M of App. C written through the moments.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void lagrange_coeffs(double du, double s, double A[3][3])
+{
+    const double inv = 1.0 / (s * s);
+    const double h = 0.5 * inv;
+    A[0][0] = (du * du + s * du) * h;
+    A[0][1] = -(2.0 * du + s) * h;
+    A[0][2] = h;
+    A[1][0] = 1.0 - du * du * inv;
+    A[1][1] = 2.0 * du * inv;
+    A[1][2] = -inv;
+    A[2][0] = (du * du - s * du) * h;
+    A[2][1] = (s - 2.0 * du) * h;
+    A[2][2] = h;
+}
+
+// ---------------------------------------------------------------------------
+// Cubic Lagrange reconstruction (App. D) for the three departure points of one
+// axis, x - (u + s c) dt, c = -1, 0, 1, written into a five-wide window centred on
+// the receiver (window column j <-> lattice offset j - 2).  Returns a nonzero
+// halo flag when a stencil would leave the window.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ int window_weights(double u, double s, double dt, T w[3][5])
+{
+    int bad = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double v = u + s * (double)(k - 1);
+        const double d = -v * dt;            // displacement of the departure point
+        const double fl = floor(d);
+        const double t = d - fl + 1.0;       // coordinate inside the 4-node stencil
+        int i0 = (int)fl;                    // stencil nodes i0-1 .. i0+2
+        const double w0 = -(t - 1.0) * (t - 2.0) * (t - 3.0) * (1.0 / 6.0);
+        const double w1 = t * (t - 2.0) * (t - 3.0) * 0.5;
+        const double w2 = -t * (t - 1.0) * (t - 3.0) * 0.5;
+        const double w3 = t * (t - 1.0) * (t - 2.0) * (1.0 / 6.0);
+        if (i0 < -1 || i0 > 0) {
+            bad = kErrHalo;
+            i0 = i0 < -1 ? -1 : 0;
+        }
+        const int o = i0 + 1; // first window column of the stencil: 0 or 1
+#pragma unroll
+        for (int j = 0; j < 5; ++j) w[k][j] = (T)0;
+        if (o == 0) {
+            w[k][0] = (T)w0; w[k][1] = (T)w1; w[k][2] = (T)w2; w[k][3] = (T)w3;
+        } else {
+            w[k][1] = (T)w0; w[k][2] = (T)w1; w[k][3] = (T)w2; w[k][4] = (T)w3;
+        }
+    }
+    return bad;
+}
+
+// ---------------------------------------------------------------------------
+// collision pieces (eqs. 9, 16-22; App. F)
+// ---------------------------------------------------------------------------
+// Force source S = G^{u}_{u+du}[rho W] - rho W per axis: the equilibrium of the gauge
+// (u + du, theta) in the gauge (u, theta) is rho prod_axes (W_c + sig_c(du)) with
+// sig_0 = -du^2/theta, sig_pm = du^2/(2 theta) pm du/(2 sqrt(theta)).
+__device__ __forceinline__ void source_axis(double du, double theta, double s, double sig[3])
+{
+    const double q = du * du / theta;
+    const double l = du / (2.0 * s);
+    sig[0] = 0.5 * q - l;
+    sig[1] = -q;
+    sig[2] = 0.5 * q + l;
+}
+
+} // namespace pond

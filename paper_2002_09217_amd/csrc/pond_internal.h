@@ -1,0 +1,94 @@
+// pond_internal.h -- data layout and launcher declarations shared by the HIP
+// kernels and the C-ABI layer of libpond.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace pond {
+
+enum { kPeriodic = 0, kOutflow = 1, kInflow = 2 };
+
+// error bits written by the kernels into flags[0]
+enum { kErrPressure = 1, kErrNonfinite = 2, kErrHalo = 4 };
+
+// Inflow ghost state of one face: the equilibrium of (rho, u, T) with F = 0, as
+// populations in its own gauge plus the scalar fields the gradient stencils read.
+struct GhostFace {
+    double f[9], g[9];     // populations, same index convention as the lattice
+    double ux, uy, theta;  // gauge
+    double rho, T, h, mu, kc;
+};
+
+// Per-lattice parameters, resident in device memory and read through a pointer.
+struct DevParams {
+    int dim, nx, ny, N;    // N = nx * ny nodes, index = x + nx * y
+    int bc[2][2];
+    int n_pass, pad_;
+    double a, b, R, delta, omega, kappa, k_scale, dt;
+    double Cv, Cp_ig;      // R/delta and R(1 + delta)/delta
+    GhostFace ghost[4];    // face 2 axis + side
+};
+
+// ---------------------------------------------------------------------------
+// Plane layout (structure of arrays, one plane of N values per entry).
+//   state:  f[Q], g[Q]       populations, PopT (double or float), node's own gauge
+//           side[5]          u_x, u_y, theta (gauge), F_x, F_y  (double)
+//   mom:    the streamed state after the predictor-corrector, gauge free:
+//           rho, u_x, u_y, then the central moments about u of f (those not fixed
+//           by rho and u) and of g.  2D: 3 + 6 + 9 = 18 planes; 1D: 2 + 1 + 3 = 6.
+//   kor:    Korteweg stress K_xx, K_xy, K_yy
+//   aux:    F_x, F_y, T, h, mu, kc, theta_final of the current step
+// ---------------------------------------------------------------------------
+template <int DIM> struct Layout;
+template <> struct Layout<2> {
+    static constexpr int Q = 9, NF = 9;
+    static constexpr int kRho = 0, kUx = 1, kUy = 2, kF = 3, kG = 9, kMomPlanes = 18;
+    // central f moments stored: (m,n) = (1,1), (2,0), (0,2), (2,1), (1,2), (2,2)
+    static constexpr int kFStored = 6;
+};
+template <> struct Layout<1> {
+    static constexpr int Q = 3, NF = 3;
+    static constexpr int kRho = 0, kUx = 1, kUy = 1, kF = 2, kG = 3, kMomPlanes = 6;
+    static constexpr int kFStored = 1; // m = 2
+};
+enum { kSideUx = 0, kSideUy = 1, kSideTh = 2, kSideFx = 3, kSideFy = 4, kSidePlanes = 5 };
+enum { kAuxFx = 0, kAuxFy = 1, kAuxT = 2, kAuxH = 3, kAuxMu = 4, kAuxKc = 5, kAuxTh = 6,
+       kAuxPlanes = 7 };
+enum { kKorPlanes = 3 };
+
+// flags[0]: error bits, flags[1]: completed-step counter of the current batch
+enum { kFlagErr = 0, kFlagSteps = 1, kFlagWords = 4 };
+
+// device buffers of one lattice
+struct DevState {
+    void *pop[2];       // 2 Q planes each: f then g
+    double *side[2];    // kSidePlanes planes each
+    double *mom;        // kMomPlanes planes
+    double *kor;        // kKorPlanes planes
+    double *aux;        // kAuxPlanes planes
+    int *flags;         // kFlagWords ints
+    DevParams *params;  // device copy
+};
+
+// ---------------------------------------------------------------------------
+// launchers (pond_kernels.hip); all enqueue on `st` and return hipError_t
+// ---------------------------------------------------------------------------
+struct LaunchCtx {
+    int dim, nx, ny, N;
+    int fp32;           // populations stored as float
+    hipStream_t st;
+};
+
+hipError_t launch_reset_flags(const LaunchCtx &c, int *flags);
+hipError_t launch_stream(const LaunchCtx &c, const DevState &s, int cur);
+hipError_t launch_korteweg(const LaunchCtx &c, const DevState &s, const double *rho);
+hipError_t launch_force_thermo(const LaunchCtx &c, const DevState &s);
+hipError_t launch_collide(const LaunchCtx &c, const DevState &s, int dst, int count_step);
+hipError_t launch_init_equilibrium(const LaunchCtx &c, const DevState &s, const double *rho,
+                                   const double *u, const double *T);
+hipError_t launch_macro(const LaunchCtx &c, const DevState &s, int cur, double *out);
+hipError_t launch_monitors(const LaunchCtx &c, const DevState &s, int cur, double *partials,
+                           int nblocks, double *out);
+int monitor_blocks(const LaunchCtx &c);
+
+} // namespace pond

@@ -1,0 +1,875 @@
+// pond_kernels.hip -- HIP kernels (gfx950) of the two-population Particles-on-Demand
+// time step of Reyhanian, Dorschner & Karlin, arXiv:2002.09217.
+//
+// One time step is four kernels on the device state (see pond_internal.h):
+//   k_stream        semi-Lagrangian streaming of f and g at v_i = sqrt(theta) c_i + u
+//                   (eqs. 1, 3-4) with donors re-expressed in the receiver gauge
+//                   (App. C) and cubic reconstruction (App. D), inside the fixed-count
+//                   predictor-corrector on (rho, u, E) through the EoS; writes the
+//                   streamed state as gauge-free moments
+//   k_korteweg      Korteweg stress K (eq. 18)
+//   k_force_thermo  F = -div K, actual velocity, T, p, h, mu, k of the step
+//   k_collide       heat-flux correction M0 (eq. 9), re-expression of the streamed
+//                   state in the collision gauge (u, theta), BGK collision of f with
+//                   the force source (eqs. 16-17) and of g with the force-extended
+//                   equilibrium and the sources g~ + phi (eqs. 19-22)
+//
+// The streaming kernel works "moment first": every donor's populations are reduced
+// once to their nine moments about a tile reference velocity (LDS), the nine moment
+// fields are interpolated at the departure points, and the receiver-gauge
+// populations follow from the quadratic Lagrange coefficients of the receiver
+// velocities.  Since the transfer matrix is M'^{-1} M and the reconstruction is
+// linear, this equals re-gauging every donor first and interpolating afterwards.
+#include <hip/hip_runtime.h>
+
+#include "pond_device.h"
+#include "pond_internal.h"
+
+namespace pond {
+
+// ---------------------------------------------------------------------------
+// flags
+// ---------------------------------------------------------------------------
+__global__ void k_reset_flags(int *flags)
+{
+    if (threadIdx.x < kFlagWords) flags[threadIdx.x] = 0;
+}
+
+hipError_t launch_reset_flags(const LaunchCtx &c, int *flags)
+{
+    hipLaunchKernelGGL(k_reset_flags, dim3(1), dim3(64), 0, c.st, flags);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// streaming with the predictor-corrector
+// ---------------------------------------------------------------------------
+template <int DIM> struct StreamTile;
+template <> struct StreamTile<2> { static constexpr int TX = 32, TY = 8; };
+template <> struct StreamTile<1> { static constexpr int TX = 256, TY = 1; };
+
+template <int DIM, typename PopT, typename LdsT, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY)
+    k_stream(const DevParams *__restrict__ Pp, const PopT *__restrict__ fpop,
+             const double *__restrict__ side, double *__restrict__ mom, int *__restrict__ flags)
+{
+    using L = Layout<DIM>;
+    constexpr int Q = L::Q, NF = L::NF, H = 2;
+    constexpr int LX = TX + 2 * H;
+    constexpr int LY = DIM == 2 ? TY + 2 * H : 1;
+    constexpr int LN = LX * LY;
+    __shared__ LdsT lds[2 * NF][LN];
+    __shared__ int abort_block;
+
+    // leave the state alone after an earlier failure; the decision is taken once per
+    // block so that every wave of the block reaches the barrier below or none does
+    const int tid = threadIdx.x + TX * threadIdx.y;
+    if (tid == 0) abort_block = flags[kFlagErr];
+    __syncthreads();
+    if (abort_block != 0) return;
+    const DevParams &P = *Pp;
+    const int N = P.N;
+    const PopT *gpop = fpop + (size_t)Q * N;
+    const int bx0 = blockIdx.x * TX;
+    const int by0 = DIM == 2 ? blockIdx.y * TY : 0;
+
+    // reference velocity of the tile: gauge velocity at its (clamped) centre node
+    const int cnode = min(bx0 + TX / 2, P.nx - 1) + P.nx * (DIM == 2 ? min(by0 + TY / 2, P.ny - 1) : 0);
+    const double rx = side[kSideUx * N + cnode];
+    const double ry = DIM == 2 ? side[kSideUy * N + cnode] : 0.0;
+
+    // donors of the tile and its halo: moments about (rx, ry) into LDS
+    for (int li = tid; li < LN; li += TX * TY) {
+        const int lx = li % LX, ly = li / LX;
+        const int node = map_node<DIM>(P, bx0 - H + lx, by0 - H + ly);
+        double m[2 * NF];
+        if (node >= 0) {
+            PopT pf[Q], pg[Q];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                pf[q] = fpop[(size_t)q * N + node];
+                pg[q] = gpop[(size_t)q * N + node];
+            }
+            const double ux = side[kSideUx * N + node];
+            const double uy = DIM == 2 ? side[kSideUy * N + node] : 0.0;
+            const double s = sqrt(side[kSideTh * N + node]);
+            moments_about<DIM>(pf, ux - rx, uy - ry, s, m);
+            moments_about<DIM>(pg, ux - rx, uy - ry, s, m + NF);
+        } else {
+            const GhostFace &G = P.ghost[-node - 1];
+            const double s = sqrt(G.theta);
+            moments_about<DIM>(G.f, G.ux - rx, G.uy - ry, s, m);
+            moments_about<DIM>(G.g, G.ux - rx, G.uy - ry, s, m + NF);
+        }
+#pragma unroll
+        for (int i = 0; i < 2 * NF; ++i) lds[i][li] = (LdsT)m[i];
+    }
+    __syncthreads();
+
+    const int gx = bx0 + threadIdx.x;
+    const int gy = by0 + (DIM == 2 ? threadIdx.y : 0);
+    if (gx >= P.nx || (DIM == 2 && gy >= P.ny)) return;
+    const int node = gx + P.nx * gy;
+    double Ux = side[kSideUx * N + node];
+    double Uy = DIM == 2 ? side[kSideUy * N + node] : 0.0;
+    double th = side[kSideTh * N + node];
+    const double Fpx = side[kSideFx * N + node];
+    const double Fpy = DIM == 2 ? side[kSideFy * N + node] : 0.0;
+    const int wbase = (DIM == 2 ? threadIdx.y * LX : 0) + threadIdx.x; // window (gx-2, gy-2)
+    const double dt = P.dt;
+
+    double fq[Q], gq[Q];
+    double sUx = Ux, sUy = Uy, sS = 1.0; // gauge of the last pass's populations
+    double rho = 0.0;
+    int err = 0;
+    for (int pass = 0; pass < P.n_pass; ++pass) {
+        const double s = sqrt(th);
+        LdsT wx[3][5], wy[3][5];
+        err |= window_weights<LdsT>(Ux, s, dt, wx);
+        if (DIM == 2) err |= window_weights<LdsT>(Uy, s, dt, wy);
+        double A[3][3], B[3][3];
+        lagrange_coeffs(Ux - rx, s, A);
+        if (DIM == 2) lagrange_coeffs(Uy - ry, s, B);
+#pragma unroll 1
+        for (int set = 0; set < 2; ++set) {
+            // populations of this set in the receiver gauge, one per direction
+            double acc[Q];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) acc[q] = 0.0;
+            const LdsT *sbase = &lds[set * NF][wbase];
+#pragma unroll
+            for (int mn = 0; mn < NF; ++mn) {
+                const LdsT *win = sbase + mn * LN;
+                if (DIM == 2) {
+                    const int m = mn / 3, n = mn % 3;
+                    // I[k][l]: moment field mn interpolated at the departure point of
+                    // direction (k-1, l-1); rows are streamed through the x weights
+                    LdsT I[9];
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) I[i] = (LdsT)0;
+#pragma unroll
+                    for (int r = 0; r < 5; ++r) {
+                        const LdsT v0 = win[r * LX + 0], v1 = win[r * LX + 1], v2 = win[r * LX + 2],
+                                   v3 = win[r * LX + 3], v4 = win[r * LX + 4];
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) {
+                            const LdsT xk = wx[k][0] * v0 + wx[k][1] * v1 + wx[k][2] * v2 +
+                                            wx[k][3] * v3 + wx[k][4] * v4;
+#pragma unroll
+                            for (int l = 0; l < 3; ++l) I[3 * k + l] += wy[l][r] * xk;
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < 3; ++k)
+#pragma unroll
+                        for (int l = 0; l < 3; ++l) acc[3 * k + l] += A[k][m] * B[l][n] * (double)I[3 * k + l];
+                } else {
+                    const LdsT v0 = win[0], v1 = win[1], v2 = win[2], v3 = win[3], v4 = win[4];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const LdsT I = wx[k][0] * v0 + wx[k][1] * v1 + wx[k][2] * v2 + wx[k][3] * v3 +
+                                       wx[k][4] * v4;
+                        acc[k] += A[k][mn] * (double)I;
+                    }
+                }
+                // keep the fields apart: the scheduler would otherwise hoist the loads of
+                // all fields and run out of registers
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (set == 0) {
+#pragma unroll
+                for (int q = 0; q < Q; ++q) fq[q] = acc[q];
+            } else {
+#pragma unroll
+                for (int q = 0; q < Q; ++q) gq[q] = acc[q];
+            }
+        }
+        // moments of the streamed populations (eq. 2) and the EoS closure
+        double jx = 0.0, jy = 0.0, G2 = 0.0;
+        rho = 0.0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const double cx = DIM == 2 ? (double)(q / 3 - 1) : (double)(q - 1);
+            const double cy = DIM == 2 ? (double)(q % 3 - 1) : 0.0;
+            rho += fq[q];
+            jx += fq[q] * (Ux + s * cx);
+            if (DIM == 2) jy += fq[q] * (Uy + s * cy);
+            G2 += gq[q];
+        }
+        const double E = G2 / (2.0 * rho);
+        const double ux = jx / rho;
+        const double uy = DIM == 2 ? jy / rho : 0.0;
+        const double uhx = ux + Fpx * dt / (2.0 * rho);
+        const double uhy = DIM == 2 ? uy + Fpy * dt / (2.0 * rho) : 0.0;
+        const double e = E - 0.5 * (uhx * uhx + uhy * uhy);
+        const double T = vdw_T_of_e(P, rho, e);
+        const double p = vdw_p(P, rho, T);
+        err |= vdw_bad(P, rho, p);
+        sUx = Ux;
+        sUy = Uy;
+        sS = s;
+        Ux = ux;
+        Uy = uy;
+        th = p / (rho * kTL);
+    }
+
+    // streamed state for the collision: rho, u and central moments about u
+    double mf[NF], mg[NF];
+    moments_about<DIM>(fq, sUx - Ux, sUy - Uy, sS, mf);
+    moments_about<DIM>(gq, sUx - Ux, sUy - Uy, sS, mg);
+    mom[(size_t)L::kRho * N + node] = rho;
+    mom[(size_t)L::kUx * N + node] = Ux;
+    if (DIM == 2) {
+        mom[(size_t)L::kUy * N + node] = Uy;
+        mom[(size_t)(L::kF + 0) * N + node] = mf[4]; // (1,1)
+        mom[(size_t)(L::kF + 1) * N + node] = mf[6]; // (2,0)
+        mom[(size_t)(L::kF + 2) * N + node] = mf[2]; // (0,2)
+        mom[(size_t)(L::kF + 3) * N + node] = mf[7]; // (2,1)
+        mom[(size_t)(L::kF + 4) * N + node] = mf[5]; // (1,2)
+        mom[(size_t)(L::kF + 5) * N + node] = mf[8]; // (2,2)
+    } else {
+        mom[(size_t)L::kF * N + node] = mf[2];
+    }
+#pragma unroll
+    for (int i = 0; i < NF; ++i) mom[(size_t)(L::kG + i) * N + node] = mg[i];
+    if (err) atomicOr(&flags[kFlagErr], err);
+}
+
+template <int DIM, typename PopT, typename LdsT>
+static hipError_t launch_stream_t(const LaunchCtx &c, const DevState &s, int cur)
+{
+    constexpr int TX = StreamTile<DIM>::TX, TY = StreamTile<DIM>::TY;
+    dim3 block(TX, TY);
+    dim3 grid((c.nx + TX - 1) / TX, DIM == 2 ? (c.ny + TY - 1) / TY : 1);
+    hipLaunchKernelGGL((k_stream<DIM, PopT, LdsT, TX, TY>), grid, block, 0, c.st, s.params,
+                       (const PopT *)s.pop[cur], s.side[cur], s.mom, s.flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream(const LaunchCtx &c, const DevState &s, int cur)
+{
+    if (c.dim == 2)
+        return c.fp32 ? launch_stream_t<2, float, float>(c, s, cur)
+                      : launch_stream_t<2, double, double>(c, s, cur);
+    return c.fp32 ? launch_stream_t<1, float, float>(c, s, cur)
+                  : launch_stream_t<1, double, double>(c, s, cur);
+}
+
+// ---------------------------------------------------------------------------
+// Korteweg stress K = -kappa (rho lap rho + |grad rho|^2/2) I + kappa grad rho grad rho
+// with the isotropic lattice stencils grad = (1/T_L) sum W c, lap = (2/T_L) sum W (. - .0)
+// ---------------------------------------------------------------------------
+template <int DIM>
+__global__ void k_korteweg(const DevParams *__restrict__ Pp, const double *__restrict__ rho,
+                           double *__restrict__ kor, const int *__restrict__ flags)
+{
+    if (flags[kFlagErr] != 0) return;
+    const DevParams &P = *Pp;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = DIM == 2 ? blockIdx.y * blockDim.y + threadIdx.y : 0;
+    if (x >= P.nx || y >= (DIM == 2 ? P.ny : 1)) return;
+    const int node = x + P.nx * y;
+    const int N = P.N;
+    const double r0 = rho[node];
+    double gx = 0.0, gy = 0.0, lap = 0.0;
+    constexpr int Q = Layout<DIM>::Q;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int cx = DIM == 2 ? q / 3 - 1 : q - 1;
+        const int cy = DIM == 2 ? q % 3 - 1 : 0;
+        const double w = DIM == 2 ? kW1[q / 3] * kW1[q % 3] : kW1[q];
+        const int nb = map_node<DIM>(P, x + cx, y + cy);
+        const double rq = nb >= 0 ? rho[nb] : P.ghost[-nb - 1].rho;
+        gx += w * (double)cx * rq;
+        gy += w * (double)cy * rq;
+        lap += w * (rq - r0);
+    }
+    gx /= kTL;
+    gy /= kTL;
+    lap *= 2.0 / kTL;
+    const double iso = -P.kappa * (r0 * lap + 0.5 * (gx * gx + gy * gy));
+    kor[0 * (size_t)N + node] = iso + P.kappa * gx * gx;
+    kor[1 * (size_t)N + node] = P.kappa * gx * gy;
+    kor[2 * (size_t)N + node] = DIM == 2 ? iso + P.kappa * gy * gy : 0.0;
+}
+
+static inline void grid2(const LaunchCtx &c, dim3 &grid, dim3 &block)
+{
+    if (c.dim == 2) {
+        block = dim3(64, 4);
+        grid = dim3((c.nx + 63) / 64, (c.ny + 3) / 4);
+    } else {
+        block = dim3(256, 1);
+        grid = dim3((c.nx + 255) / 256, 1);
+    }
+}
+
+hipError_t launch_korteweg(const LaunchCtx &c, const DevState &s, const double *rho)
+{
+    dim3 grid, block;
+    grid2(c, grid, block);
+    if (c.dim == 2)
+        hipLaunchKernelGGL(k_korteweg<2>, grid, block, 0, c.st, s.params, rho, s.kor, s.flags);
+    else
+        hipLaunchKernelGGL(k_korteweg<1>, grid, block, 0, c.st, s.params, rho, s.kor, s.flags);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// F = -div K, actual velocity and the thermodynamic state of the step (App. F)
+// ---------------------------------------------------------------------------
+template <int DIM>
+__device__ __forceinline__ void korteweg_force_at(const DevParams &P, const double *__restrict__ kor,
+                                                  int x, int y, double &Fx, double &Fy)
+{
+    Fx = 0.0;
+    Fy = 0.0;
+    if (P.kappa == 0.0) return;
+    const size_t N = P.N;
+    double dvx = 0.0, dvy = 0.0;
+    constexpr int Q = Layout<DIM>::Q;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int cx = DIM == 2 ? q / 3 - 1 : q - 1;
+        const int cy = DIM == 2 ? q % 3 - 1 : 0;
+        const double w = DIM == 2 ? kW1[q / 3] * kW1[q % 3] : kW1[q];
+        const int nb = map_node<DIM>(P, x + cx, y + cy);
+        double kxx = 0.0, kxy = 0.0, kyy = 0.0; // inflow ghosts are uniform: K = 0
+        if (nb >= 0) {
+            kxx = kor[0 * N + nb];
+            kxy = kor[1 * N + nb];
+            kyy = kor[2 * N + nb];
+        }
+        dvx += w * (kxx * (double)cx + kxy * (double)cy);
+        dvy += w * (kxy * (double)cx + kyy * (double)cy);
+    }
+    Fx = -dvx / kTL;
+    Fy = DIM == 2 ? -dvy / kTL : 0.0;
+}
+
+template <int DIM>
+__global__ void k_force_thermo(const DevParams *__restrict__ Pp, const double *__restrict__ mom,
+                               const double *__restrict__ kor, double *__restrict__ aux,
+                               int *__restrict__ flags)
+{
+    if (flags[kFlagErr] != 0) return;
+    using L = Layout<DIM>;
+    const DevParams &P = *Pp;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = DIM == 2 ? blockIdx.y * blockDim.y + threadIdx.y : 0;
+    if (x >= P.nx || y >= (DIM == 2 ? P.ny : 1)) return;
+    const int node = x + P.nx * y;
+    const size_t N = P.N;
+    double Fx, Fy;
+    korteweg_force_at<DIM>(P, kor, x, y, Fx, Fy);
+    const double rho = mom[L::kRho * N + node];
+    const double ux = mom[L::kUx * N + node];
+    const double uy = DIM == 2 ? mom[L::kUy * N + node] : 0.0;
+    const double E = mom[L::kG * N + node] / (2.0 * rho);
+    const double uhx = ux + Fx * P.dt / (2.0 * rho);
+    const double uhy = DIM == 2 ? uy + Fy * P.dt / (2.0 * rho) : 0.0;
+    const double e = E - 0.5 * (uhx * uhx + uhy * uhy);
+    const double T = vdw_T_of_e(P, rho, e);
+    const double p = vdw_p(P, rho, T);
+    const int bad = vdw_bad(P, rho, p);
+    if (bad) atomicOr(&flags[kFlagErr], bad);
+    const double mu = (1.0 / P.omega - 0.5) * p * P.dt;
+    aux[kAuxFx * N + node] = Fx;
+    aux[kAuxFy * N + node] = Fy;
+    aux[kAuxT * N + node] = T;
+    aux[kAuxH * N + node] = e + p / rho;
+    aux[kAuxMu * N + node] = mu;
+    aux[kAuxKc * N + node] = P.k_scale * mu * P.R * (1.0 + P.delta) / P.delta;
+    aux[kAuxTh * N + node] = p; // pressure of the step (theta = p/(rho T_L))
+}
+
+hipError_t launch_force_thermo(const LaunchCtx &c, const DevState &s)
+{
+    dim3 grid, block;
+    grid2(c, grid, block);
+    if (c.dim == 2)
+        hipLaunchKernelGGL(k_force_thermo<2>, grid, block, 0, c.st, s.params, s.mom, s.kor, s.aux,
+                           s.flags);
+    else
+        hipLaunchKernelGGL(k_force_thermo<1>, grid, block, 0, c.st, s.params, s.mom, s.kor, s.aux,
+                           s.flags);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// collision (eqs. 9, 16-22; App. F)
+// ---------------------------------------------------------------------------
+template <int DIM, typename PopT>
+__global__ void k_collide(const DevParams *__restrict__ Pp, const double *__restrict__ mom,
+                          const double *__restrict__ aux, PopT *__restrict__ fout,
+                          double *__restrict__ side_out, int *__restrict__ flags, int count_step)
+{
+    using L = Layout<DIM>;
+    constexpr int Q = L::Q, NF = L::NF;
+    if (count_step && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
+        if (flags[kFlagErr] == 0) atomicAdd(&flags[kFlagSteps], 1);
+    }
+    if (flags[kFlagErr] != 0) return;
+    const DevParams &P = *Pp;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = DIM == 2 ? blockIdx.y * blockDim.y + threadIdx.y : 0;
+    if (x >= P.nx || y >= (DIM == 2 ? P.ny : 1)) return;
+    const int node = x + P.nx * y;
+    const size_t N = P.N;
+    const double dt = P.dt;
+
+    // heat-flux correction M0 = 2 div(-mu grad h + k grad T), flux form (eq. 9)
+    double M0 = 0.0;
+    if (P.k_scale >= 0.0) {
+        const double T0 = aux[kAuxT * N + node], h0 = aux[kAuxH * N + node];
+        const double m0 = aux[kAuxMu * N + node], k0 = aux[kAuxKc * N + node];
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int cx = DIM == 2 ? q / 3 - 1 : q - 1;
+            const int cy = DIM == 2 ? q % 3 - 1 : 0;
+            const double w = DIM == 2 ? kW1[q / 3] * kW1[q % 3] : kW1[q];
+            const int nb = map_node<DIM>(P, x + cx, y + cy);
+            double Tq, hq, mq, kq;
+            if (nb >= 0) {
+                Tq = aux[kAuxT * N + nb];
+                hq = aux[kAuxH * N + nb];
+                mq = aux[kAuxMu * N + nb];
+                kq = aux[kAuxKc * N + nb];
+            } else {
+                const GhostFace &G = P.ghost[-nb - 1];
+                Tq = G.T;
+                hq = G.h;
+                mq = G.mu;
+                kq = G.kc;
+            }
+            const double kmid = 0.5 * (kq + k0);
+            const double mmid = 0.5 * (mq + m0);
+            acc += w * (kmid * (Tq - T0) - mmid * (hq - h0));
+        }
+        M0 = 2.0 * (2.0 / kTL) * acc;
+    }
+
+    const double rho = mom[L::kRho * N + node];
+    const double u[2] = {mom[L::kUx * N + node], DIM == 2 ? mom[L::kUy * N + node] : 0.0};
+    const double F[2] = {aux[kAuxFx * N + node], DIM == 2 ? aux[kAuxFy * N + node] : 0.0};
+    const double p = aux[kAuxTh * N + node];
+    const double theta = p / (rho * kTL);
+    const double s = sqrt(theta);
+    const double E = mom[L::kG * N + node] / (2.0 * rho);
+    const double uh[2] = {u[0] + F[0] * dt / (2.0 * rho), DIM == 2 ? u[1] + F[1] * dt / (2.0 * rho) : 0.0};
+
+    // streamed populations in the collision gauge (u, theta) from their central moments
+    double mf[NF], mg[NF];
+    if (DIM == 2) {
+        mf[0] = rho;
+        mf[1] = 0.0; // (0,1): zero about u
+        mf[3] = 0.0; // (1,0)
+        mf[4] = mom[(L::kF + 0) * N + node];
+        mf[6] = mom[(L::kF + 1) * N + node];
+        mf[2] = mom[(L::kF + 2) * N + node];
+        mf[7] = mom[(L::kF + 3) * N + node];
+        mf[5] = mom[(L::kF + 4) * N + node];
+        mf[8] = mom[(L::kF + 5) * N + node];
+    } else {
+        mf[0] = rho;
+        mf[1] = 0.0;
+        mf[2] = mom[L::kF * N + node];
+    }
+#pragma unroll
+    for (int i = 0; i < NF; ++i) mg[i] = mom[(L::kG + i) * N + node];
+    double A[3][3];
+    lagrange_coeffs(0.0, s, A);
+    double f[Q], g[Q];
+    if (DIM == 2) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                double sf = 0.0, sg = 0.0;
+#pragma unroll
+                for (int m = 0; m < 3; ++m)
+#pragma unroll
+                    for (int n = 0; n < 3; ++n) {
+                        sf += A[k][m] * A[l][n] * mf[3 * m + n];
+                        sg += A[k][m] * A[l][n] * mg[3 * m + n];
+                    }
+                f[3 * k + l] = sf;
+                g[3 * k + l] = sg;
+            }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            f[k] = A[k][0] * mf[0] + A[k][1] * mf[1] + A[k][2] * mf[2];
+            g[k] = A[k][0] * mg[0] + A[k][1] * mg[1] + A[k][2] * mg[2];
+        }
+    }
+
+    // f: BGK towards rho W plus the force source (eqs. 16-17)
+    double sx[3], sy[3] = {0.0, 0.0, 0.0};
+    source_axis(F[0] * dt / rho, theta, s, sx);
+    if (DIM == 2) source_axis(F[1] * dt / rho, theta, s, sy);
+    PopT *gout = fout + (size_t)Q * N;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int k = DIM == 2 ? q / 3 : q;
+        const int l = DIM == 2 ? q % 3 : 1;
+        const double wk = kW1[k], wl = DIM == 2 ? kW1[l] : 1.0;
+        const double S = DIM == 2 ? rho * (wk * sy[l] + sx[k] * wl + sx[k] * sy[l]) : rho * sx[k];
+        const double feq = rho * (wk * wl);
+        fout[(size_t)q * N + node] = (PopT)(f[q] + P.omega * (feq - f[q]) + S);
+    }
+
+    // g: BGK towards the force-extended equilibrium plus (g~ + phi) dt (eqs. 19-22)
+    const double Pr = p / rho;
+    const double H = E + Pr;
+    double X[2][2], M[2], Nm[2][2];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+        for (int b = 0; b < DIM; ++b)
+            X[a][b] = uh[a] * F[b] + F[a] * uh[b] + dt * F[a] * F[b] * E / (2.0 * p);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        double xu = 0.0;
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) xu += X[a][b] * u[b];
+        M[a] = dt / Pr * (F[a] * H - xu);
+    }
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) Nm[a][b] = (a == b ? rho : 0.0) + dt / (2.0 * Pr) * X[a][b];
+    double work = 0.0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) work += 2.0 * uh[a] * F[a];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const double c[2] = {DIM == 2 ? (double)(q / 3 - 1) : (double)(q - 1),
+                             DIM == 2 ? (double)(q % 3 - 1) : 0.0};
+        const double wq = DIM == 2 ? kW1[q / 3] * kW1[q % 3] : kW1[q];
+        double v[2], t1 = 0.0, t2 = 0.0, uc = 0.0, v2 = 0.0;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            v[a] = u[a] + s * c[a];
+            uc += u[a] * c[a];
+            v2 += v[a] * v[a];
+        }
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) t1 += M[a] * (v[a] - u[a]);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+#pragma unroll
+            for (int b = 0; b < DIM; ++b) t2 += Nm[a][b] * (v[a] * v[b] - (a == b ? Pr : 0.0) - u[a] * u[b]);
+        const double geq = wq * (2.0 * rho * E + t1 + t2);
+        const double psi = wq * (1.0 + rho * uc * uc / (2.0 * p * kTL) - rho * v2 / (2.0 * p) + 0.5 * (double)DIM);
+        gout[(size_t)q * N + node] = (PopT)(g[q] + P.omega * (geq - g[q]) + (M0 + work) * psi * dt);
+    }
+    side_out[kSideUx * N + node] = u[0];
+    side_out[kSideTh * N + node] = theta;
+    side_out[kSideFx * N + node] = F[0];
+    if (DIM == 2) {
+        side_out[kSideUy * N + node] = u[1];
+        side_out[kSideFy * N + node] = F[1];
+    }
+}
+
+hipError_t launch_collide(const LaunchCtx &c, const DevState &s, int dst, int count_step)
+{
+    dim3 grid, block;
+    grid2(c, grid, block);
+    if (c.dim == 2) {
+        if (c.fp32)
+            hipLaunchKernelGGL((k_collide<2, float>), grid, block, 0, c.st, s.params, s.mom, s.aux,
+                               (float *)s.pop[dst], s.side[dst], s.flags, count_step);
+        else
+            hipLaunchKernelGGL((k_collide<2, double>), grid, block, 0, c.st, s.params, s.mom, s.aux,
+                               (double *)s.pop[dst], s.side[dst], s.flags, count_step);
+    } else {
+        if (c.fp32)
+            hipLaunchKernelGGL((k_collide<1, float>), grid, block, 0, c.st, s.params, s.mom, s.aux,
+                               (float *)s.pop[dst], s.side[dst], s.flags, count_step);
+        else
+            hipLaunchKernelGGL((k_collide<1, double>), grid, block, 0, c.st, s.params, s.mom, s.aux,
+                               (double *)s.pop[dst], s.side[dst], s.flags, count_step);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// initial state: equilibrium of (rho, u_hat, T) with the force F0 = -div K(rho),
+// written as the streamed-state moments so that the regular closure and collision
+// kernels turn it into the stored populations
+// ---------------------------------------------------------------------------
+template <int DIM>
+__global__ void k_init_equilibrium(const DevParams *__restrict__ Pp, const double *__restrict__ rho_in,
+                                   const double *__restrict__ u_in, const double *__restrict__ T_in,
+                                   const double *__restrict__ kor, double *__restrict__ mom,
+                                   int *__restrict__ flags)
+{
+    using L = Layout<DIM>;
+    constexpr int Q = L::Q, NF = L::NF;
+    const DevParams &P = *Pp;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = DIM == 2 ? blockIdx.y * blockDim.y + threadIdx.y : 0;
+    if (x >= P.nx || y >= (DIM == 2 ? P.ny : 1)) return;
+    const int node = x + P.nx * y;
+    const size_t N = P.N;
+    const double dt = P.dt;
+    double F[2];
+    korteweg_force_at<DIM>(P, kor, x, y, F[0], F[1]);
+    const double r = rho_in[node];
+    const double uh[2] = {u_in[node], DIM == 2 ? u_in[N + node] : 0.0};
+    const double u[2] = {uh[0] - F[0] * dt / (2.0 * r), DIM == 2 ? uh[1] - F[1] * dt / (2.0 * r) : 0.0};
+    const double T = T_in[node];
+    const double p = vdw_p(P, r, T);
+    const int bad = vdw_bad(P, r, p);
+    if (bad) atomicOr(&flags[kFlagErr], bad);
+    const double e = (P.R / P.delta) * T - P.a * r;
+    const double E = e + 0.5 * (uh[0] * uh[0] + uh[1] * uh[1]);
+    const double theta = p / (r * kTL);
+    const double s = sqrt(theta);
+    const double Pr = p / r;
+    const double H = E + Pr;
+    double X[2][2], M[2], Nm[2][2];
+    for (int a = 0; a < DIM; ++a)
+        for (int b = 0; b < DIM; ++b)
+            X[a][b] = uh[a] * F[b] + F[a] * uh[b] + dt * F[a] * F[b] * E / (2.0 * p);
+    for (int a = 0; a < DIM; ++a) {
+        double xu = 0.0;
+        for (int b = 0; b < DIM; ++b) xu += X[a][b] * u[b];
+        M[a] = dt / Pr * (F[a] * H - xu);
+    }
+    for (int a = 0; a < DIM; ++a)
+        for (int b = 0; b < DIM; ++b) Nm[a][b] = (a == b ? r : 0.0) + dt / (2.0 * Pr) * X[a][b];
+    double f[Q], g[Q];
+    for (int q = 0; q < Q; ++q) {
+        const double c[2] = {DIM == 2 ? (double)(q / 3 - 1) : (double)(q - 1),
+                             DIM == 2 ? (double)(q % 3 - 1) : 0.0};
+        const double wq = DIM == 2 ? kW1[q / 3] * kW1[q % 3] : kW1[q];
+        double v[2], t1 = 0.0, t2 = 0.0;
+        for (int a = 0; a < DIM; ++a) v[a] = u[a] + s * c[a];
+        for (int a = 0; a < DIM; ++a) t1 += M[a] * (v[a] - u[a]);
+        for (int a = 0; a < DIM; ++a)
+            for (int b = 0; b < DIM; ++b) t2 += Nm[a][b] * (v[a] * v[b] - (a == b ? Pr : 0.0) - u[a] * u[b]);
+        f[q] = r * wq;
+        g[q] = wq * (2.0 * r * E + t1 + t2);
+    }
+    double mf[NF], mg[NF];
+    moments_about<DIM>(f, 0.0, 0.0, s, mf);
+    moments_about<DIM>(g, 0.0, 0.0, s, mg);
+    mom[L::kRho * N + node] = r;
+    mom[L::kUx * N + node] = u[0];
+    if (DIM == 2) {
+        mom[L::kUy * N + node] = u[1];
+        mom[(L::kF + 0) * N + node] = mf[4];
+        mom[(L::kF + 1) * N + node] = mf[6];
+        mom[(L::kF + 2) * N + node] = mf[2];
+        mom[(L::kF + 3) * N + node] = mf[7];
+        mom[(L::kF + 4) * N + node] = mf[5];
+        mom[(L::kF + 5) * N + node] = mf[8];
+    } else {
+        mom[L::kF * N + node] = mf[2];
+    }
+    for (int i = 0; i < NF; ++i) mom[(L::kG + i) * N + node] = mg[i];
+}
+
+hipError_t launch_init_equilibrium(const LaunchCtx &c, const DevState &s, const double *rho,
+                                   const double *u, const double *T)
+{
+    dim3 grid, block;
+    grid2(c, grid, block);
+    if (c.dim == 2)
+        hipLaunchKernelGGL(k_init_equilibrium<2>, grid, block, 0, c.st, s.params, rho, u, T, s.kor,
+                           s.mom, s.flags);
+    else
+        hipLaunchKernelGGL(k_init_equilibrium<1>, grid, block, 0, c.st, s.params, rho, u, T, s.kor,
+                           s.mom, s.flags);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// macroscopic fields of a state: rho, u_hat (dim planes), T, p, E
+// ---------------------------------------------------------------------------
+template <int DIM, typename PopT>
+__global__ void k_macro(const DevParams *__restrict__ Pp, const PopT *__restrict__ fpop,
+                        const double *__restrict__ side, double *__restrict__ out)
+{
+    constexpr int Q = Layout<DIM>::Q;
+    const DevParams &P = *Pp;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = DIM == 2 ? blockIdx.y * blockDim.y + threadIdx.y : 0;
+    if (x >= P.nx || y >= (DIM == 2 ? P.ny : 1)) return;
+    const int n = x + P.nx * y;
+    const size_t N = P.N;
+    double r = 0.0;
+    for (int q = 0; q < Q; ++q) r += (double)fpop[q * N + n];
+    const double hx = side[kSideUx * N + n] + side[kSideFx * N + n] * P.dt / (2.0 * r);
+    const double hy = DIM == 2 ? side[kSideUy * N + n] + side[kSideFy * N + n] * P.dt / (2.0 * r) : 0.0;
+    const double pr = r * side[kSideTh * N + n] * kTL;
+    const double T = (pr + P.a * r * r) * (1.0 - P.b * r) / (r * P.R);
+    const double e = (P.R / P.delta) * T - P.a * r;
+    out[0 * N + n] = r;
+    out[1 * N + n] = hx;
+    if (DIM == 2) out[2 * N + n] = hy;
+    out[(1 + DIM) * N + n] = T;
+    out[(2 + DIM) * N + n] = pr;
+    out[(3 + DIM) * N + n] = e + 0.5 * (hx * hx + hy * hy);
+}
+
+hipError_t launch_macro(const LaunchCtx &c, const DevState &s, int cur, double *out)
+{
+    dim3 grid, block;
+    grid2(c, grid, block);
+    if (c.dim == 2) {
+        if (c.fp32)
+            hipLaunchKernelGGL((k_macro<2, float>), grid, block, 0, c.st, s.params,
+                               (const float *)s.pop[cur], s.side[cur], out);
+        else
+            hipLaunchKernelGGL((k_macro<2, double>), grid, block, 0, c.st, s.params,
+                               (const double *)s.pop[cur], s.side[cur], out);
+    } else {
+        if (c.fp32)
+            hipLaunchKernelGGL((k_macro<1, float>), grid, block, 0, c.st, s.params,
+                               (const float *)s.pop[cur], s.side[cur], out);
+        else
+            hipLaunchKernelGGL((k_macro<1, double>), grid, block, 0, c.st, s.params,
+                               (const double *)s.pop[cur], s.side[cur], out);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// conservation monitors: per-block partial sums (wavefront shuffles, then LDS),
+// reduced in a fixed order by one block.  Inputs are the macroscopic planes
+// written by k_macro (rho, u_hat, T, p, E).
+//   0 sum rho, 1..DIM sum rho u_hat, DIM+1 sum rho E,
+//   DIM+2 sum (rho E + kappa |grad rho|^2 / 2), DIM+3 min p, DIM+4 max |v_i| dt
+// ---------------------------------------------------------------------------
+constexpr int kMonWords = 8;
+constexpr int kMonThreads = 256;
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+template <int DIM>
+__global__ void __launch_bounds__(kMonThreads)
+    k_monitor_partials(const DevParams *__restrict__ Pp, const double *__restrict__ macro,
+                       const double *__restrict__ side, double *__restrict__ partials)
+{
+    const DevParams &P = *Pp;
+    const size_t N = P.N;
+    const int n = blockIdx.x * kMonThreads + threadIdx.x;
+    double v[kMonWords];
+    for (int i = 0; i < kMonWords; ++i) v[i] = 0.0;
+    v[DIM + 3] = 1e300;  // min p
+    v[DIM + 4] = 0.0;    // max |v| dt
+    if (n < P.N) {
+        const int x = n % P.nx, y = n / P.nx;
+        const double r = macro[n];
+        const double E = macro[(3 + DIM) * N + n];
+        double gx = 0.0, gy = 0.0;
+        constexpr int Q = Layout<DIM>::Q;
+        for (int q = 0; q < Q; ++q) {
+            const int cx = DIM == 2 ? q / 3 - 1 : q - 1;
+            const int cy = DIM == 2 ? q % 3 - 1 : 0;
+            const double w = DIM == 2 ? kW1[q / 3] * kW1[q % 3] : kW1[q];
+            const int nb = map_node<DIM>(P, x + cx, y + cy);
+            const double rq = nb >= 0 ? macro[nb] : P.ghost[-nb - 1].rho;
+            gx += w * (double)cx * rq;
+            gy += w * (double)cy * rq;
+        }
+        gx /= kTL;
+        gy /= kTL;
+        v[0] = r;
+        v[1] = r * macro[1 * N + n];
+        if (DIM == 2) v[2] = r * macro[2 * N + n];
+        v[DIM + 1] = r * E;
+        v[DIM + 2] = r * E + 0.5 * P.kappa * (gx * gx + gy * gy);
+        v[DIM + 3] = macro[(2 + DIM) * N + n];
+        const double s = sqrt(side[kSideTh * N + n]);
+        const double ax = fabs(side[kSideUx * N + n]) + s;
+        const double ay = DIM == 2 ? fabs(side[kSideUy * N + n]) + s : 0.0;
+        v[DIM + 4] = sqrt(ax * ax + ay * ay) * P.dt;
+    }
+    __shared__ double red[kMonThreads / 64][kMonWords];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int i = 0; i < kMonWords; ++i) {
+        double w;
+        if (i == DIM + 3)
+            w = wave_min(v[i]);
+        else if (i == DIM + 4)
+            w = wave_max(v[i]);
+        else
+            w = wave_sum(v[i]);
+        if (lane == 0) red[wave][i] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x < kMonWords) {
+        const int i = threadIdx.x;
+        double acc = red[0][i];
+        for (int wv = 1; wv < kMonThreads / 64; ++wv) {
+            if (i == DIM + 3)
+                acc = fmin(acc, red[wv][i]);
+            else if (i == DIM + 4)
+                acc = fmax(acc, red[wv][i]);
+            else
+                acc += red[wv][i];
+        }
+        partials[(size_t)blockIdx.x * kMonWords + i] = acc;
+    }
+}
+
+// one block; every thread owns one output word and walks the partials in order
+__global__ void k_monitor_final(const double *__restrict__ partials, int nblocks, int dim,
+                                double *__restrict__ out)
+{
+    const int i = threadIdx.x;
+    if (i >= kMonWords) return;
+    double acc = partials[i];
+    for (int b = 1; b < nblocks; ++b) {
+        const double x = partials[(size_t)b * kMonWords + i];
+        if (i == dim + 3)
+            acc = fmin(acc, x);
+        else if (i == dim + 4)
+            acc = fmax(acc, x);
+        else
+            acc += x;
+    }
+    out[i] = acc;
+}
+
+int monitor_blocks(const LaunchCtx &c) { return (c.N + kMonThreads - 1) / kMonThreads; }
+
+hipError_t launch_monitors(const LaunchCtx &c, const DevState &s, int cur, double *partials,
+                           int nblocks, double *out)
+{
+    hipError_t e = launch_macro(c, s, cur, s.aux);
+    if (e != hipSuccess) return e;
+    if (c.dim == 2)
+        hipLaunchKernelGGL(k_monitor_partials<2>, dim3(nblocks), dim3(kMonThreads), 0, c.st,
+                           s.params, s.aux, s.side[cur], partials);
+    else
+        hipLaunchKernelGGL(k_monitor_partials<1>, dim3(nblocks), dim3(kMonThreads), 0, c.st,
+                           s.params, s.aux, s.side[cur], partials);
+    hipLaunchKernelGGL(k_monitor_final, dim3(1), dim3(64), 0, c.st, partials, nblocks, c.dim, out);
+    return hipGetLastError();
+}
+
+} // namespace pond

@@ -1,0 +1,211 @@
+"""Python binding of libpond (include/pond.h): argument marshalling only.
+
+Every step of the method runs in the HIP kernels of libpond.so; this module only
+converts numpy arrays and Python values into the C ABI.  There is no fallback: a
+missing or unloadable library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libpond.so")
+
+POND_OK = 0
+STATUS = {
+    0: "POND_OK", -1: "POND_E_INVALID", -2: "POND_E_NOMEM", -3: "POND_E_DEVICE",
+    -4: "POND_E_PRESSURE", -5: "POND_E_NONFINITE", -6: "POND_E_HALO", -7: "POND_E_STATE",
+}
+BC_PERIODIC, BC_OUTFLOW, BC_INFLOW = 0, 1, 2
+FP64, FP32_STORE = 0, 1
+
+# kernel ids of pond_time_kernel
+K_STREAM, K_KORTEWEG, K_FORCE_THERMO, K_COLLIDE = 0, 1, 2, 3
+KERNEL_NAMES = {K_STREAM: "k_stream", K_KORTEWEG: "k_korteweg", K_FORCE_THERMO: "k_force_thermo",
+                K_COLLIDE: "k_collide"}
+
+EXPORTED = ["pond_create", "pond_init_fields", "pond_step", "pond_moments", "pond_monitors",
+            "pond_steps_done", "pond_last_error", "pond_destroy", "pond_time_kernel"]
+
+
+class pond_config(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int),
+        ("n", ctypes.c_int * 3),
+        ("bc", (ctypes.c_int * 2) * 3),
+        ("inflow", ((ctypes.c_double * 5) * 2) * 3),
+        ("a", ctypes.c_double),
+        ("b", ctypes.c_double),
+        ("R", ctypes.c_double),
+        ("delta", ctypes.c_double),
+        ("omega", ctypes.c_double),
+        ("kappa", ctypes.c_double),
+        ("k_scale", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("n_pass", ctypes.c_int),
+        ("precision", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class PondError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str = ""):
+        super().__init__(f"{where}: {STATUS.get(code, code)} {msg}".strip())
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libpond.so; raises when it is missing (build it with paper_2002_09217_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2002_09217_amd.build`")
+    L = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    hp = ctypes.c_void_p
+    L.pond_create.argtypes = [ctypes.POINTER(pond_config), ctypes.POINTER(hp)]
+    L.pond_init_fields.argtypes = [hp, dp, dp, dp]
+    L.pond_step.argtypes = [hp, ctypes.c_int]
+    L.pond_moments.argtypes = [hp, dp, dp, dp, dp, dp]
+    L.pond_monitors.argtypes = [hp, dp]
+    L.pond_steps_done.argtypes = [hp, ctypes.POINTER(ctypes.c_longlong)]
+    L.pond_last_error.argtypes = [hp]
+    L.pond_last_error.restype = ctypes.c_char_p
+    L.pond_destroy.argtypes = [hp]
+    L.pond_time_kernel.argtypes = [hp, ctypes.c_int, ctypes.c_int, dp]
+    for name in EXPORTED:
+        getattr(L, name).restype = getattr(L, name).restype or ctypes.c_int
+    L.pond_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+@dataclass
+class Config:
+    """Mirror of pond_config (lattice units: dx = 1)."""
+    dim: int = 2
+    n: tuple = (64, 64)
+    bc: tuple = ((BC_PERIODIC, BC_PERIODIC), (BC_PERIODIC, BC_PERIODIC))
+    inflow: tuple = ()          # ((axis, side, (rho, ux, uy, T)), ...)
+    a: float = 2.0 / 49.0
+    b: float = 2.0 / 21.0
+    R: float = 1.0
+    delta: float = 1.0 / 3.0
+    omega: float = 1.5
+    kappa: float = 0.0
+    k_scale: float = 1.0
+    dt: float = 0.2
+    n_pass: int = 2
+    precision: int = FP64
+    stream: int | None = None   # hipStream_t as an integer (e.g. torch's cuda_stream)
+
+    def to_c(self) -> pond_config:
+        c = pond_config()
+        c.dim = self.dim
+        n = tuple(self.n) + (1,) * (3 - len(self.n))
+        for i in range(3):
+            c.n[i] = int(n[i])
+        for a in range(min(self.dim, 2)):
+            for s in range(2):
+                c.bc[a][s] = int(self.bc[a][s])
+        for a, s, st in self.inflow:
+            rho, ux, uy, T = st
+            vals = (rho, ux, uy, 0.0, T)
+            for k in range(5):
+                c.inflow[a][s][k] = float(vals[k])
+        c.a, c.b, c.R, c.delta = self.a, self.b, self.R, self.delta
+        c.omega, c.kappa, c.k_scale, c.dt = self.omega, self.kappa, self.k_scale, self.dt
+        c.n_pass, c.precision = self.n_pass, self.precision
+        c.stream = self.stream
+        return c
+
+    @property
+    def N(self) -> int:
+        return int(np.prod(self.n[: self.dim]))
+
+
+@dataclass
+class Lattice:
+    """One libpond handle."""
+    cfg: Config
+    _h: ctypes.c_void_p = field(default=None, init=False, repr=False)
+
+    def __post_init__(self):
+        L = load()
+        self._c = self.cfg.to_c()
+        h = ctypes.c_void_p()
+        rc = L.pond_create(ctypes.byref(self._c), ctypes.byref(h))
+        if rc != POND_OK:
+            raise PondError(rc, "pond_create")
+        self._h = h
+
+    def _check(self, rc: int, where: str):
+        if rc != POND_OK:
+            raise PondError(rc, where, load().pond_last_error(self._h).decode())
+
+    def init_fields(self, rho, u, T):
+        N, dim = self.cfg.N, self.cfg.dim
+        rho = np.ascontiguousarray(rho, dtype=np.float64).ravel()
+        u = np.ascontiguousarray(u, dtype=np.float64).ravel()
+        T = np.ascontiguousarray(T, dtype=np.float64).ravel()
+        if rho.size != N or T.size != N or u.size != dim * N:
+            raise ValueError("field sizes do not match the lattice")
+        self._check(load().pond_init_fields(self._h, _dp(rho), _dp(u), _dp(T)), "pond_init_fields")
+        return self
+
+    def step(self, n: int = 1):
+        self._check(load().pond_step(self._h, int(n)), "pond_step")
+        return self
+
+    def moments(self) -> dict:
+        N, dim = self.cfg.N, self.cfg.dim
+        rho, u, T, p, E = np.empty(N), np.empty(dim * N), np.empty(N), np.empty(N), np.empty(N)
+        self._check(load().pond_moments(self._h, _dp(rho), _dp(u), _dp(T), _dp(p), _dp(E)), "pond_moments")
+        out = {"rho": rho, "ux": u[:N], "T": T, "p": p, "E": E}
+        out["uy"] = u[N:] if dim == 2 else np.zeros(N)
+        return out
+
+    def monitors(self) -> dict:
+        dim = self.cfg.dim
+        out = np.empty(dim + 5)
+        self._check(load().pond_monitors(self._h, _dp(out)), "pond_monitors")
+        return {"mass": out[0], "momentum": out[1:1 + dim].copy(), "energy": out[dim + 1],
+                "energy_total": out[dim + 2], "min_p": out[dim + 3], "max_v_dt": out[dim + 4]}
+
+    def steps_done(self) -> int:
+        v = ctypes.c_longlong()
+        self._check(load().pond_steps_done(self._h, ctypes.byref(v)), "pond_steps_done")
+        return v.value
+
+    def time_kernel(self, which: int, reps: int) -> float:
+        """Mean duration of one launch of a kernel in microseconds (HIP events)."""
+        us = ctypes.c_double()
+        self._check(load().pond_time_kernel(self._h, int(which), int(reps), ctypes.byref(us)),
+                    "pond_time_kernel")
+        return us.value
+
+    def last_error(self) -> str:
+        return load().pond_last_error(self._h).decode()
+
+    def close(self):
+        if self._h is not None:
+            load().pond_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

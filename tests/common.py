@@ -1,0 +1,62 @@
+"""Helpers shared by the tests: run one workload Case on the oracle and on the HIP
+path through the C ABI, and compare fields."""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import core
+from paper_2002_09217_amd import pond
+
+# relative velocity errors are taken against max(|u|, U_ch), U_ch = sqrt(p_cr/rho_cr)
+U_CH = float(np.sqrt((1.0 / 6.0) / 3.5))
+
+
+def oracle_config(case) -> core.Config:
+    p = case.params
+    inflow = [[(0.0,) * 4, (0.0,) * 4], [(0.0,) * 4, (0.0,) * 4]]
+    for a, s, st in case.inflow:
+        inflow[a][s] = tuple(st)
+    return core.Config(dim=case.dim, nx=case.n[0], ny=case.n[1] if case.dim == 2 else 1,
+                       bc=case.bc, inflow=tuple(tuple(x) for x in inflow), a=p["a"], b=p["b"],
+                       R=p["R"], delta=p["delta"], omega=p["omega"], kappa=p["kappa"],
+                       k_scale=p["k_scale"], dt=p["dt"], n_pass=p["n_pass"])
+
+
+def pond_config(case, precision=pond.FP64, stream=None) -> pond.Config:
+    p = case.params
+    return pond.Config(dim=case.dim, n=tuple(case.n), bc=case.bc, inflow=case.inflow,
+                       a=p["a"], b=p["b"], R=p["R"], delta=p["delta"], omega=p["omega"],
+                       kappa=p["kappa"], k_scale=p["k_scale"], dt=p["dt"], n_pass=p["n_pass"],
+                       precision=precision, stream=stream)
+
+
+def run_oracle(case, steps):
+    sim = core.Sim(oracle_config(case))
+    uy = case.u[1] if case.dim == 2 else None
+    sim.init(case.rho, case.u[0], case.T, uy=uy)
+    if steps:
+        sim.step(steps)
+    return sim.moments()
+
+
+def run_gpu(case, steps, precision=pond.FP64):
+    lat = pond.Lattice(pond_config(case, precision))
+    try:
+        lat.init_fields(case.rho, case.u, case.T)
+        if steps:
+            lat.step(steps)
+        return lat.moments()
+    finally:
+        lat.close()
+
+
+def rel_err(a, b, field):
+    """Relative L-infinity error; velocities against max(max|b|, U_ch)."""
+    den = np.max(np.abs(b))
+    if field in ("ux", "uy"):
+        den = max(den, U_CH)
+    return float(np.max(np.abs(a - b)) / den)
+
+
+def compare(gpu, ref, fields=("rho", "ux", "uy", "E", "T", "p")):
+    return {f: rel_err(gpu[f], ref[f], f) for f in fields}

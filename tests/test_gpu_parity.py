@@ -1,0 +1,80 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on identical seeded
+inputs.  Bar: 1e-12 relative L-infinity on rho, u, E (and T, p) for the FP64 form;
+1e-4 for the FP32-storage form on smooth cases.
+
+Sizes span several 32 x 8 streaming tiles with ragged tails; the full 256 x 256
+droplet of the benchmark is compared after a few steps, where the oracle finishes in
+seconds."""
+import numpy as np
+import pytest
+
+from paper_2002_09217_amd import pond, workloads as W
+from tests.common import compare, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def _check(case, steps, tol=TOL64, precision=pond.FP64, fields=("rho", "ux", "uy", "E", "T", "p")):
+    ref = run_oracle(case, steps)
+    got = run_gpu(case, steps, precision)
+    errs = compare(got, ref, fields)
+    print(case.name, steps, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    assert not bad, f"{case.name}: {bad}"
+    return errs
+
+
+@pytest.mark.parametrize("n_pass", [1, 2, 3])
+@pytest.mark.parametrize("kappa", [0.0, 0.0176])
+def test_perturbed_2d_100_steps(n_pass, kappa):
+    case = W.perturbed(40, 36, seed=11 + n_pass, rho0=2.0, t_over_tcr=1.05, u0=(0.05, -0.03),
+                       n_pass=n_pass, kappa=kappa)
+    _check(case, 100)
+
+
+def test_perturbed_2d_one_step_large_velocity():
+    case = W.perturbed(33, 17, seed=5, rho0=1.0, t_over_tcr=1.4, u0=(1.0911, 0.3))
+    _check(case, 1)
+    _check(case, 20)
+
+
+def test_droplet_64_100_steps():
+    case = W.static_droplet(n=64, radius=14.0, steps=100)
+    _check(case, 100)
+
+
+def test_shock_tube_1d_100_steps():
+    case = W.shock_tube(n=1000)
+    _check(case, 100, fields=("rho", "ux", "E", "T", "p"))
+
+
+def test_perturbed_1d_ragged():
+    case = W.perturbed(300, 1, seed=3, dim=1, kappa=0.0176)
+    _check(case, 100, fields=("rho", "ux", "E", "T", "p"))
+
+
+def test_inflow_outflow_2d():
+    case = W.droplet_shock(nx=96, ny=40, radius=8.0, x_drop=50.0, x_shock=20.0)
+    _check(case, 50)
+
+
+def test_tiny_periodic_lattices():
+    for nx, ny in ((3, 5), (1, 9), (7, 1)):
+        case = W.perturbed(nx, ny, seed=nx * 10 + ny, kappa=0.0176)
+        _check(case, 10)
+
+
+def test_full_size_droplet_256_few_steps():
+    case = W.static_droplet(n=256)
+    _check(case, 3)
+
+
+@pytest.mark.parametrize("which", ["perturbed", "droplet"])
+def test_fp32_storage_within_1e4(which):
+    if which == "perturbed":
+        case = W.perturbed(40, 36, seed=21, kappa=0.0176)
+    else:
+        case = W.static_droplet(n=64, radius=14.0)
+    _check(case, 100, tol=1e-4, precision=pond.FP32_STORE)
