@@ -80,6 +80,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run a plain device-to-device copy of this many MiB (5 times), whose "
+                         "FETCH_SIZE/WRITE_SIZE counters calibrate the HBM-traffic readings")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)",
@@ -96,6 +99,16 @@ def main():
     case = W.static_droplet(n=256)
     N = case.N
     n_pass = case.params["n_pass"]
+
+    if args.copy_calibration_mib:
+        nb = args.copy_calibration_mib * (1 << 20)
+        src = torch.empty(nb // 4, dtype=torch.float32, device="cuda").uniform_()
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"bench: copy calibration, 5 copies of {args.copy_calibration_mib} MiB")
+        del src, dst
 
     log(f"bench: {case.name} FP64, warmup {args.warmup}, timed {args.steps} steps")
     t64, kern64, mon64 = gpu_run(case, pond.FP64, args.steps, args.warmup, stream.cuda_stream)
