@@ -9,7 +9,8 @@ whole lattice.  Prints one JSON line:
                in HBM, timed between stream synchronisations;
   fp32_store   the same with FP32 population storage;
   roofline     the streaming kernel (dominant) against the FP64 VALU peak, its mean
-               launch duration from HIP events on its stream;
+               launch duration from HIP events recorded on its stream around every
+               launch of a second timed run of steps;
   cpu_baseline the FP64 oracle on the host cores for a bounded number of steps.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
@@ -44,11 +45,8 @@ def gpu_run(case, precision, steps, warmup, stream):
     lat.step(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kern = {}
-    for k, name in pond.KERNEL_NAMES.items():
-        if k == pond.K_KORTEWEG and case.params["kappa"] == 0.0:
-            continue
-        kern[name] = lat.time_kernel(k, 200)
+    # per-kernel durations inside the step pipeline (HIP events on the same stream)
+    kern = lat.step_timed(min(steps, 500))
     mon = lat.monitors()
     lat.close()
     return (t1 - t0), kern, mon

@@ -15,6 +15,7 @@
  *      and the heat-flux correction M0                                (eq. 9)
  *   3. relaxes f and g to their equilibria with the force source S_i, the
  *      force-extended g equilibrium and the sources g~ + phi          (eqs. 16-22)
+ * on the device as two kernels (streaming; force, closure and collision).
  *
  * Conventions for every call below
  *   - All functions return a pond_status (0 = POND_OK, negative = error).
@@ -112,12 +113,19 @@ const char *pond_last_error(const pond_handle *h);
 int pond_destroy(pond_handle *h);
 
 /* Measurement: launch kernel `which` (0 = streaming with the predictor-corrector,
- * 1 = Korteweg stress, 2 = force and thermodynamic closure, 3 = collision) `reps`
- * times on the handle's stream on the current state and return the mean duration
- * per launch in microseconds, from HIP events recorded on that stream.  The
- * launches read the current state and overwrite only scratch planes, so the state
- * is unchanged.  Errors: POND_E_STATE (not initialised), POND_E_INVALID. */
+ * 1 = Korteweg force, closure and collision) `reps` times back to back on the
+ * handle's stream on the current state and return the mean duration per launch in
+ * microseconds, from HIP events recorded on that stream.  The launches read the
+ * current state and overwrite only scratch planes and the next-state buffer, so the
+ * state is unchanged.  Errors: POND_E_STATE (not initialised), POND_E_INVALID. */
 int pond_time_kernel(pond_handle *h, int which, int reps, double *avg_us);
+
+/* Measurement: advance nsteps >= 1 time steps exactly as pond_step does, but with
+ * the kernels launched one by one and HIP events recorded on the handle's stream
+ * around every launch; kernel_us[0] and kernel_us[1] receive the mean duration of
+ * the streaming kernel and of the force/collision kernel inside the step pipeline.
+ * Errors and state as for pond_step. */
+int pond_step_timed(pond_handle *h, int nsteps, double *kernel_us);
 
 #ifdef __cplusplus
 }

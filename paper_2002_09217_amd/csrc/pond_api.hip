@@ -97,9 +97,7 @@ int enqueue_step(pond_handle *h, hipStream_t st, int from)
     c.st = st;
     const DevState &s = h->ds;
     HIP_TRY(h, launch_stream(c, s, from));
-    if (h->cfg.kappa != 0.0) HIP_TRY(h, launch_korteweg(c, s, s.mom));
-    HIP_TRY(h, launch_force_thermo(c, s));
-    HIP_TRY(h, launch_collide(c, s, 1 - from, 1));
+    HIP_TRY(h, launch_force_collide(c, s, 1 - from));
     return POND_OK;
 }
 
@@ -163,6 +161,22 @@ void free_all(pond_handle *h)
     if (h->mon_out) hipFree(h->mon_out);
     if (h->capture_stream) hipStreamDestroy(h->capture_stream);
     if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
+}
+
+// read the flags after a batch of steps and move the handle to the last completed state
+int finish_batch(pond_handle *h)
+{
+    int fl[kFlagWords];
+    int rc = read_flags(h, fl);
+    if (rc != POND_OK) return rc;
+    const int done = fl[kFlagErr] ? fl[kFlagSteps] - 1 : fl[kFlagSteps];
+    h->cur = (h->cur + done) % 2;
+    h->steps += done;
+    if (fl[kFlagErr]) {
+        h->failed = true;
+        return fail(h, err_code(fl[kFlagErr]), "step %lld: %s", h->steps + 1, err_name(fl[kFlagErr]));
+    }
+    return POND_OK;
 }
 
 } // namespace
@@ -285,9 +299,7 @@ int pond_init_fields(pond_handle *h, const double *rho, const double *u, const d
     HIP_TRY(h, launch_reset_flags(h->lc, h->ds.flags));
     if (h->cfg.kappa != 0.0) HIP_TRY(h, launch_korteweg(h->lc, h->ds, d_rho));
     HIP_TRY(h, launch_init_equilibrium(h->lc, h->ds, d_rho, d_u, d_T));
-    if (h->cfg.kappa != 0.0) HIP_TRY(h, launch_korteweg(h->lc, h->ds, h->ds.mom));
-    HIP_TRY(h, launch_force_thermo(h->lc, h->ds));
-    HIP_TRY(h, launch_collide(h->lc, h->ds, 0, 0));
+    HIP_TRY(h, launch_force_collide(h->lc, h->ds, 0));
     int fl[kFlagWords];
     int rc = read_flags(h, fl);
     if (rc != POND_OK) return rc;
@@ -319,17 +331,7 @@ int pond_step(pond_handle *h, int nsteps)
         if (rc != POND_OK) return rc;
         parity = 1 - parity;
     }
-    int fl[kFlagWords];
-    int rc = read_flags(h, fl);
-    if (rc != POND_OK) return rc;
-    const int done = fl[kFlagSteps];
-    h->cur = (h->cur + done) % 2;
-    h->steps += done;
-    if (fl[kFlagErr]) {
-        h->failed = true;
-        return fail(h, err_code(fl[kFlagErr]), "step %lld: %s", h->steps + 1, err_name(fl[kFlagErr]));
-    }
-    return POND_OK;
+    return finish_batch(h);
 }
 
 int pond_moments(pond_handle *h, double *rho, double *u, double *T, double *p, double *E)
@@ -385,27 +387,19 @@ int pond_destroy(pond_handle *h)
 
 int pond_time_kernel(pond_handle *h, int which, int reps, double *avg_us)
 {
-    if (!h || !avg_us || reps < 1 || which < 0 || which > 3) return POND_E_INVALID;
+    if (!h || !avg_us || reps < 1 || which < 0 || which > 1) return POND_E_INVALID;
     if (!h->initialised || h->failed) return fail(h, POND_E_STATE, "not initialised");
     const DevState &s = h->ds;
     const LaunchCtx &c = h->lc;
     HIP_TRY(h, launch_reset_flags(c, s.flags));
     // bring the scratch planes to the current step's values first
     HIP_TRY(h, launch_stream(c, s, h->cur));
-    if (h->cfg.kappa != 0.0) HIP_TRY(h, launch_korteweg(c, s, s.mom));
-    HIP_TRY(h, launch_force_thermo(c, s));
     hipEvent_t e0, e1;
     HIP_TRY(h, hipEventCreate(&e0));
     HIP_TRY(h, hipEventCreate(&e1));
     HIP_TRY(h, hipEventRecord(e0, h->stream));
     for (int r = 0; r < reps; ++r) {
-        hipError_t e = hipSuccess;
-        switch (which) {
-        case 0: e = launch_stream(c, s, h->cur); break;
-        case 1: e = launch_korteweg(c, s, s.mom); break;
-        case 2: e = launch_force_thermo(c, s); break;
-        case 3: e = launch_collide(c, s, 1 - h->cur, 0); break;
-        }
+        hipError_t e = which == 0 ? launch_stream(c, s, h->cur) : launch_force_collide(c, s, 1 - h->cur);
         if (e != hipSuccess) return fail(h, POND_E_DEVICE, "timing launch: %s", hipGetErrorString(e));
     }
     HIP_TRY(h, hipEventRecord(e1, h->stream));
@@ -420,6 +414,48 @@ int pond_time_kernel(pond_handle *h, int which, int reps, double *avg_us)
     if (rc != POND_OK) return rc;
     if (fl[kFlagErr]) return fail(h, err_code(fl[kFlagErr]), "timing: %s", err_name(fl[kFlagErr]));
     return POND_OK;
+}
+
+int pond_step_timed(pond_handle *h, int nsteps, double *kernel_us)
+{
+    if (!h || !kernel_us || nsteps < 1) return POND_E_INVALID;
+    if (!h->initialised || h->failed) return fail(h, POND_E_STATE, h->failed ? "handle in error state" : "not initialised");
+    HIP_TRY(h, launch_reset_flags(h->lc, h->ds.flags));
+    hipEvent_t *ev = (hipEvent_t *)std::calloc((size_t)4 * nsteps, sizeof(hipEvent_t));
+    if (!ev) return fail(h, POND_E_NOMEM, "event array");
+    int rc = POND_OK;
+    int created = 0;
+    for (; created < 4 * nsteps; ++created)
+        if (hipEventCreate(&ev[created]) != hipSuccess) {
+            rc = fail(h, POND_E_DEVICE, "hipEventCreate");
+            break;
+        }
+    int parity = h->cur;
+    LaunchCtx c = h->lc;
+    for (int i = 0; rc == POND_OK && i < nsteps; ++i) {
+        hipEvent_t *e = ev + 4 * i;
+        if (hipEventRecord(e[0], h->stream) != hipSuccess || launch_stream(c, h->ds, parity) != hipSuccess ||
+            hipEventRecord(e[1], h->stream) != hipSuccess || hipEventRecord(e[2], h->stream) != hipSuccess ||
+            launch_force_collide(c, h->ds, 1 - parity) != hipSuccess || hipEventRecord(e[3], h->stream) != hipSuccess)
+            rc = fail(h, POND_E_DEVICE, "timed step launch");
+        parity = 1 - parity;
+    }
+    if (rc == POND_OK && hipStreamSynchronize(h->stream) != hipSuccess) rc = fail(h, POND_E_DEVICE, "sync");
+    double acc[2] = {0.0, 0.0};
+    for (int i = 0; rc == POND_OK && i < nsteps; ++i) {
+        float a = 0.0f, b = 0.0f;
+        if (hipEventElapsedTime(&a, ev[4 * i], ev[4 * i + 1]) != hipSuccess ||
+            hipEventElapsedTime(&b, ev[4 * i + 2], ev[4 * i + 3]) != hipSuccess)
+            rc = fail(h, POND_E_DEVICE, "hipEventElapsedTime");
+        acc[0] += a;
+        acc[1] += b;
+    }
+    for (int i = 0; i < created; ++i) hipEventDestroy(ev[i]);
+    std::free(ev);
+    if (rc != POND_OK) return rc;
+    kernel_us[0] = 1000.0 * acc[0] / nsteps;
+    kernel_us[1] = 1000.0 * acc[1] / nsteps;
+    return finish_batch(h);
 }
 
 } // extern "C"

@@ -36,6 +36,22 @@ __device__ __forceinline__ int vdw_bad(const DevParams &P, double rho, double p)
 }
 
 // ---------------------------------------------------------------------------
+// Workgroups are dispatched to the 8 XCDs of the MI355X round-robin (workgroup b
+// runs on XCD b mod 8), and each XCD has its own L2.  Renumber so that every XCD
+// owns one contiguous run of tiles (row-major): neighbouring tiles, and the halos
+// they share, then go through the same L2, and consecutive kernels that use the
+// same tiling find their inputs where the previous kernel wrote them.  The map is
+// a bijection of [0, nb).
+// ---------------------------------------------------------------------------
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_tile(int b, int nb)
+{
+    const int xcd = b % kXcds, local = b / kXcds;
+    const int per = nb / kXcds, rem = nb % kXcds;
+    return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
+}
+
+// ---------------------------------------------------------------------------
 // boundary mapping: node index >= 0, or -(1 + face) for an inflow ghost,
 // face = 2 axis + side.  Periodic faces wrap, outflow faces clamp.
 // ---------------------------------------------------------------------------

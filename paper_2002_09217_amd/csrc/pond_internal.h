@@ -36,8 +36,8 @@ struct DevParams {
 //   mom:    the streamed state after the predictor-corrector, gauge free:
 //           rho, u_x, u_y, then the central moments about u of f (those not fixed
 //           by rho and u) and of g.  2D: 3 + 6 + 9 = 18 planes; 1D: 2 + 1 + 3 = 6.
-//   kor:    Korteweg stress K_xx, K_xy, K_yy
-//   aux:    F_x, F_y, T, h, mu, kc, theta_final of the current step
+//   kor:    Korteweg stress K_xx, K_xy, K_yy (initial state only)
+//   aux:    staging of the initial fields and of the macroscopic read-back
 // ---------------------------------------------------------------------------
 template <int DIM> struct Layout;
 template <> struct Layout<2> {
@@ -52,11 +52,12 @@ template <> struct Layout<1> {
     static constexpr int kFStored = 1; // m = 2
 };
 enum { kSideUx = 0, kSideUy = 1, kSideTh = 2, kSideFx = 3, kSideFy = 4, kSidePlanes = 5 };
-enum { kAuxFx = 0, kAuxFy = 1, kAuxT = 2, kAuxH = 3, kAuxMu = 4, kAuxKc = 5, kAuxTh = 6,
-       kAuxPlanes = 7 };
+enum { kAuxPlanes = 7 };
 enum { kKorPlanes = 3 };
 
-// flags[0]: error bits, flags[1]: completed-step counter of the current batch
+// flags[0]: error bits; flags[1]: number of streaming launches of the current batch
+// that started without an earlier failure (= completed steps, or completed + 1
+// when a step failed)
 enum { kFlagErr = 0, kFlagSteps = 1, kFlagWords = 4 };
 
 // device buffers of one lattice
@@ -82,8 +83,7 @@ struct LaunchCtx {
 hipError_t launch_reset_flags(const LaunchCtx &c, int *flags);
 hipError_t launch_stream(const LaunchCtx &c, const DevState &s, int cur);
 hipError_t launch_korteweg(const LaunchCtx &c, const DevState &s, const double *rho);
-hipError_t launch_force_thermo(const LaunchCtx &c, const DevState &s);
-hipError_t launch_collide(const LaunchCtx &c, const DevState &s, int dst, int count_step);
+hipError_t launch_force_collide(const LaunchCtx &c, const DevState &s, int dst);
 hipError_t launch_init_equilibrium(const LaunchCtx &c, const DevState &s, const double *rho,
                                    const double *u, const double *T);
 hipError_t launch_macro(const LaunchCtx &c, const DevState &s, int cur, double *out);

@@ -1,18 +1,19 @@
 // pond_kernels.hip -- HIP kernels (gfx950) of the two-population Particles-on-Demand
 // time step of Reyhanian, Dorschner & Karlin, arXiv:2002.09217.
 //
-// One time step is four kernels on the device state (see pond_internal.h):
-//   k_stream        semi-Lagrangian streaming of f and g at v_i = sqrt(theta) c_i + u
-//                   (eqs. 1, 3-4) with donors re-expressed in the receiver gauge
-//                   (App. C) and cubic reconstruction (App. D), inside the fixed-count
-//                   predictor-corrector on (rho, u, E) through the EoS; writes the
-//                   streamed state as gauge-free moments
-//   k_korteweg      Korteweg stress K (eq. 18)
-//   k_force_thermo  F = -div K, actual velocity, T, p, h, mu, k of the step
-//   k_collide       heat-flux correction M0 (eq. 9), re-expression of the streamed
-//                   state in the collision gauge (u, theta), BGK collision of f with
-//                   the force source (eqs. 16-17) and of g with the force-extended
-//                   equilibrium and the sources g~ + phi (eqs. 19-22)
+// One time step is two kernels on the device state (see pond_internal.h):
+//   k_stream         semi-Lagrangian streaming of f and g at v_i = sqrt(theta) c_i + u
+//                    (eqs. 1, 3-4) with donors re-expressed in the receiver gauge
+//                    (App. C) and cubic reconstruction (App. D), inside the fixed-count
+//                    predictor-corrector on (rho, u, E) through the EoS; writes the
+//                    streamed state as gauge-free moments
+//   k_force_collide  Korteweg stress K (eq. 18) and force F = -div K, the
+//                    thermodynamic state of the step, the heat-flux correction M0
+//                    (eq. 9), re-expression of the streamed state in the collision
+//                    gauge (u, theta), BGK collision of f with the force source
+//                    (eqs. 16-17) and of g with the force-extended equilibrium and the
+//                    sources g~ + phi (eqs. 19-22); LDS-staged halos
+// The initial state additionally uses k_korteweg and k_init_equilibrium.
 //
 // The streaming kernel works "moment first": every donor's populations are reduced
 // once to their nine moments about a tile reference velocity (LDS), the nine moment
@@ -51,7 +52,8 @@ template <> struct StreamTile<1> { static constexpr int TX = 256, TY = 1; };
 template <int DIM, typename PopT, typename LdsT, int TX, int TY>
 __global__ void __launch_bounds__(TX *TY)
     k_stream(const DevParams *__restrict__ Pp, const PopT *__restrict__ fpop,
-             const double *__restrict__ side, double *__restrict__ mom, int *__restrict__ flags)
+             const double *__restrict__ side, double *__restrict__ mom, int *__restrict__ flags,
+             int tiles_x)
 {
     using L = Layout<DIM>;
     constexpr int Q = L::Q, NF = L::NF, H = 2;
@@ -64,14 +66,19 @@ __global__ void __launch_bounds__(TX *TY)
     // leave the state alone after an earlier failure; the decision is taken once per
     // block so that every wave of the block reaches the barrier below or none does
     const int tid = threadIdx.x + TX * threadIdx.y;
-    if (tid == 0) abort_block = flags[kFlagErr];
+    if (tid == 0) {
+        abort_block = flags[kFlagErr];
+        // one step more has started without an earlier failure
+        if (blockIdx.x == 0 && abort_block == 0) atomicAdd(&flags[kFlagSteps], 1);
+    }
     __syncthreads();
     if (abort_block != 0) return;
     const DevParams &P = *Pp;
     const int N = P.N;
     const PopT *gpop = fpop + (size_t)Q * N;
-    const int bx0 = blockIdx.x * TX;
-    const int by0 = DIM == 2 ? blockIdx.y * TY : 0;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int bx0 = (tile % tiles_x) * TX;
+    const int by0 = DIM == 2 ? (tile / tiles_x) * TY : 0;
 
     // reference velocity of the tile: gauge velocity at its (clamped) centre node
     const int cnode = min(bx0 + TX / 2, P.nx - 1) + P.nx * (DIM == 2 ? min(by0 + TY / 2, P.ny - 1) : 0);
@@ -240,9 +247,9 @@ static hipError_t launch_stream_t(const LaunchCtx &c, const DevState &s, int cur
 {
     constexpr int TX = StreamTile<DIM>::TX, TY = StreamTile<DIM>::TY;
     dim3 block(TX, TY);
-    dim3 grid((c.nx + TX - 1) / TX, DIM == 2 ? (c.ny + TY - 1) / TY : 1);
-    hipLaunchKernelGGL((k_stream<DIM, PopT, LdsT, TX, TY>), grid, block, 0, c.st, s.params,
-                       (const PopT *)s.pop[cur], s.side[cur], s.mom, s.flags);
+    const int tx = (c.nx + TX - 1) / TX, ty = DIM == 2 ? (c.ny + TY - 1) / TY : 1;
+    hipLaunchKernelGGL((k_stream<DIM, PopT, LdsT, TX, TY>), dim3(tx * ty), block, 0, c.st, s.params,
+                       (const PopT *)s.pop[cur], s.side[cur], s.mom, s.flags, tx);
     return hipGetLastError();
 }
 
@@ -316,7 +323,7 @@ hipError_t launch_korteweg(const LaunchCtx &c, const DevState &s, const double *
 }
 
 // ---------------------------------------------------------------------------
-// F = -div K, actual velocity and the thermodynamic state of the step (App. F)
+// F = -div K at a node from the stress planes (initial state only)
 // ---------------------------------------------------------------------------
 template <int DIM>
 __device__ __forceinline__ void korteweg_force_at(const DevParams &P, const double *__restrict__ kor,
@@ -347,113 +354,236 @@ __device__ __forceinline__ void korteweg_force_at(const DevParams &P, const doub
     Fy = DIM == 2 ? -dvy / kTL : 0.0;
 }
 
+// ---------------------------------------------------------------------------
+// How a derived field is read at lattice position (x, y) (same rule as map_node):
+//   kSelf   the position is a node, or wraps onto one (periodic): evaluate there;
+//   kCopy   an outflow face clamps it: take the value of the clamped node (cx, cy);
+//   kGhost  an inflow face: the ghost state's value (face in *face).
+// ---------------------------------------------------------------------------
+enum { kSelf = 0, kCopy = 1, kGhost = 2 };
 template <int DIM>
-__global__ void k_force_thermo(const DevParams *__restrict__ Pp, const double *__restrict__ mom,
-                               const double *__restrict__ kor, double *__restrict__ aux,
-                               int *__restrict__ flags)
+__device__ __forceinline__ int classify(const DevParams &P, int x, int y, int &cx, int &cy, int &face)
 {
-    if (flags[kFlagErr] != 0) return;
-    using L = Layout<DIM>;
-    const DevParams &P = *Pp;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = DIM == 2 ? blockIdx.y * blockDim.y + threadIdx.y : 0;
-    if (x >= P.nx || y >= (DIM == 2 ? P.ny : 1)) return;
-    const int node = x + P.nx * y;
-    const size_t N = P.N;
-    double Fx, Fy;
-    korteweg_force_at<DIM>(P, kor, x, y, Fx, Fy);
-    const double rho = mom[L::kRho * N + node];
-    const double ux = mom[L::kUx * N + node];
-    const double uy = DIM == 2 ? mom[L::kUy * N + node] : 0.0;
-    const double E = mom[L::kG * N + node] / (2.0 * rho);
-    const double uhx = ux + Fx * P.dt / (2.0 * rho);
-    const double uhy = DIM == 2 ? uy + Fy * P.dt / (2.0 * rho) : 0.0;
-    const double e = E - 0.5 * (uhx * uhx + uhy * uhy);
-    const double T = vdw_T_of_e(P, rho, e);
-    const double p = vdw_p(P, rho, T);
-    const int bad = vdw_bad(P, rho, p);
-    if (bad) atomicOr(&flags[kFlagErr], bad);
-    const double mu = (1.0 / P.omega - 0.5) * p * P.dt;
-    aux[kAuxFx * N + node] = Fx;
-    aux[kAuxFy * N + node] = Fy;
-    aux[kAuxT * N + node] = T;
-    aux[kAuxH * N + node] = e + p / rho;
-    aux[kAuxMu * N + node] = mu;
-    aux[kAuxKc * N + node] = P.k_scale * mu * P.R * (1.0 + P.delta) / P.delta;
-    aux[kAuxTh * N + node] = p; // pressure of the step (theta = p/(rho T_L))
-}
-
-hipError_t launch_force_thermo(const LaunchCtx &c, const DevState &s)
-{
-    dim3 grid, block;
-    grid2(c, grid, block);
-    if (c.dim == 2)
-        hipLaunchKernelGGL(k_force_thermo<2>, grid, block, 0, c.st, s.params, s.mom, s.kor, s.aux,
-                           s.flags);
-    else
-        hipLaunchKernelGGL(k_force_thermo<1>, grid, block, 0, c.st, s.params, s.mom, s.kor, s.aux,
-                           s.flags);
-    return hipGetLastError();
+    int cls = kSelf;
+    cx = x;
+    cy = y;
+    if (x < 0 || x >= P.nx) {
+        const int side = x < 0 ? 0 : 1;
+        const int bc = P.bc[0][side];
+        if (bc == kInflow) {
+            face = side;
+            return kGhost;
+        }
+        if (bc == kOutflow) {
+            cx = x < 0 ? 0 : P.nx - 1;
+            cls = kCopy;
+        }
+    }
+    if (DIM == 2 && (y < 0 || y >= P.ny)) {
+        const int side = y < 0 ? 0 : 1;
+        const int bc = P.bc[1][side];
+        if (bc == kInflow) {
+            face = 2 + side;
+            return kGhost;
+        }
+        if (bc == kOutflow) {
+            cy = y < 0 ? 0 : P.ny - 1;
+            cls = kCopy;
+        }
+    }
+    return cls;
 }
 
 // ---------------------------------------------------------------------------
-// collision (eqs. 9, 16-22; App. F)
+// Fused non-local closure and collision of one tile (eqs. 9, 16-22; App. F):
+//   LDS stage 1  rho on the tile + 3-node halo (from the streamed state)
+//   LDS stage 2  Korteweg stress K on the tile + 2-node halo
+//   LDS stage 3  F = -div K, actual velocity, T, p, h, mu, k on the tile + 1-node halo
+//   per node     heat-flux correction M0, re-expression of the streamed state in the
+//                collision gauge (u, theta), BGK collision of f (force source S) and g
+//                (force-extended equilibrium, sources g~ + phi); writes the new state.
 // ---------------------------------------------------------------------------
-template <int DIM, typename PopT>
-__global__ void k_collide(const DevParams *__restrict__ Pp, const double *__restrict__ mom,
-                          const double *__restrict__ aux, PopT *__restrict__ fout,
-                          double *__restrict__ side_out, int *__restrict__ flags, int count_step)
+template <int DIM> struct CollideTile;
+template <> struct CollideTile<2> { static constexpr int TX = 32, TY = 8; };
+template <> struct CollideTile<1> { static constexpr int TX = 256, TY = 1; };
+
+enum { kThFx = 0, kThFy, kThT, kThH, kThMu, kThKc, kThP, kThFields };
+
+template <int DIM, typename PopT, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY)
+    k_force_collide(const DevParams *__restrict__ Pp, const double *__restrict__ mom,
+                    PopT *__restrict__ fout, double *__restrict__ side_out, int *__restrict__ flags,
+                    int tiles_x)
 {
     using L = Layout<DIM>;
     constexpr int Q = L::Q, NF = L::NF;
-    if (count_step && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
-        if (flags[kFlagErr] == 0) atomicAdd(&flags[kFlagSteps], 1);
-    }
-    if (flags[kFlagErr] != 0) return;
+    constexpr int RX = TX + 6, RY = DIM == 2 ? TY + 6 : 1; // rho region (halo 3)
+    constexpr int KX = TX + 4, KY = DIM == 2 ? TY + 4 : 1; // K region (halo 2)
+    constexpr int HX = TX + 2, HY = DIM == 2 ? TY + 2 : 1; // thermo region (halo 1)
+    constexpr int NT = TX * TY;
+    __shared__ double s_rho[RX * RY];
+    __shared__ double s_K[3][KX * KY];
+    __shared__ double s_th[kThFields][HX * HY];
+    __shared__ int abort_block;
+
+    const int tid = threadIdx.x + TX * threadIdx.y;
+    if (tid == 0) abort_block = flags[kFlagErr];
+    __syncthreads();
+    if (abort_block != 0) return;
+
     const DevParams &P = *Pp;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = DIM == 2 ? blockIdx.y * blockDim.y + threadIdx.y : 0;
-    if (x >= P.nx || y >= (DIM == 2 ? P.ny : 1)) return;
-    const int node = x + P.nx * y;
     const size_t N = P.N;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int x0 = (tile % tiles_x) * TX;
+    const int y0 = DIM == 2 ? (tile / tiles_x) * TY : 0;
     const double dt = P.dt;
+    const bool force = P.kappa != 0.0;
+
+    // stage 1: density of the streamed state
+    if (force) {
+        for (int li = tid; li < RX * RY; li += NT) {
+            const int gx = x0 - 3 + li % RX, gy = y0 - 3 + li / RX;
+            const int nb = map_node<DIM>(P, gx, DIM == 2 ? gy : 0);
+            s_rho[li] = nb >= 0 ? mom[L::kRho * N + nb] : P.ghost[-nb - 1].rho;
+        }
+        __syncthreads();
+        // stage 2: K = -kappa (rho lap rho + |grad rho|^2/2) I + kappa grad rho grad rho
+        for (int li = tid; li < KX * KY; li += NT) {
+            const int kx = li % KX, ky = li / KX;
+            int cx, cy, face;
+            const int cls = classify<DIM>(P, x0 - 2 + kx, y0 - 2 + ky, cx, cy, face);
+            if (cls == kSelf) {
+                const int rb = (DIM == 2 ? (ky + 1) * RX : 0) + kx + 1;
+                const double r0 = s_rho[rb];
+                double gx = 0.0, gy = 0.0, lap = 0.0;
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    const int ex = DIM == 2 ? q / 3 - 1 : q - 1;
+                    const int ey = DIM == 2 ? q % 3 - 1 : 0;
+                    const double w = DIM == 2 ? kW1[q / 3] * kW1[q % 3] : kW1[q];
+                    const double rq = s_rho[rb + ex + ey * RX];
+                    gx += w * (double)ex * rq;
+                    gy += w * (double)ey * rq;
+                    lap += w * (rq - r0);
+                }
+                gx /= kTL;
+                gy /= kTL;
+                lap *= 2.0 / kTL;
+                const double iso = -P.kappa * (r0 * lap + 0.5 * (gx * gx + gy * gy));
+                s_K[0][li] = iso + P.kappa * gx * gx;
+                s_K[1][li] = P.kappa * gx * gy;
+                s_K[2][li] = DIM == 2 ? iso + P.kappa * gy * gy : 0.0;
+            } else if (cls == kGhost) {
+                s_K[0][li] = s_K[1][li] = s_K[2][li] = 0.0; // uniform inflow state
+            }
+        }
+        __syncthreads();
+        for (int li = tid; li < KX * KY; li += NT) {
+            const int kx = li % KX, ky = li / KX;
+            int cx, cy, face;
+            if (classify<DIM>(P, x0 - 2 + kx, y0 - 2 + ky, cx, cy, face) == kCopy) {
+                const int src = (cx - (x0 - 2)) + (DIM == 2 ? (cy - (y0 - 2)) * KX : 0);
+                s_K[0][li] = s_K[0][src];
+                s_K[1][li] = s_K[1][src];
+                s_K[2][li] = s_K[2][src];
+            }
+        }
+        __syncthreads();
+    }
+
+    // stage 3: force and thermodynamic state of the step
+    int err = 0;
+    for (int li = tid; li < HX * HY; li += NT) {
+        const int hx = li % HX, hy = li / HX;
+        const int gx = x0 - 1 + hx, gy = y0 - 1 + hy;
+        int cx, cy, face;
+        const int cls = classify<DIM>(P, gx, gy, cx, cy, face);
+        if (cls == kSelf) {
+            double Fx = 0.0, Fy = 0.0;
+            if (force) {
+                const int kb = (DIM == 2 ? (hy + 1) * KX : 0) + hx + 1;
+                double dvx = 0.0, dvy = 0.0;
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    const int ex = DIM == 2 ? q / 3 - 1 : q - 1;
+                    const int ey = DIM == 2 ? q % 3 - 1 : 0;
+                    const double w = DIM == 2 ? kW1[q / 3] * kW1[q % 3] : kW1[q];
+                    const int k = kb + ex + ey * KX;
+                    dvx += w * (s_K[0][k] * (double)ex + s_K[1][k] * (double)ey);
+                    dvy += w * (s_K[1][k] * (double)ex + s_K[2][k] * (double)ey);
+                }
+                Fx = -dvx / kTL;
+                Fy = DIM == 2 ? -dvy / kTL : 0.0;
+            }
+            const int nb = map_node<DIM>(P, gx, DIM == 2 ? gy : 0);
+            const double rho = mom[L::kRho * N + nb];
+            const double ux = mom[L::kUx * N + nb];
+            const double uy = DIM == 2 ? mom[L::kUy * N + nb] : 0.0;
+            const double E = mom[L::kG * N + nb] / (2.0 * rho);
+            const double uhx = ux + Fx * dt / (2.0 * rho);
+            const double uhy = DIM == 2 ? uy + Fy * dt / (2.0 * rho) : 0.0;
+            const double e = E - 0.5 * (uhx * uhx + uhy * uhy);
+            const double T = vdw_T_of_e(P, rho, e);
+            const double p = vdw_p(P, rho, T);
+            err |= vdw_bad(P, rho, p);
+            const double mu = (1.0 / P.omega - 0.5) * p * dt;
+            s_th[kThFx][li] = Fx;
+            s_th[kThFy][li] = Fy;
+            s_th[kThT][li] = T;
+            s_th[kThH][li] = e + p / rho;
+            s_th[kThMu][li] = mu;
+            s_th[kThKc][li] = P.k_scale * mu * P.R * (1.0 + P.delta) / P.delta;
+            s_th[kThP][li] = p;
+        } else if (cls == kGhost) {
+            const GhostFace &G = P.ghost[face];
+            s_th[kThT][li] = G.T;
+            s_th[kThH][li] = G.h;
+            s_th[kThMu][li] = G.mu;
+            s_th[kThKc][li] = G.kc;
+        }
+    }
+    __syncthreads();
+    for (int li = tid; li < HX * HY; li += NT) {
+        const int hx = li % HX, hy = li / HX;
+        int cx, cy, face;
+        if (classify<DIM>(P, x0 - 1 + hx, y0 - 1 + hy, cx, cy, face) == kCopy) {
+            const int src = (cx - (x0 - 1)) + (DIM == 2 ? (cy - (y0 - 1)) * HX : 0);
+#pragma unroll
+            for (int f = 0; f < kThFields; ++f) s_th[f][li] = s_th[f][src];
+        }
+    }
+    __syncthreads();
+    if (err) atomicOr(&flags[kFlagErr], err);
+
+    const int x = x0 + threadIdx.x;
+    const int y = y0 + (DIM == 2 ? threadIdx.y : 0);
+    if (x >= P.nx || (DIM == 2 && y >= P.ny)) return;
+    const int node = x + P.nx * y;
+    const int hb = (DIM == 2 ? (threadIdx.y + 1) * HX : 0) + threadIdx.x + 1;
 
     // heat-flux correction M0 = 2 div(-mu grad h + k grad T), flux form (eq. 9)
     double M0 = 0.0;
     if (P.k_scale >= 0.0) {
-        const double T0 = aux[kAuxT * N + node], h0 = aux[kAuxH * N + node];
-        const double m0 = aux[kAuxMu * N + node], k0 = aux[kAuxKc * N + node];
+        const double T0 = s_th[kThT][hb], h0 = s_th[kThH][hb];
+        const double m0 = s_th[kThMu][hb], k0 = s_th[kThKc][hb];
         double acc = 0.0;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            const int cx = DIM == 2 ? q / 3 - 1 : q - 1;
-            const int cy = DIM == 2 ? q % 3 - 1 : 0;
+            const int ex = DIM == 2 ? q / 3 - 1 : q - 1;
+            const int ey = DIM == 2 ? q % 3 - 1 : 0;
             const double w = DIM == 2 ? kW1[q / 3] * kW1[q % 3] : kW1[q];
-            const int nb = map_node<DIM>(P, x + cx, y + cy);
-            double Tq, hq, mq, kq;
-            if (nb >= 0) {
-                Tq = aux[kAuxT * N + nb];
-                hq = aux[kAuxH * N + nb];
-                mq = aux[kAuxMu * N + nb];
-                kq = aux[kAuxKc * N + nb];
-            } else {
-                const GhostFace &G = P.ghost[-nb - 1];
-                Tq = G.T;
-                hq = G.h;
-                mq = G.mu;
-                kq = G.kc;
-            }
-            const double kmid = 0.5 * (kq + k0);
-            const double mmid = 0.5 * (mq + m0);
-            acc += w * (kmid * (Tq - T0) - mmid * (hq - h0));
+            const int k = hb + ex + ey * HX;
+            const double kmid = 0.5 * (s_th[kThKc][k] + k0);
+            const double mmid = 0.5 * (s_th[kThMu][k] + m0);
+            acc += w * (kmid * (s_th[kThT][k] - T0) - mmid * (s_th[kThH][k] - h0));
         }
         M0 = 2.0 * (2.0 / kTL) * acc;
     }
 
     const double rho = mom[L::kRho * N + node];
     const double u[2] = {mom[L::kUx * N + node], DIM == 2 ? mom[L::kUy * N + node] : 0.0};
-    const double F[2] = {aux[kAuxFx * N + node], DIM == 2 ? aux[kAuxFy * N + node] : 0.0};
-    const double p = aux[kAuxTh * N + node];
+    const double F[2] = {s_th[kThFx][hb], DIM == 2 ? s_th[kThFy][hb] : 0.0};
+    const double p = s_th[kThP][hb];
     const double theta = p / (rho * kTL);
     const double s = sqrt(theta);
     const double E = mom[L::kG * N + node] / (2.0 * rho);
@@ -574,26 +704,23 @@ __global__ void k_collide(const DevParams *__restrict__ Pp, const double *__rest
     }
 }
 
-hipError_t launch_collide(const LaunchCtx &c, const DevState &s, int dst, int count_step)
+template <int DIM, typename PopT>
+static hipError_t launch_force_collide_t(const LaunchCtx &c, const DevState &s, int dst)
 {
-    dim3 grid, block;
-    grid2(c, grid, block);
-    if (c.dim == 2) {
-        if (c.fp32)
-            hipLaunchKernelGGL((k_collide<2, float>), grid, block, 0, c.st, s.params, s.mom, s.aux,
-                               (float *)s.pop[dst], s.side[dst], s.flags, count_step);
-        else
-            hipLaunchKernelGGL((k_collide<2, double>), grid, block, 0, c.st, s.params, s.mom, s.aux,
-                               (double *)s.pop[dst], s.side[dst], s.flags, count_step);
-    } else {
-        if (c.fp32)
-            hipLaunchKernelGGL((k_collide<1, float>), grid, block, 0, c.st, s.params, s.mom, s.aux,
-                               (float *)s.pop[dst], s.side[dst], s.flags, count_step);
-        else
-            hipLaunchKernelGGL((k_collide<1, double>), grid, block, 0, c.st, s.params, s.mom, s.aux,
-                               (double *)s.pop[dst], s.side[dst], s.flags, count_step);
-    }
+    constexpr int TX = CollideTile<DIM>::TX, TY = CollideTile<DIM>::TY;
+    const int tx = (c.nx + TX - 1) / TX, ty = DIM == 2 ? (c.ny + TY - 1) / TY : 1;
+    hipLaunchKernelGGL((k_force_collide<DIM, PopT, TX, TY>), dim3(tx * ty), dim3(TX, TY), 0, c.st,
+                       s.params, s.mom, (PopT *)s.pop[dst], s.side[dst], s.flags, tx);
     return hipGetLastError();
+}
+
+hipError_t launch_force_collide(const LaunchCtx &c, const DevState &s, int dst)
+{
+    if (c.dim == 2)
+        return c.fp32 ? launch_force_collide_t<2, float>(c, s, dst)
+                      : launch_force_collide_t<2, double>(c, s, dst);
+    return c.fp32 ? launch_force_collide_t<1, float>(c, s, dst)
+                  : launch_force_collide_t<1, double>(c, s, dst);
 }
 
 // ---------------------------------------------------------------------------

@@ -24,12 +24,12 @@ BC_PERIODIC, BC_OUTFLOW, BC_INFLOW = 0, 1, 2
 FP64, FP32_STORE = 0, 1
 
 # kernel ids of pond_time_kernel
-K_STREAM, K_KORTEWEG, K_FORCE_THERMO, K_COLLIDE = 0, 1, 2, 3
-KERNEL_NAMES = {K_STREAM: "k_stream", K_KORTEWEG: "k_korteweg", K_FORCE_THERMO: "k_force_thermo",
-                K_COLLIDE: "k_collide"}
+K_STREAM, K_FORCE_COLLIDE = 0, 1
+KERNEL_NAMES = {K_STREAM: "k_stream", K_FORCE_COLLIDE: "k_force_collide"}
 
 EXPORTED = ["pond_create", "pond_init_fields", "pond_step", "pond_moments", "pond_monitors",
-            "pond_steps_done", "pond_last_error", "pond_destroy", "pond_time_kernel"]
+            "pond_steps_done", "pond_last_error", "pond_destroy", "pond_time_kernel",
+            "pond_step_timed"]
 
 
 class pond_config(ctypes.Structure):
@@ -81,6 +81,7 @@ def load(path: str = LIB_PATH):
     L.pond_last_error.restype = ctypes.c_char_p
     L.pond_destroy.argtypes = [hp]
     L.pond_time_kernel.argtypes = [hp, ctypes.c_int, ctypes.c_int, dp]
+    L.pond_step_timed.argtypes = [hp, ctypes.c_int, dp]
     for name in EXPORTED:
         getattr(L, name).restype = getattr(L, name).restype or ctypes.c_int
     L.pond_last_error.restype = ctypes.c_char_p
@@ -195,6 +196,13 @@ class Lattice:
         self._check(load().pond_time_kernel(self._h, int(which), int(reps), ctypes.byref(us)),
                     "pond_time_kernel")
         return us.value
+
+    def step_timed(self, n: int) -> dict:
+        """Advance n steps with HIP events around every kernel launch; mean microseconds
+        per launch of each kernel inside the step pipeline."""
+        out = np.zeros(2)
+        self._check(load().pond_step_timed(self._h, int(n), _dp(out)), "pond_step_timed")
+        return {KERNEL_NAMES[K_STREAM]: float(out[0]), KERNEL_NAMES[K_FORCE_COLLIDE]: float(out[1])}
 
     def last_error(self) -> str:
         return load().pond_last_error(self._h).decode()

@@ -1,0 +1,93 @@
+"""Behaviour of the HIP path through the C ABI: determinism, equivalence of the
+step schedules (graph pairs, single launches, instrumented launches), monitors,
+and the error paths (forced from the host through the inputs, kernels exit normally)."""
+import numpy as np
+import pytest
+
+from paper_2002_09217_amd import pond, workloads as W
+from tests.common import pond_config, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _lattice(case, **kw):
+    lat = pond.Lattice(pond_config(case, **kw))
+    lat.init_fields(case.rho, case.u, case.T)
+    return lat
+
+
+def _fields(m):
+    return np.concatenate([m[k] for k in ("rho", "ux", "uy", "T", "p", "E")])
+
+
+@pytest.mark.parametrize("precision", [pond.FP64, pond.FP32_STORE])
+def test_runs_are_bitwise_deterministic(precision):
+    case = W.static_droplet(n=64, radius=14.0)
+    out = []
+    for _ in range(2):
+        lat = _lattice(case, precision=precision)
+        lat.step(37)
+        out.append(_fields(lat.moments()))
+        lat.close()
+    assert np.array_equal(out[0], out[1])
+
+
+def test_step_schedules_agree_bitwise():
+    case = W.perturbed(45, 19, seed=9, kappa=0.0176)
+    a = _lattice(case)
+    a.step(12)
+    b = _lattice(case)
+    for n in (1, 2, 3, 1, 5):
+        b.step(n)
+    c = _lattice(case)
+    c.step_timed(5)
+    c.step(7)
+    assert a.steps_done() == b.steps_done() == c.steps_done() == 12
+    fa, fb, fc = (_fields(x.moments()) for x in (a, b, c))
+    assert np.array_equal(fa, fb) and np.array_equal(fa, fc)
+    for x in (a, b, c):
+        x.close()
+
+
+def test_monitors_match_oracle_sums():
+    case = W.static_droplet(n=48, radius=10.0)
+    lat = _lattice(case)
+    lat.step(10)
+    mon = lat.monitors()
+    lat.close()
+    ref = run_oracle(case, 10)
+    rho, E = ref["rho"], ref["E"]
+    assert mon["mass"] == pytest.approx(np.sum(rho), rel=1e-13)
+    assert mon["momentum"][0] == pytest.approx(np.sum(rho * ref["ux"]), abs=1e-12 * np.sum(rho))
+    assert mon["energy"] == pytest.approx(np.sum(rho * E), rel=1e-13)
+    assert mon["min_p"] == pytest.approx(np.min(ref["p"]), rel=1e-12)
+    assert mon["energy_total"] > mon["energy"]
+    assert 0.0 < mon["max_v_dt"] < 1.0
+
+
+def test_init_outside_eos_domain_is_rejected():
+    case = W.perturbed(16, 16, seed=1, rho0=3.5, t_over_tcr=0.5)   # p < 0 on the vdW loop
+    lat = pond.Lattice(pond_config(case))
+    with pytest.raises(pond.PondError) as err:
+        lat.init_fields(case.rho, case.u, case.T)
+    assert err.value.code == -4
+    with pytest.raises(pond.PondError) as err:
+        lat.step(1)
+    assert err.value.code == -7
+    lat.close()
+
+
+def test_halo_violation_keeps_last_state():
+    # |u| + sqrt(theta) > 1/dt: the departure stencil would leave the +-2 window
+    case = W.perturbed(24, 24, seed=2, rho0=1.0, t_over_tcr=1.5, u0=(0.7, 0.0), dt=1.0, amp=0.0)
+    lat = _lattice(case)
+    before = _fields(lat.moments())
+    with pytest.raises(pond.PondError) as err:
+        lat.step(3)
+    assert err.value.code == -6
+    assert lat.steps_done() == 0
+    assert np.array_equal(_fields(lat.moments()), before)
+    with pytest.raises(pond.PondError) as err:
+        lat.step(1)
+    assert err.value.code == -7
+    lat.close()
