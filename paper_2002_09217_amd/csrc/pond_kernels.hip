@@ -47,10 +47,12 @@ hipError_t launch_reset_flags(const LaunchCtx &c, int *flags)
 // ---------------------------------------------------------------------------
 template <int DIM> struct StreamTile;
 template <> struct StreamTile<2> { static constexpr int TX = 32, TY = 8; };
-template <> struct StreamTile<1> { static constexpr int TX = 256, TY = 1; };
+template <> struct StreamTile<1> { static constexpr int TX = 128, TY = 1; };
 
-template <int DIM, typename PopT, typename LdsT, int TX, int TY>
-__global__ void __launch_bounds__(TX *TY)
+// Two lanes per receiver (SPLIT = 2): lane 2 i + set works on population set `set`
+// (0 = f, 1 = g) of receiver i; the pass moments are exchanged between the two lanes.
+template <int DIM, typename PopT, typename LdsT, int TX, int TY, int SPLIT>
+__global__ void __launch_bounds__(SPLIT *TX *TY)
     k_stream(const DevParams *__restrict__ Pp, const PopT *__restrict__ fpop,
              const double *__restrict__ side, double *__restrict__ mom, int *__restrict__ flags,
              int tiles_x)
@@ -60,12 +62,17 @@ __global__ void __launch_bounds__(TX *TY)
     constexpr int LX = TX + 2 * H;
     constexpr int LY = DIM == 2 ? TY + 2 * H : 1;
     constexpr int LN = LX * LY;
-    __shared__ LdsT lds[2 * NF][LN];
+    constexpr int NT = SPLIT * TX * TY;
+    // Moment fields of the tile.  With split lanes the two sets of a node are adjacent
+    // (index ((mn LN + node) 2 + set)), so the two lanes of a receiver and neighbouring
+    // receivers read one contiguous run of LDS words: no bank conflicts.
+    constexpr int CS = SPLIT == 2 ? 2 : 1;                        // column stride
+    __shared__ LdsT lds[2 * NF * LN];
     __shared__ int abort_block;
 
     // leave the state alone after an earlier failure; the decision is taken once per
     // block so that every wave of the block reaches the barrier below or none does
-    const int tid = threadIdx.x + TX * threadIdx.y;
+    const int tid = threadIdx.x + SPLIT * TX * threadIdx.y;
     if (tid == 0) {
         abort_block = flags[kFlagErr];
         // one step more has started without an earlier failure
@@ -75,7 +82,6 @@ __global__ void __launch_bounds__(TX *TY)
     if (abort_block != 0) return;
     const DevParams &P = *Pp;
     const int N = P.N;
-    const PopT *gpop = fpop + (size_t)Q * N;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int bx0 = (tile % tiles_x) * TX;
     const int by0 = DIM == 2 ? (tile / tiles_x) * TY : 0;
@@ -85,36 +91,54 @@ __global__ void __launch_bounds__(TX *TY)
     const double rx = side[kSideUx * N + cnode];
     const double ry = DIM == 2 ? side[kSideUy * N + cnode] : 0.0;
 
-    // donors of the tile and its halo: moments about (rx, ry) into LDS
-    for (int li = tid; li < LN; li += TX * TY) {
+    // donors of the tile and its halo: moments about (rx, ry) into LDS, one work item
+    // per (node, set) when the sets are split over lanes
+    constexpr int SETS_PER_ITEM = SPLIT == 2 ? 1 : 2;
+    for (int it = tid; it < LN * SPLIT; it += NT) {
+        const int li = SPLIT == 2 ? it >> 1 : it;
+        const int set0 = SPLIT == 2 ? it & 1 : 0;
         const int lx = li % LX, ly = li / LX;
         const int node = map_node<DIM>(P, bx0 - H + lx, by0 - H + ly);
-        double m[2 * NF];
+        double ux, uy, th;
+        const double *gf = nullptr, *gg = nullptr;
         if (node >= 0) {
-            PopT pf[Q], pg[Q];
-#pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                pf[q] = fpop[(size_t)q * N + node];
-                pg[q] = gpop[(size_t)q * N + node];
-            }
-            const double ux = side[kSideUx * N + node];
-            const double uy = DIM == 2 ? side[kSideUy * N + node] : 0.0;
-            const double s = sqrt(side[kSideTh * N + node]);
-            moments_about<DIM>(pf, ux - rx, uy - ry, s, m);
-            moments_about<DIM>(pg, ux - rx, uy - ry, s, m + NF);
+            ux = side[kSideUx * N + node];
+            uy = DIM == 2 ? side[kSideUy * N + node] : 0.0;
+            th = side[kSideTh * N + node];
         } else {
             const GhostFace &G = P.ghost[-node - 1];
-            const double s = sqrt(G.theta);
-            moments_about<DIM>(G.f, G.ux - rx, G.uy - ry, s, m);
-            moments_about<DIM>(G.g, G.ux - rx, G.uy - ry, s, m + NF);
+            ux = G.ux;
+            uy = G.uy;
+            th = G.theta;
+            gf = G.f;
+            gg = G.g;
         }
+        const double s = sqrt(th);
 #pragma unroll
-        for (int i = 0; i < 2 * NF; ++i) lds[i][li] = (LdsT)m[i];
+        for (int k = 0; k < SETS_PER_ITEM; ++k) {
+            const int set = set0 + k;
+            double m[NF];
+            if (node >= 0) {
+                PopT pp[Q];
+                const PopT *src = fpop + (size_t)set * Q * N;
+#pragma unroll
+                for (int q = 0; q < Q; ++q) pp[q] = src[(size_t)q * N + node];
+                moments_about<DIM>(pp, ux - rx, uy - ry, s, m);
+            } else {
+                moments_about<DIM>(set == 0 ? gf : gg, ux - rx, uy - ry, s, m);
+            }
+#pragma unroll
+            for (int i = 0; i < NF; ++i)
+                lds[SPLIT == 2 ? (i * LN + li) * 2 + set : (set * NF + i) * LN + li] = (LdsT)m[i];
+        }
     }
     __syncthreads();
 
-    const int gx = bx0 + threadIdx.x;
+    const int lxr = SPLIT == 2 ? (int)threadIdx.x >> 1 : (int)threadIdx.x;
+    const int myset = SPLIT == 2 ? (int)threadIdx.x & 1 : 0;
+    const int gx = bx0 + lxr;
     const int gy = by0 + (DIM == 2 ? threadIdx.y : 0);
+    // both lanes of a split receiver leave together, so the exchanges below always pair up
     if (gx >= P.nx || (DIM == 2 && gy >= P.ny)) return;
     const int node = gx + P.nx * gy;
     double Ux = side[kSideUx * N + node];
@@ -122,7 +146,7 @@ __global__ void __launch_bounds__(TX *TY)
     double th = side[kSideTh * N + node];
     const double Fpx = side[kSideFx * N + node];
     const double Fpy = DIM == 2 ? side[kSideFy * N + node] : 0.0;
-    const int wbase = (DIM == 2 ? threadIdx.y * LX : 0) + threadIdx.x; // window (gx-2, gy-2)
+    const int wbase = (DIM == 2 ? threadIdx.y * LX : 0) + lxr; // window (gx-2, gy-2)
     const double dt = P.dt;
 
     double fq[Q], gq[Q];
@@ -134,54 +158,71 @@ __global__ void __launch_bounds__(TX *TY)
         LdsT wx[3][5], wy[3][5];
         err |= window_weights<LdsT>(Ux, s, dt, wx);
         if (DIM == 2) err |= window_weights<LdsT>(Uy, s, dt, wy);
-        double A[3][3], B[3][3];
-        lagrange_coeffs(Ux - rx, s, A);
-        if (DIM == 2) lagrange_coeffs(Uy - ry, s, B);
+        double Ad[3][3], Bd[3][3];
+        lagrange_coeffs(Ux - rx, s, Ad);
+        if (DIM == 2) lagrange_coeffs(Uy - ry, s, Bd);
+        LdsT A[3][3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int m = 0; m < 3; ++m) A[k][m] = (LdsT)Ad[k][m];
+
 #pragma unroll 1
-        for (int set = 0; set < 2; ++set) {
-            // populations of this set in the receiver gauge, one per direction
+        for (int set = (SPLIT == 2 ? myset : 0); set < (SPLIT == 2 ? myset + 1 : 2); ++set) {
+            // populations of this set in the receiver gauge, one per direction:
+            //   f_kl = sum_n B_ln sum_r wy_l[r] sum_m A_km sum_c wx_k[c] M_mn[r][c]
             double acc[Q];
 #pragma unroll
             for (int q = 0; q < Q; ++q) acc[q] = 0.0;
-            const LdsT *sbase = &lds[set * NF][wbase];
+            const LdsT *sbase = SPLIT == 2 ? &lds[wbase * 2 + set] : &lds[set * NF * LN + wbase];
+            if (DIM == 2) {
 #pragma unroll
-            for (int mn = 0; mn < NF; ++mn) {
-                const LdsT *win = sbase + mn * LN;
-                if (DIM == 2) {
-                    const int m = mn / 3, n = mn % 3;
-                    // I[k][l]: moment field mn interpolated at the departure point of
-                    // direction (k-1, l-1); rows are streamed through the x weights
-                    LdsT I[9];
+                for (int n = 0; n < 3; ++n) {
+                    LdsT Z[3][5]; // sum_m A_km (x-interpolated M_mn) per row
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) I[i] = (LdsT)0;
+                    for (int k = 0; k < 3; ++k)
+#pragma unroll
+                        for (int r = 0; r < 5; ++r) Z[k][r] = (LdsT)0;
 #pragma unroll
                     for (int r = 0; r < 5; ++r) {
-                        const LdsT v0 = win[r * LX + 0], v1 = win[r * LX + 1], v2 = win[r * LX + 2],
-                                   v3 = win[r * LX + 3], v4 = win[r * LX + 4];
 #pragma unroll
-                        for (int k = 0; k < 3; ++k) {
-                            const LdsT xk = wx[k][0] * v0 + wx[k][1] * v1 + wx[k][2] * v2 +
-                                            wx[k][3] * v3 + wx[k][4] * v4;
+                        for (int m = 0; m < 3; ++m) {
+                            const LdsT *row = sbase + ((3 * m + n) * LN + r * LX) * CS;
+                            const LdsT v0 = row[0], v1 = row[CS], v2 = row[2 * CS], v3 = row[3 * CS],
+                                       v4 = row[4 * CS];
 #pragma unroll
-                            for (int l = 0; l < 3; ++l) I[3 * k + l] += wy[l][r] * xk;
+                            for (int k = 0; k < 3; ++k) {
+                                const LdsT xk = wx[k][0] * v0 + wx[k][1] * v1 + wx[k][2] * v2 +
+                                                wx[k][3] * v3 + wx[k][4] * v4;
+                                Z[k][r] += A[k][m] * xk;
+                            }
                         }
                     }
 #pragma unroll
                     for (int k = 0; k < 3; ++k)
 #pragma unroll
-                        for (int l = 0; l < 3; ++l) acc[3 * k + l] += A[k][m] * B[l][n] * (double)I[3 * k + l];
-                } else {
-                    const LdsT v0 = win[0], v1 = win[1], v2 = win[2], v3 = win[3], v4 = win[4];
+                        for (int l = 0; l < 3; ++l) {
+                            const LdsT I = wy[l][0] * Z[k][0] + wy[l][1] * Z[k][1] + wy[l][2] * Z[k][2] +
+                                           wy[l][3] * Z[k][3] + wy[l][4] * Z[k][4];
+                            acc[3 * k + l] += Bd[l][n] * (double)I;
+                        }
+                    // keep the three n-blocks apart: the scheduler would otherwise hoist the
+                    // loads of all of them and run out of registers
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < 3; ++m) {
+                    const LdsT *row = sbase + m * LN * CS;
+                    const LdsT v0 = row[0], v1 = row[CS], v2 = row[2 * CS], v3 = row[3 * CS],
+                               v4 = row[4 * CS];
 #pragma unroll
                     for (int k = 0; k < 3; ++k) {
-                        const LdsT I = wx[k][0] * v0 + wx[k][1] * v1 + wx[k][2] * v2 + wx[k][3] * v3 +
-                                       wx[k][4] * v4;
-                        acc[k] += A[k][mn] * (double)I;
+                        const LdsT xk = wx[k][0] * v0 + wx[k][1] * v1 + wx[k][2] * v2 + wx[k][3] * v3 +
+                                        wx[k][4] * v4;
+                        acc[k] += Ad[k][m] * (double)xk;
                     }
                 }
-                // keep the fields apart: the scheduler would otherwise hoist the loads of
-                // all fields and run out of registers
-                __builtin_amdgcn_sched_barrier(0);
             }
             if (set == 0) {
 #pragma unroll
@@ -192,17 +233,38 @@ __global__ void __launch_bounds__(TX *TY)
             }
         }
         // moments of the streamed populations (eq. 2) and the EoS closure
-        double jx = 0.0, jy = 0.0, G2 = 0.0;
-        rho = 0.0;
+        double jx = 0.0, jy = 0.0, G2 = 0.0, r0 = 0.0;
+        if (SPLIT == 2) {
+            // each lane sums its own set; the partner lane supplies the other sums
+            const double *own = myset == 0 ? fq : gq;
+            double s0 = 0.0, sx = 0.0, sy = 0.0;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const double cx = DIM == 2 ? (double)(q / 3 - 1) : (double)(q - 1);
-            const double cy = DIM == 2 ? (double)(q % 3 - 1) : 0.0;
-            rho += fq[q];
-            jx += fq[q] * (Ux + s * cx);
-            if (DIM == 2) jy += fq[q] * (Uy + s * cy);
-            G2 += gq[q];
+            for (int q = 0; q < Q; ++q) {
+                const double cx = DIM == 2 ? (double)(q / 3 - 1) : (double)(q - 1);
+                const double cy = DIM == 2 ? (double)(q % 3 - 1) : 0.0;
+                s0 += own[q];
+                sx += own[q] * (Ux + s * cx);
+                if (DIM == 2) sy += own[q] * (Uy + s * cy);
+            }
+            const double o0 = __shfl_xor(s0, 1, 64);
+            const double ox = __shfl_xor(sx, 1, 64);
+            const double oy = DIM == 2 ? __shfl_xor(sy, 1, 64) : 0.0;
+            r0 = myset == 0 ? s0 : o0;
+            jx = myset == 0 ? sx : ox;
+            jy = myset == 0 ? sy : oy;
+            G2 = myset == 0 ? o0 : s0;
+        } else {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const double cx = DIM == 2 ? (double)(q / 3 - 1) : (double)(q - 1);
+                const double cy = DIM == 2 ? (double)(q % 3 - 1) : 0.0;
+                r0 += fq[q];
+                jx += fq[q] * (Ux + s * cx);
+                if (DIM == 2) jy += fq[q] * (Uy + s * cy);
+                G2 += gq[q];
+            }
         }
+        rho = r0;
         const double E = G2 / (2.0 * rho);
         const double ux = jx / rho;
         const double uy = DIM == 2 ? jy / rho : 0.0;
@@ -221,45 +283,50 @@ __global__ void __launch_bounds__(TX *TY)
     }
 
     // streamed state for the collision: rho, u and central moments about u
-    double mf[NF], mg[NF];
-    moments_about<DIM>(fq, sUx - Ux, sUy - Uy, sS, mf);
-    moments_about<DIM>(gq, sUx - Ux, sUy - Uy, sS, mg);
-    mom[(size_t)L::kRho * N + node] = rho;
-    mom[(size_t)L::kUx * N + node] = Ux;
-    if (DIM == 2) {
-        mom[(size_t)L::kUy * N + node] = Uy;
-        mom[(size_t)(L::kF + 0) * N + node] = mf[4]; // (1,1)
-        mom[(size_t)(L::kF + 1) * N + node] = mf[6]; // (2,0)
-        mom[(size_t)(L::kF + 2) * N + node] = mf[2]; // (0,2)
-        mom[(size_t)(L::kF + 3) * N + node] = mf[7]; // (2,1)
-        mom[(size_t)(L::kF + 4) * N + node] = mf[5]; // (1,2)
-        mom[(size_t)(L::kF + 5) * N + node] = mf[8]; // (2,2)
-    } else {
-        mom[(size_t)L::kF * N + node] = mf[2];
+    if (SPLIT == 1 || myset == 0) {
+        double mf[NF];
+        moments_about<DIM>(fq, sUx - Ux, sUy - Uy, sS, mf);
+        mom[(size_t)L::kRho * N + node] = rho;
+        mom[(size_t)L::kUx * N + node] = Ux;
+        if (DIM == 2) {
+            mom[(size_t)L::kUy * N + node] = Uy;
+            mom[(size_t)(L::kF + 0) * N + node] = mf[4]; // (1,1)
+            mom[(size_t)(L::kF + 1) * N + node] = mf[6]; // (2,0)
+            mom[(size_t)(L::kF + 2) * N + node] = mf[2]; // (0,2)
+            mom[(size_t)(L::kF + 3) * N + node] = mf[7]; // (2,1)
+            mom[(size_t)(L::kF + 4) * N + node] = mf[5]; // (1,2)
+            mom[(size_t)(L::kF + 5) * N + node] = mf[8]; // (2,2)
+        } else {
+            mom[(size_t)L::kF * N + node] = mf[2];
+        }
     }
+    if (SPLIT == 1 || myset == 1) {
+        double mg[NF];
+        moments_about<DIM>(gq, sUx - Ux, sUy - Uy, sS, mg);
 #pragma unroll
-    for (int i = 0; i < NF; ++i) mom[(size_t)(L::kG + i) * N + node] = mg[i];
+        for (int i = 0; i < NF; ++i) mom[(size_t)(L::kG + i) * N + node] = mg[i];
+    }
     if (err) atomicOr(&flags[kFlagErr], err);
 }
 
-template <int DIM, typename PopT, typename LdsT>
+template <int DIM, typename PopT, typename LdsT, int SPLIT>
 static hipError_t launch_stream_t(const LaunchCtx &c, const DevState &s, int cur)
 {
     constexpr int TX = StreamTile<DIM>::TX, TY = StreamTile<DIM>::TY;
-    dim3 block(TX, TY);
+    dim3 block(SPLIT * TX, TY);
     const int tx = (c.nx + TX - 1) / TX, ty = DIM == 2 ? (c.ny + TY - 1) / TY : 1;
-    hipLaunchKernelGGL((k_stream<DIM, PopT, LdsT, TX, TY>), dim3(tx * ty), block, 0, c.st, s.params,
-                       (const PopT *)s.pop[cur], s.side[cur], s.mom, s.flags, tx);
+    hipLaunchKernelGGL((k_stream<DIM, PopT, LdsT, TX, TY, SPLIT>), dim3(tx * ty), block, 0, c.st,
+                       s.params, (const PopT *)s.pop[cur], s.side[cur], s.mom, s.flags, tx);
     return hipGetLastError();
 }
 
 hipError_t launch_stream(const LaunchCtx &c, const DevState &s, int cur)
 {
     if (c.dim == 2)
-        return c.fp32 ? launch_stream_t<2, float, float>(c, s, cur)
-                      : launch_stream_t<2, double, double>(c, s, cur);
-    return c.fp32 ? launch_stream_t<1, float, float>(c, s, cur)
-                  : launch_stream_t<1, double, double>(c, s, cur);
+        return c.fp32 ? launch_stream_t<2, float, float, 2>(c, s, cur)
+                      : launch_stream_t<2, double, double, 2>(c, s, cur);
+    return c.fp32 ? launch_stream_t<1, float, float, 2>(c, s, cur)
+                  : launch_stream_t<1, double, double, 2>(c, s, cur);
 }
 
 // ---------------------------------------------------------------------------
