@@ -47,6 +47,7 @@ def gpu_run(case, precision, steps, warmup, stream):
     t1 = time.perf_counter()
     # per-kernel durations inside the step pipeline (HIP events on the same stream)
     kern = lat.step_timed(min(steps, 500))
+    kern["tile"] = lat.tile_info()
     mon = lat.monitors()
     lat.close()
     return (t1 - t0), kern, mon
@@ -154,8 +155,8 @@ def main():
                 "frac": round(b64 * mlups64 * 1e6 / 1e9 / cost.HBM_PEAK_GBS, 4)},
         "fp32_store": {"value": round(mlups32, 2), "unit": "MLUPS", "ratio_vs_fp64": round(mlups32 / mlups64, 3),
                        "bytes_per_node_step": b32, "k_stream_us": round(kern32["k_stream"], 3)},
-        "kernels_us": {"fp64": {k: round(v, 3) for k, v in kern64.items()},
-                       "fp32_store": {k: round(v, 3) for k, v in kern32.items()}},
+        "kernels_us": {"fp64": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in kern64.items()},
+                       "fp32_store": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in kern32.items()}},
         "monitors_after": {"mass": mon64["mass"], "min_p": mon64["min_p"], "max_v_dt": mon64["max_v_dt"]},
         "cpu_baseline": cpu,
     }

@@ -72,12 +72,17 @@ typedef struct {
     int precision;            /* POND_FP64, or POND_FP32_STORE: populations stored and
                                  interpolated in FP32; moments, EoS, gauge, forcing and
                                  collision in FP64                                      */
+    int tile;                 /* tile shape of the streaming kernel: -1 = measure the
+                                 compiled shapes on the first pond_init_fields and keep
+                                 the fastest; k >= 0 = shape k (see pond_tile_info).
+                                 Results depend on the shape at round-off level only. */
     void *stream;             /* hipStream_t or NULL                                    */
 } pond_config;
 
 /* Validate cfg and allocate the device state.  *out receives the handle (NULL on
  * error).  Errors: POND_E_INVALID (dim, sizes, 0 < delta <= 2/3, 0 < omega < 2,
- * n_pass >= 1, dt > 0, inflow state with p <= 0), POND_E_NOMEM, POND_E_DEVICE. */
+ * n_pass >= 1, dt > 0, tile in range, inflow state with p <= 0), POND_E_NOMEM,
+ * POND_E_DEVICE. */
 int pond_create(const pond_config *cfg, pond_handle **out);
 
 /* Set the state from the macroscopic fields rho (N), actual velocity u (dim planes
@@ -108,6 +113,11 @@ int pond_steps_done(const pond_handle *h, long long *out);
 
 /* Human-readable description of the last error of the handle (never NULL). */
 const char *pond_last_error(const pond_handle *h);
+
+/* Tile shape in use by the streaming kernel: out[0] = shape index, out[1], out[2] =
+ * receivers per workgroup along x and y; out[3] = number of compiled shapes for the
+ * handle's dimension. */
+int pond_tile_info(const pond_handle *h, int *out);
 
 /* Release everything owned by h.  NULL is accepted. */
 int pond_destroy(pond_handle *h);

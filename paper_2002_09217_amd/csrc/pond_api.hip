@@ -23,6 +23,7 @@ struct pond_handle {
     hipStream_t capture_stream = nullptr; // used only to record graphs
     hipGraphExec_t pair_exec[2] = {nullptr, nullptr}; // two steps starting from state 0 / 1
     bool graphs_ok = true;
+    bool tuned = false;                 // streaming tile shape fixed
     int cur = 0;                        // state buffer holding the current state
     long long steps = 0;
     bool initialised = false;
@@ -163,6 +164,48 @@ void free_all(pond_handle *h)
     if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
 }
 
+void drop_graphs(pond_handle *h)
+{
+    for (int i = 0; i < 2; ++i)
+        if (h->pair_exec[i]) {
+            hipGraphExecDestroy(h->pair_exec[i]);
+            h->pair_exec[i] = nullptr;
+        }
+}
+
+// Time every compiled tile shape of the streaming kernel on the current state (one
+// warm-up launch, then `reps` launches between HIP events) and keep the fastest.
+int tune_stream_tile(pond_handle *h, int reps)
+{
+    const int nv = stream_variants(h->lc.dim);
+    hipEvent_t e0, e1;
+    HIP_TRY(h, hipEventCreate(&e0));
+    HIP_TRY(h, hipEventCreate(&e1));
+    int best = 0;
+    float best_ms = 1e30f;
+    for (int v = 0; v < nv; ++v) {
+        LaunchCtx c = h->lc;
+        c.stream_tile = v;
+        HIP_TRY(h, launch_stream(c, h->ds, h->cur));
+        HIP_TRY(h, hipEventRecord(e0, h->stream));
+        for (int r = 0; r < reps; ++r) HIP_TRY(h, launch_stream(c, h->ds, h->cur));
+        HIP_TRY(h, hipEventRecord(e1, h->stream));
+        HIP_TRY(h, hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIP_TRY(h, hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = v;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (best != h->lc.stream_tile) drop_graphs(h);
+    h->lc.stream_tile = best;
+    h->tuned = true;
+    return POND_OK;
+}
+
 // read the flags after a batch of steps and move the handle to the last completed state
 int finish_batch(pond_handle *h)
 {
@@ -196,6 +239,7 @@ int pond_create(const pond_config *cfg, pond_handle **out)
     if (!(c.omega > 0.0 && c.omega < 2.0)) return POND_E_INVALID;
     if (c.n_pass < 1 || c.n_pass > 64 || !(c.dt > 0.0) || !(c.R > 0.0)) return POND_E_INVALID;
     if (c.precision != POND_FP64 && c.precision != POND_FP32_STORE) return POND_E_INVALID;
+    if (c.tile < -1 || c.tile >= stream_variants(c.dim)) return POND_E_INVALID;
     for (int a = 0; a < c.dim; ++a)
         for (int s = 0; s < 2; ++s)
             if (c.bc[a][s] < 0 || c.bc[a][s] > 2) return POND_E_INVALID;
@@ -209,7 +253,9 @@ int pond_create(const pond_config *cfg, pond_handle **out)
     }
     const int N = nx * ny;
     const int Q = c.dim == 2 ? 9 : 3;
-    h->lc = LaunchCtx{c.dim, nx, ny, N, c.precision == POND_FP32_STORE ? 1 : 0, nullptr};
+    h->lc = LaunchCtx{c.dim, nx, ny, N, c.precision == POND_FP32_STORE ? 1 : 0, nullptr,
+                      c.tile < 0 ? 0 : c.tile};
+    h->tuned = c.tile >= 0;
 
     DevParams P;
     std::memset(&P, 0, sizeof P);
@@ -306,6 +352,12 @@ int pond_init_fields(pond_handle *h, const double *rho, const double *u, const d
     if (fl[kFlagErr]) return fail(h, err_code(fl[kFlagErr]), "init: %s", err_name(fl[kFlagErr]));
     h->cur = 0;
     h->steps = 0;
+    if (!h->tuned) {
+        rc = tune_stream_tile(h, 10);
+        if (rc != POND_OK) return rc;
+        // the tuning launches count as started steps: clear the counters again
+        HIP_TRY(h, launch_reset_flags(h->lc, h->ds.flags));
+    }
     h->initialised = true;
     std::snprintf(h->msg, sizeof h->msg, "ok");
     return POND_OK;
@@ -375,6 +427,15 @@ int pond_steps_done(const pond_handle *h, long long *out)
 }
 
 const char *pond_last_error(const pond_handle *h) { return h ? h->msg : "NULL handle"; }
+
+int pond_tile_info(const pond_handle *h, int *out)
+{
+    if (!h || !out) return POND_E_INVALID;
+    out[0] = h->lc.stream_tile;
+    stream_tile_shape(h->lc.dim, h->lc.stream_tile, &out[1], &out[2]);
+    out[3] = stream_variants(h->lc.dim);
+    return POND_OK;
+}
 
 int pond_destroy(pond_handle *h)
 {

@@ -78,7 +78,11 @@ struct LaunchCtx {
     int dim, nx, ny, N;
     int fp32;           // populations stored as float
     hipStream_t st;
+    int stream_tile;    // tile-shape variant of the streaming kernel
 };
+
+int stream_variants(int dim);
+void stream_tile_shape(int dim, int variant, int *tx, int *ty);
 
 hipError_t launch_reset_flags(const LaunchCtx &c, int *flags);
 hipError_t launch_stream(const LaunchCtx &c, const DevState &s, int cur);

@@ -45,10 +45,6 @@ hipError_t launch_reset_flags(const LaunchCtx &c, int *flags)
 // ---------------------------------------------------------------------------
 // streaming with the predictor-corrector
 // ---------------------------------------------------------------------------
-template <int DIM> struct StreamTile;
-template <> struct StreamTile<2> { static constexpr int TX = 32, TY = 8; };
-template <> struct StreamTile<1> { static constexpr int TX = 128, TY = 1; };
-
 // Two lanes per receiver (SPLIT = 2): lane 2 i + set works on population set `set`
 // (0 = f, 1 = g) of receiver i; the pass moments are exchanged between the two lanes.
 template <int DIM, typename PopT, typename LdsT, int TX, int TY, int SPLIT>
@@ -91,61 +87,82 @@ __global__ void __launch_bounds__(SPLIT *TX *TY)
     const double rx = side[kSideUx * N + cnode];
     const double ry = DIM == 2 ? side[kSideUy * N + cnode] : 0.0;
 
-    // donors of the tile and its halo: moments about (rx, ry) into LDS, one work item
-    // per (node, set) when the sets are split over lanes
-    constexpr int SETS_PER_ITEM = SPLIT == 2 ? 1 : 2;
-    for (int it = tid; it < LN * SPLIT; it += NT) {
-        const int li = SPLIT == 2 ? it >> 1 : it;
-        const int set0 = SPLIT == 2 ? it & 1 : 0;
-        const int lx = li % LX, ly = li / LX;
-        const int node = map_node<DIM>(P, bx0 - H + lx, by0 - H + ly);
-        double ux, uy, th;
-        const double *gf = nullptr, *gg = nullptr;
-        if (node >= 0) {
-            ux = side[kSideUx * N + node];
-            uy = DIM == 2 ? side[kSideUy * N + node] : 0.0;
-            th = side[kSideTh * N + node];
-        } else {
-            const GhostFace &G = P.ghost[-node - 1];
-            ux = G.ux;
-            uy = G.uy;
-            th = G.theta;
-            gf = G.f;
-            gg = G.g;
-        }
-        const double s = sqrt(th);
-#pragma unroll
-        for (int k = 0; k < SETS_PER_ITEM; ++k) {
-            const int set = set0 + k;
-            double m[NF];
-            if (node >= 0) {
-                PopT pp[Q];
-                const PopT *src = fpop + (size_t)set * Q * N;
-#pragma unroll
-                for (int q = 0; q < Q; ++q) pp[q] = src[(size_t)q * N + node];
-                moments_about<DIM>(pp, ux - rx, uy - ry, s, m);
-            } else {
-                moments_about<DIM>(set == 0 ? gf : gg, ux - rx, uy - ry, s, m);
-            }
-#pragma unroll
-            for (int i = 0; i < NF; ++i)
-                lds[SPLIT == 2 ? (i * LN + li) * 2 + set : (set * NF + i) * LN + li] = (LdsT)m[i];
-        }
-    }
-    __syncthreads();
-
+    // the receiver's own gauge and force, loaded now so that the latency overlaps the fill
     const int lxr = SPLIT == 2 ? (int)threadIdx.x >> 1 : (int)threadIdx.x;
     const int myset = SPLIT == 2 ? (int)threadIdx.x & 1 : 0;
     const int gx = bx0 + lxr;
     const int gy = by0 + (DIM == 2 ? threadIdx.y : 0);
-    // both lanes of a split receiver leave together, so the exchanges below always pair up
-    if (gx >= P.nx || (DIM == 2 && gy >= P.ny)) return;
-    const int node = gx + P.nx * gy;
+    const bool inside = gx < P.nx && (DIM == 1 || gy < P.ny);
+    const int node = inside ? gx + P.nx * gy : cnode;
     double Ux = side[kSideUx * N + node];
     double Uy = DIM == 2 ? side[kSideUy * N + node] : 0.0;
     double th = side[kSideTh * N + node];
     const double Fpx = side[kSideFx * N + node];
     const double Fpy = DIM == 2 ? side[kSideFy * N + node] : 0.0;
+
+    // donors of the tile and its halo: moments about (rx, ry) into LDS, one work item
+    // per (node, set) when the sets are split over lanes.  Each thread takes its items
+    // two at a time and issues the global loads of both before using either, so the
+    // memory latency of the fill is paid once per pair.
+    constexpr int SETS_PER_ITEM = SPLIT == 2 ? 1 : 2;
+    constexpr int NITEMS = LN * SPLIT;
+    struct Raw {
+        int li, set0, node;
+        double ux, uy, th;
+        PopT p[SETS_PER_ITEM * Q];
+    };
+    auto load_raw = [&](int it, Raw &r) {
+        r.li = SPLIT == 2 ? it >> 1 : it;
+        r.set0 = SPLIT == 2 ? it & 1 : 0;
+        const int lx = r.li % LX, ly = r.li / LX;
+        r.node = map_node<DIM>(P, bx0 - H + lx, by0 - H + ly);
+        if (r.node >= 0) {
+            r.ux = side[kSideUx * N + r.node];
+            r.uy = DIM == 2 ? side[kSideUy * N + r.node] : 0.0;
+            r.th = side[kSideTh * N + r.node];
+#pragma unroll
+            for (int k = 0; k < SETS_PER_ITEM; ++k) {
+                const PopT *src = fpop + (size_t)(r.set0 + k) * Q * N;
+#pragma unroll
+                for (int q = 0; q < Q; ++q) r.p[k * Q + q] = src[(size_t)q * N + r.node];
+            }
+        } else {
+            const GhostFace &G = P.ghost[-r.node - 1];
+            r.ux = G.ux;
+            r.uy = G.uy;
+            r.th = G.theta;
+#pragma unroll
+            for (int k = 0; k < SETS_PER_ITEM; ++k) {
+                const double *src = r.set0 + k == 0 ? G.f : G.g;
+#pragma unroll
+                for (int q = 0; q < Q; ++q) r.p[k * Q + q] = (PopT)src[q];
+            }
+        }
+    };
+    auto store_moments = [&](const Raw &r) {
+        const double s = sqrt(r.th);
+#pragma unroll
+        for (int k = 0; k < SETS_PER_ITEM; ++k) {
+            const int set = r.set0 + k;
+            double m[NF];
+            moments_about<DIM>(r.p + k * Q, r.ux - rx, r.uy - ry, s, m);
+#pragma unroll
+            for (int i = 0; i < NF; ++i)
+                lds[SPLIT == 2 ? (i * LN + r.li) * 2 + set : (set * NF + i) * LN + r.li] = (LdsT)m[i];
+        }
+    };
+    for (int it = tid; it < NITEMS; it += 2 * NT) {
+        Raw ra, rb;
+        const bool two = it + NT < NITEMS;
+        load_raw(it, ra);
+        if (two) load_raw(it + NT, rb);
+        store_moments(ra);
+        if (two) store_moments(rb);
+    }
+    __syncthreads();
+
+    // both lanes of a split receiver leave together, so the exchanges below always pair up
+    if (!inside) return;
     const int wbase = (DIM == 2 ? threadIdx.y * LX : 0) + lxr; // window (gx-2, gy-2)
     const double dt = P.dt;
 
@@ -309,10 +326,9 @@ __global__ void __launch_bounds__(SPLIT *TX *TY)
     if (err) atomicOr(&flags[kFlagErr], err);
 }
 
-template <int DIM, typename PopT, typename LdsT, int SPLIT>
+template <int DIM, typename PopT, typename LdsT, int SPLIT, int TX, int TY>
 static hipError_t launch_stream_t(const LaunchCtx &c, const DevState &s, int cur)
 {
-    constexpr int TX = StreamTile<DIM>::TX, TY = StreamTile<DIM>::TY;
     dim3 block(SPLIT * TX, TY);
     const int tx = (c.nx + TX - 1) / TX, ty = DIM == 2 ? (c.ny + TY - 1) / TY : 1;
     hipLaunchKernelGGL((k_stream<DIM, PopT, LdsT, TX, TY, SPLIT>), dim3(tx * ty), block, 0, c.st,
@@ -320,13 +336,37 @@ static hipError_t launch_stream_t(const LaunchCtx &c, const DevState &s, int cur
     return hipGetLastError();
 }
 
+// Tile shapes of the streaming kernel (receivers per block, x by y); the library picks
+// one per lattice, by measurement or as requested (pond_config.tile).
+static const int kTiles2D[][2] = {{32, 8}, {32, 4}, {16, 8}, {64, 4}, {16, 4}};
+static const int kTiles1D[][2] = {{128, 1}, {64, 1}};
+
+int stream_variants(int dim) { return dim == 2 ? 5 : 2; }
+void stream_tile_shape(int dim, int v, int *tx, int *ty)
+{
+    *tx = dim == 2 ? kTiles2D[v][0] : kTiles1D[v][0];
+    *ty = dim == 2 ? kTiles2D[v][1] : kTiles1D[v][1];
+}
+
+template <typename PopT, typename LdsT>
+static hipError_t launch_stream_v(const LaunchCtx &c, const DevState &s, int cur)
+{
+    if (c.dim == 2) {
+        switch (c.stream_tile) {
+        case 1: return launch_stream_t<2, PopT, LdsT, 2, 32, 4>(c, s, cur);
+        case 2: return launch_stream_t<2, PopT, LdsT, 2, 16, 8>(c, s, cur);
+        case 3: return launch_stream_t<2, PopT, LdsT, 2, 64, 4>(c, s, cur);
+        case 4: return launch_stream_t<2, PopT, LdsT, 2, 16, 4>(c, s, cur);
+        default: return launch_stream_t<2, PopT, LdsT, 2, 32, 8>(c, s, cur);
+        }
+    }
+    if (c.stream_tile == 1) return launch_stream_t<1, PopT, LdsT, 2, 64, 1>(c, s, cur);
+    return launch_stream_t<1, PopT, LdsT, 2, 128, 1>(c, s, cur);
+}
+
 hipError_t launch_stream(const LaunchCtx &c, const DevState &s, int cur)
 {
-    if (c.dim == 2)
-        return c.fp32 ? launch_stream_t<2, float, float, 2>(c, s, cur)
-                      : launch_stream_t<2, double, double, 2>(c, s, cur);
-    return c.fp32 ? launch_stream_t<1, float, float, 2>(c, s, cur)
-                  : launch_stream_t<1, double, double, 2>(c, s, cur);
+    return c.fp32 ? launch_stream_v<float, float>(c, s, cur) : launch_stream_v<double, double>(c, s, cur);
 }
 
 // ---------------------------------------------------------------------------
@@ -506,6 +546,38 @@ __global__ void __launch_bounds__(TX *TY)
     const double dt = P.dt;
     const bool force = P.kappa != 0.0;
 
+    // Issue every global load this thread needs before the LDS stages, so that their
+    // latencies overlap: the streamed state of its own node (used last) and the
+    // velocity and energy of its thermo-stage positions (used in stage 3).
+    const int x = x0 + threadIdx.x;
+    const int y = y0 + (DIM == 2 ? threadIdx.y : 0);
+    const bool inside = x < P.nx && (DIM == 1 || y < P.ny);
+    const int node = inside ? x + P.nx * y : 0;
+    double own[L::kMomPlanes];
+    if (inside) {
+#pragma unroll
+        for (int i = 0; i < L::kMomPlanes; ++i) own[i] = mom[i * N + node];
+    }
+    constexpr int HITEMS = (HX * HY + NT - 1) / NT;
+    double pre_u[HITEMS][3];
+    int pre_nb[HITEMS];
+#pragma unroll
+    for (int j = 0; j < HITEMS; ++j) {
+        const int li = tid + j * NT;
+        pre_nb[j] = -1;
+        if (li < HX * HY) {
+            const int gx = x0 - 1 + li % HX, gy = y0 - 1 + li / HX;
+            int cx, cy, face;
+            if (classify<DIM>(P, gx, gy, cx, cy, face) == kSelf) {
+                const int nb = map_node<DIM>(P, gx, DIM == 2 ? gy : 0);
+                pre_nb[j] = nb;
+                pre_u[j][0] = mom[L::kUx * N + nb];
+                pre_u[j][1] = DIM == 2 ? mom[L::kUy * N + nb] : 0.0;
+                pre_u[j][2] = mom[L::kG * N + nb];
+            }
+        }
+    }
+
     // stage 1: density of the streamed state
     if (force) {
         for (int li = tid; li < RX * RY; li += NT) {
@@ -560,7 +632,10 @@ __global__ void __launch_bounds__(TX *TY)
 
     // stage 3: force and thermodynamic state of the step
     int err = 0;
-    for (int li = tid; li < HX * HY; li += NT) {
+#pragma unroll
+    for (int j = 0; j < HITEMS; ++j) {
+        const int li = tid + j * NT;
+        if (li >= HX * HY) break;
         const int hx = li % HX, hy = li / HX;
         const int gx = x0 - 1 + hx, gy = y0 - 1 + hy;
         int cx, cy, face;
@@ -582,11 +657,11 @@ __global__ void __launch_bounds__(TX *TY)
                 Fx = -dvx / kTL;
                 Fy = DIM == 2 ? -dvy / kTL : 0.0;
             }
-            const int nb = map_node<DIM>(P, gx, DIM == 2 ? gy : 0);
-            const double rho = mom[L::kRho * N + nb];
-            const double ux = mom[L::kUx * N + nb];
-            const double uy = DIM == 2 ? mom[L::kUy * N + nb] : 0.0;
-            const double E = mom[L::kG * N + nb] / (2.0 * rho);
+            const int nb = pre_nb[j];
+            const double rho = force ? s_rho[(DIM == 2 ? (hy + 2) * RX : 0) + hx + 2] : mom[L::kRho * N + nb];
+            const double ux = pre_u[j][0];
+            const double uy = pre_u[j][1];
+            const double E = pre_u[j][2] / (2.0 * rho);
             const double uhx = ux + Fx * dt / (2.0 * rho);
             const double uhy = DIM == 2 ? uy + Fy * dt / (2.0 * rho) : 0.0;
             const double e = E - 0.5 * (uhx * uhx + uhy * uhy);
@@ -622,10 +697,7 @@ __global__ void __launch_bounds__(TX *TY)
     __syncthreads();
     if (err) atomicOr(&flags[kFlagErr], err);
 
-    const int x = x0 + threadIdx.x;
-    const int y = y0 + (DIM == 2 ? threadIdx.y : 0);
-    if (x >= P.nx || (DIM == 2 && y >= P.ny)) return;
-    const int node = x + P.nx * y;
+    if (!inside) return;
     const int hb = (DIM == 2 ? (threadIdx.y + 1) * HX : 0) + threadIdx.x + 1;
 
     // heat-flux correction M0 = 2 div(-mu grad h + k grad T), flux form (eq. 9)
@@ -647,13 +719,13 @@ __global__ void __launch_bounds__(TX *TY)
         M0 = 2.0 * (2.0 / kTL) * acc;
     }
 
-    const double rho = mom[L::kRho * N + node];
-    const double u[2] = {mom[L::kUx * N + node], DIM == 2 ? mom[L::kUy * N + node] : 0.0};
+    const double rho = own[L::kRho];
+    const double u[2] = {own[L::kUx], DIM == 2 ? own[L::kUy] : 0.0};
     const double F[2] = {s_th[kThFx][hb], DIM == 2 ? s_th[kThFy][hb] : 0.0};
     const double p = s_th[kThP][hb];
     const double theta = p / (rho * kTL);
     const double s = sqrt(theta);
-    const double E = mom[L::kG * N + node] / (2.0 * rho);
+    const double E = own[L::kG] / (2.0 * rho);
     const double uh[2] = {u[0] + F[0] * dt / (2.0 * rho), DIM == 2 ? u[1] + F[1] * dt / (2.0 * rho) : 0.0};
 
     // streamed populations in the collision gauge (u, theta) from their central moments
@@ -662,19 +734,19 @@ __global__ void __launch_bounds__(TX *TY)
         mf[0] = rho;
         mf[1] = 0.0; // (0,1): zero about u
         mf[3] = 0.0; // (1,0)
-        mf[4] = mom[(L::kF + 0) * N + node];
-        mf[6] = mom[(L::kF + 1) * N + node];
-        mf[2] = mom[(L::kF + 2) * N + node];
-        mf[7] = mom[(L::kF + 3) * N + node];
-        mf[5] = mom[(L::kF + 4) * N + node];
-        mf[8] = mom[(L::kF + 5) * N + node];
+        mf[4] = own[L::kF + 0];
+        mf[6] = own[L::kF + 1];
+        mf[2] = own[L::kF + 2];
+        mf[7] = own[L::kF + 3];
+        mf[5] = own[L::kF + 4];
+        mf[8] = own[L::kF + 5];
     } else {
         mf[0] = rho;
         mf[1] = 0.0;
-        mf[2] = mom[L::kF * N + node];
+        mf[2] = own[L::kF];
     }
 #pragma unroll
-    for (int i = 0; i < NF; ++i) mg[i] = mom[(L::kG + i) * N + node];
+    for (int i = 0; i < NF; ++i) mg[i] = own[L::kG + i];
     double A[3][3];
     lagrange_coeffs(0.0, s, A);
     double f[Q], g[Q];

@@ -29,7 +29,7 @@ KERNEL_NAMES = {K_STREAM: "k_stream", K_FORCE_COLLIDE: "k_force_collide"}
 
 EXPORTED = ["pond_create", "pond_init_fields", "pond_step", "pond_moments", "pond_monitors",
             "pond_steps_done", "pond_last_error", "pond_destroy", "pond_time_kernel",
-            "pond_step_timed"]
+            "pond_step_timed", "pond_tile_info"]
 
 
 class pond_config(ctypes.Structure):
@@ -48,6 +48,7 @@ class pond_config(ctypes.Structure):
         ("dt", ctypes.c_double),
         ("n_pass", ctypes.c_int),
         ("precision", ctypes.c_int),
+        ("tile", ctypes.c_int),
         ("stream", ctypes.c_void_p),
     ]
 
@@ -82,6 +83,7 @@ def load(path: str = LIB_PATH):
     L.pond_destroy.argtypes = [hp]
     L.pond_time_kernel.argtypes = [hp, ctypes.c_int, ctypes.c_int, dp]
     L.pond_step_timed.argtypes = [hp, ctypes.c_int, dp]
+    L.pond_tile_info.argtypes = [hp, ctypes.POINTER(ctypes.c_int)]
     for name in EXPORTED:
         getattr(L, name).restype = getattr(L, name).restype or ctypes.c_int
     L.pond_last_error.restype = ctypes.c_char_p
@@ -110,6 +112,7 @@ class Config:
     dt: float = 0.2
     n_pass: int = 2
     precision: int = FP64
+    tile: int = -1              # streaming tile shape; -1: measured at the first init
     stream: int | None = None   # hipStream_t as an integer (e.g. torch's cuda_stream)
 
     def to_c(self) -> pond_config:
@@ -128,7 +131,7 @@ class Config:
                 c.inflow[a][s][k] = float(vals[k])
         c.a, c.b, c.R, c.delta = self.a, self.b, self.R, self.delta
         c.omega, c.kappa, c.k_scale, c.dt = self.omega, self.kappa, self.k_scale, self.dt
-        c.n_pass, c.precision = self.n_pass, self.precision
+        c.n_pass, c.precision, c.tile = self.n_pass, self.precision, self.tile
         c.stream = self.stream
         return c
 
@@ -203,6 +206,11 @@ class Lattice:
         out = np.zeros(2)
         self._check(load().pond_step_timed(self._h, int(n), _dp(out)), "pond_step_timed")
         return {KERNEL_NAMES[K_STREAM]: float(out[0]), KERNEL_NAMES[K_FORCE_COLLIDE]: float(out[1])}
+
+    def tile_info(self) -> dict:
+        out = (ctypes.c_int * 4)()
+        self._check(load().pond_tile_info(self._h, out), "pond_tile_info")
+        return {"variant": out[0], "tx": out[1], "ty": out[2], "variants": out[3]}
 
     def last_error(self) -> str:
         return load().pond_last_error(self._h).decode()

@@ -22,12 +22,12 @@ def oracle_config(case) -> core.Config:
                        k_scale=p["k_scale"], dt=p["dt"], n_pass=p["n_pass"])
 
 
-def pond_config(case, precision=pond.FP64, stream=None) -> pond.Config:
+def pond_config(case, precision=pond.FP64, stream=None, tile=-1) -> pond.Config:
     p = case.params
     return pond.Config(dim=case.dim, n=tuple(case.n), bc=case.bc, inflow=case.inflow,
                        a=p["a"], b=p["b"], R=p["R"], delta=p["delta"], omega=p["omega"],
                        kappa=p["kappa"], k_scale=p["k_scale"], dt=p["dt"], n_pass=p["n_pass"],
-                       precision=precision, stream=stream)
+                       precision=precision, tile=tile, stream=stream)
 
 
 def run_oracle(case, steps):
@@ -39,8 +39,8 @@ def run_oracle(case, steps):
     return sim.moments()
 
 
-def run_gpu(case, steps, precision=pond.FP64):
-    lat = pond.Lattice(pond_config(case, precision))
+def run_gpu(case, steps, precision=pond.FP64, tile=-1):
+    lat = pond.Lattice(pond_config(case, precision, tile=tile))
     try:
         lat.init_fields(case.rho, case.u, case.T)
         if steps:

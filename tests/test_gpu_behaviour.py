@@ -10,8 +10,8 @@ from tests.common import pond_config, run_oracle
 pytestmark = pytest.mark.gpu
 
 
-def _lattice(case, **kw):
-    lat = pond.Lattice(pond_config(case, **kw))
+def _lattice(case, tile=0, **kw):
+    lat = pond.Lattice(pond_config(case, tile=tile, **kw))
     lat.init_fields(case.rho, case.u, case.T)
     return lat
 
@@ -91,3 +91,18 @@ def test_halo_violation_keeps_last_state():
         lat.step(1)
     assert err.value.code == -7
     lat.close()
+
+
+def test_autotuned_tile_is_valid_and_results_agree_to_roundoff():
+    case = W.perturbed(64, 48, seed=12, kappa=0.0176)
+    auto = _lattice(case, tile=-1)
+    info = auto.tile_info()
+    assert 0 <= info["variant"] < info["variants"] and info["tx"] * info["ty"] >= 64
+    auto.step(20)
+    fixed = _lattice(case, tile=(info["variant"] + 1) % info["variants"])
+    fixed.step(20)
+    a, b = auto.moments(), fixed.moments()
+    for k in ("rho", "E"):
+        assert np.max(np.abs(a[k] - b[k])) <= 1e-13 * np.max(np.abs(b[k]))
+    auto.close()
+    fixed.close()

@@ -16,9 +16,9 @@ pytestmark = pytest.mark.gpu
 TOL64 = 1e-12
 
 
-def _check(case, steps, tol=TOL64, precision=pond.FP64, fields=("rho", "ux", "uy", "E", "T", "p")):
+def _check(case, steps, tol=TOL64, precision=pond.FP64, fields=("rho", "ux", "uy", "E", "T", "p"), tile=-1):
     ref = run_oracle(case, steps)
-    got = run_gpu(case, steps, precision)
+    got = run_gpu(case, steps, precision, tile=tile)
     errs = compare(got, ref, fields)
     print(case.name, steps, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
     bad = {k: v for k, v in errs.items() if not v <= tol}
@@ -78,3 +78,15 @@ def test_fp32_storage_within_1e4(which):
     else:
         case = W.static_droplet(n=64, radius=14.0)
     _check(case, 100, tol=1e-4, precision=pond.FP32_STORE)
+
+
+@pytest.mark.parametrize("tile", range(5))
+def test_every_stream_tile_shape_2d(tile):
+    case = W.perturbed(70, 45, seed=30 + tile, kappa=0.0176, u0=(0.1, -0.2))
+    _check(case, 30, tile=tile)
+
+
+@pytest.mark.parametrize("tile", range(2))
+def test_every_stream_tile_shape_1d(tile):
+    case = W.perturbed(333, 1, seed=40 + tile, dim=1, kappa=0.0176, u0=(0.2, 0.0))
+    _check(case, 30, tile=tile, fields=("rho", "ux", "E", "T", "p"))
