@@ -38,6 +38,7 @@ extern "C" {
 #endif
 
 typedef struct pond_handle pond_handle; /* opaque, library-owned */
+typedef struct pond_batch pond_batch;   /* opaque, library-owned */
 
 typedef enum {
     POND_OK = 0,
@@ -131,11 +132,58 @@ int pond_destroy(pond_handle *h);
 int pond_time_kernel(pond_handle *h, int which, int reps, double *avg_us);
 
 /* Measurement: advance nsteps >= 1 time steps exactly as pond_step does, but with
- * the kernels launched one by one and HIP events recorded on the handle's stream
- * around every launch; kernel_us[0] and kernel_us[1] receive the mean duration of
- * the streaming kernel and of the force/collision kernel inside the step pipeline.
+ * the kernels launched one by one, each with a pair of HIP events that the runtime
+ * records at that kernel's start and end on the handle's stream; kernel_us[0] and
+ * kernel_us[1] receive the mean duration of the streaming kernel and of the
+ * force/collision kernel inside the step pipeline.
  * Errors and state as for pond_step. */
 int pond_step_timed(pond_handle *h, int nsteps, double *kernel_us);
+
+/* Device bytes that pond_create allocates for cfg (all state, scratch and monitor
+ * buffers; HIP's own allocation granularity not included).  For admission control of
+ * many resident lattices.  Errors: POND_E_INVALID as for pond_create. */
+int pond_footprint(const pond_config *cfg, unsigned long long *bytes);
+
+/* ---------------------------------------------------------------------------
+ * Batches: many independent lattices advanced together.  Every step of a batch is
+ * one launch of each step kernel per group of members that share dim, precision and
+ * streaming tile shape, over the tiles of all of them; each member keeps its own
+ * device state, parameters, error flags and step counter, so its results are
+ * bitwise those of pond_step on the same handle alone.  The main-text time step of
+ * each lattice is unchanged (eqs. 1-22); batching is scheduling only.
+ * --------------------------------------------------------------------------- */
+
+/* Create an empty batch whose steps run on `stream` (a hipStream_t; NULL = a
+ * library-owned stream).  Errors: POND_E_INVALID (out NULL), POND_E_NOMEM,
+ * POND_E_DEVICE. */
+int pond_batch_create(void *stream, pond_batch **out);
+
+/* Add an initialised handle that is in no batch.  While it is a member, pond_step,
+ * pond_step_timed, pond_time_kernel and pond_init_fields refuse the handle
+ * (POND_E_STATE); pond_moments, pond_monitors, pond_steps_done, pond_last_error and
+ * pond_tile_info work as usual, and pond_destroy removes it first.  The handle's
+ * stream is synchronised before it joins.  Errors: POND_E_INVALID (NULL, already
+ * a member of a batch, or its group would exceed 2^21 workgroups per launch),
+ * POND_E_STATE (not initialised or in the error state), POND_E_NOMEM. */
+int pond_batch_add(pond_batch *b, pond_handle *h);
+
+/* Remove a member (its state and step count are kept).  Errors: POND_E_INVALID when
+ * h is not a member of b. */
+int pond_batch_remove(pond_batch *b, pond_handle *h);
+
+/* Advance every member nsteps >= 0 time steps, then synchronise.  A member that fails
+ * is left as pond_step leaves a failed handle (state of its last completed step,
+ * error state, pond_last_error set) and leaves the batch; the others complete all
+ * nsteps.  Returns POND_OK when every member completed, else the status of the
+ * first failed member in order of addition (POND_E_PRESSURE, POND_E_NONFINITE,
+ * POND_E_HALO), or POND_E_DEVICE. */
+int pond_batch_step(pond_batch *b, int nsteps);
+
+/* Number of members. */
+int pond_batch_size(const pond_batch *b, int *out);
+
+/* Remove all members and release the batch.  NULL is accepted. */
+int pond_batch_destroy(pond_batch *b);
 
 #ifdef __cplusplus
 }

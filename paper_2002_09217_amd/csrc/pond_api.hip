@@ -10,35 +10,21 @@
 #include <new>
 
 #include "pond.h"
+#include "pond_handle.h"
 #include "pond_internal.h"
 
 using namespace pond;
 
-struct pond_handle {
-    pond_config cfg;
-    LaunchCtx lc;
-    DevState ds;
-    hipStream_t stream = nullptr;       // where work runs (caller's or owned)
-    bool own_stream = false;
-    hipStream_t capture_stream = nullptr; // used only to record graphs
-    hipGraphExec_t pair_exec[2] = {nullptr, nullptr}; // two steps starting from state 0 / 1
-    bool graphs_ok = true;
-    bool tuned = false;                 // streaming tile shape fixed
-    int cur = 0;                        // state buffer holding the current state
-    long long steps = 0;
-    bool initialised = false;
-    bool failed = false;
-    double *mon_partials = nullptr;
-    double *mon_out = nullptr;
-    int mon_blocks = 0;
-    char msg[256] = "ok";
-};
+#define HIP_TRY(h, expr)                                                                        \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return handle_fail((h), POND_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
 
-namespace {
+namespace pond {
 
-const double kW1h[3] = {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0};
-
-int fail(pond_handle *h, int code, const char *fmt, ...)
+int handle_fail(pond_handle *h, int code, const char *fmt, ...)
 {
     if (h) {
         va_list ap;
@@ -49,12 +35,69 @@ int fail(pond_handle *h, int code, const char *fmt, ...)
     return code;
 }
 
-#define HIP_TRY(h, expr)                                                                        \
-    do {                                                                                        \
-        hipError_t e_ = (expr);                                                                 \
-        if (e_ != hipSuccess)                                                                   \
-            return fail((h), POND_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));            \
-    } while (0)
+// rebuild the two step descriptors of a lattice (after allocation or a tile change)
+int handle_update_desc(pond_handle *h)
+{
+    int stx, stc, fcx, fcc;
+    tile_counts(h->lc, &stx, &stc, &fcx, &fcc);
+    h->st_tiles = stc;
+    h->fc_tiles = fcc;
+    for (int p = 0; p < 2; ++p) {
+        SlotDesc &d = h->desc_h[p];
+        d.P = h->ds.params;
+        d.pop_src = h->ds.pop[p];
+        d.side_src = h->ds.side[p];
+        d.pop_dst = h->ds.pop[1 - p];
+        d.side_dst = h->ds.side[1 - p];
+        d.mom = h->ds.mom;
+        d.flags = h->ds.flags;
+        d.st_tiles_x = stx;
+        d.st_begin = 0;
+        d.st_count = stc;
+        d.fc_tiles_x = fcx;
+        d.fc_begin = 0;
+        d.fc_count = fcc;
+    }
+    // synchronous: the descriptors are read by work already queued on the stream
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    HIP_TRY(h, hipMemcpy(h->desc_d, h->desc_h, sizeof h->desc_h, hipMemcpyHostToDevice));
+    return POND_OK;
+}
+
+int err_code(int bits)
+{
+    if (bits & kErrNonfinite) return POND_E_NONFINITE;
+    if (bits & kErrPressure) return POND_E_PRESSURE;
+    if (bits & kErrHalo) return POND_E_HALO;
+    return POND_E_DEVICE;
+}
+
+const char *err_name(int bits)
+{
+    if (bits & kErrNonfinite) return "non-finite state";
+    if (bits & kErrPressure) return "state outside the EoS domain (p <= 0, rho <= 0 or 1 - b rho <= 0)";
+    if (bits & kErrHalo) return "departure stencil outside the +-2 window (|v| dt >= 1)";
+    return "unknown";
+}
+
+// move the handle to the last completed state of a batch of steps, given its flags
+int handle_finish_batch(pond_handle *h, const int *fl)
+{
+    const int done = fl[kFlagErr] ? fl[kFlagSteps] - 1 : fl[kFlagSteps];
+    h->cur = (h->cur + done) % 2;
+    h->steps += done;
+    if (fl[kFlagErr]) {
+        h->failed = true;
+        return handle_fail(h, err_code(fl[kFlagErr]), "step %lld: %s", h->steps + 1, err_name(fl[kFlagErr]));
+    }
+    return POND_OK;
+}
+
+} // namespace pond
+
+namespace {
+
+const double kW1h[3] = {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0};
 
 double host_p(const pond_config &c, double rho, double T)
 {
@@ -92,144 +135,19 @@ bool make_ghost(const pond_config &c, const double st[5], GhostFace &G)
     return true;
 }
 
-int enqueue_step(pond_handle *h, hipStream_t st, int from)
+// device bytes of one lattice of the given shape (all buffers of pond_create)
+size_t footprint(int dim, long long N, int fp32)
 {
-    LaunchCtx c = h->lc;
-    c.st = st;
-    const DevState &s = h->ds;
-    HIP_TRY(h, launch_stream(c, s, from));
-    HIP_TRY(h, launch_force_collide(c, s, 1 - from));
-    return POND_OK;
+    const int Q = dim == 2 ? 9 : 3;
+    const int momPlanes = dim == 2 ? Layout<2>::kMomPlanes : Layout<1>::kMomPlanes;
+    const size_t pop = fp32 ? sizeof(float) : sizeof(double);
+    const size_t mon = sizeof(double) * 8 * ((N + 255) / 256) + sizeof(double) * 8;
+    return (size_t)N * (2 * 2 * Q * pop + sizeof(double) * (2 * kSidePlanes + momPlanes + kKorPlanes + kAuxPlanes)) +
+           sizeof(int) * kFlagWords + sizeof(DevParams) + 2 * sizeof(SlotDesc) + mon;
 }
 
-// record two steps starting from state `from` into an executable graph
-int build_pair_graph(pond_handle *h, int from)
+int validate(const pond_config *cfg)
 {
-    if (h->pair_exec[from]) return POND_OK;
-    hipGraph_t g = nullptr;
-    HIP_TRY(h, hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal));
-    int rc = enqueue_step(h, h->capture_stream, from);
-    if (rc == POND_OK) rc = enqueue_step(h, h->capture_stream, 1 - from);
-    hipError_t e = hipStreamEndCapture(h->capture_stream, &g);
-    if (rc != POND_OK) return rc;
-    if (e != hipSuccess) return fail(h, POND_E_DEVICE, "graph capture: %s", hipGetErrorString(e));
-    e = hipGraphInstantiate(&h->pair_exec[from], g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
-    if (e != hipSuccess) {
-        h->pair_exec[from] = nullptr;
-        return fail(h, POND_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
-    }
-    return POND_OK;
-}
-
-int read_flags(pond_handle *h, int out[kFlagWords])
-{
-    HIP_TRY(h, hipMemcpyAsync(out, h->ds.flags, sizeof(int) * kFlagWords, hipMemcpyDeviceToHost,
-                              h->stream));
-    HIP_TRY(h, hipStreamSynchronize(h->stream));
-    return POND_OK;
-}
-
-int err_code(int bits)
-{
-    if (bits & kErrNonfinite) return POND_E_NONFINITE;
-    if (bits & kErrPressure) return POND_E_PRESSURE;
-    if (bits & kErrHalo) return POND_E_HALO;
-    return POND_E_DEVICE;
-}
-
-const char *err_name(int bits)
-{
-    if (bits & kErrNonfinite) return "non-finite state";
-    if (bits & kErrPressure) return "state outside the EoS domain (p <= 0, rho <= 0 or 1 - b rho <= 0)";
-    if (bits & kErrHalo) return "departure stencil outside the +-2 window (|v| dt >= 1)";
-    return "unknown";
-}
-
-void free_all(pond_handle *h)
-{
-    for (int i = 0; i < 2; ++i) {
-        if (h->pair_exec[i]) hipGraphExecDestroy(h->pair_exec[i]);
-        if (h->ds.pop[i]) hipFree(h->ds.pop[i]);
-        if (h->ds.side[i]) hipFree(h->ds.side[i]);
-    }
-    if (h->ds.mom) hipFree(h->ds.mom);
-    if (h->ds.kor) hipFree(h->ds.kor);
-    if (h->ds.aux) hipFree(h->ds.aux);
-    if (h->ds.flags) hipFree(h->ds.flags);
-    if (h->ds.params) hipFree(h->ds.params);
-    if (h->mon_partials) hipFree(h->mon_partials);
-    if (h->mon_out) hipFree(h->mon_out);
-    if (h->capture_stream) hipStreamDestroy(h->capture_stream);
-    if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
-}
-
-void drop_graphs(pond_handle *h)
-{
-    for (int i = 0; i < 2; ++i)
-        if (h->pair_exec[i]) {
-            hipGraphExecDestroy(h->pair_exec[i]);
-            h->pair_exec[i] = nullptr;
-        }
-}
-
-// Time every compiled tile shape of the streaming kernel on the current state (one
-// warm-up launch, then `reps` launches between HIP events) and keep the fastest.
-int tune_stream_tile(pond_handle *h, int reps)
-{
-    const int nv = stream_variants(h->lc.dim);
-    hipEvent_t e0, e1;
-    HIP_TRY(h, hipEventCreate(&e0));
-    HIP_TRY(h, hipEventCreate(&e1));
-    int best = 0;
-    float best_ms = 1e30f;
-    for (int v = 0; v < nv; ++v) {
-        LaunchCtx c = h->lc;
-        c.stream_tile = v;
-        HIP_TRY(h, launch_stream(c, h->ds, h->cur));
-        HIP_TRY(h, hipEventRecord(e0, h->stream));
-        for (int r = 0; r < reps; ++r) HIP_TRY(h, launch_stream(c, h->ds, h->cur));
-        HIP_TRY(h, hipEventRecord(e1, h->stream));
-        HIP_TRY(h, hipEventSynchronize(e1));
-        float ms = 0.0f;
-        HIP_TRY(h, hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = v;
-        }
-    }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    if (best != h->lc.stream_tile) drop_graphs(h);
-    h->lc.stream_tile = best;
-    h->tuned = true;
-    return POND_OK;
-}
-
-// read the flags after a batch of steps and move the handle to the last completed state
-int finish_batch(pond_handle *h)
-{
-    int fl[kFlagWords];
-    int rc = read_flags(h, fl);
-    if (rc != POND_OK) return rc;
-    const int done = fl[kFlagErr] ? fl[kFlagSteps] - 1 : fl[kFlagSteps];
-    h->cur = (h->cur + done) % 2;
-    h->steps += done;
-    if (fl[kFlagErr]) {
-        h->failed = true;
-        return fail(h, err_code(fl[kFlagErr]), "step %lld: %s", h->steps + 1, err_name(fl[kFlagErr]));
-    }
-    return POND_OK;
-}
-
-} // namespace
-
-extern "C" {
-
-int pond_create(const pond_config *cfg, pond_handle **out)
-{
-    if (!out) return POND_E_INVALID;
-    *out = nullptr;
     if (!cfg) return POND_E_INVALID;
     const pond_config &c = *cfg;
     if (c.dim != 1 && c.dim != 2) return POND_E_INVALID;
@@ -243,6 +161,140 @@ int pond_create(const pond_config *cfg, pond_handle **out)
     for (int a = 0; a < c.dim; ++a)
         for (int s = 0; s < 2; ++s)
             if (c.bc[a][s] < 0 || c.bc[a][s] > 2) return POND_E_INVALID;
+    return POND_OK;
+}
+
+int enqueue_step(pond_handle *h, hipStream_t st, int from)
+{
+    LaunchCtx c = h->lc;
+    c.st = st;
+    HIP_TRY(h, launch_stream(c, h->desc_d + from, 1, h->st_tiles));
+    HIP_TRY(h, launch_force_collide(c, h->desc_d + from, 1, h->fc_tiles));
+    return POND_OK;
+}
+
+// record two steps starting from state `from` into an executable graph
+int build_pair_graph(pond_handle *h, int from)
+{
+    if (h->pair_exec[from]) return POND_OK;
+    hipGraph_t g = nullptr;
+    HIP_TRY(h, hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue_step(h, h->capture_stream, from);
+    if (rc == POND_OK) rc = enqueue_step(h, h->capture_stream, 1 - from);
+    hipError_t e = hipStreamEndCapture(h->capture_stream, &g);
+    if (rc != POND_OK) return rc;
+    if (e != hipSuccess) return handle_fail(h, POND_E_DEVICE, "graph capture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&h->pair_exec[from], g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        h->pair_exec[from] = nullptr;
+        return handle_fail(h, POND_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
+    }
+    return POND_OK;
+}
+
+int read_flags(pond_handle *h, int out[kFlagWords])
+{
+    HIP_TRY(h, hipMemcpyAsync(out, h->ds.flags, sizeof(int) * kFlagWords, hipMemcpyDeviceToHost,
+                              h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return POND_OK;
+}
+
+int finish_batch(pond_handle *h)
+{
+    int fl[kFlagWords];
+    int rc = read_flags(h, fl);
+    if (rc != POND_OK) return rc;
+    return handle_finish_batch(h, fl);
+}
+
+void drop_graphs(pond_handle *h)
+{
+    for (int i = 0; i < 2; ++i)
+        if (h->pair_exec[i]) {
+            hipGraphExecDestroy(h->pair_exec[i]);
+            h->pair_exec[i] = nullptr;
+        }
+}
+
+void free_all(pond_handle *h)
+{
+    drop_graphs(h);
+    for (int i = 0; i < 2; ++i) {
+        if (h->ds.pop[i]) hipFree(h->ds.pop[i]);
+        if (h->ds.side[i]) hipFree(h->ds.side[i]);
+    }
+    if (h->ds.mom) hipFree(h->ds.mom);
+    if (h->ds.kor) hipFree(h->ds.kor);
+    if (h->ds.aux) hipFree(h->ds.aux);
+    if (h->ds.flags) hipFree(h->ds.flags);
+    if (h->ds.params) hipFree(h->ds.params);
+    if (h->desc_d) hipFree(h->desc_d);
+    if (h->mon_partials) hipFree(h->mon_partials);
+    if (h->mon_out) hipFree(h->mon_out);
+    if (h->capture_stream) hipStreamDestroy(h->capture_stream);
+    if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
+}
+
+// Time every compiled tile shape of the streaming kernel on the current state (one
+// warm-up launch, then `reps` launches between HIP events) and keep the fastest.
+int tune_stream_tile(pond_handle *h, int reps)
+{
+    const int nv = stream_variants(h->lc.dim);
+    hipEvent_t e0, e1;
+    HIP_TRY(h, hipEventCreate(&e0));
+    HIP_TRY(h, hipEventCreate(&e1));
+    int best = 0;
+    float best_ms = 1e30f;
+    int rc = POND_OK;
+    for (int v = 0; v < nv && rc == POND_OK; ++v) {
+        h->lc.stream_tile = v;
+        rc = handle_update_desc(h);
+        if (rc != POND_OK) break;
+        HIP_TRY(h, launch_stream(h->lc, h->desc_d + h->cur, 1, h->st_tiles));
+        HIP_TRY(h, hipEventRecord(e0, h->stream));
+        for (int r = 0; r < reps; ++r) HIP_TRY(h, launch_stream(h->lc, h->desc_d + h->cur, 1, h->st_tiles));
+        HIP_TRY(h, hipEventRecord(e1, h->stream));
+        HIP_TRY(h, hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIP_TRY(h, hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = v;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc != POND_OK) return rc;
+    drop_graphs(h);
+    h->lc.stream_tile = best;
+    h->tuned = true;
+    return handle_update_desc(h);
+}
+
+} // namespace
+
+extern "C" {
+
+int pond_footprint(const pond_config *cfg, unsigned long long *bytes)
+{
+    if (!bytes) return POND_E_INVALID;
+    const int rc = validate(cfg);
+    if (rc != POND_OK) return rc;
+    const long long N = (long long)cfg->n[0] * (cfg->dim == 2 ? cfg->n[1] : 1);
+    *bytes = footprint(cfg->dim, N, cfg->precision == POND_FP32_STORE);
+    return POND_OK;
+}
+
+int pond_create(const pond_config *cfg, pond_handle **out)
+{
+    if (!out) return POND_E_INVALID;
+    *out = nullptr;
+    int rc = validate(cfg);
+    if (rc != POND_OK) return rc;
+    const pond_config &c = *cfg;
+    const int nx = c.n[0], ny = c.dim == 2 ? c.n[1] : 1;
 
     pond_handle *h = new (std::nothrow) pond_handle();
     if (!h) return POND_E_NOMEM;
@@ -283,14 +335,13 @@ int pond_create(const pond_config *cfg, pond_handle **out)
                 return POND_E_INVALID;
             }
 
-    int rc = POND_OK;
     const size_t popb = (size_t)2 * Q * N * (h->lc.fp32 ? sizeof(float) : sizeof(double));
     const int momPlanes = c.dim == 2 ? Layout<2>::kMomPlanes : Layout<1>::kMomPlanes;
     auto alloc = [&](void **p, size_t bytes) {
         if (rc != POND_OK) return;
         if (hipMalloc(p, bytes) != hipSuccess) {
             *p = nullptr;
-            rc = fail(h, POND_E_NOMEM, "hipMalloc of %zu bytes failed", bytes);
+            rc = handle_fail(h, POND_E_NOMEM, "hipMalloc of %zu bytes failed", bytes);
         }
     };
     for (int i = 0; i < 2; ++i) {
@@ -302,6 +353,7 @@ int pond_create(const pond_config *cfg, pond_handle **out)
     alloc((void **)&h->ds.aux, sizeof(double) * kAuxPlanes * N);
     alloc((void **)&h->ds.flags, sizeof(int) * kFlagWords);
     alloc((void **)&h->ds.params, sizeof(DevParams));
+    alloc((void **)&h->desc_d, 2 * sizeof(SlotDesc));
     h->mon_blocks = monitor_blocks(h->lc);
     alloc((void **)&h->mon_partials, sizeof(double) * 8 * h->mon_blocks);
     alloc((void **)&h->mon_out, sizeof(double) * 8);
@@ -318,9 +370,10 @@ int pond_create(const pond_config *cfg, pond_handle **out)
         rc = POND_E_DEVICE;
     if (rc == POND_OK) {
         h->lc.st = h->stream;
-        if (hipMemcpy(h->ds.params, &P, sizeof P, hipMemcpyHostToDevice) != hipSuccess)
-            rc = POND_E_DEVICE;
+        if (hipMemcpy(h->ds.params, &P, sizeof P, hipMemcpyHostToDevice) != hipSuccess) rc = POND_E_DEVICE;
     }
+    if (rc == POND_OK && launch_reset_flags(h->lc, h->ds.flags) != hipSuccess) rc = POND_E_DEVICE;
+    if (rc == POND_OK) rc = handle_update_desc(h);
     if (rc != POND_OK) {
         free_all(h);
         delete h;
@@ -333,7 +386,8 @@ int pond_create(const pond_config *cfg, pond_handle **out)
 int pond_init_fields(pond_handle *h, const double *rho, const double *u, const double *T)
 {
     if (!h) return POND_E_INVALID;
-    if (!rho || !u || !T) return fail(h, POND_E_INVALID, "NULL field");
+    if (!rho || !u || !T) return handle_fail(h, POND_E_INVALID, "NULL field");
+    if (h->batch) return handle_fail(h, POND_E_STATE, "handle is a member of a batch");
     const int N = h->lc.N, dim = h->lc.dim;
     h->initialised = false;
     h->failed = false;
@@ -345,19 +399,21 @@ int pond_init_fields(pond_handle *h, const double *rho, const double *u, const d
     HIP_TRY(h, launch_reset_flags(h->lc, h->ds.flags));
     if (h->cfg.kappa != 0.0) HIP_TRY(h, launch_korteweg(h->lc, h->ds, d_rho));
     HIP_TRY(h, launch_init_equilibrium(h->lc, h->ds, d_rho, d_u, d_T));
-    HIP_TRY(h, launch_force_collide(h->lc, h->ds, 0));
+    // the descriptor of parity 1 writes state 0
+    HIP_TRY(h, launch_force_collide(h->lc, h->desc_d + 1, 1, h->fc_tiles));
     int fl[kFlagWords];
     int rc = read_flags(h, fl);
     if (rc != POND_OK) return rc;
-    if (fl[kFlagErr]) return fail(h, err_code(fl[kFlagErr]), "init: %s", err_name(fl[kFlagErr]));
+    if (fl[kFlagErr]) return handle_fail(h, err_code(fl[kFlagErr]), "init: %s", err_name(fl[kFlagErr]));
     h->cur = 0;
     h->steps = 0;
     if (!h->tuned) {
         rc = tune_stream_tile(h, 10);
         if (rc != POND_OK) return rc;
-        // the tuning launches count as started steps: clear the counters again
-        HIP_TRY(h, launch_reset_flags(h->lc, h->ds.flags));
     }
+    // the tuning launches count as started steps: clear the counters again
+    HIP_TRY(h, launch_reset_flags(h->lc, h->ds.flags));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
     h->initialised = true;
     std::snprintf(h->msg, sizeof h->msg, "ok");
     return POND_OK;
@@ -366,7 +422,9 @@ int pond_init_fields(pond_handle *h, const double *rho, const double *u, const d
 int pond_step(pond_handle *h, int nsteps)
 {
     if (!h || nsteps < 0) return POND_E_INVALID;
-    if (!h->initialised || h->failed) return fail(h, POND_E_STATE, h->failed ? "handle in error state" : "not initialised");
+    if (!h->initialised || h->failed)
+        return handle_fail(h, POND_E_STATE, h->failed ? "handle in error state" : "not initialised");
+    if (h->batch) return handle_fail(h, POND_E_STATE, "handle is a member of a batch");
     if (nsteps == 0) return POND_OK;
     HIP_TRY(h, launch_reset_flags(h->lc, h->ds.flags));
     int parity = h->cur;
@@ -389,7 +447,7 @@ int pond_step(pond_handle *h, int nsteps)
 int pond_moments(pond_handle *h, double *rho, double *u, double *T, double *p, double *E)
 {
     if (!h) return POND_E_INVALID;
-    if (!h->initialised) return fail(h, POND_E_STATE, "not initialised");
+    if (!h->initialised) return handle_fail(h, POND_E_STATE, "not initialised");
     const size_t N = h->lc.N;
     const int dim = h->lc.dim;
     HIP_TRY(h, launch_macro(h->lc, h->ds, h->cur, h->ds.aux));
@@ -410,7 +468,7 @@ int pond_moments(pond_handle *h, double *rho, double *u, double *T, double *p, d
 int pond_monitors(pond_handle *h, double *out)
 {
     if (!h || !out) return POND_E_INVALID;
-    if (!h->initialised) return fail(h, POND_E_STATE, "not initialised");
+    if (!h->initialised) return handle_fail(h, POND_E_STATE, "not initialised");
     HIP_TRY(h, launch_monitors(h->lc, h->ds, h->cur, h->mon_partials, h->mon_blocks, h->mon_out));
     double tmp[8];
     HIP_TRY(h, hipMemcpyAsync(tmp, h->mon_out, sizeof tmp, hipMemcpyDeviceToHost, h->stream));
@@ -440,6 +498,7 @@ int pond_tile_info(const pond_handle *h, int *out)
 int pond_destroy(pond_handle *h)
 {
     if (!h) return POND_OK;
+    if (h->batch) pond_batch_remove(h->batch, h);
     if (h->stream) hipStreamSynchronize(h->stream);
     free_all(h);
     delete h;
@@ -449,19 +508,20 @@ int pond_destroy(pond_handle *h)
 int pond_time_kernel(pond_handle *h, int which, int reps, double *avg_us)
 {
     if (!h || !avg_us || reps < 1 || which < 0 || which > 1) return POND_E_INVALID;
-    if (!h->initialised || h->failed) return fail(h, POND_E_STATE, "not initialised");
-    const DevState &s = h->ds;
+    if (!h->initialised || h->failed) return handle_fail(h, POND_E_STATE, "not initialised");
+    if (h->batch) return handle_fail(h, POND_E_STATE, "handle is a member of a batch");
     const LaunchCtx &c = h->lc;
-    HIP_TRY(h, launch_reset_flags(c, s.flags));
+    const SlotDesc *d = h->desc_d + h->cur;
+    HIP_TRY(h, launch_reset_flags(c, h->ds.flags));
     // bring the scratch planes to the current step's values first
-    HIP_TRY(h, launch_stream(c, s, h->cur));
+    HIP_TRY(h, launch_stream(c, d, 1, h->st_tiles));
     hipEvent_t e0, e1;
     HIP_TRY(h, hipEventCreate(&e0));
     HIP_TRY(h, hipEventCreate(&e1));
     HIP_TRY(h, hipEventRecord(e0, h->stream));
     for (int r = 0; r < reps; ++r) {
-        hipError_t e = which == 0 ? launch_stream(c, s, h->cur) : launch_force_collide(c, s, 1 - h->cur);
-        if (e != hipSuccess) return fail(h, POND_E_DEVICE, "timing launch: %s", hipGetErrorString(e));
+        hipError_t e = which == 0 ? launch_stream(c, d, 1, h->st_tiles) : launch_force_collide(c, d, 1, h->fc_tiles);
+        if (e != hipSuccess) return handle_fail(h, POND_E_DEVICE, "timing launch: %s", hipGetErrorString(e));
     }
     HIP_TRY(h, hipEventRecord(e1, h->stream));
     HIP_TRY(h, hipEventSynchronize(e1));
@@ -473,41 +533,46 @@ int pond_time_kernel(pond_handle *h, int which, int reps, double *avg_us)
     int fl[kFlagWords];
     int rc = read_flags(h, fl);
     if (rc != POND_OK) return rc;
-    if (fl[kFlagErr]) return fail(h, err_code(fl[kFlagErr]), "timing: %s", err_name(fl[kFlagErr]));
+    if (fl[kFlagErr]) return handle_fail(h, err_code(fl[kFlagErr]), "timing: %s", err_name(fl[kFlagErr]));
     return POND_OK;
 }
 
 int pond_step_timed(pond_handle *h, int nsteps, double *kernel_us)
 {
     if (!h || !kernel_us || nsteps < 1) return POND_E_INVALID;
-    if (!h->initialised || h->failed) return fail(h, POND_E_STATE, h->failed ? "handle in error state" : "not initialised");
+    if (!h->initialised || h->failed)
+        return handle_fail(h, POND_E_STATE, h->failed ? "handle in error state" : "not initialised");
+    if (h->batch) return handle_fail(h, POND_E_STATE, "handle is a member of a batch");
     HIP_TRY(h, launch_reset_flags(h->lc, h->ds.flags));
     hipEvent_t *ev = (hipEvent_t *)std::calloc((size_t)4 * nsteps, sizeof(hipEvent_t));
-    if (!ev) return fail(h, POND_E_NOMEM, "event array");
+    if (!ev) return handle_fail(h, POND_E_NOMEM, "event array");
     int rc = POND_OK;
     int created = 0;
     for (; created < 4 * nsteps; ++created)
         if (hipEventCreate(&ev[created]) != hipSuccess) {
-            rc = fail(h, POND_E_DEVICE, "hipEventCreate");
+            rc = handle_fail(h, POND_E_DEVICE, "hipEventCreate");
             break;
         }
     int parity = h->cur;
-    LaunchCtx c = h->lc;
     for (int i = 0; rc == POND_OK && i < nsteps; ++i) {
         hipEvent_t *e = ev + 4 * i;
-        if (hipEventRecord(e[0], h->stream) != hipSuccess || launch_stream(c, h->ds, parity) != hipSuccess ||
-            hipEventRecord(e[1], h->stream) != hipSuccess || hipEventRecord(e[2], h->stream) != hipSuccess ||
-            launch_force_collide(c, h->ds, 1 - parity) != hipSuccess || hipEventRecord(e[3], h->stream) != hipSuccess)
-            rc = fail(h, POND_E_DEVICE, "timed step launch");
+        LaunchCtx c1 = h->lc, c2 = h->lc;
+        c1.ev_start = e[0];
+        c1.ev_stop = e[1];
+        c2.ev_start = e[2];
+        c2.ev_stop = e[3];
+        if (launch_stream(c1, h->desc_d + parity, 1, h->st_tiles) != hipSuccess ||
+            launch_force_collide(c2, h->desc_d + parity, 1, h->fc_tiles) != hipSuccess)
+            rc = handle_fail(h, POND_E_DEVICE, "timed step launch");
         parity = 1 - parity;
     }
-    if (rc == POND_OK && hipStreamSynchronize(h->stream) != hipSuccess) rc = fail(h, POND_E_DEVICE, "sync");
+    if (rc == POND_OK && hipStreamSynchronize(h->stream) != hipSuccess) rc = handle_fail(h, POND_E_DEVICE, "sync");
     double acc[2] = {0.0, 0.0};
     for (int i = 0; rc == POND_OK && i < nsteps; ++i) {
         float a = 0.0f, b = 0.0f;
         if (hipEventElapsedTime(&a, ev[4 * i], ev[4 * i + 1]) != hipSuccess ||
             hipEventElapsedTime(&b, ev[4 * i + 2], ev[4 * i + 3]) != hipSuccess)
-            rc = fail(h, POND_E_DEVICE, "hipEventElapsedTime");
+            rc = handle_fail(h, POND_E_DEVICE, "hipEventElapsedTime");
         acc[0] += a;
         acc[1] += b;
     }

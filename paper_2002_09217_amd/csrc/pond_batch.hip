@@ -1,0 +1,299 @@
+// pond_batch.hip -- batches of independent lattices advanced together (C ABI in
+// include/pond.h).  Scheduling only: every member keeps its own state, parameters,
+// error flags and step counter, and each step kernel reads a member's descriptor
+// exactly as it does for a lattice stepped alone, so results are bitwise identical.
+//
+// Members that share (dim, precision, streaming tile shape) form a group; a batch
+// step is one launch of each step kernel per group over the concatenated tiles of
+// its members.  Two descriptor arrays per batch: array 0 holds, for every member,
+// the descriptor reading the state that was current when the arrays were built, and
+// array 1 the other one; a step alternates between them, so pairs of steps replay
+// one captured HIP graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "pond.h"
+#include "pond_handle.h"
+#include "pond_internal.h"
+
+using namespace pond;
+
+namespace {
+
+// largest tile count of one launch: keeps blocks x threads per block below 2^31
+constexpr long long kMaxLaunchTiles = 1LL << 21;
+
+struct Group {
+    int dim, fp32, tile;
+    int first, count;        // slot range in the descriptor arrays
+    int st_tiles, fc_tiles;  // total tiles of the two step kernels
+};
+
+} // namespace
+
+struct pond_batch {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipStream_t capture_stream = nullptr;
+    std::vector<pond_handle *> members;  // order of addition
+    // built from the members on demand
+    bool dirty = true;
+    std::vector<Group> groups;
+    std::vector<int> slot_of;            // member index -> slot
+    std::vector<SlotDesc> desc_h;        // [2][slots]
+    SlotDesc *desc_d = nullptr;
+    int *flags_d = nullptr;
+    std::vector<int> flags_h;
+    int cap = 0;                         // slots the device arrays hold
+    int phase = 0;                       // descriptor array reading the current states
+    hipGraphExec_t pair_exec[2] = {nullptr, nullptr};
+    bool graphs_ok = true;
+};
+
+namespace {
+
+void drop_graphs(pond_batch *b)
+{
+    for (auto &g : b->pair_exec)
+        if (g) {
+            hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+}
+
+// regroup the members and upload both descriptor arrays
+int rebuild(pond_batch *b)
+{
+    drop_graphs(b);
+    const int M = (int)b->members.size();
+    b->groups.clear();
+    b->slot_of.assign(M, -1);
+    std::vector<int> order(M);
+    for (int i = 0; i < M; ++i) order[i] = i;
+    auto key = [&](int i) {
+        const pond_handle *h = b->members[i];
+        return (h->lc.dim * 2 + h->lc.fp32) * 16 + h->lc.stream_tile;
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return key(x) < key(y); });
+    if (M > b->cap) {
+        if (hipStreamSynchronize(b->stream) != hipSuccess) return POND_E_DEVICE;
+        if (b->desc_d) hipFree(b->desc_d);
+        if (b->flags_d) hipFree(b->flags_d);
+        const int cap = std::max(M, 2 * b->cap);
+        b->desc_d = nullptr;
+        b->flags_d = nullptr;
+        b->cap = 0;
+        if (hipMalloc((void **)&b->desc_d, sizeof(SlotDesc) * 2 * cap) != hipSuccess ||
+            hipMalloc((void **)&b->flags_d, sizeof(int) * kFlagWords * cap) != hipSuccess)
+            return POND_E_NOMEM;
+        b->cap = cap;
+    }
+    b->desc_h.assign((size_t)2 * std::max(M, 1), SlotDesc{});
+    b->flags_h.assign((size_t)kFlagWords * std::max(M, 1), 0);
+    int gkey = -1;
+    for (int s = 0; s < M; ++s) {
+        const int i = order[s];
+        pond_handle *h = b->members[i];
+        if (key(i) != gkey) {
+            gkey = key(i);
+            b->groups.push_back(Group{h->lc.dim, h->lc.fp32, h->lc.stream_tile, s, 0, 0, 0});
+        }
+        Group &g = b->groups.back();
+        b->slot_of[i] = s;
+        for (int a = 0; a < 2; ++a) {
+            SlotDesc d = h->desc_h[(h->cur + a) % 2];
+            d.st_begin = g.st_tiles;
+            d.fc_begin = g.fc_tiles;
+            b->desc_h[(size_t)a * M + s] = d;
+        }
+        g.count += 1;
+        g.st_tiles += h->st_tiles;
+        g.fc_tiles += h->fc_tiles;
+    }
+    if (M > 0 && hipMemcpy(b->desc_d, b->desc_h.data(), sizeof(SlotDesc) * 2 * M, hipMemcpyHostToDevice) != hipSuccess)
+        return POND_E_DEVICE;
+    b->phase = 0;
+    b->dirty = false;
+    return POND_OK;
+}
+
+hipError_t enqueue_step(pond_batch *b, hipStream_t st, int arr)
+{
+    const int M = (int)b->members.size();
+    for (const Group &g : b->groups) {
+        LaunchCtx c{g.dim, 0, 0, 0, g.fp32, st, g.tile};
+        const SlotDesc *d = b->desc_d + (size_t)arr * M + g.first;
+        hipError_t e = launch_stream(c, d, g.count, g.st_tiles);
+        if (e == hipSuccess) e = launch_force_collide(c, d, g.count, g.fc_tiles);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+bool build_pair_graph(pond_batch *b, int arr)
+{
+    if (b->pair_exec[arr]) return true;
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
+    hipError_t e = enqueue_step(b, b->capture_stream, arr);
+    if (e == hipSuccess) e = enqueue_step(b, b->capture_stream, 1 - arr);
+    const hipError_t ec = hipStreamEndCapture(b->capture_stream, &g);
+    if (e != hipSuccess || ec != hipSuccess || !g) {
+        if (g) hipGraphDestroy(g);
+        return false;
+    }
+    e = hipGraphInstantiate(&b->pair_exec[arr], g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        b->pair_exec[arr] = nullptr;
+        return false;
+    }
+    return true;
+}
+
+int find_member(const pond_batch *b, const pond_handle *h)
+{
+    for (size_t i = 0; i < b->members.size(); ++i)
+        if (b->members[i] == h) return (int)i;
+    return -1;
+}
+
+} // namespace
+
+extern "C" {
+
+int pond_batch_create(void *stream, pond_batch **out)
+{
+    if (!out) return POND_E_INVALID;
+    *out = nullptr;
+    pond_batch *b = new (std::nothrow) pond_batch();
+    if (!b) return POND_E_NOMEM;
+    int rc = POND_OK;
+    if (stream) {
+        b->stream = (hipStream_t)stream;
+    } else if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) == hipSuccess) {
+        b->own_stream = true;
+    } else {
+        rc = POND_E_DEVICE;
+    }
+    if (rc == POND_OK && hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking) != hipSuccess)
+        rc = POND_E_DEVICE;
+    if (rc != POND_OK) {
+        if (b->own_stream) hipStreamDestroy(b->stream);
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return POND_OK;
+}
+
+int pond_batch_add(pond_batch *b, pond_handle *h)
+{
+    if (!b || !h || h->batch) return POND_E_INVALID;
+    if (!h->initialised || h->failed)
+        return handle_fail(h, POND_E_STATE, h->failed ? "handle in error state" : "not initialised");
+    long long st = h->st_tiles, fc = h->fc_tiles;
+    for (const pond_handle *m : b->members)
+        if (m->lc.dim == h->lc.dim && m->lc.fp32 == h->lc.fp32 && m->lc.stream_tile == h->lc.stream_tile) {
+            st += m->st_tiles;
+            fc += m->fc_tiles;
+        }
+    if (st > kMaxLaunchTiles || fc > kMaxLaunchTiles)
+        return handle_fail(h, POND_E_INVALID, "batch group would exceed %lld tiles per launch", kMaxLaunchTiles);
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return handle_fail(h, POND_E_DEVICE, "stream sync");
+    try {
+        b->members.push_back(h);
+    } catch (...) {
+        return POND_E_NOMEM;
+    }
+    h->batch = b;
+    b->dirty = true;
+    return POND_OK;
+}
+
+int pond_batch_remove(pond_batch *b, pond_handle *h)
+{
+    if (!b || !h) return POND_E_INVALID;
+    const int i = find_member(b, h);
+    if (i < 0) return POND_E_INVALID;
+    hipStreamSynchronize(b->stream);
+    b->members.erase(b->members.begin() + i);
+    h->batch = nullptr;
+    b->dirty = true;
+    return POND_OK;
+}
+
+int pond_batch_step(pond_batch *b, int nsteps)
+{
+    if (!b || nsteps < 0) return POND_E_INVALID;
+    if (nsteps == 0 || b->members.empty()) return POND_OK;
+    if (b->dirty) {
+        const int rc = rebuild(b);
+        if (rc != POND_OK) return rc;
+    }
+    const int M = (int)b->members.size();
+    if (launch_reset_slot_flags(b->stream, b->desc_d, M) != hipSuccess) return POND_E_DEVICE;
+    int arr = b->phase;
+    int left = nsteps;
+    if (b->graphs_ok && left >= 2 && !build_pair_graph(b, arr)) b->graphs_ok = false;
+    if (b->graphs_ok)
+        for (; left >= 2; left -= 2)
+            if (hipGraphLaunch(b->pair_exec[arr], b->stream) != hipSuccess) return POND_E_DEVICE;
+    for (; left > 0; --left) {
+        if (enqueue_step(b, b->stream, arr) != hipSuccess) return POND_E_DEVICE;
+        arr = 1 - arr;
+    }
+    if (launch_gather_slot_flags(b->stream, b->desc_d, M, b->flags_d) != hipSuccess) return POND_E_DEVICE;
+    if (hipMemcpyAsync(b->flags_h.data(), b->flags_d, sizeof(int) * kFlagWords * M, hipMemcpyDeviceToHost,
+                       b->stream) != hipSuccess ||
+        hipStreamSynchronize(b->stream) != hipSuccess)
+        return POND_E_DEVICE;
+    b->phase = arr;
+    // every member moves on by its own count of completed steps; failed ones leave
+    int first_err = POND_OK;
+    std::vector<pond_handle *> keep;
+    keep.reserve(M);
+    for (int i = 0; i < M; ++i) {
+        pond_handle *h = b->members[i];
+        const int rc = handle_finish_batch(h, &b->flags_h[(size_t)kFlagWords * b->slot_of[i]]);
+        if (rc == POND_OK) {
+            keep.push_back(h);
+        } else {
+            h->batch = nullptr;
+            if (first_err == POND_OK) first_err = rc;
+        }
+    }
+    if ((int)keep.size() != M) {
+        b->members.swap(keep);
+        b->dirty = true;
+    }
+    return first_err;
+}
+
+int pond_batch_size(const pond_batch *b, int *out)
+{
+    if (!b || !out) return POND_E_INVALID;
+    *out = (int)b->members.size();
+    return POND_OK;
+}
+
+int pond_batch_destroy(pond_batch *b)
+{
+    if (!b) return POND_OK;
+    if (b->stream) hipStreamSynchronize(b->stream);
+    for (pond_handle *h : b->members) h->batch = nullptr;
+    drop_graphs(b);
+    if (b->desc_d) hipFree(b->desc_d);
+    if (b->flags_d) hipFree(b->flags_d);
+    if (b->capture_stream) hipStreamDestroy(b->capture_stream);
+    if (b->own_stream && b->stream) hipStreamDestroy(b->stream);
+    delete b;
+    return POND_OK;
+}
+
+} // extern "C"

@@ -51,6 +51,22 @@ __device__ __forceinline__ int xcd_tile(int b, int nb)
     return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
 }
 
+// slot of a global tile: the last slot whose first tile is <= tile (binary search)
+template <bool STREAM>
+__device__ __forceinline__ int find_slot(const SlotDesc *slots, int nslots, int tile)
+{
+    int lo = 0, hi = nslots - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int b = STREAM ? slots[mid].st_begin : slots[mid].fc_begin;
+        if (b <= tile)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
 // ---------------------------------------------------------------------------
 // boundary mapping: node index >= 0, or -(1 + face) for an inflow ghost,
 // face = 2 axis + side.  Periodic faces wrap, outflow faces clamp.

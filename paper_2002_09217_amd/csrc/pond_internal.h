@@ -60,6 +60,21 @@ enum { kKorPlanes = 3 };
 // when a step failed)
 enum { kFlagErr = 0, kFlagSteps = 1, kFlagWords = 4 };
 
+// One lattice of a launch of the step kernels: where the step reads and writes and
+// which workgroups of the launch are its tiles.  A single lattice is a launch of one
+// slot; a batch launches the tiles of all its lattices together.
+struct SlotDesc {
+    const DevParams *P;
+    const void *pop_src;     // state read by the streaming kernel
+    const double *side_src;
+    void *pop_dst;           // state written by the collision kernel
+    double *side_dst;
+    double *mom;             // streamed-state scratch of this lattice
+    int *flags;              // error bits and step counter of this lattice
+    int st_tiles_x, st_begin, st_count; // streaming-kernel tiles: per row, first, number
+    int fc_tiles_x, fc_begin, fc_count; // collision-kernel tiles
+};
+
 // device buffers of one lattice
 struct DevState {
     void *pop[2];       // 2 Q planes each: f then g
@@ -79,15 +94,26 @@ struct LaunchCtx {
     int fp32;           // populations stored as float
     hipStream_t st;
     int stream_tile;    // tile-shape variant of the streaming kernel
+    // when set, the step kernels are launched with these start/stop events, which the
+    // runtime records at the kernel's own start and end (measurement only)
+    hipEvent_t ev_start = nullptr, ev_stop = nullptr;
 };
 
 int stream_variants(int dim);
 void stream_tile_shape(int dim, int variant, int *tx, int *ty);
 
 hipError_t launch_reset_flags(const LaunchCtx &c, int *flags);
-hipError_t launch_stream(const LaunchCtx &c, const DevState &s, int cur);
+// clear the flags of every slot of a device descriptor array / copy them into `out`
+// (kFlagWords ints per slot, in slot order)
+hipError_t launch_reset_slot_flags(hipStream_t st, const SlotDesc *slots, int nslots);
+hipError_t launch_gather_slot_flags(hipStream_t st, const SlotDesc *slots, int nslots, int *out);
+// step kernels over the tiles of `nslots` lattices (device descriptor array); every
+// lattice must share dim and precision with c; `tiles` is the total tile count
+hipError_t launch_stream(const LaunchCtx &c, const SlotDesc *slots, int nslots, int tiles);
+hipError_t launch_force_collide(const LaunchCtx &c, const SlotDesc *slots, int nslots, int tiles);
+// tile counts of one lattice for the current tile shapes
+void tile_counts(const LaunchCtx &c, int *st_tiles_x, int *st_count, int *fc_tiles_x, int *fc_count);
 hipError_t launch_korteweg(const LaunchCtx &c, const DevState &s, const double *rho);
-hipError_t launch_force_collide(const LaunchCtx &c, const DevState &s, int dst);
 hipError_t launch_init_equilibrium(const LaunchCtx &c, const DevState &s, const double *rho,
                                    const double *u, const double *T);
 hipError_t launch_macro(const LaunchCtx &c, const DevState &s, int cur, double *out);

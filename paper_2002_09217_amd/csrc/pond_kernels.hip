@@ -21,6 +21,7 @@
 // populations follow from the quadratic Lagrange coefficients of the receiver
 // velocities.  Since the transfer matrix is M'^{-1} M and the reconstruction is
 // linear, this equals re-gauging every donor first and interpolating afterwards.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "pond_device.h"
@@ -42,6 +43,34 @@ hipError_t launch_reset_flags(const LaunchCtx &c, int *flags)
     return hipGetLastError();
 }
 
+// flags of every lattice of a descriptor array: clear them, or copy them into one
+// array (slot s at out[s kFlagWords ...]) for a single read-back
+__global__ void k_reset_slot_flags(const SlotDesc *__restrict__ slots, int nslots)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nslots * kFlagWords) slots[i / kFlagWords].flags[i % kFlagWords] = 0;
+}
+
+__global__ void k_gather_slot_flags(const SlotDesc *__restrict__ slots, int nslots, int *__restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nslots * kFlagWords) out[i] = slots[i / kFlagWords].flags[i % kFlagWords];
+}
+
+hipError_t launch_reset_slot_flags(hipStream_t st, const SlotDesc *slots, int nslots)
+{
+    const int n = nslots * kFlagWords;
+    hipLaunchKernelGGL(k_reset_slot_flags, dim3((n + 255) / 256), dim3(256), 0, st, slots, nslots);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_slot_flags(hipStream_t st, const SlotDesc *slots, int nslots, int *out)
+{
+    const int n = nslots * kFlagWords;
+    hipLaunchKernelGGL(k_gather_slot_flags, dim3((n + 255) / 256), dim3(256), 0, st, slots, nslots, out);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // streaming with the predictor-corrector
 // ---------------------------------------------------------------------------
@@ -49,9 +78,7 @@ hipError_t launch_reset_flags(const LaunchCtx &c, int *flags)
 // (0 = f, 1 = g) of receiver i; the pass moments are exchanged between the two lanes.
 template <int DIM, typename PopT, typename LdsT, int TX, int TY, int SPLIT>
 __global__ void __launch_bounds__(SPLIT *TX *TY)
-    k_stream(const DevParams *__restrict__ Pp, const PopT *__restrict__ fpop,
-             const double *__restrict__ side, double *__restrict__ mom, int *__restrict__ flags,
-             int tiles_x)
+    k_stream(const SlotDesc *__restrict__ slots, int nslots)
 {
     using L = Layout<DIM>;
     constexpr int Q = L::Q, NF = L::NF, H = 2;
@@ -66,21 +93,29 @@ __global__ void __launch_bounds__(SPLIT *TX *TY)
     __shared__ LdsT lds[2 * NF * LN];
     __shared__ int abort_block;
 
+    // lattice and tile of this workgroup
+    const int gtile = xcd_tile(blockIdx.x, gridDim.x);
+    const SlotDesc &S = slots[find_slot<true>(slots, nslots, gtile)];
+    const int tile = gtile - S.st_begin;
+    int *__restrict__ flags = S.flags;
+    const PopT *__restrict__ fpop = (const PopT *)S.pop_src;
+    const double *__restrict__ side = S.side_src;
+    double *__restrict__ mom = S.mom;
+
     // leave the state alone after an earlier failure; the decision is taken once per
     // block so that every wave of the block reaches the barrier below or none does
     const int tid = threadIdx.x + SPLIT * TX * threadIdx.y;
     if (tid == 0) {
         abort_block = flags[kFlagErr];
         // one step more has started without an earlier failure
-        if (blockIdx.x == 0 && abort_block == 0) atomicAdd(&flags[kFlagSteps], 1);
+        if (tile == 0 && abort_block == 0) atomicAdd(&flags[kFlagSteps], 1);
     }
     __syncthreads();
     if (abort_block != 0) return;
-    const DevParams &P = *Pp;
+    const DevParams &P = *S.P;
     const int N = P.N;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int bx0 = (tile % tiles_x) * TX;
-    const int by0 = DIM == 2 ? (tile / tiles_x) * TY : 0;
+    const int bx0 = (tile % S.st_tiles_x) * TX;
+    const int by0 = DIM == 2 ? (tile / S.st_tiles_x) * TY : 0;
 
     // reference velocity of the tile: gauge velocity at its (clamped) centre node
     const int cnode = min(bx0 + TX / 2, P.nx - 1) + P.nx * (DIM == 2 ? min(by0 + TY / 2, P.ny - 1) : 0);
@@ -327,12 +362,15 @@ __global__ void __launch_bounds__(SPLIT *TX *TY)
 }
 
 template <int DIM, typename PopT, typename LdsT, int SPLIT, int TX, int TY>
-static hipError_t launch_stream_t(const LaunchCtx &c, const DevState &s, int cur)
+static hipError_t launch_stream_t(const LaunchCtx &c, const SlotDesc *slots, int nslots, int tiles)
 {
     dim3 block(SPLIT * TX, TY);
-    const int tx = (c.nx + TX - 1) / TX, ty = DIM == 2 ? (c.ny + TY - 1) / TY : 1;
-    hipLaunchKernelGGL((k_stream<DIM, PopT, LdsT, TX, TY, SPLIT>), dim3(tx * ty), block, 0, c.st,
-                       s.params, (const PopT *)s.pop[cur], s.side[cur], s.mom, s.flags, tx);
+    if (c.ev_start)
+        hipExtLaunchKernelGGL((k_stream<DIM, PopT, LdsT, TX, TY, SPLIT>), dim3(tiles), block, 0, c.st,
+                              c.ev_start, c.ev_stop, 0, slots, nslots);
+    else
+        hipLaunchKernelGGL((k_stream<DIM, PopT, LdsT, TX, TY, SPLIT>), dim3(tiles), block, 0, c.st, slots,
+                           nslots);
     return hipGetLastError();
 }
 
@@ -349,24 +387,25 @@ void stream_tile_shape(int dim, int v, int *tx, int *ty)
 }
 
 template <typename PopT, typename LdsT>
-static hipError_t launch_stream_v(const LaunchCtx &c, const DevState &s, int cur)
+static hipError_t launch_stream_v(const LaunchCtx &c, const SlotDesc *slots, int nslots, int tiles)
 {
     if (c.dim == 2) {
         switch (c.stream_tile) {
-        case 1: return launch_stream_t<2, PopT, LdsT, 2, 32, 4>(c, s, cur);
-        case 2: return launch_stream_t<2, PopT, LdsT, 2, 16, 8>(c, s, cur);
-        case 3: return launch_stream_t<2, PopT, LdsT, 2, 64, 4>(c, s, cur);
-        case 4: return launch_stream_t<2, PopT, LdsT, 2, 16, 4>(c, s, cur);
-        default: return launch_stream_t<2, PopT, LdsT, 2, 32, 8>(c, s, cur);
+        case 1: return launch_stream_t<2, PopT, LdsT, 2, 32, 4>(c, slots, nslots, tiles);
+        case 2: return launch_stream_t<2, PopT, LdsT, 2, 16, 8>(c, slots, nslots, tiles);
+        case 3: return launch_stream_t<2, PopT, LdsT, 2, 64, 4>(c, slots, nslots, tiles);
+        case 4: return launch_stream_t<2, PopT, LdsT, 2, 16, 4>(c, slots, nslots, tiles);
+        default: return launch_stream_t<2, PopT, LdsT, 2, 32, 8>(c, slots, nslots, tiles);
         }
     }
-    if (c.stream_tile == 1) return launch_stream_t<1, PopT, LdsT, 2, 64, 1>(c, s, cur);
-    return launch_stream_t<1, PopT, LdsT, 2, 128, 1>(c, s, cur);
+    if (c.stream_tile == 1) return launch_stream_t<1, PopT, LdsT, 2, 64, 1>(c, slots, nslots, tiles);
+    return launch_stream_t<1, PopT, LdsT, 2, 128, 1>(c, slots, nslots, tiles);
 }
 
-hipError_t launch_stream(const LaunchCtx &c, const DevState &s, int cur)
+hipError_t launch_stream(const LaunchCtx &c, const SlotDesc *slots, int nslots, int tiles)
 {
-    return c.fp32 ? launch_stream_v<float, float>(c, s, cur) : launch_stream_v<double, double>(c, s, cur);
+    return c.fp32 ? launch_stream_v<float, float>(c, slots, nslots, tiles)
+                  : launch_stream_v<double, double>(c, slots, nslots, tiles);
 }
 
 // ---------------------------------------------------------------------------
@@ -518,9 +557,7 @@ enum { kThFx = 0, kThFy, kThT, kThH, kThMu, kThKc, kThP, kThFields };
 
 template <int DIM, typename PopT, int TX, int TY>
 __global__ void __launch_bounds__(TX *TY)
-    k_force_collide(const DevParams *__restrict__ Pp, const double *__restrict__ mom,
-                    PopT *__restrict__ fout, double *__restrict__ side_out, int *__restrict__ flags,
-                    int tiles_x)
+    k_force_collide(const SlotDesc *__restrict__ slots, int nslots)
 {
     using L = Layout<DIM>;
     constexpr int Q = L::Q, NF = L::NF;
@@ -533,16 +570,24 @@ __global__ void __launch_bounds__(TX *TY)
     __shared__ double s_th[kThFields][HX * HY];
     __shared__ int abort_block;
 
+    // lattice and tile of this workgroup
+    const int gtile = xcd_tile(blockIdx.x, gridDim.x);
+    const SlotDesc &S = slots[find_slot<false>(slots, nslots, gtile)];
+    const int tile = gtile - S.fc_begin;
+    int *__restrict__ flags = S.flags;
+    const double *__restrict__ mom = S.mom;
+    PopT *__restrict__ fout = (PopT *)S.pop_dst;
+    double *__restrict__ side_out = S.side_dst;
+
     const int tid = threadIdx.x + TX * threadIdx.y;
     if (tid == 0) abort_block = flags[kFlagErr];
     __syncthreads();
     if (abort_block != 0) return;
 
-    const DevParams &P = *Pp;
+    const DevParams &P = *S.P;
     const size_t N = P.N;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int x0 = (tile % tiles_x) * TX;
-    const int y0 = DIM == 2 ? (tile / tiles_x) * TY : 0;
+    const int x0 = (tile % S.fc_tiles_x) * TX;
+    const int y0 = DIM == 2 ? (tile / S.fc_tiles_x) * TY : 0;
     const double dt = P.dt;
     const bool force = P.kappa != 0.0;
 
@@ -844,22 +889,37 @@ __global__ void __launch_bounds__(TX *TY)
 }
 
 template <int DIM, typename PopT>
-static hipError_t launch_force_collide_t(const LaunchCtx &c, const DevState &s, int dst)
+static hipError_t launch_force_collide_t(const LaunchCtx &c, const SlotDesc *slots, int nslots, int tiles)
 {
     constexpr int TX = CollideTile<DIM>::TX, TY = CollideTile<DIM>::TY;
-    const int tx = (c.nx + TX - 1) / TX, ty = DIM == 2 ? (c.ny + TY - 1) / TY : 1;
-    hipLaunchKernelGGL((k_force_collide<DIM, PopT, TX, TY>), dim3(tx * ty), dim3(TX, TY), 0, c.st,
-                       s.params, s.mom, (PopT *)s.pop[dst], s.side[dst], s.flags, tx);
+    if (c.ev_start)
+        hipExtLaunchKernelGGL((k_force_collide<DIM, PopT, TX, TY>), dim3(tiles), dim3(TX, TY), 0, c.st,
+                              c.ev_start, c.ev_stop, 0, slots, nslots);
+    else
+        hipLaunchKernelGGL((k_force_collide<DIM, PopT, TX, TY>), dim3(tiles), dim3(TX, TY), 0, c.st, slots,
+                           nslots);
     return hipGetLastError();
 }
 
-hipError_t launch_force_collide(const LaunchCtx &c, const DevState &s, int dst)
+hipError_t launch_force_collide(const LaunchCtx &c, const SlotDesc *slots, int nslots, int tiles)
 {
     if (c.dim == 2)
-        return c.fp32 ? launch_force_collide_t<2, float>(c, s, dst)
-                      : launch_force_collide_t<2, double>(c, s, dst);
-    return c.fp32 ? launch_force_collide_t<1, float>(c, s, dst)
-                  : launch_force_collide_t<1, double>(c, s, dst);
+        return c.fp32 ? launch_force_collide_t<2, float>(c, slots, nslots, tiles)
+                      : launch_force_collide_t<2, double>(c, slots, nslots, tiles);
+    return c.fp32 ? launch_force_collide_t<1, float>(c, slots, nslots, tiles)
+                  : launch_force_collide_t<1, double>(c, slots, nslots, tiles);
+}
+
+void tile_counts(const LaunchCtx &c, int *st_tiles_x, int *st_count, int *fc_tiles_x, int *fc_count)
+{
+    int tx, ty;
+    stream_tile_shape(c.dim, c.stream_tile, &tx, &ty);
+    *st_tiles_x = (c.nx + tx - 1) / tx;
+    *st_count = *st_tiles_x * (c.dim == 2 ? (c.ny + ty - 1) / ty : 1);
+    const int fx = c.dim == 2 ? CollideTile<2>::TX : CollideTile<1>::TX;
+    const int fy = c.dim == 2 ? CollideTile<2>::TY : CollideTile<1>::TY;
+    *fc_tiles_x = (c.nx + fx - 1) / fx;
+    *fc_count = *fc_tiles_x * (c.dim == 2 ? (c.ny + fy - 1) / fy : 1);
 }
 
 // ---------------------------------------------------------------------------

@@ -29,7 +29,9 @@ KERNEL_NAMES = {K_STREAM: "k_stream", K_FORCE_COLLIDE: "k_force_collide"}
 
 EXPORTED = ["pond_create", "pond_init_fields", "pond_step", "pond_moments", "pond_monitors",
             "pond_steps_done", "pond_last_error", "pond_destroy", "pond_time_kernel",
-            "pond_step_timed", "pond_tile_info"]
+            "pond_step_timed", "pond_tile_info", "pond_footprint", "pond_batch_create",
+            "pond_batch_add", "pond_batch_remove", "pond_batch_step", "pond_batch_size",
+            "pond_batch_destroy"]
 
 
 class pond_config(ctypes.Structure):
@@ -69,6 +71,10 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_2002_09217_amd.build`")
+    # One HIP runtime per process: PyTorch ships its own libamdhip64 (soname
+    # libamdhip64.so.7), which libpond then binds to instead of loading a second copy;
+    # PyTorch's streams and memory are then valid handles for libpond.
+    import torch  # noqa: F401
     L = ctypes.CDLL(path)
     dp = ctypes.POINTER(ctypes.c_double)
     hp = ctypes.c_void_p
@@ -84,6 +90,13 @@ def load(path: str = LIB_PATH):
     L.pond_time_kernel.argtypes = [hp, ctypes.c_int, ctypes.c_int, dp]
     L.pond_step_timed.argtypes = [hp, ctypes.c_int, dp]
     L.pond_tile_info.argtypes = [hp, ctypes.POINTER(ctypes.c_int)]
+    L.pond_footprint.argtypes = [ctypes.POINTER(pond_config), ctypes.POINTER(ctypes.c_ulonglong)]
+    L.pond_batch_create.argtypes = [ctypes.c_void_p, ctypes.POINTER(hp)]
+    L.pond_batch_add.argtypes = [hp, hp]
+    L.pond_batch_remove.argtypes = [hp, hp]
+    L.pond_batch_step.argtypes = [hp, ctypes.c_int]
+    L.pond_batch_size.argtypes = [hp, ctypes.POINTER(ctypes.c_int)]
+    L.pond_batch_destroy.argtypes = [hp]
     for name in EXPORTED:
         getattr(L, name).restype = getattr(L, name).restype or ctypes.c_int
     L.pond_last_error.restype = ctypes.c_char_p
@@ -138,6 +151,16 @@ class Config:
     @property
     def N(self) -> int:
         return int(np.prod(self.n[: self.dim]))
+
+
+def footprint(cfg: Config) -> int:
+    """Device bytes pond_create allocates for cfg."""
+    c = cfg.to_c()
+    v = ctypes.c_ulonglong()
+    rc = load().pond_footprint(ctypes.byref(c), ctypes.byref(v))
+    if rc != POND_OK:
+        raise PondError(rc, "pond_footprint")
+    return int(v.value)
 
 
 @dataclass
@@ -217,8 +240,75 @@ class Lattice:
 
     def close(self):
         if self._h is not None:
+            if getattr(self, "_batch", None) is not None:   # pond_destroy leaves the batch
+                self._batch.members.remove(self)
+                self._batch = None
             load().pond_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """A libpond batch: member lattices advanced together, each bitwise as alone."""
+
+    def __init__(self, stream: int | None = None):
+        h = ctypes.c_void_p()
+        rc = load().pond_batch_create(stream, ctypes.byref(h))
+        if rc != POND_OK:
+            raise PondError(rc, "pond_batch_create")
+        self._h = h
+        self.members: list[Lattice] = []
+
+    def add(self, lat: Lattice):
+        rc = load().pond_batch_add(self._h, lat._h)
+        if rc != POND_OK:
+            raise PondError(rc, "pond_batch_add", lat.last_error() if rc != -1 else "")
+        self.members.append(lat)
+        lat._batch = self
+        return self
+
+    def remove(self, lat: Lattice):
+        rc = load().pond_batch_remove(self._h, lat._h)
+        if rc != POND_OK:
+            raise PondError(rc, "pond_batch_remove")
+        self.members.remove(lat)
+        lat._batch = None
+        return self
+
+    def step(self, n: int = 1) -> list:
+        """Advance every member n steps; returns the members that failed (they have left
+        the batch and are in the error state, as after a failed Lattice.step)."""
+        before = [m.steps_done() for m in self.members]
+        rc = load().pond_batch_step(self._h, int(n))
+        if rc == POND_OK:
+            return []
+        if rc in (-1, -2, -3):
+            raise PondError(rc, "pond_batch_step")
+        failed = [m for m, b in zip(self.members, before) if m.steps_done() - b < n]
+        for m in failed:
+            m._batch = None
+        self.members = [m for m in self.members if m not in failed]
+        return failed
+
+    def size(self) -> int:
+        v = ctypes.c_int()
+        rc = load().pond_batch_size(self._h, ctypes.byref(v))
+        if rc != POND_OK:
+            raise PondError(rc, "pond_batch_size")
+        return v.value
+
+    def close(self):
+        if self._h is not None:
+            load().pond_batch_destroy(self._h)
+            self._h = None
+            for m in self.members:
+                m._batch = None
+            self.members = []
 
     def __del__(self):
         try:

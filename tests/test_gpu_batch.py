@@ -1,0 +1,118 @@
+"""Batches through the C ABI: a lattice advanced inside a batch of other lattices
+(several groups, mixed sizes, dimensions and precisions, members joining and
+leaving) gives bitwise the same state as the same lattice advanced alone; a member
+that fails leaves the batch without disturbing the others; admission footprints."""
+import numpy as np
+import pytest
+
+from paper_2002_09217_amd import pond, workloads as W
+from tests.common import pond_config
+
+pytestmark = pytest.mark.gpu
+
+
+def _fields(m):
+    return np.concatenate([m[k] for k in ("rho", "ux", "uy", "T", "p", "E")])
+
+
+def _lat(case, tile, precision=pond.FP64):
+    lat = pond.Lattice(pond_config(case, precision=precision, tile=tile))
+    lat.init_fields(case.rho, case.u, case.T)
+    return lat
+
+
+def _mix():
+    """(case, tile, precision) of the batch members: sizes spanning one to many tiles
+    with ragged tails, both dimensions, both precisions, two tile shapes."""
+    return [
+        (W.perturbed(40, 36, seed=1, kappa=0.0176, u0=(0.05, -0.03)), 0, pond.FP64),
+        (W.static_droplet(n=64, radius=14.0), 0, pond.FP64),
+        (W.perturbed(33, 17, seed=2, t_over_tcr=1.4, u0=(0.3, 0.1)), 2, pond.FP64),
+        (W.perturbed(70, 45, seed=3, kappa=0.0176), 2, pond.FP32_STORE),
+        (W.perturbed(300, 1, seed=4, dim=1, kappa=0.0176), 0, pond.FP64),
+        (W.perturbed(7, 1, seed=5, kappa=0.0176), 0, pond.FP64),
+        (W.perturbed(129, 1, seed=6, dim=1), 1, pond.FP32_STORE),
+    ]
+
+
+def test_batch_members_bitwise_equal_to_alone():
+    mix = _mix()
+    schedule = (1, 6, 7, 2)               # odd and even chunks: both graph phases
+    total = sum(schedule)
+    alone = []
+    for case, tile, prec in mix:
+        lat = _lat(case, tile, prec)
+        lat.step(total)
+        alone.append(_fields(lat.moments()))
+        lat.close()
+
+    batch = pond.Batch()
+    lats = [_lat(case, tile, prec) for case, tile, prec in mix]
+    # the last member joins after the first chunk, and is stepped alone before it
+    for lat in lats[:-1]:
+        batch.add(lat)
+    assert batch.size() == len(mix) - 1
+    assert batch.step(schedule[0]) == []
+    lats[-1].step(schedule[0])
+    batch.add(lats[-1])
+    with pytest.raises(pond.PondError) as err:     # members are stepped by the batch only
+        lats[0].step(1)
+    assert err.value.code == -7
+    for n in schedule[1:]:
+        assert batch.step(n) == []
+    for lat, ref in zip(lats, alone):
+        assert lat.steps_done() == total
+        assert np.array_equal(_fields(lat.moments()), ref)
+    # a member that leaves continues alone from where the batch left it
+    batch.remove(lats[1])
+    lats[1].step(3)
+    assert batch.step(3) == []
+    assert lats[1].steps_done() == lats[0].steps_done() == total + 3
+    batch.close()
+    for lat in lats:
+        lat.close()
+
+
+def test_failed_member_leaves_batch_others_unaffected():
+    good = W.perturbed(48, 40, seed=7, kappa=0.0176)
+    # |u| + sqrt(theta) > 1/dt: the departure stencil would leave the +-2 window
+    bad = W.perturbed(24, 24, seed=2, rho0=1.0, t_over_tcr=1.5, u0=(0.7, 0.0), dt=1.0, amp=0.0)
+    ref_lat = _lat(good, 0)
+    ref_lat.step(10)
+    ref = _fields(ref_lat.moments())
+    ref_lat.close()
+
+    g = _lat(good, 0)
+    b = _lat(bad, 0)
+    before = _fields(b.moments())
+    batch = pond.Batch()
+    batch.add(b)
+    batch.add(g)
+    failed = batch.step(4)
+    assert failed == [b] and batch.size() == 1
+    assert b.steps_done() == 0 and np.array_equal(_fields(b.moments()), before)
+    with pytest.raises(pond.PondError) as err:
+        b.step(1)
+    assert err.value.code == -7
+    assert batch.step(6) == []
+    assert g.steps_done() == 10 and np.array_equal(_fields(g.moments()), ref)
+    batch.close()
+    g.close()
+    b.close()
+
+
+def test_footprint_matches_device_allocation():
+    import torch
+    case = W.static_droplet(n=256)
+    for prec in (pond.FP64, pond.FP32_STORE):
+        cfg = pond_config(case, precision=prec, tile=0)
+        fp = pond.footprint(cfg)
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        lat = pond.Lattice(cfg)
+        free1 = torch.cuda.mem_get_info()[0]
+        lat.close()
+        used = free0 - free1
+        print("footprint", prec, fp, "allocated", used, flush=True)
+        assert fp - (1 << 20) <= used <= fp + (64 << 20)
+    assert pond.footprint(pond_config(case, precision=pond.FP32_STORE)) < pond.footprint(pond_config(case))
