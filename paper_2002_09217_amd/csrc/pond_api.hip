@@ -177,6 +177,9 @@ int enqueue_step(pond_handle *h, hipStream_t st, int from)
 int build_pair_graph(pond_handle *h, int from)
 {
     if (h->pair_exec[from]) return POND_OK;
+    // created on first use: handles stepped only inside batches never need one
+    if (!h->capture_stream)
+        HIP_TRY(h, hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking));
     hipGraph_t g = nullptr;
     HIP_TRY(h, hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal));
     int rc = enqueue_step(h, h->capture_stream, from);
@@ -366,8 +369,6 @@ int pond_create(const pond_config *cfg, pond_handle **out)
             rc = POND_E_DEVICE;
         }
     }
-    if (rc == POND_OK && hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking) != hipSuccess)
-        rc = POND_E_DEVICE;
     if (rc == POND_OK) {
         h->lc.st = h->stream;
         if (hipMemcpy(h->ds.params, &P, sizeof P, hipMemcpyHostToDevice) != hipSuccess) rc = POND_E_DEVICE;

@@ -14,21 +14,29 @@
 namespace pond {
 
 constexpr double kTL = 1.0 / 3.0;
+constexpr double kInvTL = 3.0;
 constexpr double kW1[3] = {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0};
+
+// Device buffers reached through a descriptor are generic pointers to the compiler;
+// casting them to the global address space gives global (not flat) loads and stores.
+#define POND_GLOBAL __attribute__((address_space(1)))
 
 // ---------------------------------------------------------------------------
 // van der Waals thermodynamics (main text; App. A)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double vdw_p(const DevParams &P, double rho, double T)
+template <typename PT>
+__device__ __forceinline__ double vdw_p(const PT &P, double rho, double T)
 {
     return rho * P.R * T / (1.0 - P.b * rho) - P.a * rho * rho;
 }
-__device__ __forceinline__ double vdw_T_of_e(const DevParams &P, double rho, double e)
+template <typename PT>
+__device__ __forceinline__ double vdw_T_of_e(const PT &P, double rho, double e)
 {
     return P.delta * (e + P.a * rho) / P.R;
 }
 // bit set of the admissibility violations of a state (pressure domain, finiteness)
-__device__ __forceinline__ int vdw_bad(const DevParams &P, double rho, double p)
+template <typename PT>
+__device__ __forceinline__ int vdw_bad(const PT &P, double rho, double p)
 {
     if (!isfinite(rho) || !isfinite(p)) return kErrNonfinite;
     if (!(p > 0.0) || !(1.0 - P.b * rho > 0.0) || !(rho > 0.0)) return kErrPressure;
@@ -69,17 +77,19 @@ __device__ __forceinline__ int find_slot(const SlotDesc *slots, int nslots, int 
 
 // ---------------------------------------------------------------------------
 // boundary mapping: node index >= 0, or -(1 + face) for an inflow ghost,
-// face = 2 axis + side.  Periodic faces wrap, outflow faces clamp.
+// face = 2 axis + side.  Periodic faces wrap, outflow faces clamp.  (PT: DevParams
+// in any address space, as for the other helpers taking P.)
 // ---------------------------------------------------------------------------
-template <int DIM>
-__device__ __forceinline__ int map_node(const DevParams &P, int x, int y)
+template <int DIM, typename PT>
+__device__ __forceinline__ int map_node(const PT &P, int x, int y)
 {
     if (x < 0 || x >= P.nx) {
         const int side = x < 0 ? 0 : 1;
         const int bc = P.bc[0][side];
-        if (bc == kPeriodic)
-            x = ((x % P.nx) + P.nx) % P.nx;
-        else if (bc == kOutflow)
+        if (bc == kPeriodic) {
+            x = x < 0 ? x + P.nx : x - P.nx;
+            if (x < 0 || x >= P.nx) x = ((x % P.nx) + P.nx) % P.nx; // narrower than the halo
+        } else if (bc == kOutflow)
             x = x < 0 ? 0 : P.nx - 1;
         else
             return -(1 + side);
@@ -88,9 +98,10 @@ __device__ __forceinline__ int map_node(const DevParams &P, int x, int y)
         if (y < 0 || y >= P.ny) {
             const int side = y < 0 ? 0 : 1;
             const int bc = P.bc[1][side];
-            if (bc == kPeriodic)
-                y = ((y % P.ny) + P.ny) % P.ny;
-            else if (bc == kOutflow)
+            if (bc == kPeriodic) {
+                y = y < 0 ? y + P.ny : y - P.ny;
+                if (y < 0 || y >= P.ny) y = ((y % P.ny) + P.ny) % P.ny; // narrower than the halo
+            } else if (bc == kOutflow)
                 y = y < 0 ? 0 : P.ny - 1;
             else
                 return -(1 + 2 + side);
@@ -210,10 +221,10 @@ __device__ __forceinline__ int window_weights(double u, double s, double dt, T w
 // Force source S = G^{u}_{u+du}[rho W] - rho W per axis: the equilibrium of the gauge
 // (u + du, theta) in the gauge (u, theta) is rho prod_axes (W_c + sig_c(du)) with
 // sig_0 = -du^2/theta, sig_pm = du^2/(2 theta) pm du/(2 sqrt(theta)).
-__device__ __forceinline__ void source_axis(double du, double theta, double s, double sig[3])
+__device__ __forceinline__ void source_axis(double du, double inv_theta, double inv_s, double sig[3])
 {
-    const double q = du * du / theta;
-    const double l = du / (2.0 * s);
+    const double q = du * du * inv_theta;
+    const double l = 0.5 * du * inv_s;
     sig[0] = 0.5 * q - l;
     sig[1] = -q;
     sig[2] = 0.5 * q + l;

@@ -14,7 +14,7 @@ struct pond_handle {
     pond::DevState ds;
     hipStream_t stream = nullptr;       // where work runs (caller's or owned)
     bool own_stream = false;
-    hipStream_t capture_stream = nullptr; // used only to record graphs
+    hipStream_t capture_stream = nullptr; // used only to record graphs; created on first use
     hipGraphExec_t pair_exec[2] = {nullptr, nullptr}; // two steps starting from state 0 / 1
     bool graphs_ok = true;
     bool tuned = false;                 // streaming tile shape fixed

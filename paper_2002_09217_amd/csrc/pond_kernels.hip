@@ -98,9 +98,9 @@ __global__ void __launch_bounds__(SPLIT *TX *TY)
     const SlotDesc &S = slots[find_slot<true>(slots, nslots, gtile)];
     const int tile = gtile - S.st_begin;
     int *__restrict__ flags = S.flags;
-    const PopT *__restrict__ fpop = (const PopT *)S.pop_src;
-    const double *__restrict__ side = S.side_src;
-    double *__restrict__ mom = S.mom;
+    const POND_GLOBAL PopT *__restrict__ fpop = (const POND_GLOBAL PopT *)S.pop_src;
+    const POND_GLOBAL double *__restrict__ side = (const POND_GLOBAL double *)S.side_src;
+    POND_GLOBAL double *__restrict__ mom = (POND_GLOBAL double *)S.mom;
 
     // leave the state alone after an earlier failure; the decision is taken once per
     // block so that every wave of the block reaches the barrier below or none does
@@ -112,7 +112,7 @@ __global__ void __launch_bounds__(SPLIT *TX *TY)
     }
     __syncthreads();
     if (abort_block != 0) return;
-    const DevParams &P = *S.P;
+    const POND_GLOBAL DevParams &P = *(const POND_GLOBAL DevParams *)S.P;
     const int N = P.N;
     const int bx0 = (tile % S.st_tiles_x) * TX;
     const int by0 = DIM == 2 ? (tile / S.st_tiles_x) * TY : 0;
@@ -157,18 +157,18 @@ __global__ void __launch_bounds__(SPLIT *TX *TY)
             r.th = side[kSideTh * N + r.node];
 #pragma unroll
             for (int k = 0; k < SETS_PER_ITEM; ++k) {
-                const PopT *src = fpop + (size_t)(r.set0 + k) * Q * N;
+                const POND_GLOBAL PopT *src = fpop + (size_t)(r.set0 + k) * Q * N;
 #pragma unroll
                 for (int q = 0; q < Q; ++q) r.p[k * Q + q] = src[(size_t)q * N + r.node];
             }
         } else {
-            const GhostFace &G = P.ghost[-r.node - 1];
+            const POND_GLOBAL GhostFace &G = P.ghost[-r.node - 1];
             r.ux = G.ux;
             r.uy = G.uy;
             r.th = G.theta;
 #pragma unroll
             for (int k = 0; k < SETS_PER_ITEM; ++k) {
-                const double *src = r.set0 + k == 0 ? G.f : G.g;
+                const POND_GLOBAL double *src = r.set0 + k == 0 ? G.f : G.g;
 #pragma unroll
                 for (int q = 0; q < Q; ++q) r.p[k * Q + q] = (PopT)src[q];
             }
@@ -340,7 +340,7 @@ __global__ void __launch_bounds__(SPLIT *TX *TY)
         moments_about<DIM>(fq, sUx - Ux, sUy - Uy, sS, mf);
         mom[(size_t)L::kRho * N + node] = rho;
         mom[(size_t)L::kUx * N + node] = Ux;
-        if (DIM == 2) {
+        if constexpr (DIM == 2) {
             mom[(size_t)L::kUy * N + node] = Uy;
             mom[(size_t)(L::kF + 0) * N + node] = mf[4]; // (1,1)
             mom[(size_t)(L::kF + 1) * N + node] = mf[6]; // (2,0)
@@ -471,8 +471,8 @@ hipError_t launch_korteweg(const LaunchCtx &c, const DevState &s, const double *
 // ---------------------------------------------------------------------------
 // F = -div K at a node from the stress planes (initial state only)
 // ---------------------------------------------------------------------------
-template <int DIM>
-__device__ __forceinline__ void korteweg_force_at(const DevParams &P, const double *__restrict__ kor,
+template <int DIM, typename PT>
+__device__ __forceinline__ void korteweg_force_at(const PT &P, const double *__restrict__ kor,
                                                   int x, int y, double &Fx, double &Fy)
 {
     Fx = 0.0;
@@ -507,8 +507,8 @@ __device__ __forceinline__ void korteweg_force_at(const DevParams &P, const doub
 //   kGhost  an inflow face: the ghost state's value (face in *face).
 // ---------------------------------------------------------------------------
 enum { kSelf = 0, kCopy = 1, kGhost = 2 };
-template <int DIM>
-__device__ __forceinline__ int classify(const DevParams &P, int x, int y, int &cx, int &cy, int &face)
+template <int DIM, typename PT>
+__device__ __forceinline__ int classify(const PT &P, int x, int y, int &cx, int &cy, int &face)
 {
     int cls = kSelf;
     cx = x;
@@ -548,15 +548,18 @@ __device__ __forceinline__ int classify(const DevParams &P, int x, int y, int &c
 //   per node     heat-flux correction M0, re-expression of the streamed state in the
 //                collision gauge (u, theta), BGK collision of f (force source S) and g
 //                (force-extended equilibrium, sources g~ + phi); writes the new state.
+// Two lanes per node, in separate waves: the first half of the block works on the
+// f sets of the tile's nodes, the second half on their g sets (and the heat-flux
+// correction, which only g uses); the stencil stages use all lanes of the block.
 // ---------------------------------------------------------------------------
 template <int DIM> struct CollideTile;
-template <> struct CollideTile<2> { static constexpr int TX = 32, TY = 8; };
+template <> struct CollideTile<2> { static constexpr int TX = 16, TY = 8; };
 template <> struct CollideTile<1> { static constexpr int TX = 256, TY = 1; };
 
 enum { kThFx = 0, kThFy, kThT, kThH, kThMu, kThKc, kThP, kThFields };
 
 template <int DIM, typename PopT, int TX, int TY>
-__global__ void __launch_bounds__(TX *TY)
+__global__ void __launch_bounds__(2 * TX *TY)
     k_force_collide(const SlotDesc *__restrict__ slots, int nslots)
 {
     using L = Layout<DIM>;
@@ -564,7 +567,9 @@ __global__ void __launch_bounds__(TX *TY)
     constexpr int RX = TX + 6, RY = DIM == 2 ? TY + 6 : 1; // rho region (halo 3)
     constexpr int KX = TX + 4, KY = DIM == 2 ? TY + 4 : 1; // K region (halo 2)
     constexpr int HX = TX + 2, HY = DIM == 2 ? TY + 2 : 1; // thermo region (halo 1)
-    constexpr int NT = TX * TY;
+    constexpr int NN = TX * TY;                            // nodes of the tile
+    constexpr int NT = 2 * NN;
+    static_assert(NN % 64 == 0, "each population set must fill whole waves");
     __shared__ double s_rho[RX * RY];
     __shared__ double s_K[3][KX * KY];
     __shared__ double s_th[kThFields][HX * HY];
@@ -575,33 +580,48 @@ __global__ void __launch_bounds__(TX *TY)
     const SlotDesc &S = slots[find_slot<false>(slots, nslots, gtile)];
     const int tile = gtile - S.fc_begin;
     int *__restrict__ flags = S.flags;
-    const double *__restrict__ mom = S.mom;
-    PopT *__restrict__ fout = (PopT *)S.pop_dst;
-    double *__restrict__ side_out = S.side_dst;
+    const POND_GLOBAL double *__restrict__ mom = (const POND_GLOBAL double *)S.mom;
+    POND_GLOBAL PopT *__restrict__ fout = (POND_GLOBAL PopT *)S.pop_dst;
+    POND_GLOBAL double *__restrict__ side_out = (POND_GLOBAL double *)S.side_dst;
 
-    const int tid = threadIdx.x + TX * threadIdx.y;
+    const int tid = threadIdx.x;
     if (tid == 0) abort_block = flags[kFlagErr];
     __syncthreads();
     if (abort_block != 0) return;
 
-    const DevParams &P = *S.P;
+    const POND_GLOBAL DevParams &P = *(const POND_GLOBAL DevParams *)S.P;
     const size_t N = P.N;
     const int x0 = (tile % S.fc_tiles_x) * TX;
     const int y0 = DIM == 2 ? (tile / S.fc_tiles_x) * TY : 0;
     const double dt = P.dt;
     const bool force = P.kappa != 0.0;
+    const double visc = (1.0 / P.omega - 0.5) * dt;   // mu = visc p
 
-    // Issue every global load this thread needs before the LDS stages, so that their
-    // latencies overlap: the streamed state of its own node (used last) and the
-    // velocity and energy of its thermo-stage positions (used in stage 3).
-    const int x = x0 + threadIdx.x;
-    const int y = y0 + (DIM == 2 ? threadIdx.y : 0);
+    // this lane's population set (0 = f, 1 = g; uniform per wave) and node
+    const int set = tid >= NN ? 1 : 0;
+    const int t = tid - set * NN;
+    const int lx = t % TX;
+    const int ly = t / TX;
+    const int x = x0 + lx;
+    const int y = y0 + (DIM == 2 ? ly : 0);
     const bool inside = x < P.nx && (DIM == 1 || y < P.ny);
     const int node = inside ? x + P.nx * y : 0;
-    double own[L::kMomPlanes];
+
+    // Issue every global load this lane needs before the LDS stages, so that their
+    // latencies overlap: rho and u of its node and the moments of its set (used last),
+    // and the velocity and energy of its thermo-stage positions (used in stage 3).
+    constexpr int NOWN = DIM == 2 ? 3 : 2;           // rho, u
+    double own[NOWN], oset[NF];
     if (inside) {
 #pragma unroll
-        for (int i = 0; i < L::kMomPlanes; ++i) own[i] = mom[i * N + node];
+        for (int i = 0; i < NOWN; ++i) own[i] = mom[i * N + node];
+        if (set == 0) {
+#pragma unroll
+            for (int i = 0; i < L::kFStored; ++i) oset[i] = mom[(L::kF + i) * N + node];
+        } else {
+#pragma unroll
+            for (int i = 0; i < NF; ++i) oset[i] = mom[(L::kG + i) * N + node];
+        }
     }
     constexpr int HITEMS = (HX * HY + NT - 1) / NT;
     double pre_u[HITEMS][3];
@@ -650,9 +670,9 @@ __global__ void __launch_bounds__(TX *TY)
                     gy += w * (double)ey * rq;
                     lap += w * (rq - r0);
                 }
-                gx /= kTL;
-                gy /= kTL;
-                lap *= 2.0 / kTL;
+                gx *= kInvTL;
+                gy *= kInvTL;
+                lap *= 2.0 * kInvTL;
                 const double iso = -P.kappa * (r0 * lap + 0.5 * (gx * gx + gy * gy));
                 s_K[0][li] = iso + P.kappa * gx * gx;
                 s_K[1][li] = P.kappa * gx * gy;
@@ -699,30 +719,29 @@ __global__ void __launch_bounds__(TX *TY)
                     dvx += w * (s_K[0][k] * (double)ex + s_K[1][k] * (double)ey);
                     dvy += w * (s_K[1][k] * (double)ex + s_K[2][k] * (double)ey);
                 }
-                Fx = -dvx / kTL;
-                Fy = DIM == 2 ? -dvy / kTL : 0.0;
+                Fx = -dvx * kInvTL;
+                Fy = DIM == 2 ? -dvy * kInvTL : 0.0;
             }
             const int nb = pre_nb[j];
             const double rho = force ? s_rho[(DIM == 2 ? (hy + 2) * RX : 0) + hx + 2] : mom[L::kRho * N + nb];
-            const double ux = pre_u[j][0];
-            const double uy = pre_u[j][1];
-            const double E = pre_u[j][2] / (2.0 * rho);
-            const double uhx = ux + Fx * dt / (2.0 * rho);
-            const double uhy = DIM == 2 ? uy + Fy * dt / (2.0 * rho) : 0.0;
+            const double h_r = 0.5 / rho;
+            const double E = pre_u[j][2] * h_r;
+            const double uhx = pre_u[j][0] + Fx * dt * h_r;
+            const double uhy = DIM == 2 ? pre_u[j][1] + Fy * dt * h_r : 0.0;
             const double e = E - 0.5 * (uhx * uhx + uhy * uhy);
             const double T = vdw_T_of_e(P, rho, e);
             const double p = vdw_p(P, rho, T);
             err |= vdw_bad(P, rho, p);
-            const double mu = (1.0 / P.omega - 0.5) * p * dt;
+            const double mu = visc * p;
             s_th[kThFx][li] = Fx;
             s_th[kThFy][li] = Fy;
             s_th[kThT][li] = T;
-            s_th[kThH][li] = e + p / rho;
+            s_th[kThH][li] = e + 2.0 * p * h_r;
             s_th[kThMu][li] = mu;
-            s_th[kThKc][li] = P.k_scale * mu * P.R * (1.0 + P.delta) / P.delta;
+            s_th[kThKc][li] = P.k_scale * mu * P.Cp_ig;
             s_th[kThP][li] = p;
         } else if (cls == kGhost) {
-            const GhostFace &G = P.ghost[face];
+            const POND_GLOBAL GhostFace &G = P.ghost[face];
             s_th[kThT][li] = G.T;
             s_th[kThH][li] = G.h;
             s_th[kThMu][li] = G.mu;
@@ -743,7 +762,84 @@ __global__ void __launch_bounds__(TX *TY)
     if (err) atomicOr(&flags[kFlagErr], err);
 
     if (!inside) return;
-    const int hb = (DIM == 2 ? (threadIdx.y + 1) * HX : 0) + threadIdx.x + 1;
+    const int hb = (DIM == 2 ? (ly + 1) * HX : 0) + lx + 1;
+
+    const double rho = own[L::kRho];
+    const double i_rho = 1.0 / rho;
+    const double u[2] = {own[L::kUx], DIM == 2 ? own[L::kUy] : 0.0};
+    const double F[2] = {s_th[kThFx][hb], DIM == 2 ? s_th[kThFy][hb] : 0.0};
+    const double p = s_th[kThP][hb];
+    const double theta = p * i_rho * kInvTL;
+    const double s = sqrt(theta);
+
+    // this set's streamed populations in the collision gauge (u, theta) from their
+    // central moments
+    double mc[NF];
+    if (set == 0) {
+        if (DIM == 2) {
+            mc[0] = rho;
+            mc[1] = 0.0; // (0,1): zero about u
+            mc[3] = 0.0; // (1,0)
+            mc[4] = oset[0];
+            mc[6] = oset[1];
+            mc[2] = oset[2];
+            mc[7] = oset[3];
+            mc[5] = oset[4];
+            mc[8] = oset[5];
+        } else {
+            mc[0] = rho;
+            mc[1] = 0.0;
+            mc[2] = oset[0];
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < NF; ++i) mc[i] = oset[i];
+    }
+    double A[3][3];
+    lagrange_coeffs(0.0, s, A);
+    double pop[Q];
+    if (DIM == 2) {
+        // separable: first along y (index n -> l), then along x (m -> k)
+        double tt[3][3];
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+#pragma unroll
+            for (int l = 0; l < 3; ++l)
+                tt[m][l] = A[l][0] * mc[3 * m] + A[l][1] * mc[3 * m + 1] + A[l][2] * mc[3 * m + 2];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int l = 0; l < 3; ++l) pop[3 * k + l] = A[k][0] * tt[0][l] + A[k][1] * tt[1][l] + A[k][2] * tt[2][l];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) pop[k] = A[k][0] * mc[0] + A[k][1] * mc[1] + A[k][2] * mc[2];
+    }
+
+    if (set == 0) {
+        // f: BGK towards rho W plus the force source (eqs. 16-17)
+        const double i_theta = 1.0 / theta;
+        const double i_s = s * i_theta;
+        double sx[3], sy[3] = {0.0, 0.0, 0.0};
+        source_axis(F[0] * dt * i_rho, i_theta, i_s, sx);
+        if (DIM == 2) source_axis(F[1] * dt * i_rho, i_theta, i_s, sy);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int k = DIM == 2 ? q / 3 : q;
+            const int l = DIM == 2 ? q % 3 : 1;
+            const double wk = kW1[k], wl = DIM == 2 ? kW1[l] : 1.0;
+            const double Sq = DIM == 2 ? rho * (wk * sy[l] + sx[k] * wl + sx[k] * sy[l]) : rho * sx[k];
+            const double feq = rho * (wk * wl);
+            fout[(size_t)q * N + node] = (PopT)(pop[q] + P.omega * (feq - pop[q]) + Sq);
+        }
+        side_out[kSideUx * N + node] = u[0];
+        side_out[kSideTh * N + node] = theta;
+        side_out[kSideFx * N + node] = F[0];
+        if (DIM == 2) {
+            side_out[kSideUy * N + node] = u[1];
+            side_out[kSideFy * N + node] = F[1];
+        }
+        return;
+    }
 
     // heat-flux correction M0 = 2 div(-mu grad h + k grad T), flux form (eq. 9)
     double M0 = 0.0;
@@ -761,102 +857,39 @@ __global__ void __launch_bounds__(TX *TY)
             const double mmid = 0.5 * (s_th[kThMu][k] + m0);
             acc += w * (kmid * (s_th[kThT][k] - T0) - mmid * (s_th[kThH][k] - h0));
         }
-        M0 = 2.0 * (2.0 / kTL) * acc;
-    }
-
-    const double rho = own[L::kRho];
-    const double u[2] = {own[L::kUx], DIM == 2 ? own[L::kUy] : 0.0};
-    const double F[2] = {s_th[kThFx][hb], DIM == 2 ? s_th[kThFy][hb] : 0.0};
-    const double p = s_th[kThP][hb];
-    const double theta = p / (rho * kTL);
-    const double s = sqrt(theta);
-    const double E = own[L::kG] / (2.0 * rho);
-    const double uh[2] = {u[0] + F[0] * dt / (2.0 * rho), DIM == 2 ? u[1] + F[1] * dt / (2.0 * rho) : 0.0};
-
-    // streamed populations in the collision gauge (u, theta) from their central moments
-    double mf[NF], mg[NF];
-    if (DIM == 2) {
-        mf[0] = rho;
-        mf[1] = 0.0; // (0,1): zero about u
-        mf[3] = 0.0; // (1,0)
-        mf[4] = own[L::kF + 0];
-        mf[6] = own[L::kF + 1];
-        mf[2] = own[L::kF + 2];
-        mf[7] = own[L::kF + 3];
-        mf[5] = own[L::kF + 4];
-        mf[8] = own[L::kF + 5];
-    } else {
-        mf[0] = rho;
-        mf[1] = 0.0;
-        mf[2] = own[L::kF];
-    }
-#pragma unroll
-    for (int i = 0; i < NF; ++i) mg[i] = own[L::kG + i];
-    double A[3][3];
-    lagrange_coeffs(0.0, s, A);
-    double f[Q], g[Q];
-    if (DIM == 2) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int l = 0; l < 3; ++l) {
-                double sf = 0.0, sg = 0.0;
-#pragma unroll
-                for (int m = 0; m < 3; ++m)
-#pragma unroll
-                    for (int n = 0; n < 3; ++n) {
-                        sf += A[k][m] * A[l][n] * mf[3 * m + n];
-                        sg += A[k][m] * A[l][n] * mg[3 * m + n];
-                    }
-                f[3 * k + l] = sf;
-                g[3 * k + l] = sg;
-            }
-    } else {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            f[k] = A[k][0] * mf[0] + A[k][1] * mf[1] + A[k][2] * mf[2];
-            g[k] = A[k][0] * mg[0] + A[k][1] * mg[1] + A[k][2] * mg[2];
-        }
-    }
-
-    // f: BGK towards rho W plus the force source (eqs. 16-17)
-    double sx[3], sy[3] = {0.0, 0.0, 0.0};
-    source_axis(F[0] * dt / rho, theta, s, sx);
-    if (DIM == 2) source_axis(F[1] * dt / rho, theta, s, sy);
-    PopT *gout = fout + (size_t)Q * N;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const int k = DIM == 2 ? q / 3 : q;
-        const int l = DIM == 2 ? q % 3 : 1;
-        const double wk = kW1[k], wl = DIM == 2 ? kW1[l] : 1.0;
-        const double S = DIM == 2 ? rho * (wk * sy[l] + sx[k] * wl + sx[k] * sy[l]) : rho * sx[k];
-        const double feq = rho * (wk * wl);
-        fout[(size_t)q * N + node] = (PopT)(f[q] + P.omega * (feq - f[q]) + S);
+        M0 = 2.0 * (2.0 * kInvTL) * acc;
     }
 
     // g: BGK towards the force-extended equilibrium plus (g~ + phi) dt (eqs. 19-22)
-    const double Pr = p / rho;
+    const double i_p = 1.0 / p;
+    const double E = 0.5 * oset[0] * i_rho;
+    const double uh[2] = {u[0] + 0.5 * F[0] * dt * i_rho, DIM == 2 ? u[1] + 0.5 * F[1] * dt * i_rho : 0.0};
+    const double Pr = p * i_rho;
     const double H = E + Pr;
+    const double dt_Pr = dt * rho * i_p;                   // dt / Pr
     double X[2][2], M[2], Nm[2][2];
 #pragma unroll
     for (int a = 0; a < DIM; ++a)
 #pragma unroll
         for (int b = 0; b < DIM; ++b)
-            X[a][b] = uh[a] * F[b] + F[a] * uh[b] + dt * F[a] * F[b] * E / (2.0 * p);
+            X[a][b] = uh[a] * F[b] + F[a] * uh[b] + 0.5 * dt * F[a] * F[b] * E * i_p;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         double xu = 0.0;
 #pragma unroll
         for (int b = 0; b < DIM; ++b) xu += X[a][b] * u[b];
-        M[a] = dt / Pr * (F[a] * H - xu);
+        M[a] = dt_Pr * (F[a] * H - xu);
     }
 #pragma unroll
     for (int a = 0; a < DIM; ++a)
 #pragma unroll
-        for (int b = 0; b < DIM; ++b) Nm[a][b] = (a == b ? rho : 0.0) + dt / (2.0 * Pr) * X[a][b];
+        for (int b = 0; b < DIM; ++b) Nm[a][b] = (a == b ? rho : 0.0) + 0.5 * dt_Pr * X[a][b];
     double work = 0.0;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) work += 2.0 * uh[a] * F[a];
+    const double c_uc = 0.5 * kInvTL * rho * i_p;          // rho / (2 p T_L)
+    const double c_v2 = 0.5 * rho * i_p;                   // rho / (2 p)
+    POND_GLOBAL PopT *gout = fout + (size_t)Q * N;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const double c[2] = {DIM == 2 ? (double)(q / 3 - 1) : (double)(q - 1),
@@ -876,15 +909,8 @@ __global__ void __launch_bounds__(TX *TY)
 #pragma unroll
             for (int b = 0; b < DIM; ++b) t2 += Nm[a][b] * (v[a] * v[b] - (a == b ? Pr : 0.0) - u[a] * u[b]);
         const double geq = wq * (2.0 * rho * E + t1 + t2);
-        const double psi = wq * (1.0 + rho * uc * uc / (2.0 * p * kTL) - rho * v2 / (2.0 * p) + 0.5 * (double)DIM);
-        gout[(size_t)q * N + node] = (PopT)(g[q] + P.omega * (geq - g[q]) + (M0 + work) * psi * dt);
-    }
-    side_out[kSideUx * N + node] = u[0];
-    side_out[kSideTh * N + node] = theta;
-    side_out[kSideFx * N + node] = F[0];
-    if (DIM == 2) {
-        side_out[kSideUy * N + node] = u[1];
-        side_out[kSideFy * N + node] = F[1];
+        const double psi = wq * (1.0 + c_uc * uc * uc - c_v2 * v2 + 0.5 * (double)DIM);
+        gout[(size_t)q * N + node] = (PopT)(pop[q] + P.omega * (geq - pop[q]) + (M0 + work) * psi * dt);
     }
 }
 
@@ -893,10 +919,10 @@ static hipError_t launch_force_collide_t(const LaunchCtx &c, const SlotDesc *slo
 {
     constexpr int TX = CollideTile<DIM>::TX, TY = CollideTile<DIM>::TY;
     if (c.ev_start)
-        hipExtLaunchKernelGGL((k_force_collide<DIM, PopT, TX, TY>), dim3(tiles), dim3(TX, TY), 0, c.st,
+        hipExtLaunchKernelGGL((k_force_collide<DIM, PopT, TX, TY>), dim3(tiles), dim3(2 * TX * TY), 0, c.st,
                               c.ev_start, c.ev_stop, 0, slots, nslots);
     else
-        hipLaunchKernelGGL((k_force_collide<DIM, PopT, TX, TY>), dim3(tiles), dim3(TX, TY), 0, c.st, slots,
+        hipLaunchKernelGGL((k_force_collide<DIM, PopT, TX, TY>), dim3(tiles), dim3(2 * TX * TY), 0, c.st, slots,
                            nslots);
     return hipGetLastError();
 }

@@ -163,9 +163,9 @@ def footprint(cfg: Config) -> int:
     return int(v.value)
 
 
-@dataclass
+@dataclass(eq=False)
 class Lattice:
-    """One libpond handle."""
+    """One libpond handle (compared and hashed by identity)."""
     cfg: Config
     _h: ctypes.c_void_p = field(default=None, init=False, repr=False)
 
