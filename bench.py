@@ -8,12 +8,19 @@ whole lattice.  Prints one JSON line:
   value        MLUPS of the FP64 path (node updates per second / 1e6), state resident
                in HBM, timed between stream synchronisations;
   fp32_store   the same with FP32 population storage;
+  large        both precisions on a 2048 x 2048 droplet (state far larger than the
+               caches), with the HBM bandwidth the algorithmic bytes imply;
+  serving      the batched-serving workload (64 seeded droplet jobs of mixed sides and
+               temperatures, Poisson arrivals at 20/s, 5000 steps each) through the
+               continuous-batching server and one job at a time: runs/s, p50/p99
+               time-to-result, for FP32-store and FP64;
   roofline     the streaming kernel (dominant) against the FP64 VALU peak, its mean
                launch duration from HIP events recorded on its stream around every
-               launch of a second timed run of steps;
+               launch of a second timed run of steps; traffic from the committed
+               rocprofv3 counter summary when it was taken on the current kernels;
   cpu_baseline the FP64 oracle on the host cores for a bounded number of steps.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-serving]
 """
 from __future__ import annotations
 
@@ -31,13 +38,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def gpu_run(case, precision, steps, warmup, stream):
+def gpu_run(case, precision, steps, warmup, stream, timed_steps=500):
     import torch
 
     from paper_2002_09217_amd import pond
-    from tests.common import pond_config
+    from paper_2002_09217_amd.serve import lattice_config
 
-    lat = pond.Lattice(pond_config(case, precision=precision, stream=stream))
+    lat = pond.Lattice(lattice_config(case, precision, -1, stream))
     lat.init_fields(case.rho, case.u, case.T)
     lat.step(warmup)
     torch.cuda.synchronize()
@@ -46,11 +53,47 @@ def gpu_run(case, precision, steps, warmup, stream):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     # per-kernel durations inside the step pipeline (HIP events on the same stream)
-    kern = lat.step_timed(min(steps, 500))
+    kern = lat.step_timed(min(steps, timed_steps))
     kern["tile"] = lat.tile_info()
     mon = lat.monitors()
     lat.close()
     return (t1 - t0), kern, mon
+
+
+def traffic_from_profile(kernel_prefix):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter summary,
+    or None when the summary was taken on other kernel sources than the current ones."""
+    import glob
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("pond_kernels.hip", "pond_device.h", "pond_internal.h"):
+        with open(os.path.join(ROOT, "paper_2002_09217_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    digest = h.hexdigest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(path):
+            if not line.startswith("traffic:"):
+                continue
+            kv = dict(item.split("=", 1) for item in line.split()[1:])
+            if kv.get("kernel", "").startswith(kernel_prefix.replace(" ", "")) and kv.get("sources_sha256") == digest:
+                return int(float(kv["bytes_per_launch"])), os.path.relpath(path, ROOT)
+    return None, None
+
+
+def serving(precision, stream, jobs_n, log_prefix):
+    from paper_2002_09217_amd import serve
+
+    jobs = serve.make_jobs(count=jobs_n)
+    tiles = serve.tune_tiles([j.case.n[0] for j in jobs], precision, stream)
+    srv = serve.Server(precision, tiles=tiles, stream=stream)
+    batched = serve.summarize(srv.run(jobs))
+    batched.update(peak_bytes=srv.peak_bytes, peak_slots=srv.peak_slots, chunks=srv.chunks)
+    log(f"bench: serving {log_prefix} batched {batched}")
+    alone = serve.summarize(serve.run_sequential(jobs, precision, tiles, stream))
+    log(f"bench: serving {log_prefix} one at a time {alone}")
+    return {"batched": batched, "one_at_a_time": alone, "tiles": tiles,
+            "speedup_runs_per_s": round(batched["runs_per_s"] / alone["runs_per_s"], 3)}
 
 
 def cpu_baseline(case, budget_s):
@@ -79,6 +122,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="skip the batched-serving workload")
+    ap.add_argument("--no-large", action="store_true", help="skip the 2048 x 2048 lattice")
+    ap.add_argument("--serving-jobs", type=int, default=64)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device-to-device copy of this many MiB (5 times), whose "
                          "FETCH_SIZE/WRITE_SIZE counters calibrate the HBM-traffic readings")
@@ -118,9 +164,32 @@ def main():
     mlups32 = N * args.steps / t32 / 1e6
     log(f"bench: FP32-store {mlups32:.1f} MLUPS, kernels (us): {kern32}")
 
+    large = None
+    if not args.no_large:
+        big = W.static_droplet(n=2048, radius=320.0)
+        large = {"workload": "2D static droplet D2Q9 2048x2048 periodic, T=0.9 T_cr, R=320"}
+        for name, prec in (("fp64", pond.FP64), ("fp32_store", pond.FP32_STORE)):
+            tb, kb, _ = gpu_run(big, prec, 200, 20, stream.cuda_stream, timed_steps=50)
+            ml = big.N * 200 / tb / 1e6
+            bpn = cost.bytes_per_node_step(2, prec == pond.FP32_STORE)
+            large[name] = {"mlups": round(ml, 1), "bytes_per_node_step": bpn,
+                           "hbm_GBs": round(bpn * ml * 1e6 / 1e9, 1),
+                           "hbm_frac": round(bpn * ml * 1e6 / 1e9 / cost.HBM_PEAK_GBS, 4),
+                           "kernels_us": {k: (round(v, 2) if isinstance(v, float) else v) for k, v in kb.items()}}
+            log(f"bench: 2048^2 {name} {ml:.1f} MLUPS, kernels (us): {kb}")
+
+    serve_out = None
+    if not args.no_serving:
+        serve_out = {"workload": f"{args.serving_jobs} seeded D2Q9 droplet jobs, sides in {{64,128,256,512}}, "
+                                 "T/T_cr in [0.85,1.10], 1-4 droplets, Poisson arrivals 20/s, 5000 steps, dt=0.1",
+                     "fp32_store": serving(pond.FP32_STORE, stream.cuda_stream, args.serving_jobs, "fp32"),
+                     "fp64": serving(pond.FP64, stream.cuda_stream, args.serving_jobs, "fp64")}
+
     flops = cost.stream_flops_per_node(2, n_pass) * N
     t_stream = kern64["k_stream"] * 1e-6
     achieved = flops / t_stream / 1e12
+    k_name = "k_stream<2, double, double, {tx}, {ty}".format(**kern64["tile"])
+    traffic, traffic_src = traffic_from_profile(k_name)
     b64 = cost.bytes_per_node_step(2, False)
     b32 = cost.bytes_per_node_step(2, True)
 
@@ -148,9 +217,11 @@ def main():
                    "n_pass": n_pass, "nodes": N, "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3),
                      "peak": round(cost.VALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
-                     "frac": round(achieved / cost.VALU_PEAK_TFLOPS, 4), "traffic": None,
-                     "kernel": "k_stream", "avg_launch_us": round(kern64["k_stream"], 3),
-                     "flops_per_node": cost.stream_flops_per_node(2, n_pass)},
+                     "frac": round(achieved / cost.VALU_PEAK_TFLOPS, 4), "traffic": traffic,
+                     "kernel": k_name + ">", "avg_launch_us": round(kern64["k_stream"], 3),
+                     "flops_per_node": cost.stream_flops_per_node(2, n_pass),
+                     "algorithmic_bytes_per_launch": cost.stream_bytes_per_node(2, False) * N,
+                     "traffic_source": traffic_src},
         "hbm": {"bytes_per_node_step": b64, "achieved_GBs": round(b64 * mlups64 * 1e6 / 1e9, 1),
                 "frac": round(b64 * mlups64 * 1e6 / 1e9 / cost.HBM_PEAK_GBS, 4)},
         "fp32_store": {"value": round(mlups32, 2), "unit": "MLUPS", "ratio_vs_fp64": round(mlups32 / mlups64, 3),
@@ -158,6 +229,8 @@ def main():
         "kernels_us": {"fp64": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in kern64.items()},
                        "fp32_store": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in kern32.items()}},
         "monitors_after": {"mass": mon64["mass"], "min_p": mon64["min_p"], "max_v_dt": mon64["max_v_dt"]},
+        "large": large,
+        "serving": serve_out,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -27,6 +27,16 @@ def bytes_per_node_step(dim: int, fp32_store: bool) -> int:
     return 2 * (2 * q * pop + 5 * 8)
 
 
+def stream_bytes_per_node(dim: int, fp32_store: bool) -> int:
+    """Compulsory HBM bytes of the streaming kernel alone per receiver: it reads the
+    populations and the five side fields and writes the streamed-state moment planes
+    (rho, u and the central moments: 18 planes in 2D, 6 in 1D) for the collision kernel."""
+    q = 9 if dim == 2 else 3
+    pop = 4 if fp32_store else 8
+    mom_planes = 18 if dim == 2 else 6
+    return 2 * q * pop + 5 * 8 + mom_planes * 8
+
+
 def stream_flops_per_node(dim: int, n_pass: int) -> int:
     if dim == 2:
         per_field = 2 * (3 * 5 * 4 + 9 * 4 + 9) + 9   # 2 x 105 FMA + 9 MUL = 219

@@ -188,7 +188,7 @@ int build_pair_graph(pond_handle *h, int from)
     if (rc != POND_OK) return rc;
     if (e != hipSuccess) return handle_fail(h, POND_E_DEVICE, "graph capture: %s", hipGetErrorString(e));
     e = hipGraphInstantiate(&h->pair_exec[from], g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
         h->pair_exec[from] = nullptr;
         return handle_fail(h, POND_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
@@ -216,7 +216,7 @@ void drop_graphs(pond_handle *h)
 {
     for (int i = 0; i < 2; ++i)
         if (h->pair_exec[i]) {
-            hipGraphExecDestroy(h->pair_exec[i]);
+            (void)hipGraphExecDestroy(h->pair_exec[i]);
             h->pair_exec[i] = nullptr;
         }
 }
@@ -225,19 +225,19 @@ void free_all(pond_handle *h)
 {
     drop_graphs(h);
     for (int i = 0; i < 2; ++i) {
-        if (h->ds.pop[i]) hipFree(h->ds.pop[i]);
-        if (h->ds.side[i]) hipFree(h->ds.side[i]);
+        if (h->ds.pop[i]) (void)hipFree(h->ds.pop[i]);
+        if (h->ds.side[i]) (void)hipFree(h->ds.side[i]);
     }
-    if (h->ds.mom) hipFree(h->ds.mom);
-    if (h->ds.kor) hipFree(h->ds.kor);
-    if (h->ds.aux) hipFree(h->ds.aux);
-    if (h->ds.flags) hipFree(h->ds.flags);
-    if (h->ds.params) hipFree(h->ds.params);
-    if (h->desc_d) hipFree(h->desc_d);
-    if (h->mon_partials) hipFree(h->mon_partials);
-    if (h->mon_out) hipFree(h->mon_out);
-    if (h->capture_stream) hipStreamDestroy(h->capture_stream);
-    if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
+    if (h->ds.mom) (void)hipFree(h->ds.mom);
+    if (h->ds.kor) (void)hipFree(h->ds.kor);
+    if (h->ds.aux) (void)hipFree(h->ds.aux);
+    if (h->ds.flags) (void)hipFree(h->ds.flags);
+    if (h->ds.params) (void)hipFree(h->ds.params);
+    if (h->desc_d) (void)hipFree(h->desc_d);
+    if (h->mon_partials) (void)hipFree(h->mon_partials);
+    if (h->mon_out) (void)hipFree(h->mon_out);
+    if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
 }
 
 // Time every compiled tile shape of the streaming kernel on the current state (one
@@ -267,8 +267,8 @@ int tune_stream_tile(pond_handle *h, int reps)
             best = v;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (rc != POND_OK) return rc;
     drop_graphs(h);
     h->lc.stream_tile = best;
@@ -500,7 +500,7 @@ int pond_destroy(pond_handle *h)
 {
     if (!h) return POND_OK;
     if (h->batch) pond_batch_remove(h->batch, h);
-    if (h->stream) hipStreamSynchronize(h->stream);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
     free_all(h);
     delete h;
     return POND_OK;
@@ -528,8 +528,8 @@ int pond_time_kernel(pond_handle *h, int which, int reps, double *avg_us)
     HIP_TRY(h, hipEventSynchronize(e1));
     float ms = 0.0f;
     HIP_TRY(h, hipEventElapsedTime(&ms, e0, e1));
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     *avg_us = 1000.0 * (double)ms / reps;
     int fl[kFlagWords];
     int rc = read_flags(h, fl);
@@ -577,7 +577,7 @@ int pond_step_timed(pond_handle *h, int nsteps, double *kernel_us)
         acc[0] += a;
         acc[1] += b;
     }
-    for (int i = 0; i < created; ++i) hipEventDestroy(ev[i]);
+    for (int i = 0; i < created; ++i) (void)hipEventDestroy(ev[i]);
     std::free(ev);
     if (rc != POND_OK) return rc;
     kernel_us[0] = 1000.0 * acc[0] / nsteps;

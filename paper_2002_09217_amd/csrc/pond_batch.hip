@@ -61,7 +61,7 @@ void drop_graphs(pond_batch *b)
 {
     for (auto &g : b->pair_exec)
         if (g) {
-            hipGraphExecDestroy(g);
+            (void)hipGraphExecDestroy(g);
             g = nullptr;
         }
 }
@@ -82,8 +82,8 @@ int rebuild(pond_batch *b)
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return key(x) < key(y); });
     if (M > b->cap) {
         if (hipStreamSynchronize(b->stream) != hipSuccess) return POND_E_DEVICE;
-        if (b->desc_d) hipFree(b->desc_d);
-        if (b->flags_d) hipFree(b->flags_d);
+        if (b->desc_d) (void)hipFree(b->desc_d);
+        if (b->flags_d) (void)hipFree(b->flags_d);
         const int cap = std::max(M, 2 * b->cap);
         b->desc_d = nullptr;
         b->flags_d = nullptr;
@@ -144,11 +144,11 @@ bool build_pair_graph(pond_batch *b, int arr)
     if (e == hipSuccess) e = enqueue_step(b, b->capture_stream, 1 - arr);
     const hipError_t ec = hipStreamEndCapture(b->capture_stream, &g);
     if (e != hipSuccess || ec != hipSuccess || !g) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return false;
     }
     e = hipGraphInstantiate(&b->pair_exec[arr], g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
         b->pair_exec[arr] = nullptr;
         return false;
@@ -184,7 +184,7 @@ int pond_batch_create(void *stream, pond_batch **out)
     if (rc == POND_OK && hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking) != hipSuccess)
         rc = POND_E_DEVICE;
     if (rc != POND_OK) {
-        if (b->own_stream) hipStreamDestroy(b->stream);
+        if (b->own_stream) (void)hipStreamDestroy(b->stream);
         delete b;
         return rc;
     }
@@ -221,7 +221,7 @@ int pond_batch_remove(pond_batch *b, pond_handle *h)
     if (!b || !h) return POND_E_INVALID;
     const int i = find_member(b, h);
     if (i < 0) return POND_E_INVALID;
-    hipStreamSynchronize(b->stream);
+    (void)hipStreamSynchronize(b->stream);
     b->members.erase(b->members.begin() + i);
     h->batch = nullptr;
     b->dirty = true;
@@ -285,13 +285,13 @@ int pond_batch_size(const pond_batch *b, int *out)
 int pond_batch_destroy(pond_batch *b)
 {
     if (!b) return POND_OK;
-    if (b->stream) hipStreamSynchronize(b->stream);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
     for (pond_handle *h : b->members) h->batch = nullptr;
     drop_graphs(b);
-    if (b->desc_d) hipFree(b->desc_d);
-    if (b->flags_d) hipFree(b->flags_d);
-    if (b->capture_stream) hipStreamDestroy(b->capture_stream);
-    if (b->own_stream && b->stream) hipStreamDestroy(b->stream);
+    if (b->desc_d) (void)hipFree(b->desc_d);
+    if (b->flags_d) (void)hipFree(b->flags_d);
+    if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
     return POND_OK;
 }
