@@ -57,6 +57,7 @@ int handle_update_desc(pond_handle *h)
         d.fc_tiles_x = fcx;
         d.fc_begin = 0;
         d.fc_count = fcc;
+        d.parity = p;
     }
     // synchronous: the descriptors are read by work already queued on the stream
     HIP_TRY(h, hipStreamSynchronize(h->stream));
@@ -83,7 +84,17 @@ const char *err_name(int bits)
 // move the handle to the last completed state of a batch of steps, given its flags
 int handle_finish_batch(pond_handle *h, const int *fl)
 {
-    const int done = fl[kFlagErr] ? fl[kFlagSteps] - 1 : fl[kFlagSteps];
+    int done = fl[kFlagSteps];
+    if (fl[kFlagErr]) {
+        // The failing step k read the state of parity (cur + k) % 2, recorded with the
+        // error; the counter is k or k + 1 (whether the failing step's first tile ran
+        // before the error was raised), and the parity tells which.
+        const int p = fl[kFlagErrParity] - 1;
+        if (p < 0)
+            done -= 1; // not raised by a step kernel: the counter includes the failing step
+        else if ((done & 1) != ((p - h->cur) & 1))
+            done -= 1;
+    }
     h->cur = (h->cur + done) % 2;
     h->steps += done;
     if (fl[kFlagErr]) {

@@ -76,37 +76,55 @@ __device__ __forceinline__ int find_slot(const SlotDesc *slots, int nslots, int 
 }
 
 // ---------------------------------------------------------------------------
-// boundary mapping: node index >= 0, or -(1 + face) for an inflow ghost,
-// face = 2 axis + side.  Periodic faces wrap, outflow faces clamp.  (PT: DevParams
-// in any address space, as for the other helpers taking P.)
+// Lattice extent and face types, held in registers.  The boundary rules below select
+// between these values; indexing the parameter block with a per-lane face would be a
+// vector load with a wait in front of every neighbour load that depends on it.
 // ---------------------------------------------------------------------------
-template <int DIM, typename PT>
-__device__ __forceinline__ int map_node(const PT &P, int x, int y)
+struct Geo {
+    int nx, ny;
+    int bc00, bc01, bc10, bc11; // bc[axis][side]
+    __device__ __forceinline__ int bc(int axis, int side) const
+    {
+        return axis == 0 ? (side ? bc01 : bc00) : (side ? bc11 : bc10);
+    }
+};
+template <typename PT>
+__device__ __forceinline__ Geo make_geo(const PT &P)
 {
-    if (x < 0 || x >= P.nx) {
+    return Geo{P.nx, P.ny, P.bc[0][0], P.bc[0][1], P.bc[1][0], P.bc[1][1]};
+}
+
+// ---------------------------------------------------------------------------
+// boundary mapping: node index >= 0, or -(1 + face) for an inflow ghost,
+// face = 2 axis + side.  Periodic faces wrap, outflow faces clamp.
+// ---------------------------------------------------------------------------
+template <int DIM>
+__device__ __forceinline__ int map_node(const Geo &g, int x, int y)
+{
+    if (x < 0 || x >= g.nx) {
         const int side = x < 0 ? 0 : 1;
-        const int bc = P.bc[0][side];
+        const int bc = g.bc(0, side);
         if (bc == kPeriodic) {
-            x = x < 0 ? x + P.nx : x - P.nx;
-            if (x < 0 || x >= P.nx) x = ((x % P.nx) + P.nx) % P.nx; // narrower than the halo
+            x = x < 0 ? x + g.nx : x - g.nx;
+            if (x < 0 || x >= g.nx) x = ((x % g.nx) + g.nx) % g.nx; // narrower than the halo
         } else if (bc == kOutflow)
-            x = x < 0 ? 0 : P.nx - 1;
+            x = x < 0 ? 0 : g.nx - 1;
         else
             return -(1 + side);
     }
     if (DIM == 2) {
-        if (y < 0 || y >= P.ny) {
+        if (y < 0 || y >= g.ny) {
             const int side = y < 0 ? 0 : 1;
-            const int bc = P.bc[1][side];
+            const int bc = g.bc(1, side);
             if (bc == kPeriodic) {
-                y = y < 0 ? y + P.ny : y - P.ny;
-                if (y < 0 || y >= P.ny) y = ((y % P.ny) + P.ny) % P.ny; // narrower than the halo
+                y = y < 0 ? y + g.ny : y - g.ny;
+                if (y < 0 || y >= g.ny) y = ((y % g.ny) + g.ny) % g.ny; // narrower than the halo
             } else if (bc == kOutflow)
-                y = y < 0 ? 0 : P.ny - 1;
+                y = y < 0 ? 0 : g.ny - 1;
             else
                 return -(1 + 2 + side);
         }
-        return x + P.nx * y;
+        return x + g.nx * y;
     }
     return x;
 }

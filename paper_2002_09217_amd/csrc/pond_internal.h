@@ -55,10 +55,12 @@ enum { kSideUx = 0, kSideUy = 1, kSideTh = 2, kSideFx = 3, kSideFy = 4, kSidePla
 enum { kAuxPlanes = 7 };
 enum { kKorPlanes = 3 };
 
-// flags[0]: error bits; flags[1]: number of streaming launches of the current batch
-// that started without an earlier failure (= completed steps, or completed + 1
-// when a step failed)
-enum { kFlagErr = 0, kFlagSteps = 1, kFlagWords = 4 };
+// flags[0]: error bits.  flags[1]: streaming launches of the current batch of steps
+// whose first tile found no error (the failing step itself may or may not count: its
+// first tile can run before or after another tile raises the error).  flags[2]: 1 +
+// the parity of the state buffer read by the step that raised the first error, which
+// settles that ambiguity (the state it read is the last complete one).
+enum { kFlagErr = 0, kFlagSteps = 1, kFlagErrParity = 2, kFlagWords = 4 };
 
 // One lattice of a launch of the step kernels: where the step reads and writes and
 // which workgroups of the launch are its tiles.  A single lattice is a launch of one
@@ -73,6 +75,7 @@ struct SlotDesc {
     int *flags;              // error bits and step counter of this lattice
     int st_tiles_x, st_begin, st_count; // streaming-kernel tiles: per row, first, number
     int fc_tiles_x, fc_begin, fc_count; // collision-kernel tiles
+    int parity;              // index of the state buffer pop_src belongs to (0 or 1)
 };
 
 // device buffers of one lattice

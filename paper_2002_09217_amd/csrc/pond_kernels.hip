@@ -71,6 +71,13 @@ hipError_t launch_gather_slot_flags(hipStream_t st, const SlotDesc *slots, int n
     return hipGetLastError();
 }
 
+// error bits of a step, with the parity of the state it read if it is the first error
+__device__ __forceinline__ void raise_error(int *flags, int bits, int parity)
+{
+    atomicOr(&flags[kFlagErr], bits);
+    atomicCAS(&flags[kFlagErrParity], 0, parity + 1);
+}
+
 // ---------------------------------------------------------------------------
 // streaming with the predictor-corrector
 // ---------------------------------------------------------------------------
@@ -102,17 +109,14 @@ __global__ void __launch_bounds__(SPLIT *TX *TY)
     const POND_GLOBAL double *__restrict__ side = (const POND_GLOBAL double *)S.side_src;
     POND_GLOBAL double *__restrict__ mom = (POND_GLOBAL double *)S.mom;
 
-    // leave the state alone after an earlier failure; the decision is taken once per
-    // block so that every wave of the block reaches the barrier below or none does
+    // Error state of earlier steps: read now, acted on after the fill (which only reads),
+    // so that its latency overlaps the fill's loads.  The decision is taken once per
+    // block, so every wave of the block leaves together.
     const int tid = threadIdx.x + SPLIT * TX * threadIdx.y;
-    if (tid == 0) {
-        abort_block = flags[kFlagErr];
-        // one step more has started without an earlier failure
-        if (tile == 0 && abort_block == 0) atomicAdd(&flags[kFlagSteps], 1);
-    }
-    __syncthreads();
-    if (abort_block != 0) return;
+    int err_before = 0;
+    if (tid == 0) err_before = flags[kFlagErr];
     const POND_GLOBAL DevParams &P = *(const POND_GLOBAL DevParams *)S.P;
+    const Geo geo = make_geo(P);
     const int N = P.N;
     const int bx0 = (tile % S.st_tiles_x) * TX;
     const int by0 = DIM == 2 ? (tile / S.st_tiles_x) * TY : 0;
@@ -150,7 +154,7 @@ __global__ void __launch_bounds__(SPLIT *TX *TY)
         r.li = SPLIT == 2 ? it >> 1 : it;
         r.set0 = SPLIT == 2 ? it & 1 : 0;
         const int lx = r.li % LX, ly = r.li / LX;
-        r.node = map_node<DIM>(P, bx0 - H + lx, by0 - H + ly);
+        r.node = map_node<DIM>(geo, bx0 - H + lx, by0 - H + ly);
         if (r.node >= 0) {
             r.ux = side[kSideUx * N + r.node];
             r.uy = DIM == 2 ? side[kSideUy * N + r.node] : 0.0;
@@ -194,7 +198,14 @@ __global__ void __launch_bounds__(SPLIT *TX *TY)
         store_moments(ra);
         if (two) store_moments(rb);
     }
+    if (tid == 0) {
+        abort_block = err_before;
+        // one step more has started without an earlier failure
+        if (tile == 0 && err_before == 0) atomicAdd(&flags[kFlagSteps], 1);
+    }
     __syncthreads();
+    // leave the state alone after an earlier failure
+    if (abort_block != 0) return;
 
     // both lanes of a split receiver leave together, so the exchanges below always pair up
     if (!inside) return;
@@ -358,7 +369,7 @@ __global__ void __launch_bounds__(SPLIT *TX *TY)
 #pragma unroll
         for (int i = 0; i < NF; ++i) mom[(size_t)(L::kG + i) * N + node] = mg[i];
     }
-    if (err) atomicOr(&flags[kFlagErr], err);
+    if (err) raise_error(flags, err, S.parity);
 }
 
 template <int DIM, typename PopT, typename LdsT, int SPLIT, int TX, int TY>
@@ -418,6 +429,7 @@ __global__ void k_korteweg(const DevParams *__restrict__ Pp, const double *__res
 {
     if (flags[kFlagErr] != 0) return;
     const DevParams &P = *Pp;
+    const Geo geo = make_geo(P);
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = DIM == 2 ? blockIdx.y * blockDim.y + threadIdx.y : 0;
     if (x >= P.nx || y >= (DIM == 2 ? P.ny : 1)) return;
@@ -431,7 +443,7 @@ __global__ void k_korteweg(const DevParams *__restrict__ Pp, const double *__res
         const int cx = DIM == 2 ? q / 3 - 1 : q - 1;
         const int cy = DIM == 2 ? q % 3 - 1 : 0;
         const double w = DIM == 2 ? kW1[q / 3] * kW1[q % 3] : kW1[q];
-        const int nb = map_node<DIM>(P, x + cx, y + cy);
+        const int nb = map_node<DIM>(geo, x + cx, y + cy);
         const double rq = nb >= 0 ? rho[nb] : P.ghost[-nb - 1].rho;
         gx += w * (double)cx * rq;
         gy += w * (double)cy * rq;
@@ -475,6 +487,7 @@ template <int DIM, typename PT>
 __device__ __forceinline__ void korteweg_force_at(const PT &P, const double *__restrict__ kor,
                                                   int x, int y, double &Fx, double &Fy)
 {
+    const Geo geo = make_geo(P);
     Fx = 0.0;
     Fy = 0.0;
     if (P.kappa == 0.0) return;
@@ -486,7 +499,7 @@ __device__ __forceinline__ void korteweg_force_at(const PT &P, const double *__r
         const int cx = DIM == 2 ? q / 3 - 1 : q - 1;
         const int cy = DIM == 2 ? q % 3 - 1 : 0;
         const double w = DIM == 2 ? kW1[q / 3] * kW1[q % 3] : kW1[q];
-        const int nb = map_node<DIM>(P, x + cx, y + cy);
+        const int nb = map_node<DIM>(geo, x + cx, y + cy);
         double kxx = 0.0, kxy = 0.0, kyy = 0.0; // inflow ghosts are uniform: K = 0
         if (nb >= 0) {
             kxx = kor[0 * N + nb];
@@ -507,33 +520,33 @@ __device__ __forceinline__ void korteweg_force_at(const PT &P, const double *__r
 //   kGhost  an inflow face: the ghost state's value (face in *face).
 // ---------------------------------------------------------------------------
 enum { kSelf = 0, kCopy = 1, kGhost = 2 };
-template <int DIM, typename PT>
-__device__ __forceinline__ int classify(const PT &P, int x, int y, int &cx, int &cy, int &face)
+template <int DIM>
+__device__ __forceinline__ int classify(const Geo &g, int x, int y, int &cx, int &cy, int &face)
 {
     int cls = kSelf;
     cx = x;
     cy = y;
-    if (x < 0 || x >= P.nx) {
+    if (x < 0 || x >= g.nx) {
         const int side = x < 0 ? 0 : 1;
-        const int bc = P.bc[0][side];
+        const int bc = g.bc(0, side);
         if (bc == kInflow) {
             face = side;
             return kGhost;
         }
         if (bc == kOutflow) {
-            cx = x < 0 ? 0 : P.nx - 1;
+            cx = x < 0 ? 0 : g.nx - 1;
             cls = kCopy;
         }
     }
-    if (DIM == 2 && (y < 0 || y >= P.ny)) {
+    if (DIM == 2 && (y < 0 || y >= g.ny)) {
         const int side = y < 0 ? 0 : 1;
-        const int bc = P.bc[1][side];
+        const int bc = g.bc(1, side);
         if (bc == kInflow) {
             face = 2 + side;
             return kGhost;
         }
         if (bc == kOutflow) {
-            cy = y < 0 ? 0 : P.ny - 1;
+            cy = y < 0 ? 0 : g.ny - 1;
             cls = kCopy;
         }
     }
@@ -584,12 +597,13 @@ __global__ void __launch_bounds__(2 * TX *TY)
     POND_GLOBAL PopT *__restrict__ fout = (POND_GLOBAL PopT *)S.pop_dst;
     POND_GLOBAL double *__restrict__ side_out = (POND_GLOBAL double *)S.side_dst;
 
+    // error state of earlier steps, acted on once the loads below are under way
     const int tid = threadIdx.x;
-    if (tid == 0) abort_block = flags[kFlagErr];
-    __syncthreads();
-    if (abort_block != 0) return;
+    int err_before = 0;
+    if (tid == 0) err_before = flags[kFlagErr];
 
     const POND_GLOBAL DevParams &P = *(const POND_GLOBAL DevParams *)S.P;
+    const Geo geo = make_geo(P);
     const size_t N = P.N;
     const int x0 = (tile % S.fc_tiles_x) * TX;
     const int y0 = DIM == 2 ? (tile / S.fc_tiles_x) * TY : 0;
@@ -615,13 +629,11 @@ __global__ void __launch_bounds__(2 * TX *TY)
     if (inside) {
 #pragma unroll
         for (int i = 0; i < NOWN; ++i) own[i] = mom[i * N + node];
-        if (set == 0) {
+        // NF consecutive planes from the set's first one (the f lanes read the stored f
+        // moments and a few g planes they ignore): no branch, so no wait between the sets
+        const int base = set == 0 ? L::kF : L::kG;
 #pragma unroll
-            for (int i = 0; i < L::kFStored; ++i) oset[i] = mom[(L::kF + i) * N + node];
-        } else {
-#pragma unroll
-            for (int i = 0; i < NF; ++i) oset[i] = mom[(L::kG + i) * N + node];
-        }
+        for (int i = 0; i < NF; ++i) oset[i] = mom[(base + i) * N + node];
     }
     constexpr int HITEMS = (HX * HY + NT - 1) / NT;
     double pre_u[HITEMS][3];
@@ -633,8 +645,8 @@ __global__ void __launch_bounds__(2 * TX *TY)
         if (li < HX * HY) {
             const int gx = x0 - 1 + li % HX, gy = y0 - 1 + li / HX;
             int cx, cy, face;
-            if (classify<DIM>(P, gx, gy, cx, cy, face) == kSelf) {
-                const int nb = map_node<DIM>(P, gx, DIM == 2 ? gy : 0);
+            if (classify<DIM>(geo, gx, gy, cx, cy, face) == kSelf) {
+                const int nb = map_node<DIM>(geo, gx, DIM == 2 ? gy : 0);
                 pre_nb[j] = nb;
                 pre_u[j][0] = mom[L::kUx * N + nb];
                 pre_u[j][1] = DIM == 2 ? mom[L::kUy * N + nb] : 0.0;
@@ -643,19 +655,39 @@ __global__ void __launch_bounds__(2 * TX *TY)
         }
     }
 
-    // stage 1: density of the streamed state
+    // density of the streamed state on the rho region, loaded with the rest
+    constexpr int RITEMS = (RX * RY + NT - 1) / NT;
+    double pre_rho[RITEMS];
     if (force) {
-        for (int li = tid; li < RX * RY; li += NT) {
-            const int gx = x0 - 3 + li % RX, gy = y0 - 3 + li / RX;
-            const int nb = map_node<DIM>(P, gx, DIM == 2 ? gy : 0);
-            s_rho[li] = nb >= 0 ? mom[L::kRho * N + nb] : P.ghost[-nb - 1].rho;
+#pragma unroll
+        for (int j = 0; j < RITEMS; ++j) {
+            const int li = tid + j * NT;
+            pre_rho[j] = 0.0;
+            if (li < RX * RY) {
+                const int gx = x0 - 3 + li % RX, gy = y0 - 3 + li / RX;
+                const int nb = map_node<DIM>(geo, gx, DIM == 2 ? gy : 0);
+                pre_rho[j] = nb >= 0 ? mom[L::kRho * N + nb] : P.ghost[-nb - 1].rho;
+            }
         }
+    }
+
+    // stage 1: density of the streamed state into LDS
+    if (force) {
+#pragma unroll
+        for (int j = 0; j < RITEMS; ++j) {
+            const int li = tid + j * NT;
+            if (li < RX * RY) s_rho[li] = pre_rho[j];
+        }
+        // leave the state alone after an earlier failure (once per block, before any
+        // store; the first barrier of either path publishes the decision)
+        if (tid == 0) abort_block = err_before;
         __syncthreads();
+        if (abort_block != 0) return;
         // stage 2: K = -kappa (rho lap rho + |grad rho|^2/2) I + kappa grad rho grad rho
         for (int li = tid; li < KX * KY; li += NT) {
             const int kx = li % KX, ky = li / KX;
             int cx, cy, face;
-            const int cls = classify<DIM>(P, x0 - 2 + kx, y0 - 2 + ky, cx, cy, face);
+            const int cls = classify<DIM>(geo, x0 - 2 + kx, y0 - 2 + ky, cx, cy, face);
             if (cls == kSelf) {
                 const int rb = (DIM == 2 ? (ky + 1) * RX : 0) + kx + 1;
                 const double r0 = s_rho[rb];
@@ -685,7 +717,7 @@ __global__ void __launch_bounds__(2 * TX *TY)
         for (int li = tid; li < KX * KY; li += NT) {
             const int kx = li % KX, ky = li / KX;
             int cx, cy, face;
-            if (classify<DIM>(P, x0 - 2 + kx, y0 - 2 + ky, cx, cy, face) == kCopy) {
+            if (classify<DIM>(geo, x0 - 2 + kx, y0 - 2 + ky, cx, cy, face) == kCopy) {
                 const int src = (cx - (x0 - 2)) + (DIM == 2 ? (cy - (y0 - 2)) * KX : 0);
                 s_K[0][li] = s_K[0][src];
                 s_K[1][li] = s_K[1][src];
@@ -704,7 +736,7 @@ __global__ void __launch_bounds__(2 * TX *TY)
         const int hx = li % HX, hy = li / HX;
         const int gx = x0 - 1 + hx, gy = y0 - 1 + hy;
         int cx, cy, face;
-        const int cls = classify<DIM>(P, gx, gy, cx, cy, face);
+        const int cls = classify<DIM>(geo, gx, gy, cx, cy, face);
         if (cls == kSelf) {
             double Fx = 0.0, Fy = 0.0;
             if (force) {
@@ -748,18 +780,20 @@ __global__ void __launch_bounds__(2 * TX *TY)
             s_th[kThKc][li] = G.kc;
         }
     }
+    if (!force && tid == 0) abort_block = err_before;
     __syncthreads();
+    if (abort_block != 0) return;
     for (int li = tid; li < HX * HY; li += NT) {
         const int hx = li % HX, hy = li / HX;
         int cx, cy, face;
-        if (classify<DIM>(P, x0 - 1 + hx, y0 - 1 + hy, cx, cy, face) == kCopy) {
+        if (classify<DIM>(geo, x0 - 1 + hx, y0 - 1 + hy, cx, cy, face) == kCopy) {
             const int src = (cx - (x0 - 1)) + (DIM == 2 ? (cy - (y0 - 1)) * HX : 0);
 #pragma unroll
             for (int f = 0; f < kThFields; ++f) s_th[f][li] = s_th[f][src];
         }
     }
     __syncthreads();
-    if (err) atomicOr(&flags[kFlagErr], err);
+    if (err) raise_error(flags, err, S.parity);
 
     if (!inside) return;
     const int hb = (DIM == 2 ? (ly + 1) * HX : 0) + lx + 1;
@@ -962,6 +996,7 @@ __global__ void k_init_equilibrium(const DevParams *__restrict__ Pp, const doubl
     using L = Layout<DIM>;
     constexpr int Q = L::Q, NF = L::NF;
     const DevParams &P = *Pp;
+    const Geo geo = make_geo(P);
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = DIM == 2 ? blockIdx.y * blockDim.y + threadIdx.y : 0;
     if (x >= P.nx || y >= (DIM == 2 ? P.ny : 1)) return;
@@ -1049,6 +1084,7 @@ __global__ void k_macro(const DevParams *__restrict__ Pp, const PopT *__restrict
 {
     constexpr int Q = Layout<DIM>::Q;
     const DevParams &P = *Pp;
+    const Geo geo = make_geo(P);
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = DIM == 2 ? blockIdx.y * blockDim.y + threadIdx.y : 0;
     if (x >= P.nx || y >= (DIM == 2 ? P.ny : 1)) return;
@@ -1126,6 +1162,7 @@ __global__ void __launch_bounds__(kMonThreads)
                        const double *__restrict__ side, double *__restrict__ partials)
 {
     const DevParams &P = *Pp;
+    const Geo geo = make_geo(P);
     const size_t N = P.N;
     const int n = blockIdx.x * kMonThreads + threadIdx.x;
     double v[kMonWords];
@@ -1142,7 +1179,7 @@ __global__ void __launch_bounds__(kMonThreads)
             const int cx = DIM == 2 ? q / 3 - 1 : q - 1;
             const int cy = DIM == 2 ? q % 3 - 1 : 0;
             const double w = DIM == 2 ? kW1[q / 3] * kW1[q % 3] : kW1[q];
-            const int nb = map_node<DIM>(P, x + cx, y + cy);
+            const int nb = map_node<DIM>(geo, x + cx, y + cy);
             const double rq = nb >= 0 ? macro[nb] : P.ghost[-nb - 1].rho;
             gx += w * (double)cx * rq;
             gy += w * (double)cy * rq;
