@@ -7,9 +7,14 @@ One step = streaming with the predictor-corrector + Korteweg force + collision o
 whole lattice.  Prints one JSON line:
   value        MLUPS of the FP64 path (node updates per second / 1e6), state resident
                in HBM, timed between stream synchronisations;
-  fp32_store   the same with FP32 population storage;
+  fp32_store   the same with FP32 population storage and FP32 streaming arithmetic
+               (POND_FP32_STORE), and with FP32 storage but FP64 arithmetic
+               (POND_FP32_STORE_FP64_MATH);
   large        both precisions on a 2048 x 2048 droplet (state far larger than the
                caches), with the HBM bandwidth the algorithmic bytes imply;
+  configs      configs 1-3 (1D shock tube, the droplet for its full 20000 steps, the
+               1024 x 512 droplet-shock interaction) in both precisions: time per step,
+               MLUPS and the error of both FP32-storage forms against the FP64 path;
   serving      the batched-serving workload (64 seeded droplet jobs of mixed sides and
                temperatures, Poisson arrivals at 20/s, 5000 steps each) through the
                continuous-batching server and one job at a time: runs/s, p50/p99
@@ -20,7 +25,7 @@ whole lattice.  Prints one JSON line:
                rocprofv3 counter summary when it was taken on the current kernels;
   cpu_baseline the FP64 oracle on the host cores for a bounded number of steps.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-serving]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-serving] [--no-configs]
 """
 from __future__ import annotations
 
@@ -96,6 +101,55 @@ def serving(precision, stream, jobs_n, log_prefix):
             "speedup_runs_per_s": round(batched["runs_per_s"] / alone["runs_per_s"], 3)}
 
 
+def config_runs(stream):
+    """Configs 1-3 at their full step counts in both precisions: time per step, MLUPS,
+    status, and the FP32-store error against the FP64 path (relative L-infinity of rho,
+    u, E; velocities against max(|u|, U_ch))."""
+    import numpy as np
+    import torch
+
+    from paper_2002_09217_amd import pond, workloads as W
+    from paper_2002_09217_amd.serve import lattice_config
+
+    u_ch = float(np.sqrt(W.P_CR / W.RHO_CR))
+    out = {}
+    for key, case, steps in (("config1_shock_tube_D1Q3_1000", W.shock_tube(n=1000), 2000),
+                             ("config2_droplet_256", W.static_droplet(n=256), 20000),
+                             ("config3_droplet_shock_1024x512", W.droplet_shock(), 1500)):
+        res, fields = {}, {}
+        for name, prec in (("fp64", pond.FP64), ("fp32_store", pond.FP32_STORE),
+                           ("fp32_store_fp64_math", pond.FP32_STORE_FP64_MATH)):
+            lat = pond.Lattice(lattice_config(case, prec, -1, stream))
+            lat.init_fields(case.rho, case.u, case.T)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            try:
+                lat.step(steps)
+                status = "ok"
+            except pond.PondError as e:
+                status = str(e)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            done = lat.steps_done()
+            fields[name] = lat.moments()
+            lat.close()
+            res[name] = {"status": status, "steps": done, "us_per_step": round(1e6 * el / max(done, 1), 2),
+                         "mlups": round(case.N * done / el / 1e6, 1)}
+        for form in ("fp32_store", "fp32_store_fp64_math"):
+            if res[form]["status"] != "ok" or res["fp64"]["status"] != "ok":
+                continue
+            err = {}
+            for f in ("rho", "ux", "uy", "E"):
+                a, b = fields[form][f], fields["fp64"][f]
+                den = max(np.max(np.abs(b)), u_ch) if f in ("ux", "uy") else np.max(np.abs(b))
+                err[f] = float(np.max(np.abs(a - b)) / den)
+            res[form + "_vs_fp64_rel_linf"] = err
+        res["dt"] = case.params["dt"]
+        out[key] = res
+        log(f"bench: {key} {res}")
+    return out
+
+
 def cpu_baseline(case, budget_s):
     from oracle import core
     from tests.common import oracle_config
@@ -125,6 +179,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the batched-serving workload")
     ap.add_argument("--no-large", action="store_true", help="skip the 2048 x 2048 lattice")
     ap.add_argument("--serving-jobs", type=int, default=64)
+    ap.add_argument("--no-configs", action="store_true", help="skip the full-length runs of configs 1-3")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device-to-device copy of this many MiB (5 times), whose "
                          "FETCH_SIZE/WRITE_SIZE counters calibrate the HBM-traffic readings")
@@ -161,6 +216,9 @@ def main():
     log(f"bench: FP64 {mlups64:.1f} MLUPS, kernels (us): {kern64}")
     log(f"bench: FP32-store, warmup {args.warmup}, timed {args.steps} steps")
     t32, kern32, mon32 = gpu_run(case, pond.FP32_STORE, args.steps, args.warmup, stream.cuda_stream)
+    t32m, kern32m, _ = gpu_run(case, pond.FP32_STORE_FP64_MATH, args.steps, args.warmup, stream.cuda_stream)
+    mlups32m = N * args.steps / t32m / 1e6
+    log(f"bench: FP32-store with FP64 arithmetic {mlups32m:.1f} MLUPS, kernels (us): {kern32m}")
     mlups32 = N * args.steps / t32 / 1e6
     log(f"bench: FP32-store {mlups32:.1f} MLUPS, kernels (us): {kern32}")
 
@@ -177,6 +235,8 @@ def main():
                            "hbm_frac": round(bpn * ml * 1e6 / 1e9 / cost.HBM_PEAK_GBS, 4),
                            "kernels_us": {k: (round(v, 2) if isinstance(v, float) else v) for k, v in kb.items()}}
             log(f"bench: 2048^2 {name} {ml:.1f} MLUPS, kernels (us): {kb}")
+
+    configs = None if args.no_configs else config_runs(stream.cuda_stream)
 
     serve_out = None
     if not args.no_serving:
@@ -213,7 +273,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "2D static droplet D2Q9 256x256 periodic, T=0.9 T_cr, R=40, "
-                               "tanh width 4, kappa=0.0176, omega=1.5, dt=0.2",
+                               "tanh width 4, kappa=0.0176, omega=1.5, dt=0.1",
                    "n_pass": n_pass, "nodes": N, "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3),
                      "peak": round(cost.VALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
@@ -224,12 +284,15 @@ def main():
                      "traffic_source": traffic_src},
         "hbm": {"bytes_per_node_step": b64, "achieved_GBs": round(b64 * mlups64 * 1e6 / 1e9, 1),
                 "frac": round(b64 * mlups64 * 1e6 / 1e9 / cost.HBM_PEAK_GBS, 4)},
+        "fp32_store_fp64_math": {"value": round(mlups32m, 2), "unit": "MLUPS",
+                                 "ratio_vs_fp64": round(mlups32m / mlups64, 3), "bytes_per_node_step": b32},
         "fp32_store": {"value": round(mlups32, 2), "unit": "MLUPS", "ratio_vs_fp64": round(mlups32 / mlups64, 3),
                        "bytes_per_node_step": b32, "k_stream_us": round(kern32["k_stream"], 3)},
         "kernels_us": {"fp64": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in kern64.items()},
                        "fp32_store": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in kern32.items()}},
         "monitors_after": {"mass": mon64["mass"], "min_p": mon64["min_p"], "max_v_dt": mon64["max_v_dt"]},
         "large": large,
+        "configs": configs,
         "serving": serve_out,
         "cpu_baseline": cpu,
     }

@@ -53,7 +53,7 @@ typedef enum {
 } pond_status;
 
 enum { POND_BC_PERIODIC = 0, POND_BC_OUTFLOW = 1, POND_BC_INFLOW = 2 };
-enum { POND_FP64 = 0, POND_FP32_STORE = 1 };
+enum { POND_FP64 = 0, POND_FP32_STORE = 1, POND_FP32_STORE_FP64_MATH = 2 };
 
 typedef struct {
     int dim;                  /* 1 (D1Q3) or 2 (D2Q9), App. B                          */
@@ -70,9 +70,12 @@ typedef struct {
                                  k_scale < 0 switches the heat-flux correction off     */
     double dt;                /* time step in lattice units (dx = 1, App. D)            */
     int n_pass;               /* streaming passes of the predictor-corrector, >= 1      */
-    int precision;            /* POND_FP64, or POND_FP32_STORE: populations stored and
-                                 interpolated in FP32; moments, EoS, gauge, forcing and
-                                 collision in FP64                                      */
+    int precision;            /* POND_FP64; POND_FP32_STORE: populations stored and
+                                 streamed (interpolated) in FP32, with moments, EoS,
+                                 gauge, forcing and collision in FP64;
+                                 POND_FP32_STORE_FP64_MATH: stored in FP32, every
+                                 operation in FP64.  Both FP32 forms store each set as
+                                 its FP64 sum and FP32 deviations from W_q times it.  */
     int tile;                 /* tile shape of the streaming kernel: -1 = measure the
                                  compiled shapes on the first pond_init_fields and keep
                                  the fastest; k >= 0 = shape k (see pond_tile_info).

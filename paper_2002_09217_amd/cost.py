@@ -22,9 +22,11 @@ VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 
 def bytes_per_node_step(dim: int, fp32_store: bool) -> int:
+    """Read and write of one state: 2Q populations (FP32 storage: 2Q FP32 deviations
+    and the two FP64 set sums) and the five FP64 side fields."""
     q = 9 if dim == 2 else 3
-    pop = 4 if fp32_store else 8
-    return 2 * (2 * q * pop + 5 * 8)
+    pops = 2 * q * 4 + 2 * 8 if fp32_store else 2 * q * 8
+    return 2 * (pops + 5 * 8)
 
 
 def stream_bytes_per_node(dim: int, fp32_store: bool) -> int:
@@ -32,9 +34,9 @@ def stream_bytes_per_node(dim: int, fp32_store: bool) -> int:
     populations and the five side fields and writes the streamed-state moment planes
     (rho, u and the central moments: 18 planes in 2D, 6 in 1D) for the collision kernel."""
     q = 9 if dim == 2 else 3
-    pop = 4 if fp32_store else 8
+    pops = 2 * q * 4 + 2 * 8 if fp32_store else 2 * q * 8
     mom_planes = 18 if dim == 2 else 6
-    return 2 * q * pop + 5 * 8 + mom_planes * 8
+    return pops + 5 * 8 + mom_planes * 8
 
 
 def stream_flops_per_node(dim: int, n_pass: int) -> int:

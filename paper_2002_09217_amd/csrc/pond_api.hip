@@ -146,14 +146,20 @@ bool make_ghost(const pond_config &c, const double st[5], GhostFace &G)
     return true;
 }
 
+// bytes of one population buffer: 2Q planes, plus (FP32 storage) the two sum planes
+size_t pop_bytes(int dim, long long N, int fp32)
+{
+    const int Q = dim == 2 ? 9 : 3;
+    return fp32 ? (size_t)N * (2 * Q * sizeof(float) + 2 * sizeof(double)) : (size_t)N * 2 * Q * sizeof(double);
+}
+
 // device bytes of one lattice of the given shape (all buffers of pond_create)
 size_t footprint(int dim, long long N, int fp32)
 {
-    const int Q = dim == 2 ? 9 : 3;
     const int momPlanes = dim == 2 ? Layout<2>::kMomPlanes : Layout<1>::kMomPlanes;
-    const size_t pop = fp32 ? sizeof(float) : sizeof(double);
     const size_t mon = sizeof(double) * 8 * ((N + 255) / 256) + sizeof(double) * 8;
-    return (size_t)N * (2 * 2 * Q * pop + sizeof(double) * (2 * kSidePlanes + momPlanes + kKorPlanes + kAuxPlanes)) +
+    return 2 * pop_bytes(dim, N, fp32) +
+           (size_t)N * sizeof(double) * (2 * kSidePlanes + momPlanes + kKorPlanes + kAuxPlanes) +
            sizeof(int) * kFlagWords + sizeof(DevParams) + 2 * sizeof(SlotDesc) + mon;
 }
 
@@ -167,7 +173,8 @@ int validate(const pond_config *cfg)
     if (!(c.delta > 0.0 && c.delta <= 2.0 / 3.0)) return POND_E_INVALID;
     if (!(c.omega > 0.0 && c.omega < 2.0)) return POND_E_INVALID;
     if (c.n_pass < 1 || c.n_pass > 64 || !(c.dt > 0.0) || !(c.R > 0.0)) return POND_E_INVALID;
-    if (c.precision != POND_FP64 && c.precision != POND_FP32_STORE) return POND_E_INVALID;
+    if (c.precision != POND_FP64 && c.precision != POND_FP32_STORE && c.precision != POND_FP32_STORE_FP64_MATH)
+        return POND_E_INVALID;
     if (c.tile < -1 || c.tile >= stream_variants(c.dim)) return POND_E_INVALID;
     for (int a = 0; a < c.dim; ++a)
         for (int s = 0; s < 2; ++s)
@@ -297,7 +304,7 @@ int pond_footprint(const pond_config *cfg, unsigned long long *bytes)
     const int rc = validate(cfg);
     if (rc != POND_OK) return rc;
     const long long N = (long long)cfg->n[0] * (cfg->dim == 2 ? cfg->n[1] : 1);
-    *bytes = footprint(cfg->dim, N, cfg->precision == POND_FP32_STORE);
+    *bytes = footprint(cfg->dim, N, cfg->precision != POND_FP64);
     return POND_OK;
 }
 
@@ -318,8 +325,7 @@ int pond_create(const pond_config *cfg, pond_handle **out)
         h->cfg.n[2] = 1;
     }
     const int N = nx * ny;
-    const int Q = c.dim == 2 ? 9 : 3;
-    h->lc = LaunchCtx{c.dim, nx, ny, N, c.precision == POND_FP32_STORE ? 1 : 0, nullptr,
+    h->lc = LaunchCtx{c.dim, nx, ny, N, c.precision == POND_FP64 ? 0 : (c.precision == POND_FP32_STORE ? 1 : 2), nullptr,
                       c.tile < 0 ? 0 : c.tile};
     h->tuned = c.tile >= 0;
 
@@ -349,7 +355,7 @@ int pond_create(const pond_config *cfg, pond_handle **out)
                 return POND_E_INVALID;
             }
 
-    const size_t popb = (size_t)2 * Q * N * (h->lc.fp32 ? sizeof(float) : sizeof(double));
+    const size_t popb = pop_bytes(c.dim, N, h->lc.fp32);
     const int momPlanes = c.dim == 2 ? Layout<2>::kMomPlanes : Layout<1>::kMomPlanes;
     auto alloc = [&](void **p, size_t bytes) {
         if (rc != POND_OK) return;

@@ -77,7 +77,7 @@ int rebuild(pond_batch *b)
     for (int i = 0; i < M; ++i) order[i] = i;
     auto key = [&](int i) {
         const pond_handle *h = b->members[i];
-        return (h->lc.dim * 2 + h->lc.fp32) * 16 + h->lc.stream_tile;
+        return (h->lc.dim * 3 + h->lc.fp32) * 16 + h->lc.stream_tile;
     };
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return key(x) < key(y); });
     if (M > b->cap) {

@@ -17,6 +17,20 @@ constexpr double kTL = 1.0 / 3.0;
 constexpr double kInvTL = 3.0;
 constexpr double kW1[3] = {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0};
 
+// Weight of direction q (tensor product of W in 2D).
+template <int DIM>
+__device__ __forceinline__ double weight_q(int q)
+{
+    return DIM == 2 ? kW1[q / 3] * kW1[q % 3] : kW1[q];
+}
+
+// FP32 storage of the populations: each set is kept as its FP64 sum (one plane after
+// the 2Q population planes, f then g) and the FP32 deviations f_q - W_q sum.  The
+// conserved sums (rho and 2 rho E) keep FP64 precision; FP32 rounding only touches
+// the departure from W_q sum, which is small near equilibrium.
+template <typename PopT>
+constexpr bool kDeviationStore = sizeof(PopT) == 4;
+
 // Device buffers reached through a descriptor are generic pointers to the compiler;
 // casting them to the global address space gives global (not flat) loads and stores.
 #define POND_GLOBAL __attribute__((address_space(1)))

@@ -31,7 +31,9 @@ struct DevParams {
 
 // ---------------------------------------------------------------------------
 // Plane layout (structure of arrays, one plane of N values per entry).
-//   state:  f[Q], g[Q]       populations, PopT (double or float), node's own gauge
+//   state:  f[Q], g[Q]       populations, PopT (double or float), node's own gauge;
+//                            with float: deviations f_q - W_q sum_f, g_q - W_q sum_g,
+//                            followed by the two sum planes in double
 //           side[5]          u_x, u_y, theta (gauge), F_x, F_y  (double)
 //   mom:    the streamed state after the predictor-corrector, gauge free:
 //           rho, u_x, u_y, then the central moments about u of f (those not fixed
@@ -94,7 +96,8 @@ struct DevState {
 // ---------------------------------------------------------------------------
 struct LaunchCtx {
     int dim, nx, ny, N;
-    int fp32;           // populations stored as float
+    int fp32;           // 0: FP64; 1: populations stored as float, streamed in float;
+                        // 2: stored as float, all arithmetic in double
     hipStream_t st;
     int stream_tile;    // tile-shape variant of the streaming kernel
     // when set, the step kernels are launched with these start/stop events, which the

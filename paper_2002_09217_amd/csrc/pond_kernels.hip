@@ -145,10 +145,13 @@ __global__ void __launch_bounds__(SPLIT *TX *TY)
     // memory latency of the fill is paid once per pair.
     constexpr int SETS_PER_ITEM = SPLIT == 2 ? 1 : 2;
     constexpr int NITEMS = LN * SPLIT;
+    constexpr bool dev = kDeviationStore<PopT>;
+    const POND_GLOBAL double *__restrict__ fsum = (const POND_GLOBAL double *)(fpop + (size_t)2 * Q * N);
     struct Raw {
         int li, set0, node;
         double ux, uy, th;
         PopT p[SETS_PER_ITEM * Q];
+        double sum[SETS_PER_ITEM];   // FP32 storage: the set's sum
     };
     auto load_raw = [&](int it, Raw &r) {
         r.li = SPLIT == 2 ? it >> 1 : it;
@@ -164,6 +167,7 @@ __global__ void __launch_bounds__(SPLIT *TX *TY)
                 const POND_GLOBAL PopT *src = fpop + (size_t)(r.set0 + k) * Q * N;
 #pragma unroll
                 for (int q = 0; q < Q; ++q) r.p[k * Q + q] = src[(size_t)q * N + r.node];
+                if (dev) r.sum[k] = fsum[(size_t)(r.set0 + k) * N + r.node];
             }
         } else {
             const POND_GLOBAL GhostFace &G = P.ghost[-r.node - 1];
@@ -173,8 +177,14 @@ __global__ void __launch_bounds__(SPLIT *TX *TY)
 #pragma unroll
             for (int k = 0; k < SETS_PER_ITEM; ++k) {
                 const POND_GLOBAL double *src = r.set0 + k == 0 ? G.f : G.g;
+                double sum = 0.0;
+                if (dev) {
 #pragma unroll
-                for (int q = 0; q < Q; ++q) r.p[k * Q + q] = (PopT)src[q];
+                    for (int q = 0; q < Q; ++q) sum += src[q];
+                }
+                r.sum[k] = sum;
+#pragma unroll
+                for (int q = 0; q < Q; ++q) r.p[k * Q + q] = (PopT)(src[q] - (dev ? weight_q<DIM>(q) * sum : 0.0));
             }
         }
     };
@@ -183,8 +193,11 @@ __global__ void __launch_bounds__(SPLIT *TX *TY)
 #pragma unroll
         for (int k = 0; k < SETS_PER_ITEM; ++k) {
             const int set = r.set0 + k;
-            double m[NF];
-            moments_about<DIM>(r.p + k * Q, r.ux - rx, r.uy - ry, s, m);
+            double fr[Q], m[NF];
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+                fr[q] = dev ? weight_q<DIM>(q) * r.sum[k] + (double)r.p[k * Q + q] : (double)r.p[k * Q + q];
+            moments_about<DIM>(fr, r.ux - rx, r.uy - ry, s, m);
 #pragma unroll
             for (int i = 0; i < NF; ++i)
                 lds[SPLIT == 2 ? (i * LN + r.li) * 2 + set : (set * NF + i) * LN + r.li] = (LdsT)m[i];
@@ -415,8 +428,9 @@ static hipError_t launch_stream_v(const LaunchCtx &c, const SlotDesc *slots, int
 
 hipError_t launch_stream(const LaunchCtx &c, const SlotDesc *slots, int nslots, int tiles)
 {
-    return c.fp32 ? launch_stream_v<float, float>(c, slots, nslots, tiles)
-                  : launch_stream_v<double, double>(c, slots, nslots, tiles);
+    if (c.fp32 == 1) return launch_stream_v<float, float>(c, slots, nslots, tiles);
+    if (c.fp32 == 2) return launch_stream_v<float, double>(c, slots, nslots, tiles);
+    return launch_stream_v<double, double>(c, slots, nslots, tiles);
 }
 
 // ---------------------------------------------------------------------------
@@ -565,6 +579,28 @@ __device__ __forceinline__ int classify(const Geo &g, int x, int y, int &cx, int
 // f sets of the tile's nodes, the second half on their g sets (and the heat-flux
 // correction, which only g uses); the stencil stages use all lanes of the block.
 // ---------------------------------------------------------------------------
+// write the post-collision populations of one set (0 = f, 1 = g) of a node: as they
+// are, or (FP32 storage) as the FP64 sum and the FP32 deviations from W_q sum
+template <int DIM, typename PopT>
+__device__ __forceinline__ void store_set(POND_GLOBAL PopT *pop, size_t N, int node, int set,
+                                          const double *post)
+{
+    constexpr int Q = Layout<DIM>::Q;
+    POND_GLOBAL PopT *out = pop + (size_t)set * Q * N;
+    if constexpr (kDeviationStore<PopT>) {
+        double sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) sum += post[q];
+        POND_GLOBAL double *sums = (POND_GLOBAL double *)(pop + (size_t)2 * Q * N);
+        sums[(size_t)set * N + node] = sum;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) out[(size_t)q * N + node] = (PopT)(post[q] - weight_q<DIM>(q) * sum);
+    } else {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) out[(size_t)q * N + node] = (PopT)post[q];
+    }
+}
+
 template <int DIM> struct CollideTile;
 template <> struct CollideTile<2> { static constexpr int TX = 16, TY = 8; };
 template <> struct CollideTile<1> { static constexpr int TX = 256, TY = 1; };
@@ -856,6 +892,7 @@ __global__ void __launch_bounds__(2 * TX *TY)
         double sx[3], sy[3] = {0.0, 0.0, 0.0};
         source_axis(F[0] * dt * i_rho, i_theta, i_s, sx);
         if (DIM == 2) source_axis(F[1] * dt * i_rho, i_theta, i_s, sy);
+        double post[Q];
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int k = DIM == 2 ? q / 3 : q;
@@ -863,8 +900,9 @@ __global__ void __launch_bounds__(2 * TX *TY)
             const double wk = kW1[k], wl = DIM == 2 ? kW1[l] : 1.0;
             const double Sq = DIM == 2 ? rho * (wk * sy[l] + sx[k] * wl + sx[k] * sy[l]) : rho * sx[k];
             const double feq = rho * (wk * wl);
-            fout[(size_t)q * N + node] = (PopT)(pop[q] + P.omega * (feq - pop[q]) + Sq);
+            post[q] = pop[q] + P.omega * (feq - pop[q]) + Sq;
         }
+        store_set<DIM, PopT>(fout, N, node, 0, post);
         side_out[kSideUx * N + node] = u[0];
         side_out[kSideTh * N + node] = theta;
         side_out[kSideFx * N + node] = F[0];
@@ -923,7 +961,7 @@ __global__ void __launch_bounds__(2 * TX *TY)
     for (int a = 0; a < DIM; ++a) work += 2.0 * uh[a] * F[a];
     const double c_uc = 0.5 * kInvTL * rho * i_p;          // rho / (2 p T_L)
     const double c_v2 = 0.5 * rho * i_p;                   // rho / (2 p)
-    POND_GLOBAL PopT *gout = fout + (size_t)Q * N;
+    double post[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const double c[2] = {DIM == 2 ? (double)(q / 3 - 1) : (double)(q - 1),
@@ -944,8 +982,9 @@ __global__ void __launch_bounds__(2 * TX *TY)
             for (int b = 0; b < DIM; ++b) t2 += Nm[a][b] * (v[a] * v[b] - (a == b ? Pr : 0.0) - u[a] * u[b]);
         const double geq = wq * (2.0 * rho * E + t1 + t2);
         const double psi = wq * (1.0 + c_uc * uc * uc - c_v2 * v2 + 0.5 * (double)DIM);
-        gout[(size_t)q * N + node] = (PopT)(pop[q] + P.omega * (geq - pop[q]) + (M0 + work) * psi * dt);
+        post[q] = pop[q] + P.omega * (geq - pop[q]) + (M0 + work) * psi * dt;
     }
+    store_set<DIM, PopT>(fout, N, node, 1, post);
 }
 
 template <int DIM, typename PopT>
@@ -1092,6 +1131,7 @@ __global__ void k_macro(const DevParams *__restrict__ Pp, const PopT *__restrict
     const size_t N = P.N;
     double r = 0.0;
     for (int q = 0; q < Q; ++q) r += (double)fpop[q * N + n];
+    if (kDeviationStore<PopT>) r += ((const double *)(fpop + (size_t)2 * Q * N))[n];
     const double hx = side[kSideUx * N + n] + side[kSideFx * N + n] * P.dt / (2.0 * r);
     const double hy = DIM == 2 ? side[kSideUy * N + n] + side[kSideFy * N + n] * P.dt / (2.0 * r) : 0.0;
     const double pr = r * side[kSideTh * N + n] * kTL;

@@ -21,7 +21,7 @@ STATUS = {
     -4: "POND_E_PRESSURE", -5: "POND_E_NONFINITE", -6: "POND_E_HALO", -7: "POND_E_STATE",
 }
 BC_PERIODIC, BC_OUTFLOW, BC_INFLOW = 0, 1, 2
-FP64, FP32_STORE = 0, 1
+FP64, FP32_STORE, FP32_STORE_FP64_MATH = 0, 1, 2
 
 # kernel ids of pond_time_kernel
 K_STREAM, K_FORCE_COLLIDE = 0, 1

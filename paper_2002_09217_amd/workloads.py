@@ -8,9 +8,10 @@ oracle's Maxwell and Rankine-Hugoniot routines.  Both the oracle and the HIP pat
 take their inputs from here.
 
 Shared choices (the paper gives no grid sizes, time step, omega or kappa):
-  a = 2/49, b = 2/21, R = 1 (main text), delta = 1/3, dt = 0.2, two streaming passes,
-  omega = 1.0 for the shock cases and 1.5 for the droplets, kappa = 0.0176 for
-  droplets (a 10-90 % interface width of about 4.4 nodes at T/T_cr = 0.9).
+  a = 2/49, b = 2/21, R = 1 (main text), delta = 1/3, two streaming passes,
+  dt = 0.2 for the shock cases and 0.1 for the droplets (DT_DROPLET), omega = 1.0 for
+  the shock cases and 1.5 for the droplets, kappa = 0.0176 for droplets (a 10-90 %
+  interface width of about 4.4 nodes at T/T_cr = 0.9).
 """
 from __future__ import annotations
 
@@ -27,6 +28,14 @@ with open(_DATA) as _fh:
 A, B, R = CONST["a"], CONST["b"], CONST["R"]
 RHO_CR, T_CR, P_CR = CONST["rho_cr"], CONST["T_cr"], CONST["p_cr"]
 DT = 0.2
+# Time step of the droplet workloads.  At dt = 0.2 the 256 x 256 droplet at 0.9 T_cr
+# grows a slow mode and leaves the EoS domain after ~15000 steps; at dt = 0.1 it holds
+# for the full 20000 steps (omega = 1.5 or 1.0).  Below 0.9 T_cr (the serving jobs go
+# down to 0.85 T_cr, liquid/vapour density ratio ~7) dt = 0.2 loses positivity of p
+# within a few hundred steps, dt = 0.1 holds on single droplets.  Merging droplets at
+# T <= 0.86 T_cr can still leave the EoS domain; such jobs end with an error status,
+# the same alone and batched.
+DT_DROPLET = 0.1
 KAPPA_DROPLET = 0.0176
 PERIODIC, OUTFLOW, INFLOW = 0, 1, 2
 
@@ -96,7 +105,7 @@ def static_droplet(n=256, t_over_tcr=0.9, radius=40.0, width=4.0, steps=20000, *
     rho = droplet_field(n, n, rv, rl, [(n / 2, n / 2)], [radius], width)
     N = n * n
     return Case(name=f"droplet{n}", dim=2, n=(n, n),
-                params=base_params(omega=1.5, kappa=KAPPA_DROPLET, **kw),
+                params=base_params(**{"omega": 1.5, "kappa": KAPPA_DROPLET, "dt": DT_DROPLET, **kw}),
                 rho=rho, u=np.zeros((2, N)), T=np.full(N, t_over_tcr * T_CR), steps=steps,
                 meta=dict(rho_v=rv, rho_l=rl, radius=radius, t_over_tcr=t_over_tcr))
 
@@ -159,14 +168,6 @@ def perturbed(nx, ny, seed, dim=2, rho0=2.0, t_over_tcr=1.05, u0=(0.0, 0.0), amp
                 rho=rho.ravel(), u=u, T=T.ravel(), meta=dict(seed=seed))
 
 
-# time step of the serving jobs: down to T = 0.85 T_cr the liquid/vapour density ratio
-# is ~7 and the scheme at dt = 0.2 loses positivity of p within a few hundred steps
-# (measured on single droplets: dt = 0.2 holds from T = 0.9 T_cr, dt = 0.1 over
-# 0.85-0.89 T_cr).  Merging droplets at T <= 0.86 T_cr can still leave the EoS domain;
-# such jobs end with an error status, the same alone and batched.
-DT_SERVING = 0.1
-
-
 def serving_jobs(count=64, seed=0, steps=5000, rate=20.0, sides=(64, 128, 256, 512)):
     """Batched-serving workload: seeded D2Q9 droplet jobs with sides drawn from `sides`,
     T/T_cr uniform in [0.85, 1.10] (snapped to the 0.005 grid of the coexistence table),
@@ -190,7 +191,7 @@ def serving_jobs(count=64, seed=0, steps=5000, rate=20.0, sides=(64, 128, 256, 5
         rho = droplet_field(side, side, rv, rl, [tuple(c) for c in centres], list(radii), 4.0)
         N = side * side
         case = Case(name=f"job{j}", dim=2, n=(side, side),
-                    params=base_params(omega=1.5, kappa=KAPPA_DROPLET, dt=DT_SERVING),
+                    params=base_params(omega=1.5, kappa=KAPPA_DROPLET, dt=DT_DROPLET),
                     rho=rho, u=np.zeros((2, N)), T=np.full(N, tr * T_CR), steps=steps,
                     meta=dict(job=j, t_over_tcr=tr, droplets=nd))
         jobs.append((t, case))

@@ -23,7 +23,7 @@ def _lat(case, tile, precision=pond.FP64):
 
 def _mix():
     """(case, tile, precision) of the batch members: sizes spanning one to many tiles
-    with ragged tails, both dimensions, both precisions, two tile shapes."""
+    with ragged tails, both dimensions, all three precisions, two tile shapes."""
     return [
         (W.perturbed(40, 36, seed=1, kappa=0.0176, u0=(0.05, -0.03)), 0, pond.FP64),
         (W.static_droplet(n=64, radius=14.0), 0, pond.FP64),
@@ -32,6 +32,7 @@ def _mix():
         (W.perturbed(300, 1, seed=4, dim=1, kappa=0.0176), 0, pond.FP64),
         (W.perturbed(7, 1, seed=5, kappa=0.0176), 0, pond.FP64),
         (W.perturbed(129, 1, seed=6, dim=1), 1, pond.FP32_STORE),
+        (W.perturbed(50, 30, seed=8, kappa=0.0176), 0, pond.FP32_STORE_FP64_MATH),
     ]
 
 

@@ -80,6 +80,18 @@ def test_fp32_storage_within_1e4(which):
     _check(case, 100, tol=1e-4, precision=pond.FP32_STORE)
 
 
+@pytest.mark.parametrize("which", ["perturbed", "droplet", "shock_tube"])
+def test_fp32_storage_with_fp64_arithmetic_within_1e6(which):
+    if which == "perturbed":
+        case = W.perturbed(40, 36, seed=22, kappa=0.0176, u0=(0.1, -0.05))
+    elif which == "droplet":
+        case = W.static_droplet(n=64, radius=14.0)
+    else:
+        case = W.shock_tube(n=1000)
+    fields = ("rho", "ux", "E", "T", "p") if case.dim == 1 else ("rho", "ux", "uy", "E", "T", "p")
+    _check(case, 100, tol=1e-6, precision=pond.FP32_STORE_FP64_MATH, fields=fields)
+
+
 @pytest.mark.parametrize("tile", range(5))
 def test_every_stream_tile_shape_2d(tile):
     case = W.perturbed(70, 45, seed=30 + tile, kappa=0.0176, u0=(0.1, -0.2))
