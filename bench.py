@@ -289,7 +289,9 @@ def main():
         "fp32_store": {"value": round(mlups32, 2), "unit": "MLUPS", "ratio_vs_fp64": round(mlups32 / mlups64, 3),
                        "bytes_per_node_step": b32, "k_stream_us": round(kern32["k_stream"], 3)},
         "kernels_us": {"fp64": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in kern64.items()},
-                       "fp32_store": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in kern32.items()}},
+                       "fp32_store": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in kern32.items()},
+                       "fp32_store_fp64_math": {k: (round(v, 3) if isinstance(v, float) else v)
+                                                for k, v in kern32m.items()}},
         "monitors_after": {"mass": mon64["mass"], "min_p": mon64["min_p"], "max_v_dt": mon64["max_v_dt"]},
         "large": large,
         "configs": configs,
