@@ -126,6 +126,24 @@ int pond_tile_info(const pond_handle *h, int *out);
 /* Release everything owned by h.  NULL is accepted. */
 int pond_destroy(pond_handle *h);
 
+/* Checkpoint / resume.  A checkpoint holds the current state (the stored populations and
+ * side fields of the last completed step, in the handle's precision), the step count,
+ * the streaming tile shape in use and the configuration it belongs to.  Loading it into a
+ * handle of the same configuration and stepping on gives bitwise the results the saving
+ * handle gets (the handle adopts the checkpoint's tile shape for that).
+ *
+ * pond_checkpoint_size: bytes of a checkpoint of h (depends only on the configuration).
+ * pond_save: write the checkpoint of h's current state into the caller-owned host buffer
+ *   buf of at least that many bytes.  Errors: POND_E_INVALID (NULL, buffer too small),
+ *   POND_E_STATE (not initialised).
+ * pond_load: make the state of buf current in h, as if h had just completed the saved
+ *   number of steps; clears the error state.  Errors: POND_E_INVALID (NULL, buffer too
+ *   small, not a checkpoint, or saved from another lattice shape, precision or set of
+ *   parameters), POND_E_STATE (h is a member of a batch). */
+int pond_checkpoint_size(const pond_handle *h, unsigned long long *bytes);
+int pond_save(pond_handle *h, void *buf, unsigned long long bytes);
+int pond_load(pond_handle *h, const void *buf, unsigned long long bytes);
+
 /* Measurement: launch kernel `which` (0 = streaming with the predictor-corrector,
  * 1 = Korteweg force, closure and collision) `reps` times back to back on the
  * handle's stream on the current state and return the mean duration per launch in

@@ -81,6 +81,12 @@ class VdW:
         R = self.R
         return self.Cv + R * R * T / (R * T - 2.0 * self.a * rho * (1.0 - self.b * rho) ** 2)
 
+    # Isentrope through (rho0, T0): with constant C_v the entropy is
+    # s = C_v ln T + R ln(v - b) + const (first law with e = C_v T - a/v), so
+    # T (v - b)^(R/C_v) is constant along it.
+    def T_isentrope(self, rho, rho0, T0):
+        return T0 * ((1.0 / rho0 - self.b) / (1.0 / rho - self.b)) ** (self.R / self.Cv)
+
     # App. A: sound speed, general relation and the van der Waals closed form
     def sound_general(self, rho, T):
         return math.sqrt(self.dp_drho_T(rho, T) + T / (rho * rho * self.Cv) * self.dp_dT_rho(rho, T) ** 2)

@@ -523,6 +523,118 @@ int pond_destroy(pond_handle *h)
     return POND_OK;
 }
 
+namespace {
+// checkpoint layout: header, then the population buffer, then the kSidePlanes side planes
+struct CheckpointHeader {
+    char magic[8];          // "PONDCKP1"
+    int dim, n[3], precision, tile, n_pass, pad_;
+    int bc[3][2];
+    long long steps;
+    double a, b, R, delta, omega, kappa, k_scale, dt;
+    double inflow[3][2][5];
+    unsigned long long pop_bytes, side_bytes;
+};
+
+CheckpointHeader make_header(const pond_handle *h)
+{
+    CheckpointHeader H;
+    std::memset(&H, 0, sizeof H);
+    std::memcpy(H.magic, "PONDCKP1", 8);
+    const pond_config &c = h->cfg;
+    H.dim = c.dim;
+    for (int a = 0; a < 3; ++a) H.n[a] = c.n[a];
+    H.precision = c.precision;
+    H.tile = h->lc.stream_tile;
+    H.n_pass = c.n_pass;
+    std::memcpy(H.bc, c.bc, sizeof H.bc);
+    H.steps = h->steps;
+    H.a = c.a;
+    H.b = c.b;
+    H.R = c.R;
+    H.delta = c.delta;
+    H.omega = c.omega;
+    H.kappa = c.kappa;
+    H.k_scale = c.k_scale;
+    H.dt = c.dt;
+    std::memcpy(H.inflow, c.inflow, sizeof H.inflow);
+    H.pop_bytes = pop_bytes(c.dim, h->lc.N, h->lc.fp32);
+    H.side_bytes = sizeof(double) * kSidePlanes * (size_t)h->lc.N;
+    return H;
+}
+
+// same lattice and parameters (tile shape and step count may differ)
+bool same_config(const CheckpointHeader &x, const CheckpointHeader &y)
+{
+    return std::memcmp(x.magic, y.magic, 8) == 0 && x.dim == y.dim && std::memcmp(x.n, y.n, sizeof x.n) == 0 &&
+           x.precision == y.precision && x.n_pass == y.n_pass && std::memcmp(x.bc, y.bc, sizeof x.bc) == 0 &&
+           x.a == y.a && x.b == y.b && x.R == y.R && x.delta == y.delta && x.omega == y.omega &&
+           x.kappa == y.kappa && x.k_scale == y.k_scale && x.dt == y.dt &&
+           std::memcmp(x.inflow, y.inflow, sizeof x.inflow) == 0 && x.pop_bytes == y.pop_bytes &&
+           x.side_bytes == y.side_bytes;
+}
+} // namespace
+
+int pond_checkpoint_size(const pond_handle *h, unsigned long long *bytes)
+{
+    if (!h || !bytes) return POND_E_INVALID;
+    const CheckpointHeader H = make_header(h);
+    *bytes = sizeof H + H.pop_bytes + H.side_bytes;
+    return POND_OK;
+}
+
+int pond_save(pond_handle *h, void *buf, unsigned long long bytes)
+{
+    if (!h) return POND_E_INVALID;
+    if (!buf) return handle_fail(h, POND_E_INVALID, "NULL buffer");
+    if (!h->initialised) return handle_fail(h, POND_E_STATE, "not initialised");
+    const CheckpointHeader H = make_header(h);
+    if (bytes < sizeof H + H.pop_bytes + H.side_bytes)
+        return handle_fail(h, POND_E_INVALID, "checkpoint buffer of %llu bytes, %llu needed", bytes,
+                           (unsigned long long)(sizeof H + H.pop_bytes + H.side_bytes));
+    char *p = (char *)buf;
+    std::memcpy(p, &H, sizeof H);
+    HIP_TRY(h, hipMemcpyAsync(p + sizeof H, h->ds.pop[h->cur], H.pop_bytes, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(p + sizeof H + H.pop_bytes, h->ds.side[h->cur], H.side_bytes, hipMemcpyDeviceToHost,
+                              h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return POND_OK;
+}
+
+int pond_load(pond_handle *h, const void *buf, unsigned long long bytes)
+{
+    if (!h) return POND_E_INVALID;
+    if (!buf) return handle_fail(h, POND_E_INVALID, "NULL buffer");
+    if (h->batch) return handle_fail(h, POND_E_STATE, "handle is a member of a batch");
+    CheckpointHeader S;
+    if (bytes < sizeof S) return handle_fail(h, POND_E_INVALID, "buffer shorter than a checkpoint header");
+    std::memcpy(&S, buf, sizeof S);
+    const CheckpointHeader H = make_header(h);
+    if (!same_config(S, H)) return handle_fail(h, POND_E_INVALID, "not a checkpoint of this configuration");
+    if (bytes < sizeof S + S.pop_bytes + S.side_bytes)
+        return handle_fail(h, POND_E_INVALID, "checkpoint truncated");
+    if (S.tile < 0 || S.tile >= stream_variants(h->lc.dim))
+        return handle_fail(h, POND_E_INVALID, "checkpoint tile shape out of range");
+    const char *p = (const char *)buf;
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    HIP_TRY(h, hipMemcpy(h->ds.pop[0], p + sizeof S, S.pop_bytes, hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(h->ds.side[0], p + sizeof S + S.pop_bytes, S.side_bytes, hipMemcpyHostToDevice));
+    if (S.tile != h->lc.stream_tile) {
+        drop_graphs(h);
+        h->lc.stream_tile = S.tile;
+        const int rc = handle_update_desc(h);
+        if (rc != POND_OK) return rc;
+    }
+    h->tuned = true;
+    h->cur = 0;
+    h->steps = S.steps;
+    h->failed = false;
+    h->initialised = true;
+    HIP_TRY(h, launch_reset_flags(h->lc, h->ds.flags));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    std::snprintf(h->msg, sizeof h->msg, "ok");
+    return POND_OK;
+}
+
 int pond_time_kernel(pond_handle *h, int which, int reps, double *avg_us)
 {
     if (!h || !avg_us || reps < 1 || which < 0 || which > 1) return POND_E_INVALID;

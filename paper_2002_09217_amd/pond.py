@@ -31,7 +31,7 @@ EXPORTED = ["pond_create", "pond_init_fields", "pond_step", "pond_moments", "pon
             "pond_steps_done", "pond_last_error", "pond_destroy", "pond_time_kernel",
             "pond_step_timed", "pond_tile_info", "pond_footprint", "pond_batch_create",
             "pond_batch_add", "pond_batch_remove", "pond_batch_step", "pond_batch_size",
-            "pond_batch_destroy"]
+            "pond_batch_destroy", "pond_checkpoint_size", "pond_save", "pond_load"]
 
 
 class pond_config(ctypes.Structure):
@@ -97,6 +97,9 @@ def load(path: str = LIB_PATH):
     L.pond_batch_step.argtypes = [hp, ctypes.c_int]
     L.pond_batch_size.argtypes = [hp, ctypes.POINTER(ctypes.c_int)]
     L.pond_batch_destroy.argtypes = [hp]
+    L.pond_checkpoint_size.argtypes = [hp, ctypes.POINTER(ctypes.c_ulonglong)]
+    L.pond_save.argtypes = [hp, ctypes.c_void_p, ctypes.c_ulonglong]
+    L.pond_load.argtypes = [hp, ctypes.c_void_p, ctypes.c_ulonglong]
     for name in EXPORTED:
         getattr(L, name).restype = getattr(L, name).restype or ctypes.c_int
     L.pond_last_error.restype = ctypes.c_char_p
@@ -237,6 +240,20 @@ class Lattice:
 
     def last_error(self) -> str:
         return load().pond_last_error(self._h).decode()
+
+    def save(self) -> bytes:
+        """Checkpoint of the current state (pond_save)."""
+        n = ctypes.c_ulonglong()
+        self._check(load().pond_checkpoint_size(self._h, ctypes.byref(n)), "pond_checkpoint_size")
+        buf = ctypes.create_string_buffer(n.value)
+        self._check(load().pond_save(self._h, buf, n.value), "pond_save")
+        return buf.raw
+
+    def load(self, data: bytes):
+        """Make a checkpoint the current state (pond_load)."""
+        buf = ctypes.create_string_buffer(bytes(data), len(data))
+        self._check(load().pond_load(self._h, buf, len(data)), "pond_load")
+        return self
 
     def close(self):
         if self._h is not None:

@@ -5,6 +5,7 @@ from __future__ import annotations
 import numpy as np
 
 from oracle import core
+from oracle.thermo import VdW
 from paper_2002_09217_amd import pond
 
 # relative velocity errors are taken against max(|u|, U_ch), U_ch = sqrt(p_cr/rho_cr)
@@ -60,3 +61,25 @@ def rel_err(a, b, field):
 
 def compare(gpu, ref, fields=("rho", "ux", "uy", "E", "T", "p")):
     return {f: rel_err(gpu[f], ref[f], f) for f in fields}
+
+
+def pulse_speed(sim_factory, rho0, Tr, n=800, sigma=8.0, amp=1e-3, dt=0.2, times=(150.0, 300.0)):
+    """Speed of the right-moving half of a Gaussian isentropic density pulse: the
+    displacement of its centroid (a window of +-3 sigma around its peak) between two
+    times.  sim_factory(rho, T, dt) returns an object with step(n) and moments()."""
+    x = np.arange(n, dtype=float)
+    x0 = n / 2
+    rho = rho0 * (1.0 + amp * np.exp(-0.5 * ((x - x0) / sigma) ** 2))
+    T = VdW().T_isentrope(rho, rho0, Tr * VdW().T_cr)
+    sim = sim_factory(rho, T, dt)
+    pos, done = [], 0
+    for t in times:
+        nsteps = int(round(t / dt))
+        sim.step(nsteps - done)
+        done = nsteps
+        d = sim.moments()["rho"] - rho0
+        right = x > x0 + 2 * sigma
+        xp = x[right][np.argmax(d[right])]
+        win = np.abs(x - xp) < 3 * sigma
+        pos.append(np.sum(x[win] * d[win]) / np.sum(d[win]))
+    return (pos[1] - pos[0]) / (times[1] - times[0])

@@ -1,0 +1,68 @@
+"""Checkpoint / resume through the C ABI: a lattice saved mid-run and loaded into a fresh
+handle (or back into the same one after it moved on) continues bitwise as the
+uninterrupted run, in every precision; checkpoints of another configuration are refused."""
+import numpy as np
+import pytest
+
+from paper_2002_09217_amd import pond, workloads as W
+from tests.common import pond_config
+
+pytestmark = pytest.mark.gpu
+
+
+def _fields(m):
+    return np.concatenate([m[k] for k in ("rho", "ux", "uy", "T", "p", "E")])
+
+
+@pytest.mark.parametrize("precision", [pond.FP64, pond.FP32_STORE, pond.FP32_STORE_FP64_MATH])
+def test_resume_is_bitwise(precision):
+    case = W.perturbed(50, 34, seed=4, kappa=0.0176, u0=(0.1, 0.05))
+    a = pond.Lattice(pond_config(case, precision=precision, tile=-1))
+    a.init_fields(case.rho, case.u, case.T)
+    a.step(13)
+    ck = a.save()
+    a.step(21)
+    ref = _fields(a.moments())
+    # a fresh handle with another tile shape adopts the saved one
+    info = a.tile_info()
+    b = pond.Lattice(pond_config(case, precision=precision, tile=(info["variant"] + 1) % info["variants"]))
+    b.load(ck)
+    assert b.steps_done() == 13 and b.tile_info()["variant"] == info["variant"]
+    b.step(21)
+    assert b.steps_done() == 34
+    assert np.array_equal(_fields(b.moments()), ref)
+    # rewinding the original handle
+    a.load(ck)
+    assert a.steps_done() == 13
+    a.step(21)
+    assert np.array_equal(_fields(a.moments()), ref)
+    a.close()
+    b.close()
+
+
+def test_mismatched_checkpoints_refused_and_fresh_handle_resumes():
+    case = W.shock_tube(n=300)
+    a = pond.Lattice(pond_config(case, tile=0))
+    a.init_fields(case.rho, case.u, case.T)
+    a.step(5)
+    ck = a.save()
+    other = W.shock_tube(n=301)
+    b = pond.Lattice(pond_config(other, tile=0))
+    with pytest.raises(pond.PondError) as err:
+        b.load(ck)
+    assert err.value.code == -1
+    c = pond.Lattice(pond_config(case, precision=pond.FP32_STORE, tile=0))
+    with pytest.raises(pond.PondError) as err:
+        c.load(ck)
+    assert err.value.code == -1
+    with pytest.raises(pond.PondError) as err:
+        a.load(ck[: len(ck) // 2])
+    assert err.value.code == -1
+    # a handle that never ran can resume from a checkpoint directly
+    d = pond.Lattice(pond_config(case, tile=0))
+    d.load(ck)
+    d.step(7)
+    a.step(7)
+    assert np.array_equal(_fields(d.moments()), _fields(a.moments()))
+    for x in (a, b, c, d):
+        x.close()

@@ -9,13 +9,17 @@
 * the ideal-gas limit (a = b = 0) reproduces the exact Riemann solution (main text);
 * the shear viscosity is mu = (1/omega - 1/2) p dt (eq. 14);
 * a van der Waals slab at T < T_cr relaxes to Maxwell's coexistence densities,
-  independently of delta and of a uniform advection (main text, Fig. 2).
+  independently of delta and of a uniform advection (main text, Fig. 2);
+* a small isentropic pressure pulse travels at the adiabatic van der Waals sound speed
+  of App. A, in the gas, the saturated vapour and liquid, and at the critical density
+  above T_cr (main text, Fig. 1).
 """
 import numpy as np
 import pytest
 
 from oracle import core, riemann
 from oracle.thermo import VdW
+from tests.common import pulse_speed
 
 VDW = VdW()
 
@@ -238,3 +242,16 @@ def test_advected_vdw_slab_converges_to_maxwell_coexistence():
     fine = _bulk_error(*_slab(U=1.0911, steps=8000, N=200, kappa=4 * 0.0176, width=4.0))
     assert max(abs(fine[0]), abs(fine[1])) < 0.015
     assert abs(fine[0]) < abs(coarse[0]) / 2
+
+
+SOUND_STATES = [(1.75, 1.05), (1.490095732, 0.9), (5.800445742, 0.9), (3.5, 1.2)]
+
+
+@pytest.mark.parametrize("rho0,Tr", SOUND_STATES)
+def test_pulse_travels_at_the_vdw_sound_speed(rho0, Tr):
+    def factory(rho, T, dt):
+        c = core.Config(dim=1, nx=rho.size, ny=1, omega=1.5, kappa=0.0, dt=dt, n_pass=2)
+        return core.Sim(c).init(rho, np.zeros(rho.size), T)
+
+    c = pulse_speed(factory, rho0, Tr)
+    assert c == pytest.approx(VDW.sound_vdw(rho0, Tr * VDW.T_cr), rel=3e-3)

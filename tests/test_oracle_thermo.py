@@ -68,6 +68,26 @@ def test_sound_speed_three_routes(delta):
         assert math.sqrt(-v * v * dpdv) == pytest.approx(c_vdw, rel=1e-8)
 
 
+@pytest.mark.parametrize("delta", [1.0 / 3.0, 2.0 / 3.0])
+def test_isentrope_satisfies_the_first_law(delta):
+    """Along the oracle's isentrope de = -p dv (no heat): the numerical derivative of
+    e(T(v), v) plus p vanishes, and (dp/drho) along it is the sound speed squared."""
+    g = VdW(delta=delta)
+    for rho0, Tr in [(1.49, 0.9), (5.8, 0.9), (3.5, 1.2)]:
+        T0 = Tr * g.T_cr
+        v0, h = 1.0 / rho0, 1e-5 / rho0
+
+        def e_of_v(v):
+            T = g.T_isentrope(1.0 / v, rho0, T0)
+            return g.e(1.0 / v, T)
+
+        dedv = (e_of_v(v0 + h) - e_of_v(v0 - h)) / (2 * h)
+        assert dedv + g.p(rho0, T0) == pytest.approx(0.0, abs=1e-8 * g.p(rho0, T0))
+        r, hr = rho0, 1e-5 * rho0
+        dpdr = (g.p(r + hr, g.T_isentrope(r + hr, rho0, T0)) - g.p(r - hr, g.T_isentrope(r - hr, rho0, T0))) / (2 * hr)
+        assert math.sqrt(dpdr) == pytest.approx(g.sound_vdw(rho0, T0), rel=1e-8)
+
+
 def test_sound_speed_at_critical_point():
     """Main text: the speed of sound at the critical point is sqrt(2 p_cr v_cr) (delta = 1/3)."""
     g = VdW(delta=1.0 / 3.0)
