@@ -19,6 +19,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "pond_oracle.c")
+SRC3 = os.path.join(HERE, "pond_oracle3.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 PERIODIC, OUTFLOW, INFLOW = 0, 1, 2
@@ -28,14 +29,18 @@ ERRORS = {0: "ok", -1: "invalid", -2: "nomem", -4: "pressure", -5: "nonfinite"}
 
 def build(force: bool = True) -> str:
     """Compile the oracle with FMA contraction disabled (plain IEEE FP64)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+    if force or _stale():
         tmp = LIB + ".tmp"
         subprocess.check_call([
             "gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-std=c99",
-            "-Wall", "-Wno-unused-function", "-shared", "-fPIC", SRC, "-o", tmp, "-lm",
+            "-Wall", "-Wno-unused-function", "-shared", "-fPIC", SRC, SRC3, "-o", tmp, "-lm",
         ])
         os.replace(tmp, LIB)
     return LIB
+
+
+def _stale() -> bool:
+    return not os.path.exists(LIB) or os.path.getmtime(LIB) < max(os.path.getmtime(SRC), os.path.getmtime(SRC3))
 
 
 class Params(ctypes.Structure):
@@ -63,7 +68,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        if _stale():
             build()
         L = ctypes.CDLL(LIB)
         dp = ctypes.POINTER(ctypes.c_double)
@@ -84,6 +89,21 @@ def lib():
         L.orc_moments.argtypes = [pp] + [dp] * 12
         L.orc_korteweg_force.argtypes = [pp, dp, dp, dp]
         L.orc_heat_correction.argtypes = [pp] + [dp] * 5
+        p3 = ctypes.POINTER(Params3)
+        L.orc3_transfer_pop.argtypes = [dp, dp, dp, dp]
+        L.orc3_force_source.argtypes = [ctypes.c_double, dp, ctypes.c_double, dp, dp]
+        L.orc3_geq.argtypes = [p3, ctypes.c_double, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                               dp, dp, dp]
+        L.orc3_psi.argtypes = [ctypes.c_double, dp, ctypes.c_double, ctypes.c_double, dp]
+        L.orc3_collide.argtypes = [p3, dp, dp, dp, dp, ctypes.c_double, dp, dp, dp]
+        L.orc3_collide.restype = ctypes.c_int
+        L.orc3_init.argtypes = [p3] + [dp] * 8
+        L.orc3_init.restype = ctypes.c_int
+        L.orc3_step.argtypes = [p3, ctypes.c_int] + [dp] * 5 + [ctypes.POINTER(ctypes.c_int)]
+        L.orc3_step.restype = ctypes.c_int
+        L.orc3_moments.argtypes = [p3] + [dp] * 9
+        L.orc3_korteweg_force.argtypes = [p3, dp, dp]
+        L.orc3_heat_correction.argtypes = [p3] + [dp] * 5
         _lib = L
     return _lib
 
@@ -284,3 +304,146 @@ def velocities(cfg: Config, lam) -> np.ndarray:
 def weights(cfg: Config) -> np.ndarray:
     w1 = np.array([1 / 6, 2 / 3, 1 / 6])
     return w1 if cfg.dim == 1 else np.outer(w1, w1).ravel()
+
+
+
+# ---------------------------------------------------------------------------
+# three dimensions (D3Q27, periodic box; pond_oracle3.c)
+# ---------------------------------------------------------------------------
+class Params3(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("a", ctypes.c_double), ("b", ctypes.c_double), ("R", ctypes.c_double), ("delta", ctypes.c_double),
+        ("omega", ctypes.c_double), ("kappa", ctypes.c_double), ("k_scale", ctypes.c_double),
+        ("dt", ctypes.c_double), ("n_pass", ctypes.c_int),
+    ]
+
+
+@dataclass
+class Config3:
+    """Parameters of a run on a periodic nx x ny x nz box (lattice units)."""
+    nx: int = 8
+    ny: int = 8
+    nz: int = 8
+    a: float = 2.0 / 49.0
+    b: float = 2.0 / 21.0
+    R: float = 1.0
+    delta: float = 1.0 / 3.0
+    omega: float = 1.5
+    kappa: float = 0.0
+    k_scale: float = 1.0
+    dt: float = 1.0
+    n_pass: int = 2
+
+    def params(self) -> Params3:
+        P = Params3()
+        P.nx, P.ny, P.nz = self.nx, self.ny, self.nz
+        P.a, P.b, P.R, P.delta = self.a, self.b, self.R, self.delta
+        P.omega, P.kappa, P.k_scale, P.dt, P.n_pass = self.omega, self.kappa, self.k_scale, self.dt, self.n_pass
+        return P
+
+    Q = 27
+
+    @property
+    def N(self) -> int:
+        return self.nx * self.ny * self.nz
+
+
+@dataclass
+class Sim3:
+    """D3Q27 oracle state: populations (27 planes each), gauge u (3 planes), theta, F (3 planes)."""
+    cfg: Config3
+    steps: int = 0
+
+    def __post_init__(self):
+        N = self.cfg.N
+        self.f, self.g = np.zeros((27, N)), np.zeros((27, N))
+        self.u, self.th, self.F = np.zeros((3, N)), np.zeros(N), np.zeros((3, N))
+        self._P = self.cfg.params()
+
+    def init(self, rho, uh, T):
+        N = self.cfg.N
+        rc = lib().orc3_init(ctypes.byref(self._P), _p(_arr(rho, N)), _p(_arr(uh, 3 * N)), _p(_arr(T, N)),
+                             _p(self.f), _p(self.g), _p(self.u), _p(self.th), _p(self.F))
+        if rc:
+            raise OracleError(f"orc3_init: {ERRORS.get(rc, rc)}")
+        self.steps = 0
+        return self
+
+    def step(self, n: int = 1):
+        done = ctypes.c_int(0)
+        rc = lib().orc3_step(ctypes.byref(self._P), int(n), _p(self.f), _p(self.g), _p(self.u), _p(self.th),
+                             _p(self.F), ctypes.byref(done))
+        self.steps += done.value
+        if rc:
+            raise OracleError(f"orc3_step: {ERRORS.get(rc, rc)} after {done.value} steps")
+        return self
+
+    def moments(self) -> dict:
+        N = self.cfg.N
+        rho, uh, T, p, E = np.zeros(N), np.zeros((3, N)), np.zeros(N), np.zeros(N), np.zeros(N)
+        lib().orc3_moments(ctypes.byref(self._P), _p(self.f), _p(self.u), _p(self.th), _p(self.F), _p(rho),
+                           _p(uh), _p(T), _p(p), _p(E))
+        return {"rho": rho, "ux": uh[0], "uy": uh[1], "uz": uh[2], "T": T, "p": p, "E": E}
+
+
+def transfer3_pop(lam_from, lam_to, fin) -> np.ndarray:
+    out = np.zeros(27)
+    lib().orc3_transfer_pop(_p(_arr(lam_from, 4)), _p(_arr(lam_to, 4)), _p(_arr(fin, 27)), _p(out))
+    return out
+
+
+def force_source3(rho, u, theta, du) -> np.ndarray:
+    S = np.zeros(27)
+    lib().orc3_force_source(rho, _p(_arr(u, 3)), theta, _p(_arr(du, 3)), _p(S))
+    return S
+
+
+def geq3(cfg: Config3, rho, u, theta, p, E, uh, F) -> np.ndarray:
+    P = cfg.params()
+    g = np.zeros(27)
+    lib().orc3_geq(ctypes.byref(P), rho, _p(_arr(u, 3)), theta, p, E, _p(_arr(uh, 3)), _p(_arr(F, 3)), _p(g))
+    return g
+
+
+def psi3(rho, u, theta, p) -> np.ndarray:
+    out = np.zeros(27)
+    lib().orc3_psi(rho, _p(_arr(u, 3)), theta, p, _p(out))
+    return out
+
+
+def collide3(cfg: Config3, lam_str, fstr, gstr, F, M0):
+    P = cfg.params()
+    fo, go, lo = np.zeros(27), np.zeros(27), np.zeros(4)
+    rc = lib().orc3_collide(ctypes.byref(P), _p(_arr(lam_str, 4)), _p(_arr(fstr, 27)), _p(_arr(gstr, 27)),
+                            _p(_arr(F, 3)), float(M0), _p(fo), _p(go), _p(lo))
+    if rc:
+        raise OracleError(f"orc3_collide: {ERRORS.get(rc, rc)}")
+    return fo, go, lo
+
+
+def korteweg_force3(cfg: Config3, rho) -> np.ndarray:
+    P = cfg.params()
+    F = np.zeros((3, cfg.N))
+    lib().orc3_korteweg_force(ctypes.byref(P), _p(_arr(rho, cfg.N)), _p(F))
+    return F
+
+
+def heat_correction3(cfg: Config3, T, h, mu, kc) -> np.ndarray:
+    P = cfg.params()
+    out = np.zeros(cfg.N)
+    lib().orc3_heat_correction(ctypes.byref(P), _p(_arr(T, cfg.N)), _p(_arr(h, cfg.N)), _p(_arr(mu, cfg.N)),
+                               _p(_arr(kc, cfg.N)), _p(out))
+    return out
+
+
+def velocities3(lam) -> np.ndarray:
+    """v_i = sqrt(theta) c_i + u of a gauge (u_x, u_y, u_z, theta), shape (27, 3)."""
+    s = np.sqrt(lam[3])
+    return np.array([[lam[0] + s * i, lam[1] + s * j, lam[2] + s * k]
+                     for i in (-1, 0, 1) for j in (-1, 0, 1) for k in (-1, 0, 1)])
+
+
+def weights3() -> np.ndarray:
+    w1 = np.array([1 / 6, 2 / 3, 1 / 6])
+    return np.einsum("i,j,k->ijk", w1, w1, w1).ravel()
