@@ -4,7 +4,7 @@
  * flow: Reyhanian, Dorschner & Karlin, "Thermokinetic model of compressible
  * multiphase flows", arXiv:2002.09217.
  *
- * One handle owns one lattice (D1Q3 or D2Q9) and its device state.  A time step
+ * One handle owns one lattice (D1Q3, D2Q9 or D3Q27) and its device state.  A time step
  *   1. streams f (mass, momentum) and g (energy) semi-Lagrangianly at the shifted
  *      velocities v_i = sqrt(p/(rho T_L)) c_i + u                     (eqs. 1, 3-4)
  *      re-expressing every donor in the receiving node's gauge        (App. C)
@@ -56,7 +56,8 @@ enum { POND_BC_PERIODIC = 0, POND_BC_OUTFLOW = 1, POND_BC_INFLOW = 2 };
 enum { POND_FP64 = 0, POND_FP32_STORE = 1, POND_FP32_STORE_FP64_MATH = 2 };
 
 typedef struct {
-    int dim;                  /* 1 (D1Q3) or 2 (D2Q9), App. B                          */
+    int dim;                  /* 1 (D1Q3), 2 (D2Q9) or 3 (D3Q27, periodic faces only),
+                                 App. B                                                 */
     int n[3];                 /* nodes per axis; unused axes = 1                        */
     int bc[3][2];             /* per axis, [low face, high face]: POND_BC_*             */
     double inflow[3][2][5];   /* state of an inflow face: rho, u_x, u_y, u_z, T (the
@@ -85,8 +86,8 @@ typedef struct {
 
 /* Validate cfg and allocate the device state.  *out receives the handle (NULL on
  * error).  Errors: POND_E_INVALID (dim, sizes, 0 < delta <= 2/3, 0 < omega < 2,
- * n_pass >= 1, dt > 0, tile in range, inflow state with p <= 0), POND_E_NOMEM,
- * POND_E_DEVICE. */
+ * n_pass >= 1, dt > 0, tile in range, inflow state with p <= 0, a non-periodic face
+ * in 3D), POND_E_NOMEM, POND_E_DEVICE. */
 int pond_create(const pond_config *cfg, pond_handle **out);
 
 /* Set the state from the macroscopic fields rho (N), actual velocity u (dim planes

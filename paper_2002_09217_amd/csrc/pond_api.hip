@@ -58,6 +58,9 @@ int handle_update_desc(pond_handle *h)
         d.fc_begin = 0;
         d.fc_count = fcc;
         d.parity = p;
+        d.dmom = h->ds.dmom;
+        d.kor = h->ds.kor;
+        d.aux = h->ds.aux;
     }
     // synchronous: the descriptors are read by work already queued on the stream
     HIP_TRY(h, hipStreamSynchronize(h->stream));
@@ -149,34 +152,43 @@ bool make_ghost(const pond_config &c, const double st[5], GhostFace &G)
 // bytes of one population buffer: 2Q planes, plus (FP32 storage) the two sum planes
 size_t pop_bytes(int dim, long long N, int fp32)
 {
-    const int Q = dim == 2 ? 9 : 3;
+    const int Q = dim == 3 ? 27 : dim == 2 ? 9 : 3;
     return fp32 ? (size_t)N * (2 * Q * sizeof(float) + 2 * sizeof(double)) : (size_t)N * 2 * Q * sizeof(double);
+}
+
+// 3D donor-moment scratch: 54 planes, float when the donors are streamed in FP32
+size_t dmom_bytes(int dim, long long N, int fp32)
+{
+    return dim == 3 ? (size_t)N * 54 * (fp32 == 1 ? sizeof(float) : sizeof(double)) : 0;
 }
 
 // device bytes of one lattice of the given shape (all buffers of pond_create)
 size_t footprint(int dim, long long N, int fp32)
 {
-    const int momPlanes = dim == 2 ? Layout<2>::kMomPlanes : Layout<1>::kMomPlanes;
     const size_t mon = sizeof(double) * 8 * ((N + 255) / 256) + sizeof(double) * 8;
     return 2 * pop_bytes(dim, N, fp32) +
-           (size_t)N * sizeof(double) * (2 * kSidePlanes + momPlanes + kKorPlanes + kAuxPlanes) +
-           sizeof(int) * kFlagWords + sizeof(DevParams) + 2 * sizeof(SlotDesc) + mon;
+           (size_t)N * sizeof(double) * (2 * side_planes(dim) + mom_planes(dim) + kor_planes(dim) + aux_planes(dim)) +
+           dmom_bytes(dim, N, fp32) + sizeof(int) * kFlagWords + sizeof(DevParams) + 2 * sizeof(SlotDesc) + mon;
 }
 
 int validate(const pond_config *cfg)
 {
     if (!cfg) return POND_E_INVALID;
     const pond_config &c = *cfg;
-    if (c.dim != 1 && c.dim != 2) return POND_E_INVALID;
-    const int nx = c.n[0], ny = c.dim == 2 ? c.n[1] : 1;
-    if (nx < 1 || ny < 1 || (long long)nx * ny > (1LL << 30)) return POND_E_INVALID;
+    if (c.dim < 1 || c.dim > 3) return POND_E_INVALID;
+    const int nx = c.n[0], ny = c.dim >= 2 ? c.n[1] : 1, nz = c.dim == 3 ? c.n[2] : 1;
+    if (nx < 1 || ny < 1 || nz < 1 || (long long)nx * ny * nz > (1LL << 30)) return POND_E_INVALID;
+    if (c.dim == 3) // D3Q27: periodic box only
+        for (int a = 0; a < 3; ++a)
+            for (int s = 0; s < 2; ++s)
+                if (c.bc[a][s] != POND_BC_PERIODIC) return POND_E_INVALID;
     if (!(c.delta > 0.0 && c.delta <= 2.0 / 3.0)) return POND_E_INVALID;
     if (!(c.omega > 0.0 && c.omega < 2.0)) return POND_E_INVALID;
     if (c.n_pass < 1 || c.n_pass > 64 || !(c.dt > 0.0) || !(c.R > 0.0)) return POND_E_INVALID;
     if (c.precision != POND_FP64 && c.precision != POND_FP32_STORE && c.precision != POND_FP32_STORE_FP64_MATH)
         return POND_E_INVALID;
     if (c.tile < -1 || c.tile >= stream_variants(c.dim)) return POND_E_INVALID;
-    for (int a = 0; a < c.dim; ++a)
+    for (int a = 0; a < c.dim && a < 2; ++a)
         for (int s = 0; s < 2; ++s)
             if (c.bc[a][s] < 0 || c.bc[a][s] > 2) return POND_E_INVALID;
     return POND_OK;
@@ -249,6 +261,7 @@ void free_all(pond_handle *h)
     if (h->ds.mom) (void)hipFree(h->ds.mom);
     if (h->ds.kor) (void)hipFree(h->ds.kor);
     if (h->ds.aux) (void)hipFree(h->ds.aux);
+    if (h->ds.dmom) (void)hipFree(h->ds.dmom);
     if (h->ds.flags) (void)hipFree(h->ds.flags);
     if (h->ds.params) (void)hipFree(h->ds.params);
     if (h->desc_d) (void)hipFree(h->desc_d);
@@ -303,8 +316,9 @@ int pond_footprint(const pond_config *cfg, unsigned long long *bytes)
     if (!bytes) return POND_E_INVALID;
     const int rc = validate(cfg);
     if (rc != POND_OK) return rc;
-    const long long N = (long long)cfg->n[0] * (cfg->dim == 2 ? cfg->n[1] : 1);
-    *bytes = footprint(cfg->dim, N, cfg->precision != POND_FP64);
+    const long long N = (long long)cfg->n[0] * (cfg->dim >= 2 ? cfg->n[1] : 1) * (cfg->dim == 3 ? cfg->n[2] : 1);
+    const int fp32 = cfg->precision == POND_FP64 ? 0 : (cfg->precision == POND_FP32_STORE ? 1 : 2);
+    *bytes = footprint(cfg->dim, N, fp32);
     return POND_OK;
 }
 
@@ -315,19 +329,18 @@ int pond_create(const pond_config *cfg, pond_handle **out)
     int rc = validate(cfg);
     if (rc != POND_OK) return rc;
     const pond_config &c = *cfg;
-    const int nx = c.n[0], ny = c.dim == 2 ? c.n[1] : 1;
+    const int nx = c.n[0], ny = c.dim >= 2 ? c.n[1] : 1, nz = c.dim == 3 ? c.n[2] : 1;
 
     pond_handle *h = new (std::nothrow) pond_handle();
     if (!h) return POND_E_NOMEM;
     h->cfg = c;
-    if (c.dim == 1) {
-        h->cfg.n[1] = 1;
-        h->cfg.n[2] = 1;
-    }
-    const int N = nx * ny;
+    if (c.dim == 1) h->cfg.n[1] = 1;
+    if (c.dim < 3) h->cfg.n[2] = 1;
+    const int N = nx * ny * nz;
     h->lc = LaunchCtx{c.dim, nx, ny, N, c.precision == POND_FP64 ? 0 : (c.precision == POND_FP32_STORE ? 1 : 2), nullptr,
                       c.tile < 0 ? 0 : c.tile};
-    h->tuned = c.tile >= 0;
+    h->lc.nz = nz;
+    h->tuned = c.tile >= 0 || c.dim == 3;
 
     DevParams P;
     std::memset(&P, 0, sizeof P);
@@ -338,6 +351,7 @@ int pond_create(const pond_config *cfg, pond_handle **out)
     for (int a = 0; a < 2; ++a)
         for (int s = 0; s < 2; ++s) P.bc[a][s] = a < c.dim ? c.bc[a][s] : kPeriodic;
     P.n_pass = c.n_pass;
+    P.nz = nz;
     P.a = c.a;
     P.b = c.b;
     P.R = c.R;
@@ -356,7 +370,6 @@ int pond_create(const pond_config *cfg, pond_handle **out)
             }
 
     const size_t popb = pop_bytes(c.dim, N, h->lc.fp32);
-    const int momPlanes = c.dim == 2 ? Layout<2>::kMomPlanes : Layout<1>::kMomPlanes;
     auto alloc = [&](void **p, size_t bytes) {
         if (rc != POND_OK) return;
         if (hipMalloc(p, bytes) != hipSuccess) {
@@ -366,11 +379,12 @@ int pond_create(const pond_config *cfg, pond_handle **out)
     };
     for (int i = 0; i < 2; ++i) {
         alloc(&h->ds.pop[i], popb);
-        alloc((void **)&h->ds.side[i], sizeof(double) * kSidePlanes * N);
+        alloc((void **)&h->ds.side[i], sizeof(double) * side_planes(c.dim) * N);
     }
-    alloc((void **)&h->ds.mom, sizeof(double) * momPlanes * N);
-    alloc((void **)&h->ds.kor, sizeof(double) * kKorPlanes * N);
-    alloc((void **)&h->ds.aux, sizeof(double) * kAuxPlanes * N);
+    alloc((void **)&h->ds.mom, sizeof(double) * mom_planes(c.dim) * N);
+    alloc((void **)&h->ds.kor, sizeof(double) * kor_planes(c.dim) * N);
+    alloc((void **)&h->ds.aux, sizeof(double) * aux_planes(c.dim) * N);
+    if (c.dim == 3) alloc(&h->ds.dmom, dmom_bytes(3, N, h->lc.fp32));
     alloc((void **)&h->ds.flags, sizeof(int) * kFlagWords);
     alloc((void **)&h->ds.params, sizeof(DevParams));
     alloc((void **)&h->desc_d, 2 * sizeof(SlotDesc));
@@ -415,8 +429,13 @@ int pond_init_fields(pond_handle *h, const double *rho, const double *u, const d
     HIP_TRY(h, hipMemcpyAsync(d_u, u, sizeof(double) * N * dim, hipMemcpyHostToDevice, h->stream));
     HIP_TRY(h, hipMemcpyAsync(d_T, T, sizeof(double) * N, hipMemcpyHostToDevice, h->stream));
     HIP_TRY(h, launch_reset_flags(h->lc, h->ds.flags));
-    if (h->cfg.kappa != 0.0) HIP_TRY(h, launch_korteweg(h->lc, h->ds, d_rho));
-    HIP_TRY(h, launch_init_equilibrium(h->lc, h->ds, d_rho, d_u, d_T));
+    if (dim == 3) {
+        // the initial state's streamed-state planes, from the staged fields
+        HIP_TRY(h, launch_init3(h->lc, h->ds, h->desc_d + 1));
+    } else {
+        if (h->cfg.kappa != 0.0) HIP_TRY(h, launch_korteweg(h->lc, h->ds, d_rho));
+        HIP_TRY(h, launch_init_equilibrium(h->lc, h->ds, d_rho, d_u, d_T));
+    }
     // the descriptor of parity 1 writes state 0
     HIP_TRY(h, launch_force_collide(h->lc, h->desc_d + 1, 1, h->fc_tiles));
     int fl[kFlagWords];
@@ -508,7 +527,10 @@ int pond_tile_info(const pond_handle *h, int *out)
 {
     if (!h || !out) return POND_E_INVALID;
     out[0] = h->lc.stream_tile;
-    stream_tile_shape(h->lc.dim, h->lc.stream_tile, &out[1], &out[2]);
+    if (h->lc.dim == 3)
+        stream3_tile(h->lc.fp32, &out[1], &out[2]);
+    else
+        stream_tile_shape(h->lc.dim, h->lc.stream_tile, &out[1], &out[2]);
     out[3] = stream_variants(h->lc.dim);
     return POND_OK;
 }
@@ -558,7 +580,7 @@ CheckpointHeader make_header(const pond_handle *h)
     H.dt = c.dt;
     std::memcpy(H.inflow, c.inflow, sizeof H.inflow);
     H.pop_bytes = pop_bytes(c.dim, h->lc.N, h->lc.fp32);
-    H.side_bytes = sizeof(double) * kSidePlanes * (size_t)h->lc.N;
+    H.side_bytes = sizeof(double) * side_planes(h->lc.dim) * (size_t)h->lc.N;
     return H;
 }
 

@@ -195,6 +195,7 @@ int pond_batch_create(void *stream, pond_batch **out)
 int pond_batch_add(pond_batch *b, pond_handle *h)
 {
     if (!b || !h || h->batch) return POND_E_INVALID;
+    if (h->lc.dim == 3) return handle_fail(h, POND_E_INVALID, "D3Q27 lattices are stepped alone");
     if (!h->initialised || h->failed)
         return handle_fail(h, POND_E_STATE, h->failed ? "handle in error state" : "not initialised");
     long long st = h->st_tiles, fc = h->fc_tiles;

@@ -21,7 +21,7 @@ constexpr double kW1[3] = {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0};
 template <int DIM>
 __device__ __forceinline__ double weight_q(int q)
 {
-    return DIM == 2 ? kW1[q / 3] * kW1[q % 3] : kW1[q];
+    return DIM == 3 ? kW1[q / 9] * kW1[(q / 3) % 3] * kW1[q % 3] : DIM == 2 ? kW1[q / 3] * kW1[q % 3] : kW1[q];
 }
 
 // FP32 storage of the populations: each set is kept as its FP64 sum (one plane after
@@ -260,6 +260,54 @@ __device__ __forceinline__ void source_axis(double du, double inv_theta, double 
     sig[0] = 0.5 * q - l;
     sig[1] = -q;
     sig[2] = 0.5 * q + l;
+}
+
+// write the post-collision populations of one set (0 = f, 1 = g) of a node: as they
+// are, or (FP32 storage) as the FP64 sum and the FP32 deviations from W_q sum
+template <int DIM, typename PopT>
+__device__ __forceinline__ void store_set(POND_GLOBAL PopT *pop, size_t N, int node, int set,
+                                          const double *post)
+{
+    constexpr int Q = Layout<DIM>::Q;
+    POND_GLOBAL PopT *out = pop + (size_t)set * Q * N;
+    if constexpr (kDeviationStore<PopT>) {
+        double sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) sum += post[q];
+        POND_GLOBAL double *sums = (POND_GLOBAL double *)(pop + (size_t)2 * Q * N);
+        sums[(size_t)set * N + node] = sum;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) out[(size_t)q * N + node] = (PopT)(post[q] - weight_q<DIM>(q) * sum);
+    } else {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) out[(size_t)q * N + node] = (PopT)post[q];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// conservation monitors: words per block partial and threads per block, and the
+// wavefront reductions they use
+// ---------------------------------------------------------------------------
+constexpr int kMonWords = 8;
+constexpr int kMonThreads = 256;
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
 }
 
 } // namespace pond

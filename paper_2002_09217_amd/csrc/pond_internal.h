@@ -21,9 +21,9 @@ struct GhostFace {
 
 // Per-lattice parameters, resident in device memory and read through a pointer.
 struct DevParams {
-    int dim, nx, ny, N;    // N = nx * ny nodes, index = x + nx * y
+    int dim, nx, ny, N;    // N = nx * ny * nz nodes, index = x + nx * (y + ny * z)
     int bc[2][2];
-    int n_pass, pad_;
+    int n_pass, nz;
     double a, b, R, delta, omega, kappa, k_scale, dt;
     double Cv, Cp_ig;      // R/delta and R(1 + delta)/delta
     GhostFace ghost[4];    // face 2 axis + side
@@ -53,9 +53,22 @@ template <> struct Layout<1> {
     static constexpr int kRho = 0, kUx = 1, kUy = 1, kF = 2, kG = 3, kMomPlanes = 6;
     static constexpr int kFStored = 1; // m = 2
 };
-enum { kSideUx = 0, kSideUy = 1, kSideTh = 2, kSideFx = 3, kSideFy = 4, kSidePlanes = 5 };
-enum { kAuxPlanes = 7 };
-enum { kKorPlanes = 3 };
+// D3Q27 (periodic box): moment index 9 m + 3 n + o for sum_i f_i wx^m wy^n wz^o; the f
+// moments stored are the 23 that rho and u do not fix (all but 000, 100, 010, 001)
+template <> struct Layout<3> {
+    static constexpr int Q = 27, NF = 27;
+    static constexpr int kRho = 0, kUx = 1, kUy = 2, kUz = 3, kF = 4, kG = 27, kMomPlanes = 54;
+    static constexpr int kFStored = 23;
+};
+// side planes: 5 in 1D/2D, 7 in 3D (u_z and F_z appended)
+enum { kSideUx = 0, kSideUy = 1, kSideTh = 2, kSideFx = 3, kSideFy = 4, kSidePlanes = 5,
+       kSideUz = 5, kSideFz = 6, kSidePlanes3 = 7 };
+enum { kAuxPlanes = 7, kAuxPlanes3 = 9 };
+enum { kKorPlanes = 3, kKorPlanes3 = 6 };
+inline int side_planes(int dim) { return dim == 3 ? kSidePlanes3 : kSidePlanes; }
+inline int mom_planes(int dim) { return dim == 3 ? Layout<3>::kMomPlanes : dim == 2 ? Layout<2>::kMomPlanes : Layout<1>::kMomPlanes; }
+inline int aux_planes(int dim) { return dim == 3 ? kAuxPlanes3 : kAuxPlanes; }
+inline int kor_planes(int dim) { return dim == 3 ? kKorPlanes3 : kKorPlanes; }
 
 // flags[0]: error bits.  flags[1]: streaming launches of the current batch of steps
 // whose first tile found no error (the failing step itself may or may not count: its
@@ -78,6 +91,9 @@ struct SlotDesc {
     int st_tiles_x, st_begin, st_count; // streaming-kernel tiles: per row, first, number
     int fc_tiles_x, fc_begin, fc_count; // collision-kernel tiles
     int parity;              // index of the state buffer pop_src belongs to (0 or 1)
+    // 3D only: donor moments, Korteweg stress and thermodynamic scratch
+    void *dmom;
+    double *kor, *aux;
 };
 
 // device buffers of one lattice
@@ -89,6 +105,7 @@ struct DevState {
     double *aux;        // kAuxPlanes planes
     int *flags;         // kFlagWords ints
     DevParams *params;  // device copy
+    void *dmom;         // 3D: donor moments, 54 planes (float with FP32 streaming)
 };
 
 // ---------------------------------------------------------------------------
@@ -103,6 +120,7 @@ struct LaunchCtx {
     // when set, the step kernels are launched with these start/stop events, which the
     // runtime records at the kernel's own start and end (measurement only)
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;
+    int nz = 1;
 };
 
 int stream_variants(int dim);
@@ -126,5 +144,19 @@ hipError_t launch_macro(const LaunchCtx &c, const DevState &s, int cur, double *
 hipError_t launch_monitors(const LaunchCtx &c, const DevState &s, int cur, double *partials,
                            int nblocks, double *out);
 int monitor_blocks(const LaunchCtx &c);
+hipError_t launch_monitor_final(const LaunchCtx &c, const double *partials, int nblocks, double *out);
+
+// D3Q27 (pond_kernels3.hip), one lattice per launch, descriptor in device memory:
+// streaming = donor moments + passes; collision = Korteweg stress + thermodynamics +
+// collision.  With start/stop events set, each group is bracketed by them.
+hipError_t launch_stream3(const LaunchCtx &c, const SlotDesc *slot);
+hipError_t launch_collide3(const LaunchCtx &c, const SlotDesc *slot);
+// initial state from rho, u_hat (3 planes), T staged in aux planes 0-4: streamed-state
+// planes of the equilibrium (then launch_collide3 stores the collided populations)
+hipError_t launch_init3(const LaunchCtx &c, const DevState &s, const SlotDesc *slot);
+hipError_t launch_macro3(const LaunchCtx &c, const DevState &s, int cur, double *out);
+hipError_t launch_monitors3(const LaunchCtx &c, const DevState &s, int cur, double *partials, int nblocks,
+                            double *out);
+void stream3_tile(int fp32, int *tx, int *ty);
 
 } // namespace pond

@@ -403,9 +403,13 @@ static hipError_t launch_stream_t(const LaunchCtx &c, const SlotDesc *slots, int
 static const int kTiles2D[][2] = {{32, 8}, {32, 4}, {16, 8}, {64, 4}, {16, 4}};
 static const int kTiles1D[][2] = {{128, 1}, {64, 1}};
 
-int stream_variants(int dim) { return dim == 2 ? 5 : 2; }
+int stream_variants(int dim) { return dim == 3 ? 1 : dim == 2 ? 5 : 2; }
 void stream_tile_shape(int dim, int v, int *tx, int *ty)
 {
+    if (dim == 3) {
+        stream3_tile(1, tx, ty); // the FP32-streaming shape; FP64 streaming uses 8 x 8
+        return;
+    }
     *tx = dim == 2 ? kTiles2D[v][0] : kTiles1D[v][0];
     *ty = dim == 2 ? kTiles2D[v][1] : kTiles1D[v][1];
 }
@@ -428,6 +432,7 @@ static hipError_t launch_stream_v(const LaunchCtx &c, const SlotDesc *slots, int
 
 hipError_t launch_stream(const LaunchCtx &c, const SlotDesc *slots, int nslots, int tiles)
 {
+    if (c.dim == 3) return launch_stream3(c, slots); // one lattice per launch
     if (c.fp32 == 1) return launch_stream_v<float, float>(c, slots, nslots, tiles);
     if (c.fp32 == 2) return launch_stream_v<float, double>(c, slots, nslots, tiles);
     return launch_stream_v<double, double>(c, slots, nslots, tiles);
@@ -579,28 +584,6 @@ __device__ __forceinline__ int classify(const Geo &g, int x, int y, int &cx, int
 // f sets of the tile's nodes, the second half on their g sets (and the heat-flux
 // correction, which only g uses); the stencil stages use all lanes of the block.
 // ---------------------------------------------------------------------------
-// write the post-collision populations of one set (0 = f, 1 = g) of a node: as they
-// are, or (FP32 storage) as the FP64 sum and the FP32 deviations from W_q sum
-template <int DIM, typename PopT>
-__device__ __forceinline__ void store_set(POND_GLOBAL PopT *pop, size_t N, int node, int set,
-                                          const double *post)
-{
-    constexpr int Q = Layout<DIM>::Q;
-    POND_GLOBAL PopT *out = pop + (size_t)set * Q * N;
-    if constexpr (kDeviationStore<PopT>) {
-        double sum = 0.0;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) sum += post[q];
-        POND_GLOBAL double *sums = (POND_GLOBAL double *)(pop + (size_t)2 * Q * N);
-        sums[(size_t)set * N + node] = sum;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) out[(size_t)q * N + node] = (PopT)(post[q] - weight_q<DIM>(q) * sum);
-    } else {
-#pragma unroll
-        for (int q = 0; q < Q; ++q) out[(size_t)q * N + node] = (PopT)post[q];
-    }
-}
-
 template <int DIM> struct CollideTile;
 template <> struct CollideTile<2> { static constexpr int TX = 16, TY = 8; };
 template <> struct CollideTile<1> { static constexpr int TX = 256, TY = 1; };
@@ -1002,6 +985,7 @@ static hipError_t launch_force_collide_t(const LaunchCtx &c, const SlotDesc *slo
 
 hipError_t launch_force_collide(const LaunchCtx &c, const SlotDesc *slots, int nslots, int tiles)
 {
+    if (c.dim == 3) return launch_collide3(c, slots);
     if (c.dim == 2)
         return c.fp32 ? launch_force_collide_t<2, float>(c, slots, nslots, tiles)
                       : launch_force_collide_t<2, double>(c, slots, nslots, tiles);
@@ -1011,6 +995,10 @@ hipError_t launch_force_collide(const LaunchCtx &c, const SlotDesc *slots, int n
 
 void tile_counts(const LaunchCtx &c, int *st_tiles_x, int *st_count, int *fc_tiles_x, int *fc_count)
 {
+    if (c.dim == 3) { // the 3D launchers size their grids themselves
+        *st_tiles_x = *st_count = *fc_tiles_x = *fc_count = 1;
+        return;
+    }
     int tx, ty;
     stream_tile_shape(c.dim, c.stream_tile, &tx, &ty);
     *st_tiles_x = (c.nx + tx - 1) / tx;
@@ -1147,6 +1135,7 @@ __global__ void k_macro(const DevParams *__restrict__ Pp, const PopT *__restrict
 
 hipError_t launch_macro(const LaunchCtx &c, const DevState &s, int cur, double *out)
 {
+    if (c.dim == 3) return launch_macro3(c, s, cur, out);
     dim3 grid, block;
     grid2(c, grid, block);
     if (c.dim == 2) {
@@ -1174,27 +1163,6 @@ hipError_t launch_macro(const LaunchCtx &c, const DevState &s, int cur, double *
 //   0 sum rho, 1..DIM sum rho u_hat, DIM+1 sum rho E,
 //   DIM+2 sum (rho E + kappa |grad rho|^2 / 2), DIM+3 min p, DIM+4 max |v_i| dt
 // ---------------------------------------------------------------------------
-constexpr int kMonWords = 8;
-constexpr int kMonThreads = 256;
-
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-__device__ __forceinline__ double wave_min(double v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-    return v;
-}
-__device__ __forceinline__ double wave_max(double v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
-}
 
 template <int DIM>
 __global__ void __launch_bounds__(kMonThreads)
@@ -1286,9 +1254,16 @@ __global__ void k_monitor_final(const double *__restrict__ partials, int nblocks
 
 int monitor_blocks(const LaunchCtx &c) { return (c.N + kMonThreads - 1) / kMonThreads; }
 
+hipError_t launch_monitor_final(const LaunchCtx &c, const double *partials, int nblocks, double *out)
+{
+    hipLaunchKernelGGL(k_monitor_final, dim3(1), dim3(64), 0, c.st, partials, nblocks, c.dim, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_monitors(const LaunchCtx &c, const DevState &s, int cur, double *partials,
                            int nblocks, double *out)
 {
+    if (c.dim == 3) return launch_monitors3(c, s, cur, partials, nblocks, out);
     hipError_t e = launch_macro(c, s, cur, s.aux);
     if (e != hipSuccess) return e;
     if (c.dim == 2)

@@ -1,0 +1,848 @@
+// pond_kernels3.hip -- D3Q27 time step of the two-population Particles-on-Demand model
+// (Reyhanian, Dorschner & Karlin, arXiv:2002.09217) on a periodic box, for gfx950.
+//
+// Same method as the 1D/2D kernels (eqs. 1-4, 9, 16-22; App. B-D, F), laid out for the
+// 5 x 5 x 5 donor window of three dimensions, which does not fit in LDS as a tile plus
+// halo:
+//   k3_donor_moments  each node's 27 + 27 moments about a common reference velocity
+//                     (zero), gauge free, into a scratch buffer;
+//   k3_stream         one workgroup per x-y tile of one z plane; every predictor-corrector
+//                     pass stages the five donor planes z-2 .. z+2 through LDS one at a
+//                     time and accumulates, per plane, the x-y contraction of the D2Q9
+//                     kernel for each z power followed by the z contraction;
+//   k3_korteweg, k3_thermo, k3_collide
+//                     Korteweg stress, force and thermodynamics, heat-flux correction and
+//                     the collisions of f and g (separate waves), 27-point stencils.
+// Index conventions: direction q = 9 (cx+1) + 3 (cy+1) + (cz+1); moment 9 m + 3 n + o
+// for sum f wx^m wy^n wz^o.
+#include <hip/hip_runtime.h>
+
+#include "pond_device.h"
+#include "pond_internal.h"
+
+namespace pond {
+
+using L3 = Layout<3>;
+
+namespace {
+
+struct Box {
+    int nx, ny, nz;
+    size_t N;
+    __device__ __forceinline__ int wrap(int i, int n) const
+    {
+        i = i < 0 ? i + n : (i >= n ? i - n : i);
+        if (i < 0 || i >= n) i = ((i % n) + n) % n; // narrower than the stencil
+        return i;
+    }
+    __device__ __forceinline__ int node(int x, int y, int z) const
+    {
+        return wrap(x, nx) + nx * (wrap(y, ny) + ny * wrap(z, nz));
+    }
+};
+
+template <typename PT>
+__device__ __forceinline__ Box make_box(const PT &P)
+{
+    return Box{P.nx, P.ny, P.nz, (size_t)P.N};
+}
+
+__device__ __forceinline__ double w27(int q) { return kW1[q / 9] * kW1[(q / 3) % 3] * kW1[q % 3]; }
+
+// moments out[9m+3n+o] = sum_ijk f_ijk (dx + s(i-1))^m (dy + s(j-1))^n (dz + s(k-1))^o
+__device__ __forceinline__ void moments27(const double *f, double dx, double dy, double dz, double s, double *out)
+{
+    double a1[3][3][3]; // [i][j][o]
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const double c = dz + s * (double)(k - 1);
+                const double fv = f[9 * i + 3 * j + k];
+                s0 += fv;
+                s1 += fv * c;
+                s2 += fv * c * c;
+            }
+            a1[i][j][0] = s0;
+            a1[i][j][1] = s1;
+            a1[i][j][2] = s2;
+        }
+    double a2[3][3][3]; // [i][n][o]
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int o = 0; o < 3; ++o) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const double c = dy + s * (double)(j - 1);
+                s0 += a1[i][j][o];
+                s1 += a1[i][j][o] * c;
+                s2 += a1[i][j][o] * c * c;
+            }
+            a2[i][0][o] = s0;
+            a2[i][1][o] = s1;
+            a2[i][2][o] = s2;
+        }
+#pragma unroll
+    for (int n = 0; n < 3; ++n)
+#pragma unroll
+        for (int o = 0; o < 3; ++o) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const double c = dx + s * (double)(i - 1);
+                s0 += a2[i][n][o];
+                s1 += a2[i][n][o] * c;
+                s2 += a2[i][n][o] * c * c;
+            }
+            out[0 + 3 * n + o] = s0;
+            out[9 + 3 * n + o] = s1;
+            out[18 + 3 * n + o] = s2;
+        }
+}
+
+// populations pop[9k+3l+m] = sum A[k][a] A[l][b] A[m][c] mc[9a+3b+c] (separable)
+__device__ __forceinline__ void from_moments27(const double A[3][3], const double *mc, double *pop)
+{
+    double t1[3][3][3]; // [a][b][m]
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int m = 0; m < 3; ++m)
+                t1[a][b][m] = A[m][0] * mc[9 * a + 3 * b] + A[m][1] * mc[9 * a + 3 * b + 1] + A[m][2] * mc[9 * a + 3 * b + 2];
+    double t2[3][3][3]; // [a][l][m]
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+#pragma unroll
+            for (int m = 0; m < 3; ++m) t2[a][l][m] = A[l][0] * t1[a][0][m] + A[l][1] * t1[a][1][m] + A[l][2] * t1[a][2][m];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+#pragma unroll
+            for (int m = 0; m < 3; ++m)
+                pop[9 * k + 3 * l + m] = A[k][0] * t2[0][l][m] + A[k][1] * t2[1][l][m] + A[k][2] * t2[2][l][m];
+}
+
+// index of moment mno among the 23 stored f central moments (-1 for 000, 100, 010, 001)
+__device__ __forceinline__ int fstored_index(int mno)
+{
+    // skipped: 0 (000), 1 (001), 3 (010), 9 (100)
+    if (mno == 0 || mno == 1 || mno == 3 || mno == 9) return -1;
+    return mno - 2 - (mno > 3) - (mno > 9);
+}
+
+__device__ __forceinline__ void raise_error3(int *flags, int bits, int parity)
+{
+    atomicOr(&flags[kFlagErr], bits);
+    atomicCAS(&flags[kFlagErrParity], 0, parity + 1);
+}
+
+} // namespace
+
+// ---------------------------------------------------------------------------
+// donor moments about zero velocity, gauge free (one thread per node and set)
+// ---------------------------------------------------------------------------
+template <typename PopT, typename MomT>
+__global__ void __launch_bounds__(256) k3_donor_moments(const SlotDesc *__restrict__ slot)
+{
+    const SlotDesc &S = *slot;
+    const POND_GLOBAL DevParams &P = *(const POND_GLOBAL DevParams *)S.P;
+    const size_t N = P.N;
+    const size_t it = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (it >= 2 * N) return;
+    if (S.flags[kFlagErr] != 0) return;
+    const int set = it >= N ? 1 : 0;
+    const size_t node = it - (size_t)set * N;
+    const POND_GLOBAL PopT *pop = (const POND_GLOBAL PopT *)S.pop_src + (size_t)set * 27 * N;
+    const POND_GLOBAL double *side = (const POND_GLOBAL double *)S.side_src;
+    double f[27];
+#pragma unroll
+    for (int q = 0; q < 27; ++q) f[q] = (double)pop[(size_t)q * N + node];
+    if constexpr (kDeviationStore<PopT>) {
+        const double sum = ((const POND_GLOBAL double *)((const POND_GLOBAL PopT *)S.pop_src + (size_t)54 * N))[set * N + node];
+#pragma unroll
+        for (int q = 0; q < 27; ++q) f[q] += w27(q) * sum;
+    }
+    const double ux = side[kSideUx * N + node], uy = side[kSideUy * N + node], uz = side[kSideUz * N + node];
+    const double s = sqrt(side[kSideTh * N + node]);
+    double m[27];
+    moments27(f, ux, uy, uz, s, m);
+    POND_GLOBAL MomT *out = (POND_GLOBAL MomT *)S.dmom + (size_t)set * 27 * N;
+#pragma unroll
+    for (int i = 0; i < 27; ++i) out[(size_t)i * N + node] = (MomT)m[i];
+}
+
+// ---------------------------------------------------------------------------
+// streaming passes: x-y tile of TX x TY receivers of one z plane, two lanes per
+// receiver (set f / g), the 5 x 5 x 5 window staged plane by plane
+// ---------------------------------------------------------------------------
+template <typename LdsT, int TX, int TY>
+__global__ void __launch_bounds__(2 * TX *TY) k3_stream(const SlotDesc *__restrict__ slot)
+{
+    constexpr int LX = TX + 4, LY = TY + 4, LN = LX * LY, NT = 2 * TX * TY;
+    __shared__ LdsT lds[2 * 27 * LN];
+    __shared__ int abort_block;
+    const SlotDesc &S = *slot;
+    const POND_GLOBAL DevParams &P = *(const POND_GLOBAL DevParams *)S.P;
+    const Box box = make_box(P);
+    const size_t N = box.N;
+    int *flags = S.flags;
+    const int tid = threadIdx.x + 2 * TX * threadIdx.y;
+    int err_before = 0;
+    if (tid == 0) err_before = flags[kFlagErr];
+
+    const int tiles_x = (box.nx + TX - 1) / TX;
+    const int bx0 = (blockIdx.x % tiles_x) * TX, by0 = (blockIdx.x / tiles_x) * TY;
+    const int z = blockIdx.y;
+    const int lxr = (int)threadIdx.x >> 1, myset = (int)threadIdx.x & 1;
+    const int gx = bx0 + lxr, gy = by0 + (int)threadIdx.y;
+    const bool inside = gx < box.nx && gy < box.ny;
+    const int node = min(gx, box.nx - 1) + box.nx * (min(gy, box.ny - 1) + box.ny * z);
+    const POND_GLOBAL double *side = (const POND_GLOBAL double *)S.side_src;
+    const POND_GLOBAL LdsT *dmom = (const POND_GLOBAL LdsT *)S.dmom;
+    double U[3] = {side[kSideUx * N + node], side[kSideUy * N + node], side[kSideUz * N + node]};
+    double th = side[kSideTh * N + node];
+    const double Fp[3] = {side[kSideFx * N + node], side[kSideFy * N + node], side[kSideFz * N + node]};
+    const double dt = P.dt;
+    const int wbase = (int)threadIdx.y * LX + lxr; // window corner (gx-2, gy-2) in the tile plane
+
+    double acc[27];
+    double sU[3] = {U[0], U[1], U[2]}, sS = 1.0, rho = 0.0;
+    int err = 0;
+    for (int pass = 0; pass < P.n_pass; ++pass) {
+        const double s = sqrt(th);
+        LdsT wx[3][5], wy[3][5];
+        double wz[3][5];
+        const int werr = window_weights<LdsT>(U[0], s, dt, wx) | window_weights<LdsT>(U[1], s, dt, wy) |
+                         window_weights<double>(U[2], s, dt, wz);
+        if (inside) err |= werr; // lanes past the lattice edge only pad the tile
+        double Ad[3][3], Bd[3][3], Cd[3][3];
+        lagrange_coeffs(U[0], s, Ad);
+        lagrange_coeffs(U[1], s, Bd);
+        lagrange_coeffs(U[2], s, Cd);
+        LdsT A[3][3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int m = 0; m < 3; ++m) A[k][m] = (LdsT)Ad[k][m];
+#pragma unroll
+        for (int q = 0; q < 27; ++q) acc[q] = 0.0;
+
+#pragma unroll 1
+        for (int sz = 0; sz < 5; ++sz) {
+            // stage the donor plane z + sz - 2 of the tile window: 54 fields
+            __syncthreads();
+            // loads in batches of CH before their stores, so their latencies overlap
+            const int zz = box.wrap(z + sz - 2, box.nz);
+            constexpr int ITEMS = (54 * LN + NT - 1) / NT, CH = 8;
+#pragma unroll 1
+            for (int b0 = 0; b0 < ITEMS; b0 += CH) {
+                LdsT tmp[CH];
+                int dst[CH];
+#pragma unroll
+                for (int u = 0; u < CH; ++u) {
+                    const int li = tid + (b0 + u) * NT;
+                    dst[u] = -1;
+                    if (b0 + u < ITEMS && li < 54 * LN) {
+                        const int c = li / LN, ln = li - c * LN;
+                        const int set = c / 27, mno = c - set * 27;
+                        const int nd = box.wrap(bx0 - 2 + ln % LX, box.nx) +
+                                       box.nx * (box.wrap(by0 - 2 + ln / LX, box.ny) + box.ny * zz);
+                        tmp[u] = dmom[(size_t)c * N + nd];
+                        dst[u] = (mno * LN + ln) * 2 + set;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < CH; ++u)
+                    if (dst[u] >= 0) lds[dst[u]] = tmp[u];
+            }
+            if (pass == 0 && sz == 0 && tid == 0) {
+                abort_block = err_before;
+                // one step more has started without an earlier failure
+                if (blockIdx.x == 0 && blockIdx.y == 0 && err_before == 0) atomicAdd(&flags[kFlagSteps], 1);
+            }
+            __syncthreads();
+            if (abort_block != 0) return;
+
+            const LdsT *sbase = &lds[wbase * 2 + myset];
+#pragma unroll 1
+            for (int o = 0; o < 3; ++o) {
+                double Y[3][3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                    for (int l = 0; l < 3; ++l) Y[k][l] = 0.0;
+#pragma unroll
+                for (int n = 0; n < 3; ++n) {
+                    LdsT Z[3][5];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k)
+#pragma unroll
+                        for (int r = 0; r < 5; ++r) Z[k][r] = (LdsT)0;
+#pragma unroll
+                    for (int r = 0; r < 5; ++r) {
+#pragma unroll
+                        for (int m = 0; m < 3; ++m) {
+                            const LdsT *row = sbase + ((9 * m + 3 * n + o) * LN + r * LX) * 2;
+                            const LdsT v0 = row[0], v1 = row[2], v2 = row[4], v3 = row[6], v4 = row[8];
+#pragma unroll
+                            for (int k = 0; k < 3; ++k) {
+                                const LdsT xk = wx[k][0] * v0 + wx[k][1] * v1 + wx[k][2] * v2 + wx[k][3] * v3 +
+                                                wx[k][4] * v4;
+                                Z[k][r] += A[k][m] * xk;
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < 3; ++k)
+#pragma unroll
+                        for (int l = 0; l < 3; ++l) {
+                            const LdsT I = wy[l][0] * Z[k][0] + wy[l][1] * Z[k][1] + wy[l][2] * Z[k][2] +
+                                           wy[l][3] * Z[k][3] + wy[l][4] * Z[k][4];
+                            Y[k][l] += Bd[l][n] * (double)I;
+                        }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                // z contraction: departure point m of the receiver takes wz[m][sz] C[m][o]
+#pragma unroll
+                for (int m = 0; m < 3; ++m) {
+                    const double cz = Cd[m][o] * wz[m][sz];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k)
+#pragma unroll
+                        for (int l = 0; l < 3; ++l) acc[9 * k + 3 * l + m] += cz * Y[k][l];
+                }
+            }
+        }
+        // moments of the streamed populations (eq. 2) and the EoS closure
+        double s0 = 0.0, sx = 0.0, sy = 0.0, szm = 0.0;
+#pragma unroll
+        for (int q = 0; q < 27; ++q) {
+            s0 += acc[q];
+            sx += acc[q] * (U[0] + s * (double)(q / 9 - 1));
+            sy += acc[q] * (U[1] + s * (double)((q / 3) % 3 - 1));
+            szm += acc[q] * (U[2] + s * (double)(q % 3 - 1));
+        }
+        const double o0 = __shfl_xor(s0, 1, 64), ox = __shfl_xor(sx, 1, 64);
+        const double oy = __shfl_xor(sy, 1, 64), oz = __shfl_xor(szm, 1, 64);
+        rho = myset == 0 ? s0 : o0;
+        const double j[3] = {myset == 0 ? sx : ox, myset == 0 ? sy : oy, myset == 0 ? szm : oz};
+        const double G2 = myset == 0 ? o0 : s0;
+        const double E = G2 / (2.0 * rho);
+        double uh2 = 0.0, un[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            un[a] = j[a] / rho;
+            const double uh = un[a] + Fp[a] * dt / (2.0 * rho);
+            uh2 += uh * uh;
+        }
+        const double e = E - 0.5 * uh2;
+        const double T = vdw_T_of_e(P, rho, e);
+        const double p = vdw_p(P, rho, T);
+        if (inside) err |= vdw_bad(P, rho, p);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            sU[a] = U[a];
+            U[a] = un[a];
+        }
+        sS = s;
+        th = p / (rho * kTL);
+    }
+
+    if (inside) {
+        const size_t n = (size_t)node;
+        POND_GLOBAL double *mom = (POND_GLOBAL double *)S.mom;
+        double mc[27];
+        moments27(acc, sU[0] - U[0], sU[1] - U[1], sU[2] - U[2], sS, mc);
+        if (myset == 0) {
+            mom[(size_t)L3::kRho * N + n] = rho;
+            mom[(size_t)L3::kUx * N + n] = U[0];
+            mom[(size_t)L3::kUy * N + n] = U[1];
+            mom[(size_t)L3::kUz * N + n] = U[2];
+#pragma unroll
+            for (int i = 0; i < 27; ++i) {
+                const int si = fstored_index(i);
+                if (si >= 0) mom[(size_t)(L3::kF + si) * N + n] = mc[i];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 27; ++i) mom[(size_t)(L3::kG + i) * N + n] = mc[i];
+        }
+    }
+    if (err) raise_error3(flags, err, S.parity);
+}
+
+// ---------------------------------------------------------------------------
+// Korteweg stress K = -kappa (rho lap rho + |grad rho|^2/2) I + kappa grad rho grad rho
+// from the streamed density (planes xx, xy, xz, yy, yz, zz)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k3_korteweg(const SlotDesc *__restrict__ slot)
+{
+    const SlotDesc &S = *slot;
+    const POND_GLOBAL DevParams &P = *(const POND_GLOBAL DevParams *)S.P;
+    const Box box = make_box(P);
+    const size_t N = box.N;
+    const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N || S.flags[kFlagErr] != 0) return;
+    const int x = (int)(n % box.nx), y = (int)((n / box.nx) % box.ny), z = (int)(n / ((size_t)box.nx * box.ny));
+    const double *rho = S.mom + (size_t)L3::kRho * N;
+    const double r0 = rho[n];
+    double g[3] = {0.0, 0.0, 0.0}, lap = 0.0;
+#pragma unroll
+    for (int q = 0; q < 27; ++q) {
+        const int cx = q / 9 - 1, cy = (q / 3) % 3 - 1, cz = q % 3 - 1;
+        const double rq = rho[box.node(x + cx, y + cy, z + cz)];
+        const double w = w27(q);
+        g[0] += w * (double)cx * rq;
+        g[1] += w * (double)cy * rq;
+        g[2] += w * (double)cz * rq;
+        lap += w * (rq - r0);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) g[a] *= kInvTL;
+    lap *= 2.0 * kInvTL;
+    const double iso = -P.kappa * (r0 * lap + 0.5 * (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]));
+    double *kor = S.kor;
+    kor[0 * N + n] = iso + P.kappa * g[0] * g[0];
+    kor[1 * N + n] = P.kappa * g[0] * g[1];
+    kor[2 * N + n] = P.kappa * g[0] * g[2];
+    kor[3 * N + n] = iso + P.kappa * g[1] * g[1];
+    kor[4 * N + n] = P.kappa * g[1] * g[2];
+    kor[5 * N + n] = iso + P.kappa * g[2] * g[2];
+}
+
+__device__ __forceinline__ void force_at3(const Box &box, const double *kor, int x, int y, int z, double F[3])
+{
+    const size_t N = box.N;
+    double dv[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < 27; ++q) {
+        const int c[3] = {q / 9 - 1, (q / 3) % 3 - 1, q % 3 - 1};
+        const size_t m = box.node(x + c[0], y + c[1], z + c[2]);
+        const double w = w27(q);
+        const double kxx = kor[0 * N + m], kxy = kor[1 * N + m], kxz = kor[2 * N + m];
+        const double kyy = kor[3 * N + m], kyz = kor[4 * N + m], kzz = kor[5 * N + m];
+        dv[0] += w * (kxx * c[0] + kxy * c[1] + kxz * c[2]);
+        dv[1] += w * (kxy * c[0] + kyy * c[1] + kyz * c[2]);
+        dv[2] += w * (kxz * c[0] + kyz * c[1] + kzz * c[2]);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) F[a] = -dv[a] * kInvTL;
+}
+
+// ---------------------------------------------------------------------------
+// force and thermodynamic state of the step: aux planes F_x, F_y, F_z, T, h, mu, k, p
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k3_thermo(const SlotDesc *__restrict__ slot)
+{
+    const SlotDesc &S = *slot;
+    const POND_GLOBAL DevParams &P = *(const POND_GLOBAL DevParams *)S.P;
+    const Box box = make_box(P);
+    const size_t N = box.N;
+    const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N || S.flags[kFlagErr] != 0) return;
+    const int x = (int)(n % box.nx), y = (int)((n / box.nx) % box.ny), z = (int)(n / ((size_t)box.nx * box.ny));
+    const double *mom = S.mom;
+    double F[3] = {0.0, 0.0, 0.0};
+    if (P.kappa != 0.0) force_at3(box, S.kor, x, y, z, F);
+    const double rho = mom[L3::kRho * N + n];
+    const double h_r = 0.5 / rho;
+    const double E = mom[(size_t)L3::kG * N + n] * h_r;
+    double uh2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double uh = mom[(size_t)(L3::kUx + a) * N + n] + F[a] * P.dt * h_r;
+        uh2 += uh * uh;
+    }
+    const double e = E - 0.5 * uh2;
+    const double T = vdw_T_of_e(P, rho, e);
+    const double p = vdw_p(P, rho, T);
+    const int bad = vdw_bad(P, rho, p);
+    if (bad) raise_error3(S.flags, bad, S.parity);
+    const double mu = (1.0 / P.omega - 0.5) * p * P.dt;
+    double *aux = S.aux;
+    aux[0 * N + n] = F[0];
+    aux[1 * N + n] = F[1];
+    aux[2 * N + n] = F[2];
+    aux[3 * N + n] = T;
+    aux[4 * N + n] = e + 2.0 * p * h_r;
+    aux[5 * N + n] = mu;
+    aux[6 * N + n] = P.k_scale * mu * P.Cp_ig;
+    aux[7 * N + n] = p;
+}
+
+// ---------------------------------------------------------------------------
+// collision (eqs. 9, 16-22): blockIdx.y = 0 collides f, 1 collides g
+// ---------------------------------------------------------------------------
+template <typename PopT>
+__global__ void __launch_bounds__(256) k3_collide(const SlotDesc *__restrict__ slot)
+{
+    const SlotDesc &S = *slot;
+    const POND_GLOBAL DevParams &P = *(const POND_GLOBAL DevParams *)S.P;
+    const Box box = make_box(P);
+    const size_t N = box.N;
+    const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int set = blockIdx.y;
+    if (n >= N || S.flags[kFlagErr] != 0) return;
+    const double *mom = S.mom, *aux = S.aux;
+    const double dt = P.dt;
+    const double rho = mom[L3::kRho * N + n];
+    const double i_rho = 1.0 / rho;
+    const double u[3] = {mom[L3::kUx * N + n], mom[L3::kUy * N + n], mom[L3::kUz * N + n]};
+    const double F[3] = {aux[0 * N + n], aux[1 * N + n], aux[2 * N + n]};
+    const double p = aux[7 * N + n];
+    const double theta = p * i_rho * kInvTL;
+    const double s = sqrt(theta);
+
+    double mc[27];
+    if (set == 0) {
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            const int si = fstored_index(i);
+            mc[i] = si >= 0 ? mom[(size_t)(L3::kF + si) * N + n] : 0.0;
+        }
+        mc[0] = rho;
+    } else {
+#pragma unroll
+        for (int i = 0; i < 27; ++i) mc[i] = mom[(size_t)(L3::kG + i) * N + n];
+    }
+    double A[3][3];
+    lagrange_coeffs(0.0, s, A);
+    double pop[27], post[27];
+    from_moments27(A, mc, pop);
+    POND_GLOBAL PopT *pout = (POND_GLOBAL PopT *)S.pop_dst;
+
+    if (set == 0) {
+        // f: BGK towards rho W plus the force source, per axis rho prod (W + sigma) - rho W
+        const double i_theta = 1.0 / theta, i_s = s * i_theta;
+        double sg[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) source_axis(F[a] * dt * i_rho, i_theta, i_s, sg[a]);
+#pragma unroll
+        for (int q = 0; q < 27; ++q) {
+            const int k = q / 9, l = (q / 3) % 3, m = q % 3;
+            const double Wq = kW1[k] * kW1[l] * kW1[m];
+            const double Sq = rho * ((kW1[k] + sg[0][k]) * (kW1[l] + sg[1][l]) * (kW1[m] + sg[2][m]) - Wq);
+            post[q] = pop[q] + P.omega * (rho * Wq - pop[q]) + Sq;
+        }
+        store_set<3, PopT>(pout, N, (int)n, 0, post);
+        POND_GLOBAL double *side = (POND_GLOBAL double *)S.side_dst;
+        side[kSideUx * N + n] = u[0];
+        side[kSideUy * N + n] = u[1];
+        side[kSideUz * N + n] = u[2];
+        side[kSideTh * N + n] = theta;
+        side[kSideFx * N + n] = F[0];
+        side[kSideFy * N + n] = F[1];
+        side[kSideFz * N + n] = F[2];
+        return;
+    }
+
+    // heat-flux correction M0 = 2 div(-mu grad h + k grad T), flux form (eq. 9)
+    double M0 = 0.0;
+    if (P.k_scale >= 0.0) {
+        const int x = (int)(n % box.nx), y = (int)((n / box.nx) % box.ny), z = (int)(n / ((size_t)box.nx * box.ny));
+        const double T0 = aux[3 * N + n], h0 = aux[4 * N + n], m0 = aux[5 * N + n], k0 = aux[6 * N + n];
+        double accm = 0.0;
+#pragma unroll
+        for (int q = 0; q < 27; ++q) {
+            const size_t m = box.node(x + q / 9 - 1, y + (q / 3) % 3 - 1, z + q % 3 - 1);
+            const double kmid = 0.5 * (aux[6 * N + m] + k0);
+            const double mmid = 0.5 * (aux[5 * N + m] + m0);
+            accm += w27(q) * (kmid * (aux[3 * N + m] - T0) - mmid * (aux[4 * N + m] - h0));
+        }
+        M0 = 2.0 * (2.0 * kInvTL) * accm;
+    }
+    // g: BGK towards the force-extended equilibrium plus (g~ + phi) dt (eqs. 19-22)
+    const double i_p = 1.0 / p;
+    const double E = 0.5 * mc[0] * i_rho;
+    double uh[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) uh[a] = u[a] + 0.5 * F[a] * dt * i_rho;
+    const double Pr = p * i_rho, H = E + Pr, dt_Pr = dt * rho * i_p;
+    double X[3][3], M[3], Nm[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) X[a][b] = uh[a] * F[b] + F[a] * uh[b] + 0.5 * dt * F[a] * F[b] * E * i_p;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double xu = X[a][0] * u[0] + X[a][1] * u[1] + X[a][2] * u[2];
+        M[a] = dt_Pr * (F[a] * H - xu);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) Nm[a][b] = (a == b ? rho : 0.0) + 0.5 * dt_Pr * X[a][b];
+    }
+    const double work = 2.0 * (uh[0] * F[0] + uh[1] * F[1] + uh[2] * F[2]);
+    const double c_uc = 0.5 * kInvTL * rho * i_p, c_v2 = 0.5 * rho * i_p;
+#pragma unroll
+    for (int q = 0; q < 27; ++q) {
+        const double c[3] = {(double)(q / 9 - 1), (double)((q / 3) % 3 - 1), (double)(q % 3 - 1)};
+        double v[3], t1 = 0.0, t2 = 0.0, uc = 0.0, v2 = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            v[a] = u[a] + s * c[a];
+            uc += u[a] * c[a];
+            v2 += v[a] * v[a];
+            t1 += M[a] * (v[a] - u[a]);
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) t2 += Nm[a][b] * (v[a] * v[b] - (a == b ? Pr : 0.0) - u[a] * u[b]);
+        const double wq = w27(q);
+        const double geq = wq * (2.0 * rho * E + t1 + t2);
+        const double psi = wq * (1.0 + c_uc * uc * uc - c_v2 * v2 + 1.5);
+        post[q] = pop[q] + P.omega * (geq - pop[q]) + (M0 + work) * psi * dt;
+    }
+    store_set<3, PopT>(pout, N, (int)n, 1, post);
+}
+
+// ---------------------------------------------------------------------------
+// initial state (streamed-state planes of the equilibrium of rho, u_hat, T with the
+// force F0 = -div K(rho)); aux planes 0-4 hold rho, u_hat (3), T, mom plane 0 rho and
+// kor the stress of rho
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k3_init_equilibrium(const SlotDesc *__restrict__ slot)
+{
+    const SlotDesc &S = *slot;
+    const POND_GLOBAL DevParams &P = *(const POND_GLOBAL DevParams *)S.P;
+    const Box box = make_box(P);
+    const size_t N = box.N;
+    const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const int x = (int)(n % box.nx), y = (int)((n / box.nx) % box.ny), z = (int)(n / ((size_t)box.nx * box.ny));
+    const double *aux = S.aux;
+    double *mom = S.mom;
+    double F[3] = {0.0, 0.0, 0.0};
+    if (P.kappa != 0.0) force_at3(box, S.kor, x, y, z, F);
+    const double rho = aux[0 * N + n], T = aux[4 * N + n];
+    const double uh[3] = {aux[1 * N + n], aux[2 * N + n], aux[3 * N + n]};
+    double u[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) u[a] = uh[a] - F[a] * P.dt / (2.0 * rho);
+    const double p = vdw_p(P, rho, T);
+    const int bad = vdw_bad(P, rho, p);
+    if (bad) raise_error3(S.flags, bad, 0);
+    const double e = P.Cv * T - P.a * rho;
+    const double E = e + 0.5 * (uh[0] * uh[0] + uh[1] * uh[1] + uh[2] * uh[2]);
+    const double theta = p / (rho * kTL), s = sqrt(theta);
+    // f = rho W: central moments rho prod_axes {1, 0, theta T_L}
+    const double mu1[3] = {1.0, 0.0, theta * kTL};
+    mom[(size_t)L3::kRho * N + n] = rho;
+    mom[(size_t)L3::kUx * N + n] = u[0];
+    mom[(size_t)L3::kUy * N + n] = u[1];
+    mom[(size_t)L3::kUz * N + n] = u[2];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const int si = fstored_index(i);
+        if (si >= 0) mom[(size_t)(L3::kF + si) * N + n] = rho * mu1[i / 9] * mu1[(i / 3) % 3] * mu1[i % 3];
+    }
+    // g = g^eq (eqs. 20-22) in the gauge (u, theta), then its central moments
+    const double Pr = p / rho, H = E + Pr;
+    double X[3][3], M[3], Nm[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) X[a][b] = uh[a] * F[b] + F[a] * uh[b] + P.dt * F[a] * F[b] * E / (2.0 * p);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double xu = X[a][0] * u[0] + X[a][1] * u[1] + X[a][2] * u[2];
+        M[a] = P.dt / Pr * (F[a] * H - xu);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) Nm[a][b] = (a == b ? rho : 0.0) + P.dt / (2.0 * Pr) * X[a][b];
+    }
+    double g[27];
+#pragma unroll
+    for (int q = 0; q < 27; ++q) {
+        const double c[3] = {(double)(q / 9 - 1), (double)((q / 3) % 3 - 1), (double)(q % 3 - 1)};
+        double v[3], t1 = 0.0, t2 = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            v[a] = u[a] + s * c[a];
+            t1 += M[a] * (v[a] - u[a]);
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) t2 += Nm[a][b] * (v[a] * v[b] - (a == b ? Pr : 0.0) - u[a] * u[b]);
+        g[q] = w27(q) * (2.0 * rho * E + t1 + t2);
+    }
+    double mg[27];
+    moments27(g, 0.0, 0.0, 0.0, s, mg);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) mom[(size_t)(L3::kG + i) * N + n] = mg[i];
+}
+
+// ---------------------------------------------------------------------------
+// macroscopic fields: rho, u_hat (3 planes), T, p, E
+// ---------------------------------------------------------------------------
+template <typename PopT>
+__global__ void __launch_bounds__(256) k3_macro(const DevParams *__restrict__ Pp, const PopT *__restrict__ pop,
+                                                const double *__restrict__ side, double *__restrict__ out)
+{
+    const DevParams &P = *Pp;
+    const size_t N = P.N;
+    const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    double r = 0.0;
+    for (int q = 0; q < 27; ++q) r += (double)pop[(size_t)q * N + n];
+    if (kDeviationStore<PopT>) r += ((const double *)(pop + (size_t)54 * N))[n];
+    const int su[3] = {kSideUx, kSideUy, kSideUz}, sf[3] = {kSideFx, kSideFy, kSideFz};
+    double h2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double v = side[su[a] * N + n] + side[sf[a] * N + n] * P.dt / (2.0 * r);
+        out[(1 + a) * N + n] = v;
+        h2 += v * v;
+    }
+    const double pr = r * side[kSideTh * N + n] * kTL;
+    const double T = (pr + P.a * r * r) * (1.0 - P.b * r) / (r * P.R);
+    out[0 * N + n] = r;
+    out[4 * N + n] = T;
+    out[5 * N + n] = pr;
+    out[6 * N + n] = P.Cv * T - P.a * r + 0.5 * h2;
+}
+
+__global__ void __launch_bounds__(kMonThreads) k3_monitor_partials(const DevParams *__restrict__ Pp,
+                                                                   const double *__restrict__ macro,
+                                                                   const double *__restrict__ side,
+                                                                   double *__restrict__ partials)
+{
+    const DevParams &P = *Pp;
+    const Box box = make_box(P);
+    const size_t N = box.N;
+    const size_t n = (size_t)blockIdx.x * kMonThreads + threadIdx.x;
+    double v[kMonWords];
+    for (int i = 0; i < kMonWords; ++i) v[i] = 0.0;
+    v[6] = 1e300; // min p
+    if (n < N) {
+        const int x = (int)(n % box.nx), y = (int)((n / box.nx) % box.ny), z = (int)(n / ((size_t)box.nx * box.ny));
+        const double r = macro[n], E = macro[6 * N + n];
+        double g[3] = {0.0, 0.0, 0.0};
+        for (int q = 0; q < 27; ++q) {
+            const int c[3] = {q / 9 - 1, (q / 3) % 3 - 1, q % 3 - 1};
+            const double rq = macro[box.node(x + c[0], y + c[1], z + c[2])];
+            for (int a = 0; a < 3; ++a) g[a] += w27(q) * (double)c[a] * rq;
+        }
+        for (int a = 0; a < 3; ++a) g[a] *= kInvTL;
+        v[0] = r;
+        for (int a = 0; a < 3; ++a) v[1 + a] = r * macro[(1 + a) * N + n];
+        v[4] = r * E;
+        v[5] = r * E + 0.5 * P.kappa * (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+        v[6] = macro[5 * N + n];
+        const double s = sqrt(side[kSideTh * N + n]);
+        const double ax = fabs(side[kSideUx * N + n]) + s, ay = fabs(side[kSideUy * N + n]) + s;
+        const double az = fabs(side[kSideUz * N + n]) + s;
+        v[7] = sqrt(ax * ax + ay * ay + az * az) * P.dt;
+    }
+    __shared__ double red[kMonThreads / 64][kMonWords];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int i = 0; i < kMonWords; ++i) {
+        const double w = i == 6 ? wave_min(v[i]) : i == 7 ? wave_max(v[i]) : wave_sum(v[i]);
+        if (lane == 0) red[wave][i] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x < kMonWords) {
+        const int i = threadIdx.x;
+        double acc = red[0][i];
+        for (int wv = 1; wv < kMonThreads / 64; ++wv)
+            acc = i == 6 ? fmin(acc, red[wv][i]) : i == 7 ? fmax(acc, red[wv][i]) : acc + red[wv][i];
+        partials[(size_t)blockIdx.x * kMonWords + i] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+// streaming tile: 16 x 8 receivers with FP32 streaming, 8 x 8 with FP64 (LDS of the
+// 54 staged fields of one donor plane within 64 KB)
+void stream3_tile(int fp32, int *tx, int *ty)
+{
+    *tx = fp32 == 1 ? 16 : 8;
+    *ty = 8;
+}
+
+template <typename LdsT, int TX, int TY>
+static void launch_stream3_t(const LaunchCtx &c, const SlotDesc *slot)
+{
+    const int tiles = ((c.nx + TX - 1) / TX) * ((c.ny + TY - 1) / TY);
+    hipLaunchKernelGGL((k3_stream<LdsT, TX, TY>), dim3(tiles, c.nz), dim3(2 * TX, TY), 0, c.st, slot);
+}
+
+static inline dim3 grid_nodes(const LaunchCtx &c, int per = 1)
+{
+    return dim3((unsigned)(((size_t)c.N * per + 255) / 256));
+}
+
+hipError_t launch_stream3(const LaunchCtx &c, const SlotDesc *slot)
+{
+    if (c.ev_start) (void)hipEventRecord(c.ev_start, c.st);
+    if (c.fp32 == 1) {
+        hipLaunchKernelGGL((k3_donor_moments<float, float>), grid_nodes(c, 2), dim3(256), 0, c.st, slot);
+        launch_stream3_t<float, 16, 8>(c, slot);
+    } else if (c.fp32 == 2) {
+        hipLaunchKernelGGL((k3_donor_moments<float, double>), grid_nodes(c, 2), dim3(256), 0, c.st, slot);
+        launch_stream3_t<double, 8, 8>(c, slot);
+    } else {
+        hipLaunchKernelGGL((k3_donor_moments<double, double>), grid_nodes(c, 2), dim3(256), 0, c.st, slot);
+        launch_stream3_t<double, 8, 8>(c, slot);
+    }
+    if (c.ev_stop) (void)hipEventRecord(c.ev_stop, c.st);
+    return hipGetLastError();
+}
+
+// the Korteweg stress of the streamed density (mom plane 0) and the rest of the closure
+hipError_t launch_collide3(const LaunchCtx &c, const SlotDesc *slot)
+{
+    if (c.ev_start) (void)hipEventRecord(c.ev_start, c.st);
+    hipLaunchKernelGGL(k3_korteweg, grid_nodes(c), dim3(256), 0, c.st, slot);
+    hipLaunchKernelGGL(k3_thermo, grid_nodes(c), dim3(256), 0, c.st, slot);
+    dim3 g = grid_nodes(c);
+    g.y = 2;
+    if (c.fp32)
+        hipLaunchKernelGGL((k3_collide<float>), g, dim3(256), 0, c.st, slot);
+    else
+        hipLaunchKernelGGL((k3_collide<double>), g, dim3(256), 0, c.st, slot);
+    if (c.ev_stop) (void)hipEventRecord(c.ev_stop, c.st);
+    return hipGetLastError();
+}
+
+hipError_t launch_init3(const LaunchCtx &c, const DevState &s, const SlotDesc *slot)
+{
+    // rho of the initial state into mom plane 0, its stress, then the equilibrium planes
+    hipError_t e = hipMemcpyAsync(s.mom, s.aux, sizeof(double) * (size_t)c.N, hipMemcpyDeviceToDevice, c.st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k3_korteweg, grid_nodes(c), dim3(256), 0, c.st, slot);
+    hipLaunchKernelGGL(k3_init_equilibrium, grid_nodes(c), dim3(256), 0, c.st, slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_macro3(const LaunchCtx &c, const DevState &s, int cur, double *out)
+{
+    if (c.fp32)
+        hipLaunchKernelGGL((k3_macro<float>), grid_nodes(c), dim3(256), 0, c.st, s.params, (const float *)s.pop[cur],
+                           s.side[cur], out);
+    else
+        hipLaunchKernelGGL((k3_macro<double>), grid_nodes(c), dim3(256), 0, c.st, s.params,
+                           (const double *)s.pop[cur], s.side[cur], out);
+    return hipGetLastError();
+}
+
+hipError_t launch_monitors3(const LaunchCtx &c, const DevState &s, int cur, double *partials, int nblocks,
+                            double *out)
+{
+    hipError_t e = launch_macro3(c, s, cur, s.aux);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k3_monitor_partials, dim3(nblocks), dim3(kMonThreads), 0, c.st, s.params, s.aux,
+                       s.side[cur], partials);
+    return launch_monitor_final(c, partials, nblocks, out);
+}
+
+} // namespace pond

@@ -137,7 +137,7 @@ class Config:
         n = tuple(self.n) + (1,) * (3 - len(self.n))
         for i in range(3):
             c.n[i] = int(n[i])
-        for a in range(min(self.dim, 2)):
+        for a in range(min(self.dim, len(self.bc), 3)):
             for s in range(2):
                 c.bc[a][s] = int(self.bc[a][s])
         for a, s, st in self.inflow:
@@ -204,7 +204,9 @@ class Lattice:
         rho, u, T, p, E = np.empty(N), np.empty(dim * N), np.empty(N), np.empty(N), np.empty(N)
         self._check(load().pond_moments(self._h, _dp(rho), _dp(u), _dp(T), _dp(p), _dp(E)), "pond_moments")
         out = {"rho": rho, "ux": u[:N], "T": T, "p": p, "E": E}
-        out["uy"] = u[N:] if dim == 2 else np.zeros(N)
+        out["uy"] = u[N:2 * N] if dim >= 2 else np.zeros(N)
+        if dim == 3:
+            out["uz"] = u[2 * N:]
         return out
 
     def monitors(self) -> dict:

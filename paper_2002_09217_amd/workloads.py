@@ -168,6 +168,47 @@ def perturbed(nx, ny, seed, dim=2, rho0=2.0, t_over_tcr=1.05, u0=(0.0, 0.0), amp
                 rho=rho.ravel(), u=u, T=T.ravel(), meta=dict(seed=seed))
 
 
+def perturbed3(nx, ny, nz, seed, rho0=2.0, t_over_tcr=1.05, u0=(0.0, 0.0, 0.0), amp=0.05, modes=3,
+               **kw) -> Case:
+    """Smooth seeded single-phase state on a periodic nx x ny x nz box (D3Q27): a few
+    random Fourier modes on rho, u and T.  numpy PCG64 with the given seed."""
+    rng = np.random.default_rng(seed)
+    Z, Y, X = np.meshgrid(np.arange(nz, dtype=float), np.arange(ny, dtype=float), np.arange(nx, dtype=float),
+                          indexing="ij")  # x fastest
+
+    def field_(scale):
+        f = np.zeros_like(X)
+        for _ in range(modes):
+            k = rng.integers(1, 4), rng.integers(0, 4), rng.integers(0, 4)
+            ph = rng.uniform(0.0, 2.0 * np.pi)
+            f += rng.uniform(-1.0, 1.0) * np.sin(2 * np.pi * (k[0] * X / nx + k[1] * Y / ny + k[2] * Z / nz) + ph)
+        return scale * f / modes
+
+    rho = rho0 * (1.0 + field_(amp))
+    T = t_over_tcr * T_CR * (1.0 + field_(0.2 * amp))
+    u = np.stack([(u0[a] + field_(0.4 * amp)).ravel() for a in range(3)])
+    return Case(name=f"perturbed3_{nx}x{ny}x{nz}s{seed}", dim=3, n=(nx, ny, nz),
+                bc=((PERIODIC, PERIODIC), (PERIODIC, PERIODIC), (PERIODIC, PERIODIC)),
+                params=base_params(**kw), rho=rho.ravel(), u=u, T=T.ravel(), meta=dict(seed=seed))
+
+
+def static_droplet3(n=256, t_over_tcr=0.9, radius=48.0, width=4.0, steps=2000, **kw) -> Case:
+    """Subcritical static droplet on a periodic n^3 box (D3Q27), centred, tanh profile
+    of the given width between the Maxwell densities (radius 48 on 256^3 by default)."""
+    rv, rl = coexistence(t_over_tcr)
+    c = n / 2.0
+    z, y, x = np.meshgrid(np.arange(n, dtype=float), np.arange(n, dtype=float), np.arange(n, dtype=float),
+                          indexing="ij")
+    r = np.sqrt((x - c) ** 2 + (y - c) ** 2 + (z - c) ** 2)
+    rho = (0.5 * (rl + rv) - 0.5 * (rl - rv) * np.tanh(2.0 * (r - radius) / width)).ravel()
+    N = n ** 3
+    return Case(name=f"droplet3d{n}", dim=3, n=(n, n, n),
+                bc=((PERIODIC, PERIODIC), (PERIODIC, PERIODIC), (PERIODIC, PERIODIC)),
+                params=base_params(**{"omega": 1.5, "kappa": KAPPA_DROPLET, "dt": DT_DROPLET, **kw}),
+                rho=rho, u=np.zeros((3, N)), T=np.full(N, t_over_tcr * T_CR), steps=steps,
+                meta=dict(rho_v=rv, rho_l=rl, radius=radius, t_over_tcr=t_over_tcr))
+
+
 def serving_jobs(count=64, seed=0, steps=5000, rate=20.0, sides=(64, 128, 256, 512)):
     """Batched-serving workload: seeded D2Q9 droplet jobs with sides drawn from `sides`,
     T/T_cr uniform in [0.85, 1.10] (snapped to the 0.005 grid of the coexistence table),

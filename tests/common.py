@@ -40,6 +40,20 @@ def run_oracle(case, steps):
     return sim.moments()
 
 
+def oracle_config3(case) -> core.Config3:
+    p = case.params
+    return core.Config3(nx=case.n[0], ny=case.n[1], nz=case.n[2], a=p["a"], b=p["b"], R=p["R"],
+                        delta=p["delta"], omega=p["omega"], kappa=p["kappa"], k_scale=p["k_scale"],
+                        dt=p["dt"], n_pass=p["n_pass"])
+
+
+def run_oracle3(case, steps):
+    sim = core.Sim3(oracle_config3(case)).init(case.rho, case.u, case.T)
+    if steps:
+        sim.step(steps)
+    return sim.moments()
+
+
 def run_gpu(case, steps, precision=pond.FP64, tile=-1):
     lat = pond.Lattice(pond_config(case, precision, tile=tile))
     try:
@@ -54,7 +68,7 @@ def run_gpu(case, steps, precision=pond.FP64, tile=-1):
 def rel_err(a, b, field):
     """Relative L-infinity error; velocities against max(max|b|, U_ch)."""
     den = np.max(np.abs(b))
-    if field in ("ux", "uy"):
+    if field in ("ux", "uy", "uz"):
         den = max(den, U_CH)
     return float(np.max(np.abs(a - b)) / den)
 
