@@ -15,6 +15,7 @@ whole lattice.  Prints one JSON line:
   configs      configs 1-3 (1D shock tube, the droplet for its full 20000 steps, the
                1024 x 512 droplet-shock interaction) in both precisions: time per step,
                MLUPS and the error of both FP32-storage forms against the FP64 path;
+  config5_d3q27  the 256^3 D3Q27 droplet on a sample of 10 steps, FP32 storage and FP64;
   serving      the batched-serving workload (64 seeded droplet jobs of mixed sides and
                temperatures, Poisson arrivals at 20/s, 5000 steps each) through the
                continuous-batching server and one job at a time: runs/s, p50/p99
@@ -150,6 +151,39 @@ def config_runs(stream):
     return out
 
 
+def config5_sample(stream, steps=10, warmup=3):
+    """Config 5, the 256^3 D3Q27 droplet, on a sample of steps (the full run is 2000):
+    MLUPS from graph-replayed steps between synchronisations, per-group kernel times and
+    monitors, in FP32 storage (the configuration's precision) and FP64."""
+    import torch
+
+    from paper_2002_09217_amd import pond, workloads as W
+    from paper_2002_09217_amd.serve import lattice_config
+
+    case = W.static_droplet3(n=256)
+    out = {"workload": "3D static droplet D3Q27 256^3 periodic, T=0.9 T_cr, R=48, tanh width 4, "
+                       "kappa=0.0176, omega=1.5, dt=0.1", "steps_timed": steps, "nodes": case.N}
+    for name, prec in (("fp32_store", pond.FP32_STORE), ("fp64", pond.FP64)):
+        lat = pond.Lattice(lattice_config(case, prec, -1, stream))
+        lat.init_fields(case.rho, case.u, case.T)
+        lat.step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.step(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        kern = lat.step_timed(2)
+        mon = lat.monitors()
+        lat.close()
+        out[name] = {"mlups": round(case.N * steps / el / 1e6, 1), "ms_per_step": round(1e3 * el / steps, 2),
+                     "groups_us": {"stream": round(kern["k_stream"], 1), "collide": round(kern["k_force_collide"], 1)},
+                     "stream_tflops": round(cost.stream_flops_per_node(3, case.params["n_pass"]) * case.N /
+                                            (kern["k_stream"] * 1e-6) / 1e12, 2),
+                     "min_p": mon["min_p"], "max_v_dt": mon["max_v_dt"]}
+        log(f"bench: config 5 {name} {out[name]}")
+    return out
+
+
 def cpu_baseline(case, budget_s):
     from oracle import core
     from tests.common import oracle_config
@@ -180,6 +214,7 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the 2048 x 2048 lattice")
     ap.add_argument("--serving-jobs", type=int, default=64)
     ap.add_argument("--no-configs", action="store_true", help="skip the full-length runs of configs 1-3")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 256^3 D3Q27 sample (config 5)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device-to-device copy of this many MiB (5 times), whose "
                          "FETCH_SIZE/WRITE_SIZE counters calibrate the HBM-traffic readings")
@@ -237,6 +272,7 @@ def main():
             log(f"bench: 2048^2 {name} {ml:.1f} MLUPS, kernels (us): {kb}")
 
     configs = None if args.no_configs else config_runs(stream.cuda_stream)
+    config5 = None if args.no_3d else config5_sample(stream.cuda_stream)
 
     serve_out = None
     if not args.no_serving:
@@ -295,6 +331,7 @@ def main():
         "monitors_after": {"mass": mon64["mass"], "min_p": mon64["min_p"], "max_v_dt": mon64["max_v_dt"]},
         "large": large,
         "configs": configs,
+        "config5_d3q27": config5,
         "serving": serve_out,
         "cpu_baseline": cpu,
     }

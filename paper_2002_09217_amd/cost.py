@@ -40,6 +40,12 @@ def stream_bytes_per_node(dim: int, fp32_store: bool) -> int:
 
 
 def stream_flops_per_node(dim: int, n_pass: int) -> int:
+    if dim == 3:
+        # per z-window plane and z power: the D2Q9 x-y contraction of 9 fields (972 FMA
+        # with the zero taps) and 27 FMA of the z contraction; 5 planes x 3 powers per set
+        per_set_pass = 5 * 3 * (972 + 27)
+        fixed_pass = 3 * 16 + 3 * 20 + 81 + 20           # weights, Lagrange coeffs, moments, EoS
+        return n_pass * (2 * per_set_pass * 2 + 2 * fixed_pass) + 2 * 250 + 2 * 250
     if dim == 2:
         per_field = 2 * (3 * 5 * 4 + 9 * 4 + 9) + 9   # 2 x 105 FMA + 9 MUL = 219
         fields = 18

@@ -183,13 +183,25 @@ __global__ void __launch_bounds__(256) k3_donor_moments(const SlotDesc *__restri
 
 // ---------------------------------------------------------------------------
 // streaming passes: x-y tile of TX x TY receivers of one z plane, two lanes per
-// receiver (set f / g), the 5 x 5 x 5 window staged plane by plane
+// receiver (set f / g), the 5 x 5 x 5 window staged plane by plane.
+//
+// Interpolation and contraction are linear in the donor moments, and every cubic
+// Lagrange stencil reproduces a constant exactly.  In the FP32 form the LDS therefore
+// holds each donor moment minus a reference value of the tile (the moment of the tile's
+// centre node in the receiver plane): the FP32 window arithmetic then carries only the
+// variation across the tile, and the reference part, the same for every donor, is
+// contracted with the receiver's gauge coefficients in FP64.  A uniform region is so
+// streamed exactly, and the FP32 rounding scales with the local variation, not with
+// the moment itself.
 // ---------------------------------------------------------------------------
 template <typename LdsT, int TX, int TY>
-__global__ void __launch_bounds__(2 * TX *TY) k3_stream(const SlotDesc *__restrict__ slot)
+__global__ void __launch_bounds__(2 * TX *TY, sizeof(LdsT) == 4 ? 2 : 1) k3_stream(const SlotDesc *__restrict__ slot)
 {
     constexpr int LX = TX + 4, LY = TY + 4, LN = LX * LY, NT = 2 * TX * TY;
+    constexpr bool kDev = sizeof(LdsT) == 4;
+    using AccT = LdsT; // window accumulators: FP64, or FP32 deviations
     __shared__ LdsT lds[2 * 27 * LN];
+    __shared__ LdsT ref[kDev ? 54 : 1];
     __shared__ int abort_block;
     const SlotDesc &S = *slot;
     const POND_GLOBAL DevParams &P = *(const POND_GLOBAL DevParams *)S.P;
@@ -200,15 +212,24 @@ __global__ void __launch_bounds__(2 * TX *TY) k3_stream(const SlotDesc *__restri
     int err_before = 0;
     if (tid == 0) err_before = flags[kFlagErr];
 
+    // Block order: blocks are dealt to the XCDs in turn; xcd_tile gives each XCD a
+    // contiguous range of logical blocks, and z runs fastest in that range, so the
+    // blocks one XCD runs together are consecutive planes of one tile column and
+    // re-read their shared donor planes from that XCD's L2.
     const int tiles_x = (box.nx + TX - 1) / TX;
-    const int bx0 = (blockIdx.x % tiles_x) * TX, by0 = (blockIdx.x / tiles_x) * TY;
-    const int z = blockIdx.y;
+    const int lb = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    const int tile = lb / box.nz, z = lb - tile * box.nz;
+    const int bx0 = (tile % tiles_x) * TX, by0 = (tile / tiles_x) * TY;
     const int lxr = (int)threadIdx.x >> 1, myset = (int)threadIdx.x & 1;
     const int gx = bx0 + lxr, gy = by0 + (int)threadIdx.y;
     const bool inside = gx < box.nx && gy < box.ny;
     const int node = min(gx, box.nx - 1) + box.nx * (min(gy, box.ny - 1) + box.ny * z);
     const POND_GLOBAL double *side = (const POND_GLOBAL double *)S.side_src;
     const POND_GLOBAL LdsT *dmom = (const POND_GLOBAL LdsT *)S.dmom;
+    if (kDev && tid < 54) {
+        const int cnode = min(bx0 + TX / 2, box.nx - 1) + box.nx * (min(by0 + TY / 2, box.ny - 1) + box.ny * z);
+        ref[tid] = dmom[(size_t)tid * N + cnode]; // ordered before its readers by the first barrier
+    }
     double U[3] = {side[kSideUx * N + node], side[kSideUy * N + node], side[kSideUz * N + node]};
     double th = side[kSideTh * N + node];
     const double Fp[3] = {side[kSideFx * N + node], side[kSideFy * N + node], side[kSideFz * N + node]};
@@ -221,21 +242,29 @@ __global__ void __launch_bounds__(2 * TX *TY) k3_stream(const SlotDesc *__restri
     for (int pass = 0; pass < P.n_pass; ++pass) {
         const double s = sqrt(th);
         LdsT wx[3][5], wy[3][5];
-        double wz[3][5];
+        AccT wz[3][5];
         const int werr = window_weights<LdsT>(U[0], s, dt, wx) | window_weights<LdsT>(U[1], s, dt, wy) |
-                         window_weights<double>(U[2], s, dt, wz);
+                         window_weights<AccT>(U[2], s, dt, wz);
         if (inside) err |= werr; // lanes past the lattice edge only pad the tile
-        double Ad[3][3], Bd[3][3], Cd[3][3];
-        lagrange_coeffs(U[0], s, Ad);
-        lagrange_coeffs(U[1], s, Bd);
-        lagrange_coeffs(U[2], s, Cd);
         LdsT A[3][3];
+        AccT B[3][3], C[3][3];
+        {
+            double Ad[3][3], Bd[3][3], Cd[3][3];
+            lagrange_coeffs(U[0], s, Ad);
+            lagrange_coeffs(U[1], s, Bd);
+            lagrange_coeffs(U[2], s, Cd);
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
+            for (int k = 0; k < 3; ++k)
 #pragma unroll
-            for (int m = 0; m < 3; ++m) A[k][m] = (LdsT)Ad[k][m];
+                for (int m = 0; m < 3; ++m) {
+                    A[k][m] = (LdsT)Ad[k][m];
+                    B[k][m] = (AccT)Bd[k][m];
+                    C[k][m] = (AccT)Cd[k][m];
+                }
+        }
+        AccT av[27];
 #pragma unroll
-        for (int q = 0; q < 27; ++q) acc[q] = 0.0;
+        for (int q = 0; q < 27; ++q) av[q] = (AccT)0;
 
 #pragma unroll 1
         for (int sz = 0; sz < 5; ++sz) {
@@ -263,12 +292,19 @@ __global__ void __launch_bounds__(2 * TX *TY) k3_stream(const SlotDesc *__restri
                 }
 #pragma unroll
                 for (int u = 0; u < CH; ++u)
-                    if (dst[u] >= 0) lds[dst[u]] = tmp[u];
+                    if (dst[u] >= 0) {
+                        if (kDev) {
+                            const int c = (dst[u] >> 1) / LN + 27 * (dst[u] & 1);
+                            lds[dst[u]] = tmp[u] - ref[c];
+                        } else {
+                            lds[dst[u]] = tmp[u];
+                        }
+                    }
             }
             if (pass == 0 && sz == 0 && tid == 0) {
                 abort_block = err_before;
                 // one step more has started without an earlier failure
-                if (blockIdx.x == 0 && blockIdx.y == 0 && err_before == 0) atomicAdd(&flags[kFlagSteps], 1);
+                if (blockIdx.x == 0 && err_before == 0) atomicAdd(&flags[kFlagSteps], 1);
             }
             __syncthreads();
             if (abort_block != 0) return;
@@ -276,11 +312,11 @@ __global__ void __launch_bounds__(2 * TX *TY) k3_stream(const SlotDesc *__restri
             const LdsT *sbase = &lds[wbase * 2 + myset];
 #pragma unroll 1
             for (int o = 0; o < 3; ++o) {
-                double Y[3][3];
+                AccT Y[3][3];
 #pragma unroll
                 for (int k = 0; k < 3; ++k)
 #pragma unroll
-                    for (int l = 0; l < 3; ++l) Y[k][l] = 0.0;
+                    for (int l = 0; l < 3; ++l) Y[k][l] = (AccT)0;
 #pragma unroll
                 for (int n = 0; n < 3; ++n) {
                     LdsT Z[3][5];
@@ -308,20 +344,55 @@ __global__ void __launch_bounds__(2 * TX *TY) k3_stream(const SlotDesc *__restri
                         for (int l = 0; l < 3; ++l) {
                             const LdsT I = wy[l][0] * Z[k][0] + wy[l][1] * Z[k][1] + wy[l][2] * Z[k][2] +
                                            wy[l][3] * Z[k][3] + wy[l][4] * Z[k][4];
-                            Y[k][l] += Bd[l][n] * (double)I;
+                            Y[k][l] += B[l][n] * (AccT)I;
                         }
                     __builtin_amdgcn_sched_barrier(0);
                 }
                 // z contraction: departure point m of the receiver takes wz[m][sz] C[m][o]
 #pragma unroll
                 for (int m = 0; m < 3; ++m) {
-                    const double cz = Cd[m][o] * wz[m][sz];
+                    const AccT cz = C[m][o] * wz[m][sz];
 #pragma unroll
                     for (int k = 0; k < 3; ++k)
 #pragma unroll
-                        for (int l = 0; l < 3; ++l) acc[9 * k + 3 * l + m] += cz * Y[k][l];
+                        for (int l = 0; l < 3; ++l) av[9 * k + 3 * l + m] += cz * Y[k][l];
                 }
             }
+        }
+        if (kDev) {
+            // reference part: sum_mno A_km B_ln C_m'o R_mno in FP64 (the window weights of
+            // each axis sum to one).  The inputs pass an empty asm so that the coefficients
+            // are recomputed here rather than kept live across the window loop.
+            double su = s, u0 = U[0], u1 = U[1], u2 = U[2];
+            asm volatile("" : "+v"(su), "+v"(u0), "+v"(u1), "+v"(u2));
+            double Ad[3][3], Bd[3][3], Cd[3][3];
+            lagrange_coeffs(u0, su, Ad);
+            lagrange_coeffs(u1, su, Bd);
+            lagrange_coeffs(u2, su, Cd);
+            const LdsT *R = &ref[27 * myset];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                double T1[3][3]; // [n][o]
+#pragma unroll
+                for (int n = 0; n < 3; ++n)
+#pragma unroll
+                    for (int o = 0; o < 3; ++o)
+                        T1[n][o] = Ad[k][0] * (double)R[3 * n + o] + Ad[k][1] * (double)R[9 + 3 * n + o] +
+                                   Ad[k][2] * (double)R[18 + 3 * n + o];
+#pragma unroll
+                for (int l = 0; l < 3; ++l) {
+                    double T2[3];
+#pragma unroll
+                    for (int o = 0; o < 3; ++o) T2[o] = Bd[l][0] * T1[0][o] + Bd[l][1] * T1[1][o] + Bd[l][2] * T1[2][o];
+#pragma unroll
+                    for (int m = 0; m < 3; ++m)
+                        acc[9 * k + 3 * l + m] =
+                            (Cd[m][0] * T2[0] + Cd[m][1] * T2[1] + Cd[m][2] * T2[2]) + (double)av[9 * k + 3 * l + m];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 27; ++q) acc[q] = (double)av[q];
         }
         // moments of the streamed populations (eq. 2) and the EoS closure
         double s0 = 0.0, sx = 0.0, sy = 0.0, szm = 0.0;
@@ -773,7 +844,7 @@ template <typename LdsT, int TX, int TY>
 static void launch_stream3_t(const LaunchCtx &c, const SlotDesc *slot)
 {
     const int tiles = ((c.nx + TX - 1) / TX) * ((c.ny + TY - 1) / TY);
-    hipLaunchKernelGGL((k3_stream<LdsT, TX, TY>), dim3(tiles, c.nz), dim3(2 * TX, TY), 0, c.st, slot);
+    hipLaunchKernelGGL((k3_stream<LdsT, TX, TY>), dim3(tiles * c.nz), dim3(2 * TX, TY), 0, c.st, slot);
 }
 
 static inline dim3 grid_nodes(const LaunchCtx &c, int per = 1)

@@ -1,0 +1,103 @@
+"""D3Q27 behaviour of the HIP path through the C ABI beyond field parity: monitors equal
+the sums of the oracle's fields, checkpoints resume bitwise, and a small isentropic
+pulse along each axis of a periodic box travels at the adiabatic van der Waals sound
+speed (App. A)."""
+import numpy as np
+import pytest
+
+from oracle.thermo import VdW
+from paper_2002_09217_amd import pond, workloads as W
+from tests.common import pond_config, pulse_speed, run_oracle3
+
+pytestmark = pytest.mark.gpu
+VDW = VdW()
+
+
+def _fields(m):
+    return np.concatenate([m[k] for k in ("rho", "ux", "uy", "uz", "T", "p", "E")])
+
+
+def test_monitors_match_oracle_sums():
+    case = W.static_droplet3(n=20, radius=6.0)
+    lat = pond.Lattice(pond_config(case))
+    lat.init_fields(case.rho, case.u, case.T)
+    lat.step(6)
+    mon = lat.monitors()
+    lat.close()
+    ref = run_oracle3(case, 6)
+    rho, E = ref["rho"], ref["E"]
+    assert mon["mass"] == pytest.approx(np.sum(rho), rel=1e-13)
+    for a, k in enumerate(("ux", "uy", "uz")):
+        assert mon["momentum"][a] == pytest.approx(np.sum(rho * ref[k]), abs=1e-12 * np.sum(rho))
+    assert mon["energy"] == pytest.approx(np.sum(rho * E), rel=1e-13)
+    assert mon["min_p"] == pytest.approx(np.min(ref["p"]), rel=1e-12)
+    assert mon["energy_total"] > mon["energy"]
+    assert 0.0 < mon["max_v_dt"] < 1.0
+
+
+@pytest.mark.parametrize("precision", [pond.FP64, pond.FP32_STORE, pond.FP32_STORE_FP64_MATH])
+def test_resume_is_bitwise(precision):
+    case = W.perturbed3(18, 13, 9, seed=5, kappa=0.0176, u0=(0.05, 0.02, -0.04), dt=0.2)
+    a = pond.Lattice(pond_config(case, precision=precision))
+    a.init_fields(case.rho, case.u, case.T)
+    a.step(7)
+    ck = a.save()
+    a.step(9)
+    ref = _fields(a.moments())
+    b = pond.Lattice(pond_config(case, precision=precision))
+    b.load(ck)
+    assert b.steps_done() == 7
+    b.step(9)
+    assert b.steps_done() == 16
+    assert np.array_equal(_fields(b.moments()), ref)
+    a.close()
+    b.close()
+
+
+class _Column:
+    """A periodic box that is long along one axis and two nodes wide across it,
+    seen as a one-dimensional line of nodes along that axis."""
+
+    def __init__(self, axis, rho, T, dt, precision):
+        n = [2, 2, 2]
+        n[axis] = rho.size
+        self.axis, self.n = axis, n
+        shape = (n[2], n[1], n[0])                    # z, y, x (x fastest)
+        line = [1, 1, 1]
+        line[2 - axis] = rho.size
+        r3 = np.broadcast_to(rho.reshape(line), shape).ravel()
+        t3 = np.broadcast_to(T.reshape(line), shape).ravel()
+        case = W.perturbed3(*n, seed=0, amp=0.0)
+        p = dict(case.params, omega=1.5, kappa=0.0, dt=dt, n_pass=2)
+        cfg = pond.Config(dim=3, n=tuple(n), bc=case.bc, a=p["a"], b=p["b"], R=p["R"], delta=p["delta"],
+                          omega=p["omega"], kappa=p["kappa"], k_scale=p["k_scale"], dt=dt,
+                          n_pass=p["n_pass"], precision=precision, tile=-1)
+        self.lat = pond.Lattice(cfg)
+        self.lat.init_fields(r3, np.zeros((3, r3.size)), t3)
+        self.shape = shape
+
+    def step(self, k):
+        self.lat.step(k)
+
+    def moments(self):
+        rho = self.lat.moments()["rho"].reshape(self.shape)
+        sel = [0, 0, 0]
+        sel[2 - self.axis] = slice(None)
+        return {"rho": rho[tuple(sel)]}
+
+
+@pytest.mark.parametrize("precision", [pond.FP64, pond.FP32_STORE])
+def test_pulse_travels_at_the_vdw_sound_speed_along_each_axis(precision):
+    rho0, tr = 1.75, 1.05
+    ref = VDW.sound_vdw(rho0, tr * VDW.T_cr)
+    for axis in range(3):
+        made = []
+
+        def factory(rho, T, dt):
+            made.append(_Column(axis, rho, T, dt, precision))
+            return made[-1]
+
+        c = pulse_speed(factory, rho0, tr)
+        made[0].lat.close()
+        print(f"axis {axis}: pulse {c:.5f} vdW {ref:.5f} ({c / ref - 1:+.2e})", flush=True)
+        assert c == pytest.approx(ref, rel=3e-3)
