@@ -17,6 +17,8 @@
 // for sum f wx^m wy^n wz^o.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "pond_device.h"
 #include "pond_internal.h"
 
@@ -200,7 +202,7 @@ __global__ void __launch_bounds__(2 * TX *TY, sizeof(LdsT) == 4 ? 2 : 1) k3_stre
     constexpr int LX = TX + 4, LY = TY + 4, LN = LX * LY, NT = 2 * TX * TY;
     constexpr bool kDev = sizeof(LdsT) == 4;
     using AccT = LdsT; // window accumulators: FP64, or FP32 deviations
-    __shared__ LdsT lds[2 * 27 * LN];
+    __shared__ __align__(16) LdsT lds[2 * 27 * LN];
     __shared__ LdsT ref[kDev ? 54 : 1];
     __shared__ int abort_block;
     const SlotDesc &S = *slot;
@@ -235,6 +237,15 @@ __global__ void __launch_bounds__(2 * TX *TY, sizeof(LdsT) == 4 ? 2 : 1) k3_stre
     const double Fp[3] = {side[kSideFx * N + node], side[kSideFy * N + node], side[kSideFz * N + node]};
     const double dt = P.dt;
     const int wbase = (int)threadIdx.y * LX + lxr; // window corner (gx-2, gy-2) in the tile plane
+    // staging: lane tid < LN owns window node tid of a plane (its x-y node offset is the
+    // same in every plane) and moves both sets of all 27 moments of that node, each
+    // field read from a uniform plane base plus a 32-bit byte offset
+    static_assert(LN <= NT, "one staging lane per window node");
+    const bool stager = tid < LN;
+    const unsigned ndxy = (unsigned)(box.wrap(bx0 - 2 + tid % LX, box.nx) +
+                                     box.nx * box.wrap(by0 - 2 + tid / LX, box.ny));
+    const unsigned plane = (unsigned)box.nx * (unsigned)box.ny;
+    using Pair = typename std::conditional<kDev, float2, double2>::type;
 
     double acc[27];
     double sU[3] = {U[0], U[1], U[2]}, sS = 1.0, rho = 0.0;
@@ -270,36 +281,35 @@ __global__ void __launch_bounds__(2 * TX *TY, sizeof(LdsT) == 4 ? 2 : 1) k3_stre
         for (int sz = 0; sz < 5; ++sz) {
             // stage the donor plane z + sz - 2 of the tile window: 54 fields
             __syncthreads();
-            // loads in batches of CH before their stores, so their latencies overlap
             const int zz = box.wrap(z + sz - 2, box.nz);
-            constexpr int ITEMS = (54 * LN + NT - 1) / NT, CH = 8;
-#pragma unroll 1
-            for (int b0 = 0; b0 < ITEMS; b0 += CH) {
-                LdsT tmp[CH];
-                int dst[CH];
+            if (stager) {
+                const unsigned off = (ndxy + plane * (unsigned)zz) * (unsigned)sizeof(LdsT);
+                // loads in batches of MB fields per set before their stores, so that
+                // their latencies overlap
+                constexpr int MB = 9;
+                static_assert(27 % MB == 0, "whole batches of fields");
 #pragma unroll
-                for (int u = 0; u < CH; ++u) {
-                    const int li = tid + (b0 + u) * NT;
-                    dst[u] = -1;
-                    if (b0 + u < ITEMS && li < 54 * LN) {
-                        const int c = li / LN, ln = li - c * LN;
-                        const int set = c / 27, mno = c - set * 27;
-                        const int nd = box.wrap(bx0 - 2 + ln % LX, box.nx) +
-                                       box.nx * (box.wrap(by0 - 2 + ln / LX, box.ny) + box.ny * zz);
-                        tmp[u] = dmom[(size_t)c * N + nd];
-                        dst[u] = (mno * LN + ln) * 2 + set;
+                for (int m0 = 0; m0 < 27; m0 += MB) {
+                    LdsT a[MB], b[MB];
+#pragma unroll
+                    for (int j = 0; j < MB; ++j) {
+                        a[j] = *(const POND_GLOBAL LdsT *)((const POND_GLOBAL char *)(dmom + (size_t)(m0 + j) * N) + off);
+                        b[j] = *(const POND_GLOBAL LdsT *)((const POND_GLOBAL char *)(dmom + (size_t)(27 + m0 + j) * N) +
+                                                           off);
+                    }
+#pragma unroll
+                    for (int j = 0; j < MB; ++j) {
+                        Pair v;
+                        if (kDev) {
+                            v.x = a[j] - ref[m0 + j];
+                            v.y = b[j] - ref[27 + m0 + j];
+                        } else {
+                            v.x = a[j];
+                            v.y = b[j];
+                        }
+                        *(Pair *)&lds[((m0 + j) * LN + tid) * 2] = v;
                     }
                 }
-#pragma unroll
-                for (int u = 0; u < CH; ++u)
-                    if (dst[u] >= 0) {
-                        if (kDev) {
-                            const int c = (dst[u] >> 1) / LN + 27 * (dst[u] & 1);
-                            lds[dst[u]] = tmp[u] - ref[c];
-                        } else {
-                            lds[dst[u]] = tmp[u];
-                        }
-                    }
             }
             if (pass == 0 && sz == 0 && tid == 0) {
                 abort_block = err_before;
@@ -836,7 +846,8 @@ __global__ void __launch_bounds__(kMonThreads) k3_monitor_partials(const DevPara
 // 54 staged fields of one donor plane within 64 KB)
 void stream3_tile(int fp32, int *tx, int *ty)
 {
-    *tx = fp32 == 1 ? 16 : 8;
+    (void)fp32;
+    *tx = 16;
     *ty = 8;
 }
 
@@ -860,10 +871,10 @@ hipError_t launch_stream3(const LaunchCtx &c, const SlotDesc *slot)
         launch_stream3_t<float, 16, 8>(c, slot);
     } else if (c.fp32 == 2) {
         hipLaunchKernelGGL((k3_donor_moments<float, double>), grid_nodes(c, 2), dim3(256), 0, c.st, slot);
-        launch_stream3_t<double, 8, 8>(c, slot);
+        launch_stream3_t<double, 16, 8>(c, slot);
     } else {
         hipLaunchKernelGGL((k3_donor_moments<double, double>), grid_nodes(c, 2), dim3(256), 0, c.st, slot);
-        launch_stream3_t<double, 8, 8>(c, slot);
+        launch_stream3_t<double, 16, 8>(c, slot);
     }
     if (c.ev_stop) (void)hipEventRecord(c.ev_stop, c.st);
     return hipGetLastError();
