@@ -126,6 +126,23 @@ __global__ void __launch_bounds__(SPLIT *TX *TY)
     const double rx = side[kSideUx * N + cnode];
     const double ry = DIM == 2 ? side[kSideUy * N + cnode] : 0.0;
 
+    // FP32 streaming: the LDS holds every donor moment minus a reference moment vector of
+    // the tile, and the FP32 window arithmetic carries only that variation.  The reference
+    // is the equilibrium-shaped vector of the tile's centre node, R (1, theta, theta,
+    // theta^2) at the moments (0,0), (0,2), (2,0), (2,2) and zero elsewhere, with R its FP64
+    // set sum (rho for f, 2 rho E for g).  Each axis's Lagrange weights reproduce a
+    // constant, so the reference streams to sum_mn A_km B_ln Mref_mn = R a_k b_l with
+    // a_k = A_k0 + theta A_k2, b_l = B_l0 + theta B_l2, added in FP64.
+    constexpr bool kDevI = sizeof(LdsT) == 4;
+    static_assert(!kDevI || kDeviationStore<PopT>, "FP32 streaming comes with the FP32 store");
+    const POND_GLOBAL double *__restrict__ fsum = (const POND_GLOBAL double *)(fpop + (size_t)2 * Q * N);
+    double refR0 = 0.0, refR1 = 0.0, refT = 0.0;
+    if constexpr (kDevI) {
+        refR0 = fsum[cnode];
+        refR1 = fsum[(size_t)N + cnode];
+        refT = side[kSideTh * N + cnode];
+    }
+
     // the receiver's own gauge and force, loaded now so that the latency overlaps the fill
     const int lxr = SPLIT == 2 ? (int)threadIdx.x >> 1 : (int)threadIdx.x;
     const int myset = SPLIT == 2 ? (int)threadIdx.x & 1 : 0;
@@ -146,7 +163,6 @@ __global__ void __launch_bounds__(SPLIT *TX *TY)
     constexpr int SETS_PER_ITEM = SPLIT == 2 ? 1 : 2;
     constexpr int NITEMS = LN * SPLIT;
     constexpr bool dev = kDeviationStore<PopT>;
-    const POND_GLOBAL double *__restrict__ fsum = (const POND_GLOBAL double *)(fpop + (size_t)2 * Q * N);
     struct Raw {
         int li, set0, node;
         double ux, uy, th;
@@ -198,6 +214,15 @@ __global__ void __launch_bounds__(SPLIT *TX *TY)
             for (int q = 0; q < Q; ++q)
                 fr[q] = dev ? weight_q<DIM>(q) * r.sum[k] + (double)r.p[k * Q + q] : (double)r.p[k * Q + q];
             moments_about<DIM>(fr, r.ux - rx, r.uy - ry, s, m);
+            if constexpr (kDevI) {
+                const double R = set == 0 ? refR0 : refR1;
+                m[0] -= R;
+                m[2] -= R * refT;
+                if (DIM == 2) {
+                    m[6] -= R * refT;
+                    m[8] -= R * refT * refT;
+                }
+            }
 #pragma unroll
             for (int i = 0; i < NF; ++i)
                 lds[SPLIT == 2 ? (i * LN + r.li) * 2 + set : (set * NF + i) * LN + r.li] = (LdsT)m[i];
@@ -248,8 +273,23 @@ __global__ void __launch_bounds__(SPLIT *TX *TY)
             // populations of this set in the receiver gauge, one per direction:
             //   f_kl = sum_n B_ln sum_r wy_l[r] sum_m A_km sum_c wx_k[c] M_mn[r][c]
             double acc[Q];
+            if constexpr (kDevI) {
+                // the reference part (see the fill); the window adds the deviations
+                const double R = set == 0 ? refR0 : refR1;
 #pragma unroll
-            for (int q = 0; q < Q; ++q) acc[q] = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    const double ak = R * (Ad[k][0] + refT * Ad[k][2]);
+                    if (DIM == 2) {
+#pragma unroll
+                        for (int l = 0; l < 3; ++l) acc[3 * k + l] = ak * (Bd[l][0] + refT * Bd[l][2]);
+                    } else {
+                        acc[k] = ak;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < Q; ++q) acc[q] = 0.0;
+            }
             const LdsT *sbase = SPLIT == 2 ? &lds[wbase * 2 + set] : &lds[set * NF * LN + wbase];
             if (DIM == 2) {
 #pragma unroll
@@ -407,7 +447,7 @@ int stream_variants(int dim) { return dim == 3 ? 1 : dim == 2 ? 5 : 2; }
 void stream_tile_shape(int dim, int v, int *tx, int *ty)
 {
     if (dim == 3) {
-        stream3_tile(1, tx, ty); // the FP32-streaming shape; FP64 streaming uses 8 x 8
+        stream3_tile(1, tx, ty); // one shape in every precision
         return;
     }
     *tx = dim == 2 ? kTiles2D[v][0] : kTiles1D[v][0];
