@@ -157,7 +157,7 @@ def config5_sample(stream, steps=10, warmup=3):
     monitors, in FP32 storage (the configuration's precision) and FP64."""
     import torch
 
-    from paper_2002_09217_amd import pond, workloads as W
+    from paper_2002_09217_amd import cost, pond, workloads as W
     from paper_2002_09217_amd.serve import lattice_config
 
     case = W.static_droplet3(n=256)
