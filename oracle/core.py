@@ -43,6 +43,24 @@ def _stale() -> bool:
     return not os.path.exists(LIB) or os.path.getmtime(LIB) < max(os.path.getmtime(SRC), os.path.getmtime(SRC3))
 
 
+EOS_VDW, EOS_DIETERICI, EOS_WELL = 0, 1, 2
+
+
+class Eos(ctypes.Structure):
+    """Equation of state of a run (orc_eos): kind, isothermal switch with T0, and the
+    double-well constants (beta, rho_l, rho_v, p0)."""
+    _fields_ = [("kind", ctypes.c_int), ("isothermal", ctypes.c_int), ("T0", ctypes.c_double),
+                ("c", ctypes.c_double * 4)]
+
+
+def _eos(kind, isothermal, T0, c) -> Eos:
+    e = Eos()
+    e.kind, e.isothermal, e.T0 = int(kind), int(isothermal), float(T0)
+    for i in range(4):
+        e.c[i] = float(c[i])
+    return e
+
+
 class Params(ctypes.Structure):
     _fields_ = [
         ("dim", ctypes.c_int),
@@ -59,6 +77,7 @@ class Params(ctypes.Structure):
         ("k_scale", ctypes.c_double),
         ("dt", ctypes.c_double),
         ("n_pass", ctypes.c_int),
+        ("eos", Eos),
     ]
 
 
@@ -137,6 +156,10 @@ class Config:
     k_scale: float = 1.0
     dt: float = 1.0
     n_pass: int = 2
+    eos: int = EOS_VDW          # EOS_VDW, EOS_DIETERICI (isothermal), EOS_WELL (isothermal)
+    isothermal: int = 0         # nonzero: T = T0 everywhere
+    T0: float = 0.0
+    eos_c: tuple = (0.0, 0.0, 0.0, 0.0)   # EOS_WELL: beta, rho_l, rho_v, p0
 
     def params(self) -> Params:
         P = Params()
@@ -149,6 +172,7 @@ class Config:
         P.a, P.b, P.R, P.delta = self.a, self.b, self.R, self.delta
         P.omega, P.kappa, P.k_scale, P.dt = self.omega, self.kappa, self.k_scale, self.dt
         P.n_pass = self.n_pass
+        P.eos = _eos(self.eos, self.isothermal, self.T0, self.eos_c)
         return P
 
     @property
@@ -315,7 +339,7 @@ class Params3(ctypes.Structure):
         ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
         ("a", ctypes.c_double), ("b", ctypes.c_double), ("R", ctypes.c_double), ("delta", ctypes.c_double),
         ("omega", ctypes.c_double), ("kappa", ctypes.c_double), ("k_scale", ctypes.c_double),
-        ("dt", ctypes.c_double), ("n_pass", ctypes.c_int),
+        ("dt", ctypes.c_double), ("n_pass", ctypes.c_int), ("eos", Eos),
     ]
 
 
@@ -334,12 +358,17 @@ class Config3:
     k_scale: float = 1.0
     dt: float = 1.0
     n_pass: int = 2
+    eos: int = EOS_VDW
+    isothermal: int = 0
+    T0: float = 0.0
+    eos_c: tuple = (0.0, 0.0, 0.0, 0.0)
 
     def params(self) -> Params3:
         P = Params3()
         P.nx, P.ny, P.nz = self.nx, self.ny, self.nz
         P.a, P.b, P.R, P.delta = self.a, self.b, self.R, self.delta
         P.omega, P.kappa, P.k_scale, P.dt, P.n_pass = self.omega, self.kappa, self.k_scale, self.dt, self.n_pass
+        P.eos = _eos(self.eos, self.isothermal, self.T0, self.eos_c)
         return P
 
     Q = 27

@@ -17,6 +17,8 @@
  *     gauge with the transfer matrix G = M_{lambda'}^{-1} M_lambda             (App. C)
  *     and then interpolated with cubic Lagrange polynomials                    (App. D)
  *   - van der Waals EoS, e = C_v T - a rho, C_v = R/delta                       (main text; App. A)
+ *   - isothermal runs with the van der Waals, Dieterici or double-well
+ *     (simplified free energy) pressure                                         (Supplement)
  *   - BGK collision of f with the forcing term S_i                             (eqs. 16-17)
  *   - Korteweg stress K and force F = -div K                                   (eq. 18; App. F)
  *   - BGK collision of g with the force-extended equilibrium, the heat-flux
@@ -50,6 +52,13 @@
  *   R10 the transfer matrix is taken from its definition M'^{-1} M; its printed
  *       explicit form carries a sign error for a single axis (w(i) flips sign),
  *       which cancels for the two-axis product.
+ *   R11 isothermal runs (the Supplement's coexistence and speed-of-sound cases):
+ *       T = T0 wherever the step needs a temperature (passes, closure, initial
+ *       and inflow states, read-back); the energy population is then passive and
+ *       carries e = C_v T (- a rho for van der Waals).  The simplified free
+ *       energy is read with squares, E0 = beta (rho - rho_l)^2 (rho - rho_v)^2,
+ *       and a background pressure p0 > 0 is added so that theta stays positive:
+ *       p = p0 + rho dE0/drho - E0.
  *
  * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no FMA contraction).
  */
@@ -71,6 +80,16 @@ enum {
     ORC_E_NONFINITE = -5
 };
 
+enum { ORC_EOS_VDW = 0, ORC_EOS_DIETERICI = 1, ORC_EOS_WELL = 2 };
+
+/* equation of state: kind, isothermal switch (R11) and constants of the double well */
+typedef struct {
+    int kind;                 /* ORC_EOS_* */
+    int isothermal;           /* nonzero: T = T0 everywhere; required for kind != VDW */
+    double T0;
+    double c[4];              /* ORC_EOS_WELL: beta, rho_l, rho_v, p0 */
+} orc_eos;
+
 typedef struct {
     int dim;                  /* 1: D1Q3, 2: D2Q9 */
     int nx, ny;               /* ny = 1 for dim = 1 */
@@ -82,23 +101,80 @@ typedef struct {
     double k_scale;           /* conductivity k = k_scale mu C_p^ig; < 0 disables M0 */
     double dt;                /* time step (lattice units) */
     int n_pass;               /* streaming passes of the predictor-corrector */
+    orc_eos eos;
 } orc_params;
 
 /* ------------------------------------------------------------------------- */
-/* thermodynamics (main text; App. A)                                         */
+/* thermodynamics (main text; App. A; Supplement)                             */
+/* Exported with the constants passed apart, so that the three-dimensional     */
+/* oracle evaluates the same definitions.                                       */
 /* ------------------------------------------------------------------------- */
-static double vdw_p(const orc_params *P, double rho, double T)
+/* pressure:
+ *   van der Waals  p = rho R T/(1 - b rho) - a rho^2                  (main text)
+ *   Dieterici      p = rho R T/(1 - b rho) exp(-a rho/(R T))          (Supplement)
+ *   double well    p = p0 + rho E0'(rho) - E0(rho),
+ *                  E0 = beta (rho - rho_l)^2 (rho - rho_v)^2          (Supplement; R11) */
+double orc_eos_p(const orc_eos *E, double a, double b, double R, double rho, double T)
 {
-    return rho * P->R * T / (1.0 - P->b * rho) - P->a * rho * rho;
+    if (E->kind == ORC_EOS_DIETERICI) return rho * R * T / (1.0 - b * rho) * exp(-a * rho / (R * T));
+    if (E->kind == ORC_EOS_WELL) {
+        double beta = E->c[0], rl = E->c[1], rv = E->c[2], p0 = E->c[3];
+        double E0 = beta * (rho - rl) * (rho - rl) * (rho - rv) * (rho - rv);
+        double dE0 = 2.0 * beta * (rho - rl) * (rho - rv) * (2.0 * rho - rl - rv);
+        return p0 + rho * dE0 - E0;
+    }
+    return rho * R * T / (1.0 - b * rho) - a * rho * rho;
 }
-static double vdw_e(const orc_params *P, double rho, double T)
+/* internal energy: van der Waals e = C_v T - a rho (App. A); the other kinds are only
+ * run isothermally, where the energy population is passive, and carry e = C_v T */
+double orc_eos_e(const orc_eos *E, double a, double Cv, double rho, double T)
 {
-    return (P->R / P->delta) * T - P->a * rho;
+    return Cv * T - (E->kind == ORC_EOS_VDW ? a * rho : 0.0);
 }
-static double vdw_T_of_e(const orc_params *P, double rho, double e)
+/* temperature of a streamed state: T0 when isothermal, else the van der Waals
+ * inversion of e = C_v T - a rho */
+double orc_eos_T_of_e(const orc_eos *E, double a, double Cv, double rho, double e)
 {
-    return P->delta * (e + P->a * rho) / P->R;
+    return E->isothermal ? E->T0 : (e + a * rho) / Cv;
 }
+/* temperature from the pressure (read-back): T0 when isothermal, else the inversion
+ * of the van der Waals pressure */
+double orc_eos_T_of_p(const orc_eos *E, double a, double b, double R, double rho, double p)
+{
+    return E->isothermal ? E->T0 : (p + a * rho * rho) * (1.0 - b * rho) / (rho * R);
+}
+/* domain of the pressure law: 1 - b rho > 0 for van der Waals and Dieterici */
+int orc_eos_in_domain(const orc_eos *E, double b, double rho)
+{
+    return E->kind == ORC_EOS_WELL || 1.0 - b * rho > 0.0;
+}
+/* admissible constants: the non-van-der-Waals kinds are isothermal; T0 > 0; the
+ * double well has beta > 0, rho_l > rho_v > 0 and p0 > 0 */
+int orc_eos_valid(const orc_eos *E)
+{
+    if (E->kind < ORC_EOS_VDW || E->kind > ORC_EOS_WELL) return 0;
+    if (E->kind != ORC_EOS_VDW && !E->isothermal) return 0;
+    if (E->isothermal && !(E->T0 > 0.0)) return 0;
+    if (E->kind == ORC_EOS_WELL &&
+        !(E->c[0] > 0.0 && E->c[1] > E->c[2] && E->c[2] > 0.0 && E->c[3] > 0.0))
+        return 0;
+    return 1;
+}
+
+static double eos_p(const orc_params *P, double rho, double T)
+{
+    return orc_eos_p(&P->eos, P->a, P->b, P->R, rho, T);
+}
+static double eos_e(const orc_params *P, double rho, double T)
+{
+    return orc_eos_e(&P->eos, P->a, P->R / P->delta, rho, T);
+}
+static double eos_T_of_e(const orc_params *P, double rho, double e)
+{
+    return orc_eos_T_of_e(&P->eos, P->a, P->R / P->delta, rho, e);
+}
+/* temperature of an initial or inflow state: T0 when isothermal */
+static double state_T(const orc_params *P, double T) { return P->eos.isothermal ? P->eos.T0 : T; }
 
 /* ------------------------------------------------------------------------- */
 /* lattice                                                                     */
@@ -306,8 +382,8 @@ static void close_node(const orc_params *P, double rho, const double j[2], doubl
         uh2 += n->uh[a] * n->uh[a];
     }
     n->e = E - 0.5 * uh2;
-    n->T = vdw_T_of_e(P, rho, n->e);
-    n->p = vdw_p(P, rho, n->T);
+    n->T = eos_T_of_e(P, rho, n->e);
+    n->p = eos_p(P, rho, n->T);
     n->theta = n->p / (rho * T_L);
     n->h = n->e + n->p / rho;
     n->mu = (1.0 / P->omega - 0.5) * n->p * P->dt;
@@ -317,7 +393,7 @@ static void close_node(const orc_params *P, double rho, const double j[2], doubl
 static int thermo_bad(const orc_params *P, double rho, double p)
 {
     if (!isfinite(rho) || !isfinite(p)) return ORC_E_NONFINITE;
-    if (p <= 0.0 || 1.0 - P->b * rho <= 0.0 || rho <= 0.0) return ORC_E_PRESSURE;
+    if (p <= 0.0 || !orc_eos_in_domain(&P->eos, P->b, rho) || rho <= 0.0) return ORC_E_PRESSURE;
     return ORC_OK;
 }
 
@@ -386,10 +462,10 @@ typedef struct {
 static void make_ghost(const orc_params *P, const double st[4], ghost_state *gs)
 {
     int Q = nq(P);
-    double rho = st[0], T = st[3];
+    double rho = st[0], T = state_T(P, st[3]);
     double u[2] = {st[1], P->dim == 2 ? st[2] : 0.0};
-    double p = vdw_p(P, rho, T);
-    double e = vdw_e(P, rho, T);
+    double p = eos_p(P, rho, T);
+    double e = eos_e(P, rho, T);
     double theta = p / (rho * T_L);
     double E = e + 0.5 * (u[0] * u[0] + u[1] * u[1]);
     double F0[2] = {0.0, 0.0};
@@ -639,7 +715,7 @@ static int valid(const orc_params *P)
     if (!(P->delta > 0.0 && P->delta <= 2.0 / 3.0)) return 0;
     if (!(P->omega > 0.0 && P->omega < 2.0)) return 0;
     if (P->n_pass < 1 || !(P->dt > 0.0)) return 0;
-    return 1;
+    return orc_eos_valid(&P->eos);
 }
 
 static void build_ghosts(const orc_params *P, ghost_state gh[4])
@@ -758,13 +834,14 @@ int orc_init(const orc_params *P, const double *rho, const double *uhx, const do
         double F0[2] = {F0x[n], F0y[n]};
         double u[2] = {uh[0] - F0[0] * P->dt / (2.0 * r), uh[1] - F0[1] * P->dt / (2.0 * r)};
         if (D == 1) u[1] = 0.0;
-        double p = vdw_p(P, r, Tin[n]);
+        double Tn = state_T(P, Tin[n]);
+        double p = eos_p(P, r, Tn);
         int bad = thermo_bad(P, r, p);
         if (bad) {
             err = bad;
             goto done;
         }
-        double e = vdw_e(P, r, Tin[n]);
+        double e = eos_e(P, r, Tn);
         double E = e + 0.5 * (uh[0] * uh[0] + uh[1] * uh[1]);
         double theta = p / (r * T_L);
         double geq[9];
@@ -883,8 +960,8 @@ void orc_moments(const orc_params *P, const double *f, const double *ux, const d
         double hx = ux[n] + Fx[n] * P->dt / (2.0 * r);
         double hy = D == 2 ? uy[n] + Fy[n] * P->dt / (2.0 * r) : 0.0;
         double pr = r * th[n] * T_L;
-        double Tn = (pr + P->a * r * r) * (1.0 - P->b * r) / (r * P->R);
-        double e = vdw_e(P, r, Tn);
+        double Tn = orc_eos_T_of_p(&P->eos, P->a, P->b, P->R, r, pr);
+        double e = eos_e(P, r, Tn);
         rho[n] = r;
         uhx[n] = hx;
         if (D == 2) uhy[n] = hy;

@@ -4,7 +4,7 @@
  * A plain, slow, FP64 CPU implementation of the D3Q27 time step of the
  * two-population Particles-on-Demand model of Reyhanian, Dorschner & Karlin,
  * "Thermokinetic model of compressible multiphase flows", arXiv:2002.09217, on a
- * periodic box.  Same method and the same readings (R1-R10 of pond_oracle.c) as
+ * periodic box.  Same method and the same readings (R1-R11 of pond_oracle.c) as
  * the one- and two-dimensional oracle, written out for three axes:
  *   - D3Q27 = C1 x C1 x C1, W_ijk = W_i W_j W_k, T_L = 1/3                        (App. B)
  *   - v_i = sqrt(theta) c_i + u, moments rho, rho u, 2 rho E                       (eqs. 1-2)
@@ -30,15 +30,28 @@ static const double W1[3] = {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0};
 
 enum { ORC_OK = 0, ORC_E_INVALID = -1, ORC_E_NOMEM = -2, ORC_E_PRESSURE = -4, ORC_E_NONFINITE = -5 };
 
-/* from pond_oracle.c: one-axis transfer G[k][i] and cubic Lagrange weights */
+/* from pond_oracle.c: one-axis transfer G[k][i], cubic Lagrange weights and the
+ * equation of state (kind, isothermal switch, double-well constants; R11) */
 void orc_transfer_1d(double u_from, double th_from, double u_to, double th_to, double G[3][3]);
 void orc_lagrange4(double t, double w[4]);
+typedef struct {
+    int kind, isothermal;
+    double T0;
+    double c[4];
+} orc_eos;
+double orc_eos_p(const orc_eos *E, double a, double b, double R, double rho, double T);
+double orc_eos_e(const orc_eos *E, double a, double Cv, double rho, double T);
+double orc_eos_T_of_e(const orc_eos *E, double a, double Cv, double rho, double e);
+double orc_eos_T_of_p(const orc_eos *E, double a, double b, double R, double rho, double p);
+int orc_eos_in_domain(const orc_eos *E, double b, double rho);
+int orc_eos_valid(const orc_eos *E);
 
 typedef struct {
     int nx, ny, nz;           /* periodic box */
-    double a, b, R, delta;    /* van der Waals constants, C_v = R / delta */
+    double a, b, R, delta;    /* EoS constants, C_v = R / delta */
     double omega, kappa, k_scale, dt;
     int n_pass;
+    orc_eos eos;
 } orc3_params;
 
 /* direction q = 9 (cx + 1) + 3 (cy + 1) + (cz + 1) */
@@ -47,17 +60,22 @@ static int cyq(int q) { return (q / 3) % 3 - 1; }
 static int czq(int q) { return q % 3 - 1; }
 static double wq(int q) { return W1[q / 9] * W1[(q / 3) % 3] * W1[q % 3]; }
 
-static double vdw_p(const orc3_params *P, double rho, double T)
+static double eos_p(const orc3_params *P, double rho, double T) { return orc_eos_p(&P->eos, P->a, P->b, P->R, rho, T); }
+static double eos_e(const orc3_params *P, double rho, double T)
 {
-    return rho * P->R * T / (1.0 - P->b * rho) - P->a * rho * rho;
+    return orc_eos_e(&P->eos, P->a, P->R / P->delta, rho, T);
 }
-static double vdw_e(const orc3_params *P, double rho, double T) { return (P->R / P->delta) * T - P->a * rho; }
-static double vdw_T_of_e(const orc3_params *P, double rho, double e) { return P->delta * (e + P->a * rho) / P->R; }
+static double eos_T_of_e(const orc3_params *P, double rho, double e)
+{
+    return orc_eos_T_of_e(&P->eos, P->a, P->R / P->delta, rho, e);
+}
+/* temperature of an initial state: T0 when isothermal */
+static double state_T(const orc3_params *P, double T) { return P->eos.isothermal ? P->eos.T0 : T; }
 
 static int thermo_bad(const orc3_params *P, double rho, double p)
 {
     if (!isfinite(rho) || !isfinite(p)) return ORC_E_NONFINITE;
-    if (p <= 0.0 || 1.0 - P->b * rho <= 0.0 || rho <= 0.0) return ORC_E_PRESSURE;
+    if (p <= 0.0 || !orc_eos_in_domain(&P->eos, P->b, rho) || rho <= 0.0) return ORC_E_PRESSURE;
     return ORC_OK;
 }
 
@@ -151,8 +169,8 @@ static void close_node(const orc3_params *P, double rho, const double j[3], doub
         uh2 += n->uh[a] * n->uh[a];
     }
     n->e = E - 0.5 * uh2;
-    n->T = vdw_T_of_e(P, rho, n->e);
-    n->p = vdw_p(P, rho, n->T);
+    n->T = eos_T_of_e(P, rho, n->e);
+    n->p = eos_p(P, rho, n->T);
     n->theta = n->p / (rho * T_L);
     n->h = n->e + n->p / rho;
     n->mu = (1.0 / P->omega - 0.5) * n->p * P->dt;
@@ -350,7 +368,7 @@ static int valid(const orc3_params *P)
     if (!(P->delta > 0.0 && P->delta <= 2.0 / 3.0)) return 0;
     if (!(P->omega > 0.0 && P->omega < 2.0)) return 0;
     if (P->n_pass < 1 || !(P->dt > 0.0)) return 0;
-    return 1;
+    return orc_eos_valid(&P->eos);
 }
 
 /* Non-local closure and collision of every node (shared by the step and the initial
@@ -438,13 +456,14 @@ int orc3_init(const orc3_params *P, const double *rho, const double *uh_in, cons
             Fv[a] = F0[(size_t)a * N + n];
             uu[a] = uh[a] - Fv[a] * P->dt / (2.0 * r);
         }
-        double p = vdw_p(P, r, Tin[n]);
+        double Tn = state_T(P, Tin[n]);
+        double p = eos_p(P, r, Tn);
         int bad = thermo_bad(P, r, p);
         if (bad) {
             err = bad;
             goto done;
         }
-        double E = vdw_e(P, r, Tin[n]) + 0.5 * (uh[0] * uh[0] + uh[1] * uh[1] + uh[2] * uh[2]);
+        double E = eos_e(P, r, Tn) + 0.5 * (uh[0] * uh[0] + uh[1] * uh[1] + uh[2] * uh[2]);
         double theta = p / (r * T_L), geq[Q3];
         orc3_geq(P, r, uu, theta, p, E, uh, Fv, geq);
         for (int q = 0; q < Q3; ++q) {
@@ -533,11 +552,11 @@ void orc3_moments(const orc3_params *P, const double *f, const double *u, const 
             h2 += v * v;
         }
         double pr = r * th[n] * T_L;
-        double Tn = (pr + P->a * r * r) * (1.0 - P->b * r) / (r * P->R);
+        double Tn = orc_eos_T_of_p(&P->eos, P->a, P->b, P->R, r, pr);
         rho[n] = r;
         T[n] = Tn;
         p[n] = pr;
-        E[n] = vdw_e(P, r, Tn) + 0.5 * h2;
+        E[n] = eos_e(P, r, Tn) + 0.5 * h2;
     }
 }
 

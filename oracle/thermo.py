@@ -11,6 +11,10 @@ Everything follows Reyhanian, Dorschner & Karlin (arXiv:2002.09217):
   * the fundamental derivative Gamma(p, v) of the van der Waals fluid  (App. E, shock tube)
   * Rankine-Hugoniot post-shock state                                  (App. E)
   * Maxwell's equal-area rule for the coexistence densities            (main text, Fig. 2)
+  * the Dieterici pressure and its printed critical values             (Supplement, coexistence)
+  * the simplified (double-well) free energy near the critical point,
+    with the printed saturated sound speeds                            (Supplement, speed of sound)
+  * Maxwell's rule for any isotherm with one loop
 All arithmetic is FP64.
 """
 from __future__ import annotations
@@ -19,6 +23,7 @@ import math
 from dataclasses import dataclass
 
 import numpy as np
+from scipy.integrate import quad
 from scipy.optimize import brentq
 
 A_SIM, B_SIM, R_SIM = 2.0 / 49.0, 2.0 / 21.0, 1.0  # constants used in the paper's simulations
@@ -193,3 +198,113 @@ class VdW:
         M0_, N0_ = MN(rho0, p0, u0)
         M1_, N1_ = MN(rho1, p1, u1)
         return -s * (M1_ - M0_) + (N1_ - N0_)
+
+
+# ----------------------------------------------------------------------
+# Isothermal equations of state of the Supplement
+# ----------------------------------------------------------------------
+def maxwell_isotherm(p, dp, rho_lo, rho_hi, samples=4001):
+    """(rho_vapor, rho_liquid, p_sat) of an isotherm p(rho) (derivative dp) with one
+    loop inside (rho_lo, rho_hi): the loop's extrema from dp = 0, then the saturation
+    pressure from the equal-area rule int_{v_l}^{v_v} p dv = p_sat (v_v - v_l), with
+    the integral taken by adaptive quadrature in v."""
+    r = np.linspace(rho_lo, rho_hi, samples)
+    d = dp(r)
+    neg = np.nonzero(d < 0.0)[0]
+    if neg.size == 0:
+        raise ValueError("isotherm without a loop")
+    r_sv = brentq(dp, r[neg[0] - 1], r[neg[0]], xtol=1e-15, rtol=1e-15)       # local maximum
+    r_sl = brentq(dp, r[neg[-1]], r[neg[-1] + 1], xtol=1e-15, rtol=1e-15)     # local minimum
+    # pressures for which both outer branches have a root inside (rho_lo, rho_hi)
+    p_hi = min(p(r_sv), p(rho_hi))
+    p_lo = max(p(r_sl), p(rho_lo), 0.0)
+
+    def roots(ps):
+        rv = brentq(lambda x: p(x) - ps, rho_lo, r_sv, xtol=1e-15, rtol=1e-15, maxiter=500)
+        rl = brentq(lambda x: p(x) - ps, r_sl, rho_hi, xtol=1e-15, rtol=1e-15, maxiter=500)
+        return rv, rl
+
+    def area(ps):
+        rv, rl = roots(ps)
+        integral, _ = quad(lambda v: p(1.0 / v), 1.0 / rl, 1.0 / rv, epsabs=0.0, epsrel=2e-14, limit=200)
+        return integral - ps * (1.0 / rv - 1.0 / rl)
+
+    eps = 1e-12 * p_hi
+    ps = brentq(area, p_lo + eps, p_hi - eps, xtol=1e-16, rtol=1e-15, maxiter=500)
+    rv, rl = roots(ps)
+    return rv, rl, ps
+
+
+# Dieterici constants with the critical point of the van der Waals fluid above
+# (rho_cr = 3.5, T_cr = 8/63): b = 1/(2 rho_cr), a = 4 R b T_cr
+B_DIET = 1.0 / 7.0
+A_DIET = 4.0 * R_SIM * B_DIET * 8.0 / 63.0
+
+
+@dataclass(frozen=True)
+class Dieterici:
+    """p = rho R T/(1 - b rho) exp(-a rho/(R T)) (Supplement, coexistence curve)."""
+    a: float = A_DIET
+    b: float = B_DIET
+    R: float = R_SIM
+
+    # critical values as printed (Supplement)
+    @property
+    def rho_cr(self) -> float:
+        return 1.0 / (2.0 * self.b)
+
+    @property
+    def T_cr(self) -> float:
+        return self.a / (4.0 * self.R * self.b)
+
+    @property
+    def p_cr(self) -> float:
+        return self.a / (2.0 * math.e * self.b) ** 2
+
+    def p(self, rho, T):
+        return rho * self.R * T / (1.0 - self.b * rho) * np.exp(-self.a * rho / (self.R * T))
+
+    def dp_drho_T(self, rho, T):
+        return self.p(rho, T) * (1.0 / rho + self.b / (1.0 - self.b * rho) - self.a / (self.R * T))
+
+    def maxwell(self, T):
+        if not T < self.T_cr:
+            raise ValueError("Maxwell construction needs T < T_cr")
+        return maxwell_isotherm(lambda r: self.p(r, T), lambda r: self.dp_drho_T(r, T),
+                                1e-9, (1.0 - 1e-12) / self.b)
+
+
+@dataclass(frozen=True)
+class DoubleWell:
+    """Simplified free energy near the critical point (Supplement), read with squares:
+    E0 = beta (rho - rho_l)^2 (rho - rho_v)^2, p = p0 + rho dE0/drho - E0.  The
+    background pressure p0 keeps the gauge temperature positive and changes no
+    derivative of p."""
+    beta: float
+    rho_l: float
+    rho_v: float
+    p0: float
+
+    def E0(self, rho):
+        return self.beta * (rho - self.rho_l) ** 2 * (rho - self.rho_v) ** 2
+
+    def dE0(self, rho):
+        return 2.0 * self.beta * (rho - self.rho_l) * (rho - self.rho_v) * (2.0 * rho - self.rho_l - self.rho_v)
+
+    def p(self, rho):
+        return self.p0 + rho * self.dE0(rho) - self.E0(rho)
+
+    def dp_drho(self, rho):
+        # d/drho (rho E0' - E0) = rho E0''
+        r, rl, rv = rho, self.rho_l, self.rho_v
+        d2 = 2.0 * self.beta * ((r - rv) ** 2 + 4.0 * (r - rl) * (r - rv) + (r - rl) ** 2)
+        return rho * d2
+
+    def sound_saturated(self):
+        """Sound speeds at the saturated densities as printed (Supplement):
+        (rho_l - rho_v) sqrt(2 beta rho_l) and (rho_l - rho_v) sqrt(2 beta rho_v)."""
+        d = self.rho_l - self.rho_v
+        return d * math.sqrt(2.0 * self.beta * self.rho_l), d * math.sqrt(2.0 * self.beta * self.rho_v)
+
+    def maxwell(self):
+        return maxwell_isotherm(self.p, self.dp_drho, 0.5 * self.rho_v, self.rho_l + 2.0 * (self.rho_l - self.rho_v))
