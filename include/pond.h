@@ -54,6 +54,8 @@ typedef enum {
 
 enum { POND_BC_PERIODIC = 0, POND_BC_OUTFLOW = 1, POND_BC_INFLOW = 2 };
 enum { POND_FP64 = 0, POND_FP32_STORE = 1, POND_FP32_STORE_FP64_MATH = 2 };
+/* equation of state (main text; Supplement: coexistence curve and speed of sound) */
+enum { POND_EOS_VDW = 0, POND_EOS_DIETERICI = 1, POND_EOS_DOUBLE_WELL = 2 };
 
 typedef struct {
     int dim;                  /* 1 (D1Q3), 2 (D2Q9) or 3 (D3Q27, periodic faces only),
@@ -63,8 +65,20 @@ typedef struct {
     double inflow[3][2][5];   /* state of an inflow face: rho, u_x, u_y, u_z, T (the
                                  actual velocity); its ghost nodes hold the equilibrium
                                  of that state with F = 0                              */
-    double a, b, R;           /* van der Waals p = rho R T/(1 - b rho) - a rho^2        */
+    double a, b, R;           /* van der Waals p = rho R T/(1 - b rho) - a rho^2, or
+                                 Dieterici p = rho R T/(1 - b rho) exp(-a rho/(R T))  */
     double delta;             /* C_v = R/delta, 0 < delta <= 2/3 (main text)            */
+    int eos;                  /* POND_EOS_VDW (with the energy equation, or isothermal);
+                                 POND_EOS_DIETERICI and POND_EOS_DOUBLE_WELL need
+                                 isothermal.  Double well: p = p0 + rho dE0/drho - E0
+                                 with E0 = beta (rho - rho_l)^2 (rho - rho_v)^2        */
+    int isothermal;           /* nonzero: T = T0 wherever the step needs a temperature
+                                 (passes, closure, initial and inflow states, read-back;
+                                 the T given to pond_init_fields is not used).  The
+                                 energy population is then passive and carries
+                                 e = C_v T (- a rho for van der Waals).                */
+    double T0;                /* isothermal temperature, > 0                            */
+    double eos_c[4];          /* POND_EOS_DOUBLE_WELL: beta > 0, rho_l > rho_v > 0, p0 > 0 */
     double omega;             /* BGK relaxation, 0 < omega < 2; mu = (1/omega - 1/2) p dt */
     double kappa;             /* Korteweg coefficient of eq. 18; 0 switches the force off */
     double k_scale;           /* conductivity k = k_scale mu C_p^ig, C_p^ig = R(1+delta)/delta;

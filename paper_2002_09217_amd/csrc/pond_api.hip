@@ -113,19 +113,27 @@ namespace {
 
 const double kW1h[3] = {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0};
 
+// pressure of the configured equation of state (the device helpers' definitions)
 double host_p(const pond_config &c, double rho, double T)
 {
+    if (c.eos == POND_EOS_DIETERICI) return rho * c.R * T / (1.0 - c.b * rho) * std::exp(-c.a * rho / (c.R * T));
+    if (c.eos == POND_EOS_DOUBLE_WELL) {
+        const double dl = rho - c.eos_c[1], dv = rho - c.eos_c[2];
+        return c.eos_c[3] + c.eos_c[0] * dl * dv * (2.0 * rho * (dl + dv) - dl * dv);
+    }
     return rho * c.R * T / (1.0 - c.b * rho) - c.a * rho * rho;
 }
 
-// equilibrium populations of (rho, u, T) with F = 0 in their own gauge (eqs. 7-8)
+// equilibrium populations of (rho, u, T) with F = 0 in their own gauge (eqs. 7-8);
+// isothermal runs take T0
 bool make_ghost(const pond_config &c, const double st[5], GhostFace &G)
 {
-    const double rho = st[0], T = st[4];
+    const double rho = st[0], T = c.isothermal ? c.T0 : st[4];
     const double u[2] = {st[1], c.dim == 2 ? st[2] : 0.0};
     const double p = host_p(c, rho, T);
-    if (!(rho > 0.0) || !(p > 0.0) || !(1.0 - c.b * rho > 0.0) || !std::isfinite(p)) return false;
-    const double e = (c.R / c.delta) * T - c.a * rho;
+    const bool domain = c.eos == POND_EOS_DOUBLE_WELL || 1.0 - c.b * rho > 0.0;
+    if (!(rho > 0.0) || !(p > 0.0) || !domain || !std::isfinite(p)) return false;
+    const double e = (c.R / c.delta) * T - (c.eos == POND_EOS_VDW ? c.a * rho : 0.0);
     const double theta = p / (rho * (1.0 / 3.0));
     const double s = std::sqrt(theta);
     const int Q = c.dim == 2 ? 9 : 3;
@@ -186,6 +194,13 @@ int validate(const pond_config *cfg)
     if (!(c.omega > 0.0 && c.omega < 2.0)) return POND_E_INVALID;
     if (c.n_pass < 1 || c.n_pass > 64 || !(c.dt > 0.0) || !(c.R > 0.0)) return POND_E_INVALID;
     if (c.precision != POND_FP64 && c.precision != POND_FP32_STORE && c.precision != POND_FP32_STORE_FP64_MATH)
+        return POND_E_INVALID;
+    // equation of state: the Dieterici and double-well pressures only isothermally
+    if (c.eos < POND_EOS_VDW || c.eos > POND_EOS_DOUBLE_WELL) return POND_E_INVALID;
+    if (c.eos != POND_EOS_VDW && !c.isothermal) return POND_E_INVALID;
+    if (c.isothermal && !(c.T0 > 0.0 && std::isfinite(c.T0))) return POND_E_INVALID;
+    if (c.eos == POND_EOS_DOUBLE_WELL &&
+        !(c.eos_c[0] > 0.0 && c.eos_c[1] > c.eos_c[2] && c.eos_c[2] > 0.0 && c.eos_c[3] > 0.0))
         return POND_E_INVALID;
     if (c.tile < -1 || c.tile >= stream_variants(c.dim)) return POND_E_INVALID;
     for (int a = 0; a < c.dim && a < 2; ++a)
@@ -362,6 +377,10 @@ int pond_create(const pond_config *cfg, pond_handle **out)
     P.dt = c.dt;
     P.Cv = c.R / c.delta;
     P.Cp_ig = c.R * (1.0 + c.delta) / c.delta;
+    P.eos = c.eos;
+    P.isothermal = c.isothermal ? 1 : 0;
+    P.T0 = c.T0;
+    for (int i = 0; i < 4; ++i) P.eos_c[i] = c.eos_c[i];
     for (int a = 0; a < c.dim; ++a)
         for (int s = 0; s < 2; ++s)
             if (c.bc[a][s] == kInflow && !make_ghost(c, c.inflow[a][s], P.ghost[2 * a + s])) {
@@ -548,11 +567,13 @@ int pond_destroy(pond_handle *h)
 namespace {
 // checkpoint layout: header, then the population buffer, then the kSidePlanes side planes
 struct CheckpointHeader {
-    char magic[8];          // "PONDCKP1"
-    int dim, n[3], precision, tile, n_pass, pad_;
+    char magic[8];          // "PONDCKP2"
+    int dim, n[3], precision, tile, n_pass, eos;
     int bc[3][2];
     long long steps;
     double a, b, R, delta, omega, kappa, k_scale, dt;
+    int isothermal, pad_;
+    double T0, eos_c[4];
     double inflow[3][2][5];
     unsigned long long pop_bytes, side_bytes;
 };
@@ -561,7 +582,7 @@ CheckpointHeader make_header(const pond_handle *h)
 {
     CheckpointHeader H;
     std::memset(&H, 0, sizeof H);
-    std::memcpy(H.magic, "PONDCKP1", 8);
+    std::memcpy(H.magic, "PONDCKP2", 8);
     const pond_config &c = h->cfg;
     H.dim = c.dim;
     for (int a = 0; a < 3; ++a) H.n[a] = c.n[a];
@@ -578,6 +599,10 @@ CheckpointHeader make_header(const pond_handle *h)
     H.kappa = c.kappa;
     H.k_scale = c.k_scale;
     H.dt = c.dt;
+    H.eos = c.eos;
+    H.isothermal = c.isothermal ? 1 : 0;
+    H.T0 = c.T0;
+    for (int i = 0; i < 4; ++i) H.eos_c[i] = c.eos_c[i];
     std::memcpy(H.inflow, c.inflow, sizeof H.inflow);
     H.pop_bytes = pop_bytes(c.dim, h->lc.N, h->lc.fp32);
     H.side_bytes = sizeof(double) * side_planes(h->lc.dim) * (size_t)h->lc.N;
@@ -590,7 +615,8 @@ bool same_config(const CheckpointHeader &x, const CheckpointHeader &y)
     return std::memcmp(x.magic, y.magic, 8) == 0 && x.dim == y.dim && std::memcmp(x.n, y.n, sizeof x.n) == 0 &&
            x.precision == y.precision && x.n_pass == y.n_pass && std::memcmp(x.bc, y.bc, sizeof x.bc) == 0 &&
            x.a == y.a && x.b == y.b && x.R == y.R && x.delta == y.delta && x.omega == y.omega &&
-           x.kappa == y.kappa && x.k_scale == y.k_scale && x.dt == y.dt &&
+           x.kappa == y.kappa && x.k_scale == y.k_scale && x.dt == y.dt && x.eos == y.eos &&
+           x.isothermal == y.isothermal && x.T0 == y.T0 && std::memcmp(x.eos_c, y.eos_c, sizeof x.eos_c) == 0 &&
            std::memcmp(x.inflow, y.inflow, sizeof x.inflow) == 0 && x.pop_bytes == y.pop_bytes &&
            x.side_bytes == y.side_bytes;
 }

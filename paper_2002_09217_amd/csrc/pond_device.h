@@ -36,24 +36,54 @@ constexpr bool kDeviationStore = sizeof(PopT) == 4;
 #define POND_GLOBAL __attribute__((address_space(1)))
 
 // ---------------------------------------------------------------------------
-// van der Waals thermodynamics (main text; App. A)
+// Equations of state (main text; App. A; Supplement).  The van der Waals fluid runs
+// with the energy equation (T from e = C_v T - a rho) or isothermally; the Dieterici
+// and double-well pressures run isothermally: T = T0 wherever a temperature is
+// needed, and the energy population is passive, carrying e = C_v T (- a rho for van
+// der Waals).  The kind is uniform over a launch, so the branches are scalar.
 // ---------------------------------------------------------------------------
+enum { kEosVdw = 0, kEosDieterici = 1, kEosWell = 2 };
 template <typename PT>
-__device__ __forceinline__ double vdw_p(const PT &P, double rho, double T)
+__device__ __forceinline__ double eos_p(const PT &P, double rho, double T)
 {
+    if (P.eos == kEosDieterici) return rho * P.R * T / (1.0 - P.b * rho) * exp(-P.a * rho / (P.R * T));
+    if (P.eos == kEosWell) {
+        // p0 + rho E0' - E0 = p0 + beta dl dv (2 rho (dl + dv) - dl dv), dl = rho - rho_l,
+        // dv = rho - rho_v, for E0 = beta dl^2 dv^2
+        const double dl = rho - P.eos_c[1], dv = rho - P.eos_c[2];
+        return P.eos_c[3] + P.eos_c[0] * dl * dv * (2.0 * rho * (dl + dv) - dl * dv);
+    }
     return rho * P.R * T / (1.0 - P.b * rho) - P.a * rho * rho;
 }
+// temperature of a streamed state from its internal energy
 template <typename PT>
-__device__ __forceinline__ double vdw_T_of_e(const PT &P, double rho, double e)
+__device__ __forceinline__ double eos_T_of_e(const PT &P, double rho, double e)
 {
-    return P.delta * (e + P.a * rho) / P.R;
+    return P.isothermal ? P.T0 : P.delta * (e + P.a * rho) / P.R;
+}
+// temperature of an initial or inflow state given T
+template <typename PT>
+__device__ __forceinline__ double eos_state_T(const PT &P, double T)
+{
+    return P.isothermal ? P.T0 : T;
+}
+// temperature from the pressure (read-back): the van der Waals inversion, or T0
+template <typename PT>
+__device__ __forceinline__ double eos_T_of_p(const PT &P, double rho, double p)
+{
+    return P.isothermal ? P.T0 : (p + P.a * rho * rho) * (1.0 - P.b * rho) / (rho * P.R);
+}
+template <typename PT>
+__device__ __forceinline__ double eos_e(const PT &P, double rho, double T)
+{
+    return P.Cv * T - (P.eos == kEosVdw ? P.a * rho : 0.0);
 }
 // bit set of the admissibility violations of a state (pressure domain, finiteness)
 template <typename PT>
-__device__ __forceinline__ int vdw_bad(const PT &P, double rho, double p)
+__device__ __forceinline__ int eos_bad(const PT &P, double rho, double p)
 {
     if (!isfinite(rho) || !isfinite(p)) return kErrNonfinite;
-    if (!(p > 0.0) || !(1.0 - P.b * rho > 0.0) || !(rho > 0.0)) return kErrPressure;
+    if (!(p > 0.0) || !(rho > 0.0) || !(P.eos == kEosWell || 1.0 - P.b * rho > 0.0)) return kErrPressure;
     return 0;
 }
 

@@ -387,9 +387,9 @@ __global__ void __launch_bounds__(SPLIT *TX *TY)
         const double uhx = ux + Fpx * dt / (2.0 * rho);
         const double uhy = DIM == 2 ? uy + Fpy * dt / (2.0 * rho) : 0.0;
         const double e = E - 0.5 * (uhx * uhx + uhy * uhy);
-        const double T = vdw_T_of_e(P, rho, e);
-        const double p = vdw_p(P, rho, T);
-        err |= vdw_bad(P, rho, p);
+        const double T = eos_T_of_e(P, rho, e);
+        const double p = eos_p(P, rho, T);
+        err |= eos_bad(P, rho, p);
         sUx = Ux;
         sUy = Uy;
         sS = s;
@@ -820,9 +820,9 @@ __global__ void __launch_bounds__(2 * TX *TY)
             const double uhx = pre_u[j][0] + Fx * dt * h_r;
             const double uhy = DIM == 2 ? pre_u[j][1] + Fy * dt * h_r : 0.0;
             const double e = E - 0.5 * (uhx * uhx + uhy * uhy);
-            const double T = vdw_T_of_e(P, rho, e);
-            const double p = vdw_p(P, rho, T);
-            err |= vdw_bad(P, rho, p);
+            const double T = eos_T_of_e(P, rho, e);
+            const double p = eos_p(P, rho, T);
+            err |= eos_bad(P, rho, p);
             const double mu = visc * p;
             s_th[kThFx][li] = Fx;
             s_th[kThFy][li] = Fy;
@@ -1075,11 +1075,11 @@ __global__ void k_init_equilibrium(const DevParams *__restrict__ Pp, const doubl
     const double r = rho_in[node];
     const double uh[2] = {u_in[node], DIM == 2 ? u_in[N + node] : 0.0};
     const double u[2] = {uh[0] - F[0] * dt / (2.0 * r), DIM == 2 ? uh[1] - F[1] * dt / (2.0 * r) : 0.0};
-    const double T = T_in[node];
-    const double p = vdw_p(P, r, T);
-    const int bad = vdw_bad(P, r, p);
+    const double T = eos_state_T(P, T_in[node]);
+    const double p = eos_p(P, r, T);
+    const int bad = eos_bad(P, r, p);
     if (bad) atomicOr(&flags[kFlagErr], bad);
-    const double e = (P.R / P.delta) * T - P.a * r;
+    const double e = eos_e(P, r, T);
     const double E = e + 0.5 * (uh[0] * uh[0] + uh[1] * uh[1]);
     const double theta = p / (r * kTL);
     const double s = sqrt(theta);
@@ -1163,8 +1163,8 @@ __global__ void k_macro(const DevParams *__restrict__ Pp, const PopT *__restrict
     const double hx = side[kSideUx * N + n] + side[kSideFx * N + n] * P.dt / (2.0 * r);
     const double hy = DIM == 2 ? side[kSideUy * N + n] + side[kSideFy * N + n] * P.dt / (2.0 * r) : 0.0;
     const double pr = r * side[kSideTh * N + n] * kTL;
-    const double T = (pr + P.a * r * r) * (1.0 - P.b * r) / (r * P.R);
-    const double e = (P.R / P.delta) * T - P.a * r;
+    const double T = eos_T_of_p(P, r, pr);
+    const double e = eos_e(P, r, T);
     out[0 * N + n] = r;
     out[1 * N + n] = hx;
     if (DIM == 2) out[2 * N + n] = hy;

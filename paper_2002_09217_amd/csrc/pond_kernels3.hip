@@ -427,9 +427,9 @@ __global__ void __launch_bounds__(2 * TX *TY, sizeof(LdsT) == 4 ? 2 : 1) k3_stre
             uh2 += uh * uh;
         }
         const double e = E - 0.5 * uh2;
-        const double T = vdw_T_of_e(P, rho, e);
-        const double p = vdw_p(P, rho, T);
-        if (inside) err |= vdw_bad(P, rho, p);
+        const double T = eos_T_of_e(P, rho, e);
+        const double p = eos_p(P, rho, T);
+        if (inside) err |= eos_bad(P, rho, p);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             sU[a] = U[a];
@@ -545,9 +545,9 @@ __global__ void __launch_bounds__(256) k3_thermo(const SlotDesc *__restrict__ sl
         uh2 += uh * uh;
     }
     const double e = E - 0.5 * uh2;
-    const double T = vdw_T_of_e(P, rho, e);
-    const double p = vdw_p(P, rho, T);
-    const int bad = vdw_bad(P, rho, p);
+    const double T = eos_T_of_e(P, rho, e);
+    const double p = eos_p(P, rho, T);
+    const int bad = eos_bad(P, rho, p);
     if (bad) raise_error3(S.flags, bad, S.parity);
     const double mu = (1.0 / P.omega - 0.5) * p * P.dt;
     double *aux = S.aux;
@@ -704,15 +704,15 @@ __global__ void __launch_bounds__(256) k3_init_equilibrium(const SlotDesc *__res
     double *mom = S.mom;
     double F[3] = {0.0, 0.0, 0.0};
     if (P.kappa != 0.0) force_at3(box, S.kor, x, y, z, F);
-    const double rho = aux[0 * N + n], T = aux[4 * N + n];
+    const double rho = aux[0 * N + n], T = eos_state_T(P, aux[4 * N + n]);
     const double uh[3] = {aux[1 * N + n], aux[2 * N + n], aux[3 * N + n]};
     double u[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) u[a] = uh[a] - F[a] * P.dt / (2.0 * rho);
-    const double p = vdw_p(P, rho, T);
-    const int bad = vdw_bad(P, rho, p);
+    const double p = eos_p(P, rho, T);
+    const int bad = eos_bad(P, rho, p);
     if (bad) raise_error3(S.flags, bad, 0);
-    const double e = P.Cv * T - P.a * rho;
+    const double e = eos_e(P, rho, T);
     const double E = e + 0.5 * (uh[0] * uh[0] + uh[1] * uh[1] + uh[2] * uh[2]);
     const double theta = p / (rho * kTL), s = sqrt(theta);
     // f = rho W: central moments rho prod_axes {1, 0, theta T_L}
@@ -784,11 +784,11 @@ __global__ void __launch_bounds__(256) k3_macro(const DevParams *__restrict__ Pp
         h2 += v * v;
     }
     const double pr = r * side[kSideTh * N + n] * kTL;
-    const double T = (pr + P.a * r * r) * (1.0 - P.b * r) / (r * P.R);
+    const double T = eos_T_of_p(P, r, pr);
     out[0 * N + n] = r;
     out[4 * N + n] = T;
     out[5 * N + n] = pr;
-    out[6 * N + n] = P.Cv * T - P.a * r + 0.5 * h2;
+    out[6 * N + n] = eos_e(P, r, T) + 0.5 * h2;
 }
 
 __global__ void __launch_bounds__(kMonThreads) k3_monitor_partials(const DevParams *__restrict__ Pp,

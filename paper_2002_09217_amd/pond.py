@@ -22,6 +22,7 @@ STATUS = {
 }
 BC_PERIODIC, BC_OUTFLOW, BC_INFLOW = 0, 1, 2
 FP64, FP32_STORE, FP32_STORE_FP64_MATH = 0, 1, 2
+EOS_VDW, EOS_DIETERICI, EOS_DOUBLE_WELL = 0, 1, 2
 
 # kernel ids of pond_time_kernel
 K_STREAM, K_FORCE_COLLIDE = 0, 1
@@ -44,6 +45,10 @@ class pond_config(ctypes.Structure):
         ("b", ctypes.c_double),
         ("R", ctypes.c_double),
         ("delta", ctypes.c_double),
+        ("eos", ctypes.c_int),
+        ("isothermal", ctypes.c_int),
+        ("T0", ctypes.c_double),
+        ("eos_c", ctypes.c_double * 4),
         ("omega", ctypes.c_double),
         ("kappa", ctypes.c_double),
         ("k_scale", ctypes.c_double),
@@ -127,6 +132,10 @@ class Config:
     k_scale: float = 1.0
     dt: float = 0.2
     n_pass: int = 2
+    eos: int = 0                # EOS_VDW, EOS_DIETERICI, EOS_DOUBLE_WELL
+    isothermal: int = 0         # nonzero: T = T0 everywhere (required unless EOS_VDW)
+    T0: float = 0.0
+    eos_c: tuple = (0.0, 0.0, 0.0, 0.0)   # EOS_DOUBLE_WELL: beta, rho_l, rho_v, p0
     precision: int = FP64
     tile: int = -1              # streaming tile shape; -1: measured at the first init
     stream: int | None = None   # hipStream_t as an integer (e.g. torch's cuda_stream)
@@ -146,6 +155,9 @@ class Config:
             for k in range(5):
                 c.inflow[a][s][k] = float(vals[k])
         c.a, c.b, c.R, c.delta = self.a, self.b, self.R, self.delta
+        c.eos, c.isothermal, c.T0 = int(self.eos), int(self.isothermal), float(self.T0)
+        for i in range(4):
+            c.eos_c[i] = float(self.eos_c[i])
         c.omega, c.kappa, c.k_scale, c.dt = self.omega, self.kappa, self.k_scale, self.dt
         c.n_pass, c.precision, c.tile = self.n_pass, self.precision, self.tile
         c.stream = self.stream

@@ -69,8 +69,9 @@ def lattice_config(case: W.Case, precision: int, tile: int, stream=None) -> pond
     p = case.params
     return pond.Config(dim=case.dim, n=tuple(case.n), bc=case.bc, inflow=case.inflow, a=p["a"], b=p["b"],
                        R=p["R"], delta=p["delta"], omega=p["omega"], kappa=p["kappa"],
-                       k_scale=p["k_scale"], dt=p["dt"], n_pass=p["n_pass"], precision=precision,
-                       tile=tile, stream=stream)
+                       k_scale=p["k_scale"], dt=p["dt"], n_pass=p["n_pass"], eos=p.get("eos", 0),
+                       isothermal=p.get("isothermal", 0), T0=p.get("T0", 0.0),
+                       eos_c=p.get("eos_c", (0.0,) * 4), precision=precision, tile=tile, stream=stream)
 
 
 def tune_tiles(sides, precision: int, stream=None) -> dict:

@@ -71,7 +71,8 @@ class Case:
 
 
 def base_params(**kw) -> dict:
-    p = dict(a=A, b=B, R=R, delta=1.0 / 3.0, omega=1.5, kappa=0.0, k_scale=1.0, dt=DT, n_pass=2)
+    p = dict(a=A, b=B, R=R, delta=1.0 / 3.0, omega=1.5, kappa=0.0, k_scale=1.0, dt=DT, n_pass=2,
+             eos=0, isothermal=0, T0=0.0, eos_c=(0.0, 0.0, 0.0, 0.0))
     p.update(kw)
     return p
 

@@ -12,6 +12,11 @@ from paper_2002_09217_amd import pond
 U_CH = float(np.sqrt((1.0 / 6.0) / 3.5))
 
 
+def _eos_kw(p) -> dict:
+    return dict(eos=p.get("eos", 0), isothermal=p.get("isothermal", 0), T0=p.get("T0", 0.0),
+                eos_c=tuple(p.get("eos_c", (0.0,) * 4)))
+
+
 def oracle_config(case) -> core.Config:
     p = case.params
     inflow = [[(0.0,) * 4, (0.0,) * 4], [(0.0,) * 4, (0.0,) * 4]]
@@ -20,7 +25,7 @@ def oracle_config(case) -> core.Config:
     return core.Config(dim=case.dim, nx=case.n[0], ny=case.n[1] if case.dim == 2 else 1,
                        bc=case.bc, inflow=tuple(tuple(x) for x in inflow), a=p["a"], b=p["b"],
                        R=p["R"], delta=p["delta"], omega=p["omega"], kappa=p["kappa"],
-                       k_scale=p["k_scale"], dt=p["dt"], n_pass=p["n_pass"])
+                       k_scale=p["k_scale"], dt=p["dt"], n_pass=p["n_pass"], **_eos_kw(p))
 
 
 def pond_config(case, precision=pond.FP64, stream=None, tile=-1) -> pond.Config:
@@ -28,7 +33,7 @@ def pond_config(case, precision=pond.FP64, stream=None, tile=-1) -> pond.Config:
     return pond.Config(dim=case.dim, n=tuple(case.n), bc=case.bc, inflow=case.inflow,
                        a=p["a"], b=p["b"], R=p["R"], delta=p["delta"], omega=p["omega"],
                        kappa=p["kappa"], k_scale=p["k_scale"], dt=p["dt"], n_pass=p["n_pass"],
-                       precision=precision, tile=tile, stream=stream)
+                       precision=precision, tile=tile, stream=stream, **_eos_kw(p))
 
 
 def run_oracle(case, steps):
@@ -44,7 +49,7 @@ def oracle_config3(case) -> core.Config3:
     p = case.params
     return core.Config3(nx=case.n[0], ny=case.n[1], nz=case.n[2], a=p["a"], b=p["b"], R=p["R"],
                         delta=p["delta"], omega=p["omega"], kappa=p["kappa"], k_scale=p["k_scale"],
-                        dt=p["dt"], n_pass=p["n_pass"])
+                        dt=p["dt"], n_pass=p["n_pass"], **_eos_kw(p))
 
 
 def run_oracle3(case, steps):

@@ -1,0 +1,146 @@
+"""Isothermal equations of state on the HIP path through the C ABI (Supplement:
+coexistence curve of the Dieterici fluid, speed of sound with the simplified free
+energy and in the van der Waals fluid): parity with the oracle on identical seeded
+inputs, the admissibility rules, and the physics the paper reports."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.thermo import Dieterici, DoubleWell, VdW
+from paper_2002_09217_amd import pond, workloads as W
+from tests.common import compare, pond_config, pulse_speed, run_gpu, run_oracle, run_oracle3
+
+pytestmark = pytest.mark.gpu
+
+DIET, VDW = Dieterici(), VdW()
+WELL = DoubleWell(8e-4, 5.0, 0.5, 0.1)
+
+
+def _iso(kind, T0):
+    kw = dict(eos=kind, isothermal=1, T0=T0)
+    if kind == pond.EOS_DIETERICI:
+        kw.update(a=DIET.a, b=DIET.b, R=DIET.R)
+    if kind == pond.EOS_DOUBLE_WELL:
+        kw.update(eos_c=(WELL.beta, WELL.rho_l, WELL.rho_v, WELL.p0))
+    return kw
+
+
+# (kind, T0, a stable density of that isotherm)
+KINDS = [(pond.EOS_VDW, 0.9 * VDW.T_cr, 1.2), (pond.EOS_DIETERICI, 0.9 * DIET.T_cr, 1.5),
+         (pond.EOS_DOUBLE_WELL, 0.1, 5.0)]
+FIELDS = ("rho", "ux", "uy", "E", "T", "p")
+
+
+def _check(ref, got, fields, tol, name):
+    errs = compare(got, ref, fields)
+    print(name, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    assert not bad, f"{name}: {bad}"
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+@pytest.mark.parametrize("kind,T0,rho0", KINDS)
+def test_parity_with_the_oracle(kind, T0, rho0, dim):
+    case = W.perturbed(40, 36, seed=7 + kind, dim=dim, rho0=rho0, u0=(0.05, -0.02), kappa=0.0176, dt=0.2,
+                       **_iso(kind, T0))
+    fields = FIELDS if dim == 2 else ("rho", "ux", "E", "T", "p")
+    _check(run_oracle(case, 20), run_gpu(case, 20), fields, 1e-12, case.name)
+
+
+@pytest.mark.parametrize("precision,tol", [(pond.FP32_STORE, 1e-4), (pond.FP32_STORE_FP64_MATH, 1e-6)])
+def test_parity_fp32_storage_forms(precision, tol):
+    kind, T0, rho0 = KINDS[1]
+    case = W.perturbed(33, 29, seed=3, rho0=rho0, u0=(0.02, 0.04), kappa=0.0176, dt=0.2, **_iso(kind, T0))
+    _check(run_oracle(case, 20), run_gpu(case, 20, precision), FIELDS, tol, case.name)
+
+
+@pytest.mark.parametrize("kind,T0,rho0", KINDS[1:])
+def test_parity_three_dimensions(kind, T0, rho0):
+    case = W.perturbed3(13, 10, 7, seed=2, rho0=rho0, u0=(0.03, -0.02, 0.01), kappa=0.0176, dt=0.2,
+                        **_iso(kind, T0))
+    _check(run_oracle3(case, 8), run_gpu(case, 8), ("rho", "ux", "uy", "uz", "E", "T", "p"), 1e-12, case.name)
+
+
+def test_admissibility_rules():
+    base = W.perturbed(16, 16, seed=1, rho0=1.5)
+    bad = [dict(eos=pond.EOS_DIETERICI),                                     # not isothermal
+           dict(eos=pond.EOS_VDW, isothermal=1, T0=0.0),                     # T0 <= 0
+           dict(eos=pond.EOS_DOUBLE_WELL, isothermal=1, T0=0.1, eos_c=(1e-3, 0.5, 5.0, 0.1)),  # rho_l < rho_v
+           dict(eos=pond.EOS_DOUBLE_WELL, isothermal=1, T0=0.1, eos_c=(1e-3, 5.0, 0.5, 0.0)),  # p0 = 0
+           dict(eos=3, isothermal=1, T0=0.1)]
+    for kw in bad:
+        base.params.update(dict(eos=0, isothermal=0, T0=0.0, eos_c=(0.0,) * 4), **kw)
+        with pytest.raises(pond.PondError) as err:
+            pond.Lattice(pond_config(base))
+        assert err.value.code == -1, kw
+
+
+def test_isothermal_state_ignores_the_given_temperature_and_keeps_T0():
+    kind, T0, rho0 = KINDS[1]
+    case = W.perturbed(24, 20, seed=4, rho0=rho0, **_iso(kind, T0))
+    lat = pond.Lattice(pond_config(case))
+    lat.init_fields(case.rho, case.u, 3.0 * case.T)
+    lat.step(10)
+    m = lat.moments()
+    lat.close()
+    assert np.all(m["T"] == T0)
+
+
+def _slab(precision, kind, T0, N=400, kappa=0.0176, width=3.0, warm=4000, chunks=40, chunk=200):
+    G = DIET if kind == pond.EOS_DIETERICI else VDW
+    rv, rl, _ = G.maxwell(T0)
+    x = np.arange(N)
+    prof = 0.5 * (np.tanh((x - N / 4) / width) - np.tanh((x - 3 * N / 4) / width))
+    p = W.base_params(omega=1.0, kappa=kappa, dt=0.1, **_iso(kind, T0))
+    cfg = pond.Config(dim=1, n=(N,), bc=((0, 0),), a=p["a"], b=p["b"], R=p["R"], delta=p["delta"],
+                      omega=p["omega"], kappa=p["kappa"], k_scale=p["k_scale"], dt=p["dt"], n_pass=2,
+                      eos=kind, isothermal=1, T0=T0, precision=precision, tile=0)
+    lat = pond.Lattice(cfg)
+    lat.init_fields(rv + (rl - rv) * prof, np.zeros(N), np.full(N, T0))
+    lat.step(warm)
+    vap, liq = [], []
+    for _ in range(chunks):
+        lat.step(chunk)
+        r = lat.moments()["rho"]
+        vap.append(0.5 * (r[:20].mean() + r[-20:].mean()))
+        liq.append(r[N // 2 - 10:N // 2 + 10].mean())
+    lat.close()
+    return np.mean(vap) / rv - 1.0, np.mean(liq) / rl - 1.0
+
+
+@pytest.mark.parametrize("precision", [pond.FP64, pond.FP32_STORE])
+def test_dieterici_coexistence_curve(precision):
+    """Supplement, coexistence curve: liquid slabs in their vapour at four temperatures,
+    densities at the phase centres averaged over the slowly decaying acoustic transient,
+    against Maxwell's rule for the Dieterici isotherm."""
+    for tr in (0.8, 0.85, 0.9, 0.95):
+        ev, el = _slab(precision, pond.EOS_DIETERICI, tr * DIET.T_cr)
+        print(f"T/T_cr {tr}: vapour {ev:+.2e} liquid {el:+.2e}", flush=True)
+        assert abs(ev) < 0.015 and abs(el) < 0.015
+
+
+@pytest.mark.parametrize("precision", [pond.FP64, pond.FP32_STORE, pond.FP32_STORE_FP64_MATH])
+def test_isothermal_sound_speeds(precision):
+    """Supplement, speed of sound: the double well at its saturated densities against the
+    printed speeds, and the van der Waals fluid at 0.9 T_cr against sqrt((dp/drho)_T)."""
+    T0v = 0.9 * VDW.T_cr
+    rv, rl, _ = VDW.maxwell(T0v)
+    cases = [(pond.EOS_DOUBLE_WELL, 0.1, WELL.rho_l, WELL.sound_saturated()[0]),
+             (pond.EOS_DOUBLE_WELL, 0.1, WELL.rho_v, WELL.sound_saturated()[1]),
+             (pond.EOS_VDW, T0v, rv, math.sqrt(VDW.dp_drho_T(rv, T0v))),
+             (pond.EOS_VDW, T0v, rl, math.sqrt(VDW.dp_drho_T(rl, T0v)))]
+    for kind, T0, rho0, c_ref in cases:
+        def factory(rho, T, dt):
+            p = W.base_params(omega=1.5, dt=dt, **_iso(kind, T0))
+            cfg = pond.Config(dim=1, n=(rho.size,), bc=((0, 0),), a=p["a"], b=p["b"], R=p["R"],
+                              delta=p["delta"], omega=1.5, kappa=0.0, dt=dt, n_pass=2, eos=kind, isothermal=1,
+                              T0=T0, eos_c=p["eos_c"], precision=precision, tile=0)
+            lat = pond.Lattice(cfg)
+            lat.init_fields(rho, np.zeros(rho.size), np.full(rho.size, T0))
+            return lat
+
+        times = (round(60.0 / c_ref), round(120.0 / c_ref))
+        c = pulse_speed(factory, rho0, 1.0, times=times)
+        print(f"eos {kind} rho {rho0:.4f}: pulse {c:.5f} theory {c_ref:.5f} ({c / c_ref - 1:+.2e})", flush=True)
+        assert c == pytest.approx(c_ref, rel=3e-3)
