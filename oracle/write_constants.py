@@ -7,7 +7,10 @@ paper_2002_09217_amd/data/vdw_constants.json with
   * the coexistence densities (Maxwell's equal-area rule, main text, Fig. 2) for
     T/T_cr = 0.850, 0.855, ..., 0.995 with the paper's a = 2/49, b = 2/21, R = 1;
   * the post-shock state behind a shock with pressure ratio 3 running into saturated
-    vapour at T/T_cr = 0.95, delta = 1/3 (Rankine-Hugoniot, App. E).
+    vapour at T/T_cr = 0.95, delta = 1/3 (Rankine-Hugoniot, App. E);
+  * the shock-tube states the paper prints in reduced units (p/p_cr, rho/rho_cr) -- the
+    anomalous case of the main text (Fig. 4, delta = 0.0125) and the two cases of
+    App. E -- with the temperature of each state from the van der Waals EoS.
 """
 from __future__ import annotations
 
@@ -15,6 +18,14 @@ import json
 import os
 
 from oracle.thermo import VdW
+
+# (p_L, rho_L, p_R, rho_R) in reduced units and delta: main text, Fig. 4 caption
+# (anomalous shock), and App. E, table of shock-tube conditions (cases I and II)
+SHOCK_TUBES = {
+    "anomalous": (1.09, 0.879, 0.885, 0.562, 0.0125),
+    "case_I": (1.6077, 1.01, 0.8957, 0.594, 0.329),
+    "case_II": (3.00, 1.818, 0.575, 0.275, 0.0125),
+}
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 OUT = os.path.join(ROOT, "paper_2002_09217_amd", "data", "vdw_constants.json")
@@ -36,8 +47,16 @@ def compute() -> dict:
     shock = {"T_over_Tcr": 0.95, "delta": 1.0 / 3.0, "pressure_ratio": 3.0, "rho0": rv, "p0": ps,
              "rho_liquid": rl, "rho1": sh["rho1"], "u1": sh["u1"], "p1": sh["p1"], "T1": sh["T1"],
              "shock_speed": sh["s"], "mach": sh["Ms"]}
+    tubes = {}
+    for name, (pl, rl_, pr, rr, d) in SHOCK_TUBES.items():
+        gd = VdW(delta=d)
+        states = []
+        for p_r, rho_r in ((pl, rl_), (pr, rr)):
+            rho, p = rho_r * gd.rho_cr, p_r * gd.p_cr
+            states.append({"rho": rho, "p": p, "T": gd.T_of_p(rho, p)})
+        tubes[name] = {"delta": d, "left": states[0], "right": states[1]}
     return {"a": g.a, "b": g.b, "R": g.R, "rho_cr": g.rho_cr, "T_cr": g.T_cr, "p_cr": g.p_cr,
-            "coexistence": table, "shock": shock}
+            "coexistence": table, "shock": shock, "shock_tubes": tubes}
 
 
 def main():

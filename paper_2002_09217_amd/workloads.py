@@ -121,6 +121,26 @@ def shock_tube(n=1000, steps=2000, **kw) -> Case:
                 bc=((OUTFLOW, OUTFLOW), (PERIODIC, PERIODIC)))
 
 
+def reduced_shock_tube(name="anomalous", n=800, steps=None, delta=None, **kw) -> Case:
+    """1D van der Waals shock tube between two states the paper prints in reduced units:
+    "anomalous" (main text, Fig. 4, delta = 0.0125), "case_I" and "case_II" (App. E).
+    The diaphragm sits at the middle, u = 0, outflow at both ends, no interface energy;
+    the temperatures are those of the stored table.  delta overrides the table's value
+    (with the same rho and T on each side).  The default step count reaches the
+    paper's snapshot time t* = (t/L) sqrt(p_cr/rho_cr) = 0.45."""
+    tube = CONST["shock_tubes"][name]
+    x = np.arange(n)
+    left = x < n // 2
+    rho = np.where(left, tube["left"]["rho"], tube["right"]["rho"]).astype(np.float64)
+    T = np.where(left, tube["left"]["T"], tube["right"]["T"]).astype(np.float64)
+    d = tube["delta"] if delta is None else delta
+    p = base_params(omega=1.0, delta=d, **kw)
+    if steps is None:
+        steps = int(round(0.45 * n / np.sqrt(P_CR / RHO_CR) / p["dt"]))
+    return Case(name=f"shocktube_{name}{n}", dim=1, n=(n,), params=p, rho=rho, u=np.zeros((1, n)), T=T,
+                steps=steps, bc=((OUTFLOW, OUTFLOW), (PERIODIC, PERIODIC)), meta=dict(tube=tube))
+
+
 def droplet_shock(nx=1024, ny=512, steps=1500, radius=50.0, x_drop=300.0, x_shock=150.0, **kw) -> Case:
     """Planar shock (pressure ratio 3, post-shock state from the Rankine-Hugoniot relations)
     running into saturated vapour at 0.95 T_cr that holds a liquid droplet; inflow at x = 0

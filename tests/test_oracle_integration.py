@@ -19,7 +19,8 @@ import pytest
 
 from oracle import core, riemann
 from oracle.thermo import VdW
-from tests.common import pulse_speed
+from paper_2002_09217_amd import workloads as W
+from tests.common import oracle_config, pulse_speed
 
 VDW = VdW()
 
@@ -255,3 +256,32 @@ def test_pulse_travels_at_the_vdw_sound_speed(rho0, Tr):
 
     c = pulse_speed(factory, rho0, Tr)
     assert c == pytest.approx(VDW.sound_vdw(rho0, Tr * VDW.T_cr), rel=3e-3)
+
+
+def _wave_steepening(case, t1_steps):
+    """Largest pressure jump between neighbours in each half of a shock tube at t1 and at
+    2 t1, and where it sits.  The contact carries no pressure jump, so each half holds one
+    wave: a shock keeps its steepness, a fan's steepness falls like 1/t."""
+    sim = core.Sim(oracle_config(case))
+    sim.init(case.rho, case.u[0], case.T)
+    out = []
+    n = case.n[0]
+    for _ in range(2):
+        sim.step(t1_steps)
+        dp = np.abs(np.diff(sim.moments()["p"]))
+        out.append((dp[: n // 2].max(), dp[n // 2:].max(), int(np.argmax(dp[: n // 2])),
+                    n // 2 + int(np.argmax(dp[n // 2:]))))
+    return out
+
+
+def test_anomalous_shock_tube_has_a_rarefaction_shock_and_a_compression_fan():
+    """Main text, Fig. 4: with delta = 0.0125 both states lie where Gamma < 0; the expansion
+    running into the high-pressure side is a shock and the compression running into the
+    low-pressure side is a fan.  The same states at delta = 1/3 give the classical pair."""
+    case = W.reduced_shock_tube("anomalous", n=400, dt=0.2)
+    (l1, r1, xl1, xr1), (l2, r2, xl2, xr2) = _wave_steepening(case, case.steps // 2)
+    assert l2 / l1 > 0.85 and r2 / r1 < 0.75
+    assert xl2 < xl1 < 200 < xr1 < xr2                 # rarefaction to the left, compression right
+    classical = W.reduced_shock_tube("anomalous", n=400, dt=0.2, delta=1.0 / 3.0)
+    (l1, r1, *_), (l2, r2, *_) = _wave_steepening(classical, classical.steps // 6)
+    assert l2 / l1 < 0.75 and r2 / r1 > 0.85
