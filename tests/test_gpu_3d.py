@@ -7,7 +7,7 @@ import pytest
 
 from oracle.thermo import VdW
 from paper_2002_09217_amd import pond, workloads as W
-from tests.common import pond_config, pulse_speed, run_oracle3
+from tests.common import U_CH, pond_config, pulse_speed, run_oracle3
 
 pytestmark = pytest.mark.gpu
 VDW = VdW()
@@ -101,3 +101,36 @@ def test_pulse_travels_at_the_vdw_sound_speed_along_each_axis(precision):
         made[0].lat.close()
         print(f"axis {axis}: pulse {c:.5f} vdW {ref:.5f} ({c / ref - 1:+.2e})", flush=True)
         assert c == pytest.approx(ref, rel=3e-3)
+
+
+@pytest.mark.parametrize("precision,tol", [(pond.FP64, 1e-12), (pond.FP32_STORE_FP64_MATH, 1e-9),
+                                           (pond.FP32_STORE, 1e-5)])
+def test_full_size_droplet_keeps_its_symmetry(precision, tol):
+    """Config 5 at its full size (256^3, beyond the oracle): the centred droplet is
+    symmetric under exchanging two axes and under reflection through the centre, and the
+    step must keep both.  FP64 keeps them to round-off.  In the FP32 storage forms an
+    FP64 round-off difference between mirror nodes can tip the FP32 rounding of a stored
+    deviation either way (about 1e-11); FP32 streaming also uses per-tile references,
+    which the exchange of x and y does not map onto each other."""
+    n = 256
+    case = W.static_droplet3(n=n)
+    lat = pond.Lattice(pond_config(case, precision=precision))
+    lat.init_fields(case.rho, case.u, case.T)
+    lat.step(3)
+    m = lat.moments()
+    lat.close()
+    rho = m["rho"].reshape(n, n, n)                       # [z][y][x]
+    ux, uy, uz = (m[k].reshape(n, n, n) for k in ("ux", "uy", "uz"))
+    scale = np.max(np.abs(rho))
+    refl = (n - np.arange(n)) % n                         # x -> n - x about the centre n/2
+    errs = {
+        "swap xy": np.max(np.abs(rho - rho.transpose(0, 2, 1))) / scale,
+        "swap xz": np.max(np.abs(rho - rho.transpose(2, 1, 0))) / scale,
+        "reflect x": np.max(np.abs(rho - rho[:, :, refl])) / scale,
+        "u swap xy": np.max(np.abs(ux - uy.transpose(0, 2, 1))) / U_CH,
+        "u reflect x": np.max(np.abs(ux + ux[:, :, refl])) / U_CH,
+        "uz reflect z": np.max(np.abs(uz + uz[refl, :, :])) / U_CH,
+    }
+    print(precision, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    assert max(errs.values()) <= tol
+    assert np.all(np.isfinite(rho)) and rho.min() > 0.5 * case.meta["rho_v"]
