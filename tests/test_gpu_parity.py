@@ -71,6 +71,13 @@ def test_full_size_droplet_256_few_steps():
     _check(case, 3)
 
 
+def test_full_size_droplet_shock_1024x512_few_steps():
+    """Config 3 at its full size (inflow, outflow, periodic y, the shock and the droplet)
+    in the launch configuration the benchmark uses (autotuned tile shape)."""
+    case = W.droplet_shock()
+    _check(case, 2)
+
+
 @pytest.mark.parametrize("which", ["perturbed", "droplet"])
 def test_fp32_storage_within_1e4(which):
     if which == "perturbed":
