@@ -183,6 +183,52 @@ __global__ void __launch_bounds__(256) k3_donor_moments(const SlotDesc *__restri
     for (int i = 0; i < 27; ++i) out[(size_t)i * N + node] = (MomT)m[i];
 }
 
+// x-y contraction of the nine fields (m, n, o) of one z power o over a staged donor
+// plane, into Y[k][l] += sum_n B_ln sum_r wy_l[r] sum_m A_km sum_c wx_k[c] M_mno[r][c].
+// Each axis's cubic stencil covers four of the five window columns; for the directions
+// c = -1 and +1 the unused column is the first (k = 0) or the last (k = 2) whenever the
+// gauge velocity lies in (-s, s].  FAST (chosen per wave when every lane's weights
+// there are zero) leaves those zero taps out; the two variants agree to round-off, and
+// the choice depends only on the lanes of a wave, which the tile shape fixes.
+template <bool FAST, typename T>
+__device__ __forceinline__ T taps3(int k, const T w[5], T v0, T v1, T v2, T v3, T v4)
+{
+    if (FAST && k == 0) return w[1] * v1 + w[2] * v2 + w[3] * v3 + w[4] * v4;
+    if (FAST && k == 2) return w[0] * v0 + w[1] * v1 + w[2] * v2 + w[3] * v3;
+    return w[0] * v0 + w[1] * v1 + w[2] * v2 + w[3] * v3 + w[4] * v4;
+}
+
+template <bool FAST, typename LdsT, typename AccT, int LN, int LX>
+__device__ __forceinline__ void xy_window(const LdsT *sbase, int o, const LdsT (&wx)[3][5],
+                                          const LdsT (&wy)[3][5], const LdsT (&A)[3][3], const AccT (&B)[3][3],
+                                          AccT (&Y)[3][3])
+{
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+        LdsT Z[3][5];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int r = 0; r < 5; ++r) Z[k][r] = (LdsT)0;
+#pragma unroll
+        for (int r = 0; r < 5; ++r) {
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                const LdsT *row = sbase + ((9 * m + 3 * n + o) * LN + r * LX) * 2;
+                const LdsT v0 = row[0], v1 = row[2], v2 = row[4], v3 = row[6], v4 = row[8];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) Z[k][r] += A[k][m] * taps3<FAST>(k, wx[k], v0, v1, v2, v3, v4);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int l = 0; l < 3; ++l)
+                Y[k][l] += B[l][n] * (AccT)taps3<FAST>(l, wy[l], Z[k][0], Z[k][1], Z[k][2], Z[k][3], Z[k][4]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // streaming passes: x-y tile of TX x TY receivers of one z plane, two lanes per
 // receiver (set f / g), the 5 x 5 x 5 window staged plane by plane.
@@ -276,6 +322,9 @@ __global__ void __launch_bounds__(2 * TX *TY, sizeof(LdsT) == 4 ? 2 : 1) k3_stre
         AccT av[27];
 #pragma unroll
         for (int q = 0; q < 27; ++q) av[q] = (AccT)0;
+        // zero-tap-free window variant when every lane of the wave allows it
+        const bool fast = __all(wx[0][0] == (LdsT)0 && wx[2][4] == (LdsT)0 && wy[0][0] == (LdsT)0 &&
+                                wy[2][4] == (LdsT)0);
 
 #pragma unroll 1
         for (int sz = 0; sz < 5; ++sz) {
@@ -327,37 +376,10 @@ __global__ void __launch_bounds__(2 * TX *TY, sizeof(LdsT) == 4 ? 2 : 1) k3_stre
                 for (int k = 0; k < 3; ++k)
 #pragma unroll
                     for (int l = 0; l < 3; ++l) Y[k][l] = (AccT)0;
-#pragma unroll
-                for (int n = 0; n < 3; ++n) {
-                    LdsT Z[3][5];
-#pragma unroll
-                    for (int k = 0; k < 3; ++k)
-#pragma unroll
-                        for (int r = 0; r < 5; ++r) Z[k][r] = (LdsT)0;
-#pragma unroll
-                    for (int r = 0; r < 5; ++r) {
-#pragma unroll
-                        for (int m = 0; m < 3; ++m) {
-                            const LdsT *row = sbase + ((9 * m + 3 * n + o) * LN + r * LX) * 2;
-                            const LdsT v0 = row[0], v1 = row[2], v2 = row[4], v3 = row[6], v4 = row[8];
-#pragma unroll
-                            for (int k = 0; k < 3; ++k) {
-                                const LdsT xk = wx[k][0] * v0 + wx[k][1] * v1 + wx[k][2] * v2 + wx[k][3] * v3 +
-                                                wx[k][4] * v4;
-                                Z[k][r] += A[k][m] * xk;
-                            }
-                        }
-                    }
-#pragma unroll
-                    for (int k = 0; k < 3; ++k)
-#pragma unroll
-                        for (int l = 0; l < 3; ++l) {
-                            const LdsT I = wy[l][0] * Z[k][0] + wy[l][1] * Z[k][1] + wy[l][2] * Z[k][2] +
-                                           wy[l][3] * Z[k][3] + wy[l][4] * Z[k][4];
-                            Y[k][l] += B[l][n] * (AccT)I;
-                        }
-                    __builtin_amdgcn_sched_barrier(0);
-                }
+                if (fast)
+                    xy_window<true, LdsT, AccT, LN, LX>(sbase, o, wx, wy, A, B, Y);
+                else
+                    xy_window<false, LdsT, AccT, LN, LX>(sbase, o, wx, wy, A, B, Y);
                 // z contraction: departure point m of the receiver takes wz[m][sz] C[m][o]
 #pragma unroll
                 for (int m = 0; m < 3; ++m) {
