@@ -11,6 +11,8 @@
  *      with cubic Lagrange reconstruction                             (App. D)
  *      inside a fixed-count predictor-corrector on (rho, u, E) through the van
  *      der Waals equation of state                                    (main text; App. A)
+ *      or, in isothermal runs, the van der Waals, Dieterici or double-well
+ *      pressure at a fixed temperature                                (Supplement)
  *   2. evaluates the Korteweg stress and force F = -div K              (eq. 18; App. F)
  *      and the heat-flux correction M0                                (eq. 9)
  *   3. relaxes f and g to their equilibria with the force source S_i, the
@@ -20,8 +22,8 @@
  * Conventions for every call below
  *   - All functions return a pond_status (0 = POND_OK, negative = error).
  *   - Host arrays are caller-owned, plain C doubles, copied synchronously.
- *   - Node order: index = x + n[0] * y.  A vector field is `dim` consecutive planes
- *     of n[0]*n[1] values (x component first).
+ *   - Node order: index = x + n[0] * (y + n[1] * z).  A vector field is `dim`
+ *     consecutive planes of N = n[0]*n[1]*n[2] values (x component first).
  *   - Device memory is owned by the library (allocated in pond_create, released in
  *     pond_destroy).  Work is enqueued on cfg.stream (a hipStream_t, e.g. PyTorch's
  *     current stream) or on a library-owned stream when cfg.stream is NULL.
@@ -99,9 +101,11 @@ typedef struct {
 } pond_config;
 
 /* Validate cfg and allocate the device state.  *out receives the handle (NULL on
- * error).  Errors: POND_E_INVALID (dim, sizes, 0 < delta <= 2/3, 0 < omega < 2,
- * n_pass >= 1, dt > 0, tile in range, inflow state with p <= 0, a non-periodic face
- * in 3D), POND_E_NOMEM, POND_E_DEVICE. */
+ * error).  Errors: POND_E_INVALID (dim, sizes: N <= 2^30 nodes, 2^29 in 3D;
+ * 0 < delta <= 2/3, 0 < omega < 2, n_pass >= 1, dt > 0, tile in range, inflow state
+ * with p <= 0, a non-periodic face in 3D; eos out of range, a non-van-der-Waals eos
+ * without isothermal, T0 <= 0 when isothermal, double-well constants other than
+ * beta > 0, rho_l > rho_v > 0, p0 > 0), POND_E_NOMEM, POND_E_DEVICE. */
 int pond_create(const pond_config *cfg, pond_handle **out);
 
 /* Set the state from the macroscopic fields rho (N), actual velocity u (dim planes
@@ -118,7 +122,8 @@ int pond_step(pond_handle *h, int nsteps);
 
 /* Macroscopic fields of the current state into host arrays (any may be NULL):
  * rho = sum_i f_i; u = u_gauge + F dt/(2 rho) (the actual velocity u-hat, eq. 17 and
- * App. F); p = rho theta T_L; T from the EoS; E = e + |u|^2/2 (dim planes for u). */
+ * App. F); p = rho theta T_L; T from the EoS (T0 when isothermal); E = e + |u|^2/2
+ * (dim planes for u). */
 int pond_moments(pond_handle *h, double *rho, double *u, double *T, double *p, double *E);
 
 /* Conservation monitors of the current state (eq. 2 and App. F), FP64 sums in a
@@ -199,7 +204,8 @@ int pond_batch_create(void *stream, pond_batch **out);
  * (POND_E_STATE); pond_moments, pond_monitors, pond_steps_done, pond_last_error and
  * pond_tile_info work as usual, and pond_destroy removes it first.  The handle's
  * stream is synchronised before it joins.  Errors: POND_E_INVALID (NULL, already
- * a member of a batch, or its group would exceed 2^21 workgroups per launch),
+ * a member of a batch, a D3Q27 lattice, or its group would exceed 2^21 workgroups
+ * per launch),
  * POND_E_STATE (not initialised or in the error state), POND_E_NOMEM. */
 int pond_batch_add(pond_batch *b, pond_handle *h);
 

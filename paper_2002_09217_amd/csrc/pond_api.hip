@@ -186,6 +186,9 @@ int validate(const pond_config *cfg)
     if (c.dim < 1 || c.dim > 3) return POND_E_INVALID;
     const int nx = c.n[0], ny = c.dim >= 2 ? c.n[1] : 1, nz = c.dim == 3 ? c.n[2] : 1;
     if (nx < 1 || ny < 1 || nz < 1 || (long long)nx * ny * nz > (1LL << 30)) return POND_E_INVALID;
+    // D3Q27: the plane staging of the streaming kernel addresses a field plane with
+    // 32-bit byte offsets (N * 8 < 2^32)
+    if (c.dim == 3 && (long long)nx * ny * nz > (1LL << 29)) return POND_E_INVALID;
     if (c.dim == 3) // D3Q27: periodic box only
         for (int a = 0; a < 3; ++a)
             for (int s = 0; s < 2; ++s)
