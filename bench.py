@@ -19,7 +19,8 @@ whole lattice.  Prints one JSON line:
   serving      the batched-serving workload (64 seeded droplet jobs of mixed sides and
                temperatures, Poisson arrivals at 20/s, 5000 steps each) through the
                continuous-batching server and one job at a time: runs/s, p50/p99
-               time-to-result, for FP32-store and FP64;
+               time-to-result, for FP32-store and FP64; FP32-store also batched under
+               a 512 MiB device-memory budget, where admission holds jobs back;
   roofline     the streaming kernel (dominant) against the FP64 VALU peak, its mean
                launch duration from HIP events recorded on its stream around every
                launch of a second timed run of steps; traffic from the committed
@@ -87,7 +88,9 @@ def traffic_from_profile(kernel_prefix):
     return None, None
 
 
-def serving(precision, stream, jobs_n, log_prefix):
+def serving(precision, stream, jobs_n, log_prefix, budget_mib=None):
+    """The serving workload batched and one job at a time; with budget_mib, also batched
+    under that device-memory budget, so that admission holds jobs back."""
     from paper_2002_09217_amd import serve
 
     jobs = serve.make_jobs(count=jobs_n)
@@ -98,8 +101,17 @@ def serving(precision, stream, jobs_n, log_prefix):
     log(f"bench: serving {log_prefix} batched {batched}")
     alone = serve.summarize(serve.run_sequential(jobs, precision, tiles, stream))
     log(f"bench: serving {log_prefix} one at a time {alone}")
-    return {"batched": batched, "one_at_a_time": alone, "tiles": tiles,
-            "speedup_runs_per_s": round(batched["runs_per_s"] / alone["runs_per_s"], 3)}
+    out = {"batched": batched, "one_at_a_time": alone, "tiles": tiles,
+           "speedup_runs_per_s": round(batched["runs_per_s"] / alone["runs_per_s"], 3)}
+    if budget_mib:
+        budget = int(budget_mib * 2**20)
+        srv = serve.Server(precision, budget_bytes=budget, tiles=tiles, stream=stream)
+        capped = serve.summarize(srv.run(jobs))
+        capped.update(budget_bytes=budget, peak_bytes=srv.peak_bytes, peak_slots=srv.peak_slots,
+                      chunks=srv.chunks)
+        log(f"bench: serving {log_prefix} batched under {budget_mib} MiB {capped}")
+        out[f"batched_budget_{budget_mib}MiB"] = capped
+    return out
 
 
 def config_runs(stream):
@@ -278,7 +290,8 @@ def main():
     if not args.no_serving:
         serve_out = {"workload": f"{args.serving_jobs} seeded D2Q9 droplet jobs, sides in {{64,128,256,512}}, "
                                  "T/T_cr in [0.85,1.10], 1-4 droplets, Poisson arrivals 20/s, 5000 steps, dt=0.1",
-                     "fp32_store": serving(pond.FP32_STORE, stream.cuda_stream, args.serving_jobs, "fp32"),
+                     "fp32_store": serving(pond.FP32_STORE, stream.cuda_stream, args.serving_jobs, "fp32",
+                                           budget_mib=512),
                      "fp64": serving(pond.FP64, stream.cuda_stream, args.serving_jobs, "fp64")}
 
     flops = cost.stream_flops_per_node(2, n_pass) * N

@@ -358,6 +358,7 @@ int pond_create(const pond_config *cfg, pond_handle **out)
     h->lc = LaunchCtx{c.dim, nx, ny, N, c.precision == POND_FP64 ? 0 : (c.precision == POND_FP32_STORE ? 1 : 2), nullptr,
                       c.tile < 0 ? 0 : c.tile};
     h->lc.nz = nz;
+    h->lc.gen_eos = c.eos != POND_EOS_VDW || c.isothermal;
     h->tuned = c.tile >= 0 || c.dim == 3;
 
     DevParams P;

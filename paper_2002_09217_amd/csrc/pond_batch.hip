@@ -30,6 +30,7 @@ constexpr long long kMaxLaunchTiles = 1LL << 21;
 
 struct Group {
     int dim, fp32, tile;
+    bool gen_eos;            // streaming kernels with the general equation of state
     int first, count;        // slot range in the descriptor arrays
     int st_tiles, fc_tiles;  // total tiles of the two step kernels
 };
@@ -77,7 +78,7 @@ int rebuild(pond_batch *b)
     for (int i = 0; i < M; ++i) order[i] = i;
     auto key = [&](int i) {
         const pond_handle *h = b->members[i];
-        return (h->lc.dim * 3 + h->lc.fp32) * 16 + h->lc.stream_tile;
+        return ((h->lc.dim * 3 + h->lc.fp32) * 16 + h->lc.stream_tile) * 2 + (h->lc.gen_eos ? 1 : 0);
     };
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return key(x) < key(y); });
     if (M > b->cap) {
@@ -101,7 +102,7 @@ int rebuild(pond_batch *b)
         pond_handle *h = b->members[i];
         if (key(i) != gkey) {
             gkey = key(i);
-            b->groups.push_back(Group{h->lc.dim, h->lc.fp32, h->lc.stream_tile, s, 0, 0, 0});
+            b->groups.push_back(Group{h->lc.dim, h->lc.fp32, h->lc.stream_tile, h->lc.gen_eos, s, 0, 0, 0});
         }
         Group &g = b->groups.back();
         b->slot_of[i] = s;
@@ -127,6 +128,7 @@ hipError_t enqueue_step(pond_batch *b, hipStream_t st, int arr)
     const int M = (int)b->members.size();
     for (const Group &g : b->groups) {
         LaunchCtx c{g.dim, 0, 0, 0, g.fp32, st, g.tile};
+        c.gen_eos = g.gen_eos;
         const SlotDesc *d = b->desc_d + (size_t)arr * M + g.first;
         hipError_t e = launch_stream(c, d, g.count, g.st_tiles);
         if (e == hipSuccess) e = launch_force_collide(c, d, g.count, g.fc_tiles);

@@ -40,14 +40,17 @@ constexpr bool kDeviationStore = sizeof(PopT) == 4;
 // with the energy equation (T from e = C_v T - a rho) or isothermally; the Dieterici
 // and double-well pressures run isothermally: T = T0 wherever a temperature is
 // needed, and the energy population is passive, carrying e = C_v T (- a rho for van
-// der Waals).  The kind is uniform over a launch, so the branches are scalar.
+// der Waals).  The kind is uniform over a launch, so the branches are scalar.  GEN =
+// false compiles the van der Waals fluid with the energy equation only: the streaming
+// kernels are instantiated both ways, so that the common case carries none of the
+// other laws' code and registers.
 // ---------------------------------------------------------------------------
 enum { kEosVdw = 0, kEosDieterici = 1, kEosWell = 2 };
-template <typename PT>
+template <bool GEN = true, typename PT>
 __device__ __forceinline__ double eos_p(const PT &P, double rho, double T)
 {
-    if (P.eos == kEosDieterici) return rho * P.R * T / (1.0 - P.b * rho) * exp(-P.a * rho / (P.R * T));
-    if (P.eos == kEosWell) {
+    if (GEN && P.eos == kEosDieterici) return rho * P.R * T / (1.0 - P.b * rho) * exp(-P.a * rho / (P.R * T));
+    if (GEN && P.eos == kEosWell) {
         // p0 + rho E0' - E0 = p0 + beta dl dv (2 rho (dl + dv) - dl dv), dl = rho - rho_l,
         // dv = rho - rho_v, for E0 = beta dl^2 dv^2
         const double dl = rho - P.eos_c[1], dv = rho - P.eos_c[2];
@@ -56,10 +59,10 @@ __device__ __forceinline__ double eos_p(const PT &P, double rho, double T)
     return rho * P.R * T / (1.0 - P.b * rho) - P.a * rho * rho;
 }
 // temperature of a streamed state from its internal energy
-template <typename PT>
+template <bool GEN = true, typename PT>
 __device__ __forceinline__ double eos_T_of_e(const PT &P, double rho, double e)
 {
-    return P.isothermal ? P.T0 : P.delta * (e + P.a * rho) / P.R;
+    return GEN && P.isothermal ? P.T0 : P.delta * (e + P.a * rho) / P.R;
 }
 // temperature of an initial or inflow state given T
 template <typename PT>
@@ -79,11 +82,11 @@ __device__ __forceinline__ double eos_e(const PT &P, double rho, double T)
     return P.Cv * T - (P.eos == kEosVdw ? P.a * rho : 0.0);
 }
 // bit set of the admissibility violations of a state (pressure domain, finiteness)
-template <typename PT>
+template <bool GEN = true, typename PT>
 __device__ __forceinline__ int eos_bad(const PT &P, double rho, double p)
 {
     if (!isfinite(rho) || !isfinite(p)) return kErrNonfinite;
-    if (!(p > 0.0) || !(rho > 0.0) || !(P.eos == kEosWell || 1.0 - P.b * rho > 0.0)) return kErrPressure;
+    if (!(p > 0.0) || !(rho > 0.0) || !((GEN && P.eos == kEosWell) || 1.0 - P.b * rho > 0.0)) return kErrPressure;
     return 0;
 }
 

@@ -123,6 +123,9 @@ struct LaunchCtx {
     // runtime records at the kernel's own start and end (measurement only)
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;
     int nz = 1;
+    // streaming kernels with the general equation of state (isothermal runs or a
+    // non-van-der-Waals pressure); false: the van der Waals fluid with its energy
+    bool gen_eos = false;
 };
 
 int stream_variants(int dim);

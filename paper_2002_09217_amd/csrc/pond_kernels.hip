@@ -83,7 +83,7 @@ __device__ __forceinline__ void raise_error(int *flags, int bits, int parity)
 // ---------------------------------------------------------------------------
 // Two lanes per receiver (SPLIT = 2): lane 2 i + set works on population set `set`
 // (0 = f, 1 = g) of receiver i; the pass moments are exchanged between the two lanes.
-template <int DIM, typename PopT, typename LdsT, int TX, int TY, int SPLIT>
+template <int DIM, typename PopT, typename LdsT, int TX, int TY, int SPLIT, bool GEN>
 __global__ void __launch_bounds__(SPLIT *TX *TY)
     k_stream(const SlotDesc *__restrict__ slots, int nslots)
 {
@@ -387,9 +387,9 @@ __global__ void __launch_bounds__(SPLIT *TX *TY)
         const double uhx = ux + Fpx * dt / (2.0 * rho);
         const double uhy = DIM == 2 ? uy + Fpy * dt / (2.0 * rho) : 0.0;
         const double e = E - 0.5 * (uhx * uhx + uhy * uhy);
-        const double T = eos_T_of_e(P, rho, e);
-        const double p = eos_p(P, rho, T);
-        err |= eos_bad(P, rho, p);
+        const double T = eos_T_of_e<GEN>(P, rho, e);
+        const double p = eos_p<GEN>(P, rho, T);
+        err |= eos_bad<GEN>(P, rho, p);
         sUx = Ux;
         sUy = Uy;
         sS = s;
@@ -425,17 +425,23 @@ __global__ void __launch_bounds__(SPLIT *TX *TY)
     if (err) raise_error(flags, err, S.parity);
 }
 
-template <int DIM, typename PopT, typename LdsT, int SPLIT, int TX, int TY>
-static hipError_t launch_stream_t(const LaunchCtx &c, const SlotDesc *slots, int nslots, int tiles)
+template <int DIM, typename PopT, typename LdsT, int SPLIT, int TX, int TY, bool GEN>
+static hipError_t launch_stream_g(const LaunchCtx &c, const SlotDesc *slots, int nslots, int tiles)
 {
     dim3 block(SPLIT * TX, TY);
     if (c.ev_start)
-        hipExtLaunchKernelGGL((k_stream<DIM, PopT, LdsT, TX, TY, SPLIT>), dim3(tiles), block, 0, c.st,
+        hipExtLaunchKernelGGL((k_stream<DIM, PopT, LdsT, TX, TY, SPLIT, GEN>), dim3(tiles), block, 0, c.st,
                               c.ev_start, c.ev_stop, 0, slots, nslots);
     else
-        hipLaunchKernelGGL((k_stream<DIM, PopT, LdsT, TX, TY, SPLIT>), dim3(tiles), block, 0, c.st, slots,
+        hipLaunchKernelGGL((k_stream<DIM, PopT, LdsT, TX, TY, SPLIT, GEN>), dim3(tiles), block, 0, c.st, slots,
                            nslots);
     return hipGetLastError();
+}
+template <int DIM, typename PopT, typename LdsT, int SPLIT, int TX, int TY>
+static hipError_t launch_stream_t(const LaunchCtx &c, const SlotDesc *slots, int nslots, int tiles)
+{
+    return c.gen_eos ? launch_stream_g<DIM, PopT, LdsT, SPLIT, TX, TY, true>(c, slots, nslots, tiles)
+                     : launch_stream_g<DIM, PopT, LdsT, SPLIT, TX, TY, false>(c, slots, nslots, tiles);
 }
 
 // Tile shapes of the streaming kernel (receivers per block, x by y); the library picks

@@ -242,7 +242,7 @@ __device__ __forceinline__ void xy_window(const LdsT *sbase, int o, const LdsT (
 // streamed exactly, and the FP32 rounding scales with the local variation, not with
 // the moment itself.
 // ---------------------------------------------------------------------------
-template <typename LdsT, int TX, int TY>
+template <typename LdsT, int TX, int TY, bool GEN>
 __global__ void __launch_bounds__(2 * TX *TY, sizeof(LdsT) == 4 ? 2 : 1) k3_stream(const SlotDesc *__restrict__ slot)
 {
     constexpr int LX = TX + 4, LY = TY + 4, LN = LX * LY, NT = 2 * TX * TY;
@@ -449,9 +449,9 @@ __global__ void __launch_bounds__(2 * TX *TY, sizeof(LdsT) == 4 ? 2 : 1) k3_stre
             uh2 += uh * uh;
         }
         const double e = E - 0.5 * uh2;
-        const double T = eos_T_of_e(P, rho, e);
-        const double p = eos_p(P, rho, T);
-        if (inside) err |= eos_bad(P, rho, p);
+        const double T = eos_T_of_e<GEN>(P, rho, e);
+        const double p = eos_p<GEN>(P, rho, T);
+        if (inside) err |= eos_bad<GEN>(P, rho, p);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             sU[a] = U[a];
@@ -877,7 +877,10 @@ template <typename LdsT, int TX, int TY>
 static void launch_stream3_t(const LaunchCtx &c, const SlotDesc *slot)
 {
     const int tiles = ((c.nx + TX - 1) / TX) * ((c.ny + TY - 1) / TY);
-    hipLaunchKernelGGL((k3_stream<LdsT, TX, TY>), dim3(tiles * c.nz), dim3(2 * TX, TY), 0, c.st, slot);
+    if (c.gen_eos)
+        hipLaunchKernelGGL((k3_stream<LdsT, TX, TY, true>), dim3(tiles * c.nz), dim3(2 * TX, TY), 0, c.st, slot);
+    else
+        hipLaunchKernelGGL((k3_stream<LdsT, TX, TY, false>), dim3(tiles * c.nz), dim3(2 * TX, TY), 0, c.st, slot);
 }
 
 static inline dim3 grid_nodes(const LaunchCtx &c, int per = 1)
