@@ -1279,30 +1279,37 @@ __global__ void __launch_bounds__(kMonThreads)
     }
 }
 
-// one block; every thread owns one output word and walks the partials in order
-__global__ void k_monitor_final(const double *__restrict__ partials, int nblocks, int dim,
-                                double *__restrict__ out)
+// One block of kMonFinalThreads: thread t combines word t % kMonWords over the partial
+// blocks t / kMonWords, t / kMonWords + kMonLanes, ... in that order; the kMonLanes
+// results of a word are then combined pairwise in a fixed order, so the sums do not
+// depend on timing.  Word dim + 3 is a minimum, word dim + 4 a maximum, the rest sums.
+constexpr int kMonFinalThreads = 256;
+constexpr int kMonLanes = kMonFinalThreads / kMonWords;
+static_assert(kMonFinalThreads % kMonWords == 0, "whole lanes per word");
+
+__global__ void __launch_bounds__(kMonFinalThreads)
+    k_monitor_final(const double *__restrict__ partials, int nblocks, int dim, double *__restrict__ out)
 {
-    const int i = threadIdx.x;
-    if (i >= kMonWords) return;
-    double acc = partials[i];
-    for (int b = 1; b < nblocks; ++b) {
-        const double x = partials[(size_t)b * kMonWords + i];
-        if (i == dim + 3)
-            acc = fmin(acc, x);
-        else if (i == dim + 4)
-            acc = fmax(acc, x);
-        else
-            acc += x;
+    __shared__ double s[kMonFinalThreads];
+    const int t = threadIdx.x, i = t % kMonWords, j = t / kMonWords;
+    const int kind = i == dim + 3 ? 1 : (i == dim + 4 ? 2 : 0);
+    auto combine = [kind](double a, double x) { return kind == 1 ? fmin(a, x) : (kind == 2 ? fmax(a, x) : a + x); };
+    double acc = kind == 1 ? INFINITY : (kind == 2 ? -INFINITY : 0.0);
+    for (int b = j; b < nblocks; b += kMonLanes) acc = combine(acc, partials[(size_t)b * kMonWords + i]);
+    s[t] = acc;
+    __syncthreads();
+    for (int w = kMonLanes / 2; w >= 1; w >>= 1) {
+        if (j < w) s[t] = combine(s[t], s[t + w * kMonWords]);
+        __syncthreads();
     }
-    out[i] = acc;
+    if (t < kMonWords) out[t] = s[t];
 }
 
 int monitor_blocks(const LaunchCtx &c) { return (c.N + kMonThreads - 1) / kMonThreads; }
 
 hipError_t launch_monitor_final(const LaunchCtx &c, const double *partials, int nblocks, double *out)
 {
-    hipLaunchKernelGGL(k_monitor_final, dim3(1), dim3(64), 0, c.st, partials, nblocks, c.dim, out);
+    hipLaunchKernelGGL(k_monitor_final, dim3(1), dim3(kMonFinalThreads), 0, c.st, partials, nblocks, c.dim, out);
     return hipGetLastError();
 }
 
@@ -1318,7 +1325,7 @@ hipError_t launch_monitors(const LaunchCtx &c, const DevState &s, int cur, doubl
     else
         hipLaunchKernelGGL(k_monitor_partials<1>, dim3(nblocks), dim3(kMonThreads), 0, c.st,
                            s.params, s.aux, s.side[cur], partials);
-    hipLaunchKernelGGL(k_monitor_final, dim3(1), dim3(64), 0, c.st, partials, nblocks, c.dim, out);
+    hipLaunchKernelGGL(k_monitor_final, dim3(1), dim3(kMonFinalThreads), 0, c.st, partials, nblocks, c.dim, out);
     return hipGetLastError();
 }
 
