@@ -70,3 +70,31 @@ def test_null_arguments():
     assert lib.pond_step(None, 1) == -1
     assert lib.pond_create(None, None) == -1
     assert lib.pond_last_error(None) == b"NULL handle"
+
+
+@pytest.mark.parametrize("kw", [
+    dict(eos=3, isothermal=1, T0=0.1),                                       # unknown law
+    dict(eos=pond.EOS_DIETERICI),                                            # needs isothermal
+    dict(eos=pond.EOS_DOUBLE_WELL, T0=0.1),                                  # needs isothermal
+    dict(eos=pond.EOS_VDW, isothermal=1, T0=0.0),                            # T0 <= 0
+    dict(eos=pond.EOS_DOUBLE_WELL, isothermal=1, T0=0.1, eos_c=(0.0, 5.0, 0.5, 0.1)),   # beta
+    dict(eos=pond.EOS_DOUBLE_WELL, isothermal=1, T0=0.1, eos_c=(1e-3, 0.5, 5.0, 0.1)),  # rho_l < rho_v
+    dict(eos=pond.EOS_DOUBLE_WELL, isothermal=1, T0=0.1, eos_c=(1e-3, 5.0, 0.5, -1.0)),  # p0
+])
+def test_create_rejects_invalid_equation_of_state_without_device(kw):
+    lib = pond.load()
+    c = pond.Config(dim=2, n=(8, 8), **kw).to_c()
+    h = ctypes.c_void_p()
+    assert lib.pond_create(ctypes.byref(c), ctypes.byref(h)) == -1
+    assert not h.value
+
+
+def test_create_rejects_three_dimensional_limits_without_device():
+    lib = pond.load()
+    for n, bc in (((1024, 1024, 1024), 0), ((8, 8, 8), 1)):   # > 2^29 nodes; an outflow face
+        c = pond.Config(dim=3, n=n).to_c()
+        for a in range(3):
+            for s in range(2):
+                c.bc[a][s] = bc
+        h = ctypes.c_void_p()
+        assert lib.pond_create(ctypes.byref(c), ctypes.byref(h)) == -1
