@@ -43,6 +43,22 @@ struct Box {
     }
 };
 
+// the 27 neighbours x + c of a node, c in {-1, 0, 1}^3 in direction order q: three
+// wrapped offsets per axis, node index (< 2^29) as a 32-bit integer
+struct Nbr27 {
+    unsigned xo[3], yo[3], zo[3];
+    __device__ __forceinline__ Nbr27(const Box &b, int x, int y, int z)
+    {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            xo[d] = (unsigned)b.wrap(x + d - 1, b.nx);
+            yo[d] = (unsigned)b.nx * (unsigned)b.wrap(y + d - 1, b.ny);
+            zo[d] = (unsigned)b.nx * (unsigned)b.ny * (unsigned)b.wrap(z + d - 1, b.nz);
+        }
+    }
+    __device__ __forceinline__ unsigned at(int q) const { return xo[q / 9] + yo[(q / 3) % 3] + zo[q % 3]; }
+};
+
 template <typename PT>
 __device__ __forceinline__ Box make_box(const PT &P)
 {
@@ -499,11 +515,12 @@ __global__ void __launch_bounds__(256) k3_korteweg(const SlotDesc *__restrict__ 
     const int x = (int)(n % box.nx), y = (int)((n / box.nx) % box.ny), z = (int)(n / ((size_t)box.nx * box.ny));
     const double *rho = S.mom + (size_t)L3::kRho * N;
     const double r0 = rho[n];
+    const Nbr27 nb(box, x, y, z);
     double g[3] = {0.0, 0.0, 0.0}, lap = 0.0;
 #pragma unroll
     for (int q = 0; q < 27; ++q) {
         const int cx = q / 9 - 1, cy = (q / 3) % 3 - 1, cz = q % 3 - 1;
-        const double rq = rho[box.node(x + cx, y + cy, z + cz)];
+        const double rq = rho[nb.at(q)];
         const double w = w27(q);
         g[0] += w * (double)cx * rq;
         g[1] += w * (double)cy * rq;
@@ -526,17 +543,26 @@ __global__ void __launch_bounds__(256) k3_korteweg(const SlotDesc *__restrict__ 
 __device__ __forceinline__ void force_at3(const Box &box, const double *kor, int x, int y, int z, double F[3])
 {
     const size_t N = box.N;
+    const Nbr27 nb(box, x, y, z);
+    const double *k0 = kor, *k1 = kor + N, *k2 = kor + 2 * N, *k3 = kor + 3 * N, *k4 = kor + 4 * N, *k5 = kor + 5 * N;
     double dv[3] = {0.0, 0.0, 0.0};
+    // the neighbours in three groups of nine (one x offset each): the loads of a group
+    // are in flight together, and the next group's wait until this one is summed, which
+    // bounds the registers
 #pragma unroll
-    for (int q = 0; q < 27; ++q) {
-        const int c[3] = {q / 9 - 1, (q / 3) % 3 - 1, q % 3 - 1};
-        const size_t m = box.node(x + c[0], y + c[1], z + c[2]);
-        const double w = w27(q);
-        const double kxx = kor[0 * N + m], kxy = kor[1 * N + m], kxz = kor[2 * N + m];
-        const double kyy = kor[3 * N + m], kyz = kor[4 * N + m], kzz = kor[5 * N + m];
-        dv[0] += w * (kxx * c[0] + kxy * c[1] + kxz * c[2]);
-        dv[1] += w * (kxy * c[0] + kyy * c[1] + kyz * c[2]);
-        dv[2] += w * (kxz * c[0] + kyz * c[1] + kzz * c[2]);
+    for (int q0 = 0; q0 < 27; q0 += 9) {
+#pragma unroll
+        for (int q = q0; q < q0 + 9; ++q) {
+            const int c[3] = {q / 9 - 1, (q / 3) % 3 - 1, q % 3 - 1};
+            const unsigned m = nb.at(q);
+            const double w = w27(q);
+            const double kxx = k0[m], kxy = k1[m], kxz = k2[m];
+            const double kyy = k3[m], kyz = k4[m], kzz = k5[m];
+            dv[0] += w * (kxx * c[0] + kxy * c[1] + kxz * c[2]);
+            dv[1] += w * (kxy * c[0] + kyy * c[1] + kyz * c[2]);
+            dv[2] += w * (kxz * c[0] + kyz * c[1] + kzz * c[2]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) F[a] = -dv[a] * kInvTL;
@@ -654,13 +680,19 @@ __global__ void __launch_bounds__(256) k3_collide(const SlotDesc *__restrict__ s
     if (P.k_scale >= 0.0) {
         const int x = (int)(n % box.nx), y = (int)((n / box.nx) % box.ny), z = (int)(n / ((size_t)box.nx * box.ny));
         const double T0 = aux[3 * N + n], h0 = aux[4 * N + n], m0 = aux[5 * N + n], k0 = aux[6 * N + n];
+        const Nbr27 nb(box, x, y, z);
+        const double *aT = aux + 3 * N, *ah = aux + 4 * N, *amu = aux + 5 * N, *ak = aux + 6 * N;
         double accm = 0.0;
 #pragma unroll
-        for (int q = 0; q < 27; ++q) {
-            const size_t m = box.node(x + q / 9 - 1, y + (q / 3) % 3 - 1, z + q % 3 - 1);
-            const double kmid = 0.5 * (aux[6 * N + m] + k0);
-            const double mmid = 0.5 * (aux[5 * N + m] + m0);
-            accm += w27(q) * (kmid * (aux[3 * N + m] - T0) - mmid * (aux[4 * N + m] - h0));
+        for (int q0 = 0; q0 < 27; q0 += 9) {
+#pragma unroll
+            for (int q = q0; q < q0 + 9; ++q) {
+                const unsigned m = nb.at(q);
+                const double kmid = 0.5 * (ak[m] + k0);
+                const double mmid = 0.5 * (amu[m] + m0);
+                accm += w27(q) * (kmid * (aT[m] - T0) - mmid * (ah[m] - h0));
+            }
+            __builtin_amdgcn_sched_barrier(0);
         }
         M0 = 2.0 * (2.0 * kInvTL) * accm;
     }
