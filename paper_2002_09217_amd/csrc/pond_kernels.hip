@@ -1069,7 +1069,6 @@ __global__ void k_init_equilibrium(const DevParams *__restrict__ Pp, const doubl
     using L = Layout<DIM>;
     constexpr int Q = L::Q, NF = L::NF;
     const DevParams &P = *Pp;
-    const Geo geo = make_geo(P);
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = DIM == 2 ? blockIdx.y * blockDim.y + threadIdx.y : 0;
     if (x >= P.nx || y >= (DIM == 2 ? P.ny : 1)) return;
@@ -1157,7 +1156,6 @@ __global__ void k_macro(const DevParams *__restrict__ Pp, const PopT *__restrict
 {
     constexpr int Q = Layout<DIM>::Q;
     const DevParams &P = *Pp;
-    const Geo geo = make_geo(P);
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = DIM == 2 ? blockIdx.y * blockDim.y + threadIdx.y : 0;
     if (x >= P.nx || y >= (DIM == 2 ? P.ny : 1)) return;
