@@ -5,8 +5,11 @@ that fails leaves the batch without disturbing the others; admission footprints.
 import numpy as np
 import pytest
 
+from oracle.thermo import Dieterici
 from paper_2002_09217_amd import pond, workloads as W
 from tests.common import pond_config
+
+DIET = Dieterici()
 
 pytestmark = pytest.mark.gpu
 
@@ -23,7 +26,8 @@ def _lat(case, tile, precision=pond.FP64):
 
 def _mix():
     """(case, tile, precision) of the batch members: sizes spanning one to many tiles
-    with ragged tails, both dimensions, all three precisions, two tile shapes."""
+    with ragged tails, both dimensions, all three precisions, two tile shapes, and
+    isothermal lattices (the streaming kernels' general equation-of-state variant)."""
     return [
         (W.perturbed(40, 36, seed=1, kappa=0.0176, u0=(0.05, -0.03)), 0, pond.FP64),
         (W.static_droplet(n=64, radius=14.0), 0, pond.FP64),
@@ -33,6 +37,10 @@ def _mix():
         (W.perturbed(7, 1, seed=5, kappa=0.0176), 0, pond.FP64),
         (W.perturbed(129, 1, seed=6, dim=1), 1, pond.FP32_STORE),
         (W.perturbed(50, 30, seed=8, kappa=0.0176), 0, pond.FP32_STORE_FP64_MATH),
+        (W.perturbed(45, 20, seed=9, rho0=1.5, kappa=0.0176, eos=pond.EOS_DIETERICI, isothermal=1,
+                     T0=0.9 * DIET.T_cr, a=DIET.a, b=DIET.b), 0, pond.FP64),
+        (W.perturbed(90, 1, seed=10, dim=1, rho0=5.0, eos=pond.EOS_DOUBLE_WELL, isothermal=1, T0=0.1,
+                     eos_c=(8e-4, 5.0, 0.5, 0.1)), 0, pond.FP32_STORE),
     ]
 
 

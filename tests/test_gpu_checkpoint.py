@@ -66,3 +66,28 @@ def test_mismatched_checkpoints_refused_and_fresh_handle_resumes():
     assert np.array_equal(_fields(d.moments()), _fields(a.moments()))
     for x in (a, b, c, d):
         x.close()
+
+
+def test_isothermal_checkpoint_resumes_and_is_refused_by_another_equation_of_state():
+    from oracle.thermo import Dieterici
+    g = Dieterici()
+    iso = dict(eos=pond.EOS_DIETERICI, isothermal=1, T0=0.9 * g.T_cr, a=g.a, b=g.b)
+    case = W.perturbed(36, 28, seed=6, rho0=1.5, kappa=0.0176, **iso)
+    a = pond.Lattice(pond_config(case, tile=0))
+    a.init_fields(case.rho, case.u, case.T)
+    a.step(9)
+    ck = a.save()
+    a.step(8)
+    ref = _fields(a.moments())
+    b = pond.Lattice(pond_config(case, tile=0))
+    b.load(ck)
+    b.step(8)
+    assert np.array_equal(_fields(b.moments()), ref)
+    other = W.perturbed(36, 28, seed=6, rho0=1.5, kappa=0.0176, eos=pond.EOS_DIETERICI, isothermal=1,
+                        T0=0.85 * g.T_cr, a=g.a, b=g.b)   # another T0
+    c = pond.Lattice(pond_config(other, tile=0))
+    with pytest.raises(pond.PondError) as err:
+        c.load(ck)
+    assert err.value.code == -1
+    for x in (a, b, c):
+        x.close()
