@@ -99,6 +99,7 @@ __device__ __forceinline__ int eos_bad(const PT &P, double rho, double p)
 // a bijection of [0, nb).
 // ---------------------------------------------------------------------------
 constexpr int kXcds = 8;
+constexpr int kCUs = 256; // compute units of the device (MI355X)
 __device__ __forceinline__ int xcd_tile(int b, int nb)
 {
     const int xcd = b % kXcds, local = b / kXcds;

@@ -84,7 +84,7 @@ __device__ __forceinline__ void raise_error(int *flags, int bits, int parity)
 // Two lanes per receiver (SPLIT = 2): lane 2 i + set works on population set `set`
 // (0 = f, 1 = g) of receiver i; the pass moments are exchanged between the two lanes.
 template <int DIM, typename PopT, typename LdsT, int TX, int TY, int SPLIT, bool GEN>
-__global__ void __launch_bounds__(SPLIT *TX *TY)
+__global__ void __launch_bounds__(SPLIT *TX *TY, SPLIT *TX *TY <= 256 ? 3 : 2)
     k_stream(const SlotDesc *__restrict__ slots, int nslots)
 {
     using L = Layout<DIM>;
@@ -96,7 +96,8 @@ __global__ void __launch_bounds__(SPLIT *TX *TY)
     // Moment fields of the tile.  With split lanes the two sets of a node are adjacent
     // (index ((mn LN + node) 2 + set)), so the two lanes of a receiver and neighbouring
     // receivers read one contiguous run of LDS words: no bank conflicts.
-    constexpr int CS = SPLIT == 2 ? 2 : 1;                        // column stride
+    static_assert(SPLIT == 2, "two lanes per receiver");
+    constexpr int CS = 2;                                         // column stride
     __shared__ LdsT lds[2 * NF * LN];
     __shared__ int abort_block;
 
@@ -250,11 +251,20 @@ __global__ void __launch_bounds__(SPLIT *TX *TY)
     const int wbase = (DIM == 2 ? threadIdx.y * LX : 0) + lxr; // window (gx-2, gy-2)
     const double dt = P.dt;
 
-    double fq[Q], gq[Q];
-    double sUx = Ux, sUy = Uy, sS = 1.0; // gauge of the last pass's populations
+    // this lane's set of the receiver, in the gauge (sUx, sUy, sS) of the last pass
+    double pq[Q];
+    double sUx = Ux, sUy = Uy, sS = 1.0;
     double rho = 0.0;
     int err = 0;
+    const LdsT *sbase = &lds[wbase * 2 + myset];
+    // When the grid is one workgroup per CU (512 lanes, two waves per SIMD), the SIMD
+    // issues for the older wave first, the younger one falls behind and finishes its
+    // last pass alone, with nothing to hide its latencies.  Favouring the younger wave
+    // in the first pass lets both finish at about the same time.
+    const int young = __builtin_amdgcn_readfirstlane((tid >> 6) >= NT / 128 && NT == 512 && gridDim.x <= kCUs ? 1 : 0);
     for (int pass = 0; pass < P.n_pass; ++pass) {
+        if (pass == 0 && young) __builtin_amdgcn_s_setprio(1);
+        else __builtin_amdgcn_s_setprio(0);
         const double s = sqrt(th);
         LdsT wx[3][5], wy[3][5];
         err |= window_weights<LdsT>(Ux, s, dt, wx);
@@ -268,118 +278,114 @@ __global__ void __launch_bounds__(SPLIT *TX *TY)
 #pragma unroll
             for (int m = 0; m < 3; ++m) A[k][m] = (LdsT)Ad[k][m];
 
-#pragma unroll 1
-        for (int set = (SPLIT == 2 ? myset : 0); set < (SPLIT == 2 ? myset + 1 : 2); ++set) {
-            // populations of this set in the receiver gauge, one per direction:
-            //   f_kl = sum_n B_ln sum_r wy_l[r] sum_m A_km sum_c wx_k[c] M_mn[r][c]
-            double acc[Q];
-            if constexpr (kDevI) {
-                // the reference part (see the fill); the window adds the deviations
-                const double R = set == 0 ? refR0 : refR1;
+        // populations of this set in the receiver gauge, one per direction:
+        //   f_kl = sum_n B_ln sum_r wy_l[r] sum_m A_km sum_c wx_k[c] M_mn[r][c]
+        double acc[Q];
+        if constexpr (kDevI) {
+            // the reference part (see the fill); the window adds the deviations
+            const double R = myset == 0 ? refR0 : refR1;
 #pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    const double ak = R * (Ad[k][0] + refT * Ad[k][2]);
-                    if (DIM == 2) {
+            for (int k = 0; k < 3; ++k) {
+                const double ak = R * (Ad[k][0] + refT * Ad[k][2]);
+                if (DIM == 2) {
 #pragma unroll
-                        for (int l = 0; l < 3; ++l) acc[3 * k + l] = ak * (Bd[l][0] + refT * Bd[l][2]);
-                    } else {
-                        acc[k] = ak;
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int q = 0; q < Q; ++q) acc[q] = 0.0;
-            }
-            const LdsT *sbase = SPLIT == 2 ? &lds[wbase * 2 + set] : &lds[set * NF * LN + wbase];
-            if (DIM == 2) {
-#pragma unroll
-                for (int n = 0; n < 3; ++n) {
-                    LdsT Z[3][5]; // sum_m A_km (x-interpolated M_mn) per row
-#pragma unroll
-                    for (int k = 0; k < 3; ++k)
-#pragma unroll
-                        for (int r = 0; r < 5; ++r) Z[k][r] = (LdsT)0;
-#pragma unroll
-                    for (int r = 0; r < 5; ++r) {
-#pragma unroll
-                        for (int m = 0; m < 3; ++m) {
-                            const LdsT *row = sbase + ((3 * m + n) * LN + r * LX) * CS;
-                            const LdsT v0 = row[0], v1 = row[CS], v2 = row[2 * CS], v3 = row[3 * CS],
-                                       v4 = row[4 * CS];
-#pragma unroll
-                            for (int k = 0; k < 3; ++k) {
-                                const LdsT xk = wx[k][0] * v0 + wx[k][1] * v1 + wx[k][2] * v2 +
-                                                wx[k][3] * v3 + wx[k][4] * v4;
-                                Z[k][r] += A[k][m] * xk;
-                            }
-                        }
-                    }
-#pragma unroll
-                    for (int k = 0; k < 3; ++k)
-#pragma unroll
-                        for (int l = 0; l < 3; ++l) {
-                            const LdsT I = wy[l][0] * Z[k][0] + wy[l][1] * Z[k][1] + wy[l][2] * Z[k][2] +
-                                           wy[l][3] * Z[k][3] + wy[l][4] * Z[k][4];
-                            acc[3 * k + l] += Bd[l][n] * (double)I;
-                        }
-                    // keep the three n-blocks apart: the scheduler would otherwise hoist the
-                    // loads of all of them and run out of registers
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-            } else {
-#pragma unroll
-                for (int m = 0; m < 3; ++m) {
-                    const LdsT *row = sbase + m * LN * CS;
-                    const LdsT v0 = row[0], v1 = row[CS], v2 = row[2 * CS], v3 = row[3 * CS],
-                               v4 = row[4 * CS];
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        const LdsT xk = wx[k][0] * v0 + wx[k][1] * v1 + wx[k][2] * v2 + wx[k][3] * v3 +
-                                        wx[k][4] * v4;
-                        acc[k] += Ad[k][m] * (double)xk;
-                    }
+                    for (int l = 0; l < 3; ++l) acc[3 * k + l] = ak * (Bd[l][0] + refT * Bd[l][2]);
+                } else {
+                    acc[k] = ak;
                 }
             }
-            if (set == 0) {
-#pragma unroll
-                for (int q = 0; q < Q; ++q) fq[q] = acc[q];
-            } else {
-#pragma unroll
-                for (int q = 0; q < Q; ++q) gq[q] = acc[q];
-            }
-        }
-        // moments of the streamed populations (eq. 2) and the EoS closure
-        double jx = 0.0, jy = 0.0, G2 = 0.0, r0 = 0.0;
-        if (SPLIT == 2) {
-            // each lane sums its own set; the partner lane supplies the other sums
-            const double *own = myset == 0 ? fq : gq;
-            double s0 = 0.0, sx = 0.0, sy = 0.0;
-#pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                const double cx = DIM == 2 ? (double)(q / 3 - 1) : (double)(q - 1);
-                const double cy = DIM == 2 ? (double)(q % 3 - 1) : 0.0;
-                s0 += own[q];
-                sx += own[q] * (Ux + s * cx);
-                if (DIM == 2) sy += own[q] * (Uy + s * cy);
-            }
-            const double o0 = __shfl_xor(s0, 1, 64);
-            const double ox = __shfl_xor(sx, 1, 64);
-            const double oy = DIM == 2 ? __shfl_xor(sy, 1, 64) : 0.0;
-            r0 = myset == 0 ? s0 : o0;
-            jx = myset == 0 ? sx : ox;
-            jy = myset == 0 ? sy : oy;
-            G2 = myset == 0 ? o0 : s0;
         } else {
 #pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                const double cx = DIM == 2 ? (double)(q / 3 - 1) : (double)(q - 1);
-                const double cy = DIM == 2 ? (double)(q % 3 - 1) : 0.0;
-                r0 += fq[q];
-                jx += fq[q] * (Ux + s * cx);
-                if (DIM == 2) jy += fq[q] * (Uy + s * cy);
-                G2 += gq[q];
+            for (int q = 0; q < Q; ++q) acc[q] = 0.0;
+        }
+        if (DIM == 2) {
+#pragma unroll
+            for (int n = 0; n < 3; ++n) {
+                // Row r of field (m, n) is group g = 3 r + m of five window values; each
+                // group is read from LDS one group ahead of its use, so that the read
+                // latency overlaps the arithmetic of the group before.
+                auto load_group = [&](int g, LdsT v[5]) {
+                    const LdsT *row = sbase + ((3 * (g % 3) + n) * LN + (g / 3) * LX) * CS;
+#pragma unroll
+                    for (int c = 0; c < 5; ++c) v[c] = row[c * CS];
+                };
+                // FP64 windows add each row straight into acc with the weights
+                // B_ln wy_l[r] (no I registers); FP32 windows sum the rows in FP32 first
+                constexpr bool kRowsToAcc = sizeof(LdsT) == 8;
+                LdsT I[3][3]; // sum_r wy_l[r] Z_k[r]
+                LdsT Z[3];    // sum_m A_km (x-interpolated M_mn) of the current row
+                LdsT cur[5], nxt[5];
+                load_group(0, cur);
+#pragma unroll
+                for (int g = 0; g < 15; ++g) {
+                    const int r = g / 3, m = g % 3;
+                    if (g + 1 < 15) load_group(g + 1, nxt);
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const LdsT xk = wx[k][0] * cur[0] + wx[k][1] * cur[1] + wx[k][2] * cur[2] +
+                                        wx[k][3] * cur[3] + wx[k][4] * cur[4];
+                        Z[k] = m == 0 ? A[k][m] * xk : Z[k] + A[k][m] * xk;
+                    }
+                    if (m == 2 && kRowsToAcc) {
+                        double C[3];
+#pragma unroll
+                        for (int l = 0; l < 3; ++l) C[l] = Bd[l][n] * (double)wy[l][r];
+#pragma unroll
+                        for (int k = 0; k < 3; ++k)
+#pragma unroll
+                            for (int l = 0; l < 3; ++l) acc[3 * k + l] += C[l] * (double)Z[k];
+                    } else if (m == 2) {
+#pragma unroll
+                        for (int k = 0; k < 3; ++k)
+#pragma unroll
+                            for (int l = 0; l < 3; ++l) I[k][l] = r == 0 ? wy[l][r] * Z[k] : I[k][l] + wy[l][r] * Z[k];
+                    }
+#pragma unroll
+                    for (int c = 0; c < 5; ++c) cur[c] = nxt[c];
+                }
+                if (!kRowsToAcc) {
+#pragma unroll
+                    for (int k = 0; k < 3; ++k)
+#pragma unroll
+                        for (int l = 0; l < 3; ++l) acc[3 * k + l] += Bd[l][n] * (double)I[k][l];
+                }
+                // keep the three n-blocks apart: the scheduler would otherwise hoist the
+                // loads of all of them and run out of registers
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                const LdsT *row = sbase + m * LN * CS;
+                const LdsT v0 = row[0], v1 = row[CS], v2 = row[2 * CS], v3 = row[3 * CS], v4 = row[4 * CS];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const LdsT xk = wx[k][0] * v0 + wx[k][1] * v1 + wx[k][2] * v2 + wx[k][3] * v3 + wx[k][4] * v4;
+                    acc[k] += Ad[k][m] * (double)xk;
+                }
             }
         }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) pq[q] = acc[q];
+
+        // moments of the streamed populations (eq. 2) and the EoS closure: each lane sums
+        // its own set; the partner lane supplies the other sums
+        double s0 = 0.0, sx = 0.0, sy = 0.0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const double cx = DIM == 2 ? (double)(q / 3 - 1) : (double)(q - 1);
+            const double cy = DIM == 2 ? (double)(q % 3 - 1) : 0.0;
+            s0 += pq[q];
+            sx += pq[q] * (Ux + s * cx);
+            if (DIM == 2) sy += pq[q] * (Uy + s * cy);
+        }
+        const double o0 = __shfl_xor(s0, 1, 64);
+        const double ox = __shfl_xor(sx, 1, 64);
+        const double oy = DIM == 2 ? __shfl_xor(sy, 1, 64) : 0.0;
+        const double r0 = myset == 0 ? s0 : o0;
+        const double jx = myset == 0 ? sx : ox;
+        const double jy = myset == 0 ? sy : oy;
+        const double G2 = myset == 0 ? o0 : s0;
         rho = r0;
         const double E = G2 / (2.0 * rho);
         const double ux = jx / rho;
@@ -399,28 +405,25 @@ __global__ void __launch_bounds__(SPLIT *TX *TY)
     }
 
     // streamed state for the collision: rho, u and central moments about u
-    if (SPLIT == 1 || myset == 0) {
-        double mf[NF];
-        moments_about<DIM>(fq, sUx - Ux, sUy - Uy, sS, mf);
+    double mq[NF];
+    moments_about<DIM>(pq, sUx - Ux, sUy - Uy, sS, mq);
+    if (myset == 0) {
         mom[(size_t)L::kRho * N + node] = rho;
         mom[(size_t)L::kUx * N + node] = Ux;
         if constexpr (DIM == 2) {
             mom[(size_t)L::kUy * N + node] = Uy;
-            mom[(size_t)(L::kF + 0) * N + node] = mf[4]; // (1,1)
-            mom[(size_t)(L::kF + 1) * N + node] = mf[6]; // (2,0)
-            mom[(size_t)(L::kF + 2) * N + node] = mf[2]; // (0,2)
-            mom[(size_t)(L::kF + 3) * N + node] = mf[7]; // (2,1)
-            mom[(size_t)(L::kF + 4) * N + node] = mf[5]; // (1,2)
-            mom[(size_t)(L::kF + 5) * N + node] = mf[8]; // (2,2)
+            mom[(size_t)(L::kF + 0) * N + node] = mq[4]; // (1,1)
+            mom[(size_t)(L::kF + 1) * N + node] = mq[6]; // (2,0)
+            mom[(size_t)(L::kF + 2) * N + node] = mq[2]; // (0,2)
+            mom[(size_t)(L::kF + 3) * N + node] = mq[7]; // (2,1)
+            mom[(size_t)(L::kF + 4) * N + node] = mq[5]; // (1,2)
+            mom[(size_t)(L::kF + 5) * N + node] = mq[8]; // (2,2)
         } else {
-            mom[(size_t)L::kF * N + node] = mf[2];
+            mom[(size_t)L::kF * N + node] = mq[2];
         }
-    }
-    if (SPLIT == 1 || myset == 1) {
-        double mg[NF];
-        moments_about<DIM>(gq, sUx - Ux, sUy - Uy, sS, mg);
+    } else {
 #pragma unroll
-        for (int i = 0; i < NF; ++i) mom[(size_t)(L::kG + i) * N + node] = mg[i];
+        for (int i = 0; i < NF; ++i) mom[(size_t)(L::kG + i) * N + node] = mq[i];
     }
     if (err) raise_error(flags, err, S.parity);
 }
@@ -675,6 +678,12 @@ __global__ void __launch_bounds__(2 * TX *TY)
     const double dt = P.dt;
     const bool force = P.kappa != 0.0;
     const double visc = (1.0 / P.omega - 0.5) * dt;   // mu = visc p
+    // Whether the K region (halo 2, the widest region with copied cells) reaches an
+    // outflow face: only then do the copy stages below have work, and their barriers
+    // are skipped otherwise (uniform over the block).
+    const bool has_copy = (x0 - 2 < 0 && geo.bc(0, 0) == kOutflow) || (x0 + TX + 2 > P.nx && geo.bc(0, 1) == kOutflow) ||
+                          (DIM == 2 && ((y0 - 2 < 0 && geo.bc(1, 0) == kOutflow) ||
+                                        (y0 + TY + 2 > P.ny && geo.bc(1, 1) == kOutflow)));
 
     // this lane's population set (0 = f, 1 = g; uniform per wave) and node
     const int set = tid >= NN ? 1 : 0;
@@ -779,17 +788,19 @@ __global__ void __launch_bounds__(2 * TX *TY)
             }
         }
         __syncthreads();
-        for (int li = tid; li < KX * KY; li += NT) {
-            const int kx = li % KX, ky = li / KX;
-            int cx, cy, face;
-            if (classify<DIM>(geo, x0 - 2 + kx, y0 - 2 + ky, cx, cy, face) == kCopy) {
-                const int src = (cx - (x0 - 2)) + (DIM == 2 ? (cy - (y0 - 2)) * KX : 0);
-                s_K[0][li] = s_K[0][src];
-                s_K[1][li] = s_K[1][src];
-                s_K[2][li] = s_K[2][src];
+        if (has_copy) {
+            for (int li = tid; li < KX * KY; li += NT) {
+                const int kx = li % KX, ky = li / KX;
+                int cx, cy, face;
+                if (classify<DIM>(geo, x0 - 2 + kx, y0 - 2 + ky, cx, cy, face) == kCopy) {
+                    const int src = (cx - (x0 - 2)) + (DIM == 2 ? (cy - (y0 - 2)) * KX : 0);
+                    s_K[0][li] = s_K[0][src];
+                    s_K[1][li] = s_K[1][src];
+                    s_K[2][li] = s_K[2][src];
+                }
             }
+            __syncthreads();
         }
-        __syncthreads();
     }
 
     // stage 3: force and thermodynamic state of the step
@@ -848,16 +859,18 @@ __global__ void __launch_bounds__(2 * TX *TY)
     if (!force && tid == 0) abort_block = err_before;
     __syncthreads();
     if (abort_block != 0) return;
-    for (int li = tid; li < HX * HY; li += NT) {
-        const int hx = li % HX, hy = li / HX;
-        int cx, cy, face;
-        if (classify<DIM>(geo, x0 - 1 + hx, y0 - 1 + hy, cx, cy, face) == kCopy) {
-            const int src = (cx - (x0 - 1)) + (DIM == 2 ? (cy - (y0 - 1)) * HX : 0);
+    if (has_copy) {
+        for (int li = tid; li < HX * HY; li += NT) {
+            const int hx = li % HX, hy = li / HX;
+            int cx, cy, face;
+            if (classify<DIM>(geo, x0 - 1 + hx, y0 - 1 + hy, cx, cy, face) == kCopy) {
+                const int src = (cx - (x0 - 1)) + (DIM == 2 ? (cy - (y0 - 1)) * HX : 0);
 #pragma unroll
-            for (int f = 0; f < kThFields; ++f) s_th[f][li] = s_th[f][src];
+                for (int f = 0; f < kThFields; ++f) s_th[f][li] = s_th[f][src];
+            }
         }
+        __syncthreads();
     }
-    __syncthreads();
     if (err) raise_error(flags, err, S.parity);
 
     if (!inside) return;
