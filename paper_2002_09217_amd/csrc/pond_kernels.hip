@@ -387,11 +387,14 @@ __global__ void __launch_bounds__(SPLIT *TX *TY, SPLIT *TX *TY <= 256 ? 3 : 2)
         const double jy = myset == 0 ? sy : oy;
         const double G2 = myset == 0 ? o0 : s0;
         rho = r0;
-        const double E = G2 / (2.0 * rho);
-        const double ux = jx / rho;
-        const double uy = DIM == 2 ? jy / rho : 0.0;
-        const double uhx = ux + Fpx * dt / (2.0 * rho);
-        const double uhy = DIM == 2 ? uy + Fpy * dt / (2.0 * rho) : 0.0;
+        // one reciprocal of rho serves every quotient by it (FP64 division is a
+        // long dependent sequence on this hardware)
+        const double i_rho = 1.0 / rho;
+        const double E = 0.5 * G2 * i_rho;
+        const double ux = jx * i_rho;
+        const double uy = DIM == 2 ? jy * i_rho : 0.0;
+        const double uhx = ux + 0.5 * Fpx * dt * i_rho;
+        const double uhy = DIM == 2 ? uy + 0.5 * Fpy * dt * i_rho : 0.0;
         const double e = E - 0.5 * (uhx * uhx + uhy * uhy);
         const double T = eos_T_of_e<GEN>(P, rho, e);
         const double p = eos_p<GEN>(P, rho, T);
@@ -401,7 +404,7 @@ __global__ void __launch_bounds__(SPLIT *TX *TY, SPLIT *TX *TY <= 256 ? 3 : 2)
         sS = s;
         Ux = ux;
         Uy = uy;
-        th = p / (rho * kTL);
+        th = p * i_rho * kInvTL;
     }
 
     // streamed state for the collision: rho, u and central moments about u

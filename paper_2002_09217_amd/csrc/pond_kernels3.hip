@@ -456,12 +456,13 @@ __global__ void __launch_bounds__(2 * TX *TY, sizeof(LdsT) == 4 ? 2 : 1) k3_stre
         rho = myset == 0 ? s0 : o0;
         const double j[3] = {myset == 0 ? sx : ox, myset == 0 ? sy : oy, myset == 0 ? szm : oz};
         const double G2 = myset == 0 ? o0 : s0;
-        const double E = G2 / (2.0 * rho);
+        const double i_rho = 1.0 / rho; // one reciprocal for every quotient by rho
+        const double E = 0.5 * G2 * i_rho;
         double uh2 = 0.0, un[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            un[a] = j[a] / rho;
-            const double uh = un[a] + Fp[a] * dt / (2.0 * rho);
+            un[a] = j[a] * i_rho;
+            const double uh = un[a] + 0.5 * Fp[a] * dt * i_rho;
             uh2 += uh * uh;
         }
         const double e = E - 0.5 * uh2;
@@ -474,7 +475,7 @@ __global__ void __launch_bounds__(2 * TX *TY, sizeof(LdsT) == 4 ? 2 : 1) k3_stre
             U[a] = un[a];
         }
         sS = s;
-        th = p / (rho * kTL);
+        th = p * i_rho * kInvTL;
     }
 
     if (inside) {
