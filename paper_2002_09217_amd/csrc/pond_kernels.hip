@@ -81,10 +81,11 @@ __device__ __forceinline__ void raise_error(int *flags, int bits, int parity)
 // ---------------------------------------------------------------------------
 // streaming with the predictor-corrector
 // ---------------------------------------------------------------------------
-// Two lanes per receiver (SPLIT = 2): lane 2 i + set works on population set `set`
-// (0 = f, 1 = g) of receiver i; the pass moments are exchanged between the two lanes.
-template <int DIM, typename PopT, typename LdsT, int TX, int TY, int SPLIT, bool GEN>
-__global__ void __launch_bounds__(SPLIT *TX *TY, SPLIT *TX *TY <= 256 ? 3 : 2)
+// Two lanes per receiver: lane 2 i + set works on population set `set` (0 = f, 1 = g)
+// of receiver i; the pass moments are exchanged between the two lanes.  Blocks of at
+// most 256 lanes are compiled for three waves per SIMD, larger ones for two.
+template <int DIM, typename PopT, typename LdsT, int TX, int TY, bool GEN>
+__global__ void __launch_bounds__(2 * TX *TY, 2 * TX *TY <= 256 ? 3 : 2)
     k_stream(const SlotDesc *__restrict__ slots, int nslots)
 {
     using L = Layout<DIM>;
@@ -92,11 +93,10 @@ __global__ void __launch_bounds__(SPLIT *TX *TY, SPLIT *TX *TY <= 256 ? 3 : 2)
     constexpr int LX = TX + 2 * H;
     constexpr int LY = DIM == 2 ? TY + 2 * H : 1;
     constexpr int LN = LX * LY;
-    constexpr int NT = SPLIT * TX * TY;
-    // Moment fields of the tile.  With split lanes the two sets of a node are adjacent
-    // (index ((mn LN + node) 2 + set)), so the two lanes of a receiver and neighbouring
+    constexpr int NT = 2 * TX * TY;
+    // Moment fields of the tile.  The two sets of a node are adjacent (index
+    // ((mn LN + node) 2 + set)), so the two lanes of a receiver and neighbouring
     // receivers read one contiguous run of LDS words: no bank conflicts.
-    static_assert(SPLIT == 2, "two lanes per receiver");
     constexpr int CS = 2;                                         // column stride
     __shared__ LdsT lds[2 * NF * LN];
     __shared__ int abort_block;
@@ -113,7 +113,7 @@ __global__ void __launch_bounds__(SPLIT *TX *TY, SPLIT *TX *TY <= 256 ? 3 : 2)
     // Error state of earlier steps: read now, acted on after the fill (which only reads),
     // so that its latency overlaps the fill's loads.  The decision is taken once per
     // block, so every wave of the block leaves together.
-    const int tid = threadIdx.x + SPLIT * TX * threadIdx.y;
+    const int tid = threadIdx.x + 2 * TX * threadIdx.y;
     int err_before = 0;
     if (tid == 0) err_before = flags[kFlagErr];
     const POND_GLOBAL DevParams &P = *(const POND_GLOBAL DevParams *)S.P;
@@ -145,8 +145,8 @@ __global__ void __launch_bounds__(SPLIT *TX *TY, SPLIT *TX *TY <= 256 ? 3 : 2)
     }
 
     // the receiver's own gauge and force, loaded now so that the latency overlaps the fill
-    const int lxr = SPLIT == 2 ? (int)threadIdx.x >> 1 : (int)threadIdx.x;
-    const int myset = SPLIT == 2 ? (int)threadIdx.x & 1 : 0;
+    const int lxr = (int)threadIdx.x >> 1;
+    const int myset = (int)threadIdx.x & 1;
     const int gx = bx0 + lxr;
     const int gy = by0 + (DIM == 2 ? threadIdx.y : 0);
     const bool inside = gx < P.nx && (DIM == 1 || gy < P.ny);
@@ -158,76 +158,63 @@ __global__ void __launch_bounds__(SPLIT *TX *TY, SPLIT *TX *TY <= 256 ? 3 : 2)
     const double Fpy = DIM == 2 ? side[kSideFy * N + node] : 0.0;
 
     // donors of the tile and its halo: moments about (rx, ry) into LDS, one work item
-    // per (node, set) when the sets are split over lanes.  Each thread takes its items
-    // two at a time and issues the global loads of both before using either, so the
-    // memory latency of the fill is paid once per pair.
-    constexpr int SETS_PER_ITEM = SPLIT == 2 ? 1 : 2;
-    constexpr int NITEMS = LN * SPLIT;
+    // per (node, set).  Each thread takes its items two at a time and issues the global
+    // loads of both before using either, so the memory latency of the fill is paid once
+    // per pair.
+    constexpr int NITEMS = 2 * LN;
     constexpr bool dev = kDeviationStore<PopT>;
     struct Raw {
-        int li, set0, node;
+        int li, set, node;
         double ux, uy, th;
-        PopT p[SETS_PER_ITEM * Q];
-        double sum[SETS_PER_ITEM];   // FP32 storage: the set's sum
+        PopT p[Q];
+        double sum; // FP32 storage: the set's sum
     };
     auto load_raw = [&](int it, Raw &r) {
-        r.li = SPLIT == 2 ? it >> 1 : it;
-        r.set0 = SPLIT == 2 ? it & 1 : 0;
+        r.li = it >> 1;
+        r.set = it & 1;
         const int lx = r.li % LX, ly = r.li / LX;
         r.node = map_node<DIM>(geo, bx0 - H + lx, by0 - H + ly);
         if (r.node >= 0) {
             r.ux = side[kSideUx * N + r.node];
             r.uy = DIM == 2 ? side[kSideUy * N + r.node] : 0.0;
             r.th = side[kSideTh * N + r.node];
+            const POND_GLOBAL PopT *src = fpop + (size_t)r.set * Q * N;
 #pragma unroll
-            for (int k = 0; k < SETS_PER_ITEM; ++k) {
-                const POND_GLOBAL PopT *src = fpop + (size_t)(r.set0 + k) * Q * N;
-#pragma unroll
-                for (int q = 0; q < Q; ++q) r.p[k * Q + q] = src[(size_t)q * N + r.node];
-                if (dev) r.sum[k] = fsum[(size_t)(r.set0 + k) * N + r.node];
-            }
+            for (int q = 0; q < Q; ++q) r.p[q] = src[(size_t)q * N + r.node];
+            if (dev) r.sum = fsum[(size_t)r.set * N + r.node];
         } else {
             const POND_GLOBAL GhostFace &G = P.ghost[-r.node - 1];
             r.ux = G.ux;
             r.uy = G.uy;
             r.th = G.theta;
+            const POND_GLOBAL double *src = r.set == 0 ? G.f : G.g;
+            double sum = 0.0;
+            if (dev) {
 #pragma unroll
-            for (int k = 0; k < SETS_PER_ITEM; ++k) {
-                const POND_GLOBAL double *src = r.set0 + k == 0 ? G.f : G.g;
-                double sum = 0.0;
-                if (dev) {
-#pragma unroll
-                    for (int q = 0; q < Q; ++q) sum += src[q];
-                }
-                r.sum[k] = sum;
-#pragma unroll
-                for (int q = 0; q < Q; ++q) r.p[k * Q + q] = (PopT)(src[q] - (dev ? weight_q<DIM>(q) * sum : 0.0));
+                for (int q = 0; q < Q; ++q) sum += src[q];
             }
+            r.sum = sum;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) r.p[q] = (PopT)(src[q] - (dev ? weight_q<DIM>(q) * sum : 0.0));
         }
     };
     auto store_moments = [&](const Raw &r) {
         const double s = sqrt(r.th);
+        double fr[Q], m[NF];
 #pragma unroll
-        for (int k = 0; k < SETS_PER_ITEM; ++k) {
-            const int set = r.set0 + k;
-            double fr[Q], m[NF];
-#pragma unroll
-            for (int q = 0; q < Q; ++q)
-                fr[q] = dev ? weight_q<DIM>(q) * r.sum[k] + (double)r.p[k * Q + q] : (double)r.p[k * Q + q];
-            moments_about<DIM>(fr, r.ux - rx, r.uy - ry, s, m);
-            if constexpr (kDevI) {
-                const double R = set == 0 ? refR0 : refR1;
-                m[0] -= R;
-                m[2] -= R * refT;
-                if (DIM == 2) {
-                    m[6] -= R * refT;
-                    m[8] -= R * refT * refT;
-                }
+        for (int q = 0; q < Q; ++q) fr[q] = dev ? weight_q<DIM>(q) * r.sum + (double)r.p[q] : (double)r.p[q];
+        moments_about<DIM>(fr, r.ux - rx, r.uy - ry, s, m);
+        if constexpr (kDevI) {
+            const double R = r.set == 0 ? refR0 : refR1;
+            m[0] -= R;
+            m[2] -= R * refT;
+            if (DIM == 2) {
+                m[6] -= R * refT;
+                m[8] -= R * refT * refT;
             }
-#pragma unroll
-            for (int i = 0; i < NF; ++i)
-                lds[SPLIT == 2 ? (i * LN + r.li) * 2 + set : (set * NF + i) * LN + r.li] = (LdsT)m[i];
         }
+#pragma unroll
+        for (int i = 0; i < NF; ++i) lds[(i * LN + r.li) * 2 + r.set] = (LdsT)m[i];
     };
     for (int it = tid; it < NITEMS; it += 2 * NT) {
         Raw ra, rb;
@@ -431,23 +418,23 @@ __global__ void __launch_bounds__(SPLIT *TX *TY, SPLIT *TX *TY <= 256 ? 3 : 2)
     if (err) raise_error(flags, err, S.parity);
 }
 
-template <int DIM, typename PopT, typename LdsT, int SPLIT, int TX, int TY, bool GEN>
+template <int DIM, typename PopT, typename LdsT, int TX, int TY, bool GEN>
 static hipError_t launch_stream_g(const LaunchCtx &c, const SlotDesc *slots, int nslots, int tiles)
 {
-    dim3 block(SPLIT * TX, TY);
+    dim3 block(2 * TX, TY);
     if (c.ev_start)
-        hipExtLaunchKernelGGL((k_stream<DIM, PopT, LdsT, TX, TY, SPLIT, GEN>), dim3(tiles), block, 0, c.st,
+        hipExtLaunchKernelGGL((k_stream<DIM, PopT, LdsT, TX, TY, GEN>), dim3(tiles), block, 0, c.st,
                               c.ev_start, c.ev_stop, 0, slots, nslots);
     else
-        hipLaunchKernelGGL((k_stream<DIM, PopT, LdsT, TX, TY, SPLIT, GEN>), dim3(tiles), block, 0, c.st, slots,
+        hipLaunchKernelGGL((k_stream<DIM, PopT, LdsT, TX, TY, GEN>), dim3(tiles), block, 0, c.st, slots,
                            nslots);
     return hipGetLastError();
 }
-template <int DIM, typename PopT, typename LdsT, int SPLIT, int TX, int TY>
+template <int DIM, typename PopT, typename LdsT, int TX, int TY>
 static hipError_t launch_stream_t(const LaunchCtx &c, const SlotDesc *slots, int nslots, int tiles)
 {
-    return c.gen_eos ? launch_stream_g<DIM, PopT, LdsT, SPLIT, TX, TY, true>(c, slots, nslots, tiles)
-                     : launch_stream_g<DIM, PopT, LdsT, SPLIT, TX, TY, false>(c, slots, nslots, tiles);
+    return c.gen_eos ? launch_stream_g<DIM, PopT, LdsT, TX, TY, true>(c, slots, nslots, tiles)
+                     : launch_stream_g<DIM, PopT, LdsT, TX, TY, false>(c, slots, nslots, tiles);
 }
 
 // Tile shapes of the streaming kernel (receivers per block, x by y); the library picks
@@ -471,15 +458,15 @@ static hipError_t launch_stream_v(const LaunchCtx &c, const SlotDesc *slots, int
 {
     if (c.dim == 2) {
         switch (c.stream_tile) {
-        case 1: return launch_stream_t<2, PopT, LdsT, 2, 32, 4>(c, slots, nslots, tiles);
-        case 2: return launch_stream_t<2, PopT, LdsT, 2, 16, 8>(c, slots, nslots, tiles);
-        case 3: return launch_stream_t<2, PopT, LdsT, 2, 64, 4>(c, slots, nslots, tiles);
-        case 4: return launch_stream_t<2, PopT, LdsT, 2, 16, 4>(c, slots, nslots, tiles);
-        default: return launch_stream_t<2, PopT, LdsT, 2, 32, 8>(c, slots, nslots, tiles);
+        case 1: return launch_stream_t<2, PopT, LdsT, 32, 4>(c, slots, nslots, tiles);
+        case 2: return launch_stream_t<2, PopT, LdsT, 16, 8>(c, slots, nslots, tiles);
+        case 3: return launch_stream_t<2, PopT, LdsT, 64, 4>(c, slots, nslots, tiles);
+        case 4: return launch_stream_t<2, PopT, LdsT, 16, 4>(c, slots, nslots, tiles);
+        default: return launch_stream_t<2, PopT, LdsT, 32, 8>(c, slots, nslots, tiles);
         }
     }
-    if (c.stream_tile == 1) return launch_stream_t<1, PopT, LdsT, 2, 64, 1>(c, slots, nslots, tiles);
-    return launch_stream_t<1, PopT, LdsT, 2, 128, 1>(c, slots, nslots, tiles);
+    if (c.stream_tile == 1) return launch_stream_t<1, PopT, LdsT, 64, 1>(c, slots, nslots, tiles);
+    return launch_stream_t<1, PopT, LdsT, 128, 1>(c, slots, nslots, tiles);
 }
 
 hipError_t launch_stream(const LaunchCtx &c, const SlotDesc *slots, int nslots, int tiles)
