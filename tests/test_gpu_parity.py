@@ -105,6 +105,16 @@ def test_every_stream_tile_shape_2d(tile):
     _check(case, 30, tile=tile)
 
 
+@pytest.mark.parametrize("precision,tol", [(pond.FP32_STORE, 1e-4), (pond.FP32_STORE_FP64_MATH, 1e-6)])
+@pytest.mark.parametrize("tile", range(5))
+def test_every_stream_tile_shape_2d_fp32_storage(tile, precision, tol):
+    """Each tile shape's FP32-storage windows (FP32 rows summed in FP32, or FP64 rows added
+    straight into the accumulators), including the 256-lane shapes compiled for three
+    waves per SIMD."""
+    case = W.perturbed(70, 45, seed=50 + tile, kappa=0.0176, u0=(0.1, -0.2))
+    _check(case, 30, tol=tol, precision=precision, tile=tile)
+
+
 @pytest.mark.parametrize("tile", range(2))
 def test_every_stream_tile_shape_1d(tile):
     case = W.perturbed(333, 1, seed=40 + tile, dim=1, kappa=0.0176, u0=(0.2, 0.0))
