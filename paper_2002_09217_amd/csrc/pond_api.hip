@@ -221,24 +221,32 @@ int enqueue_step(pond_handle *h, hipStream_t st, int from)
     return POND_OK;
 }
 
-// record two steps starting from state `from` into an executable graph
-int build_pair_graph(pond_handle *h, int from)
+// record a run of steps starting from state `from` into an executable graph: two steps
+// (kind 0) or 2 kRunPairs steps (kind 1)
+int build_step_graph(pond_handle *h, int kind, int from)
 {
-    if (h->pair_exec[from]) return POND_OK;
+    hipGraphExec_t &exec = h->step_exec[kind][from];
+    if (exec) return POND_OK;
     // created on first use: handles stepped only inside batches never need one
     if (!h->capture_stream)
         HIP_TRY(h, hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking));
     hipGraph_t g = nullptr;
     HIP_TRY(h, hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal));
-    int rc = enqueue_step(h, h->capture_stream, from);
-    if (rc == POND_OK) rc = enqueue_step(h, h->capture_stream, 1 - from);
+    int rc = POND_OK;
+    for (int k = 0; k < (kind ? kRunPairs : 1) && rc == POND_OK; ++k) {
+        rc = enqueue_step(h, h->capture_stream, from);
+        if (rc == POND_OK) rc = enqueue_step(h, h->capture_stream, 1 - from);
+    }
     hipError_t e = hipStreamEndCapture(h->capture_stream, &g);
-    if (rc != POND_OK) return rc;
+    if (rc != POND_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
     if (e != hipSuccess) return handle_fail(h, POND_E_DEVICE, "graph capture: %s", hipGetErrorString(e));
-    e = hipGraphInstantiate(&h->pair_exec[from], g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
-        h->pair_exec[from] = nullptr;
+        exec = nullptr;
         return handle_fail(h, POND_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
     }
     return POND_OK;
@@ -262,11 +270,12 @@ int finish_batch(pond_handle *h)
 
 void drop_graphs(pond_handle *h)
 {
-    for (int i = 0; i < 2; ++i)
-        if (h->pair_exec[i]) {
-            (void)hipGraphExecDestroy(h->pair_exec[i]);
-            h->pair_exec[i] = nullptr;
-        }
+    for (auto &kind : h->step_exec)
+        for (auto &g : kind)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
 }
 
 void free_all(pond_handle *h)
@@ -489,12 +498,15 @@ int pond_step(pond_handle *h, int nsteps)
     HIP_TRY(h, launch_reset_flags(h->lc, h->ds.flags));
     int parity = h->cur;
     int left = nsteps;
-    if (h->graphs_ok && nsteps >= 2) {
-        if (build_pair_graph(h, parity) != POND_OK) h->graphs_ok = false;
-    }
-    if (h->graphs_ok && nsteps >= 2) {
-        // a pair returns to the same buffer parity
-        for (; left >= 2; left -= 2) HIP_TRY(h, hipGraphLaunch(h->pair_exec[parity], h->stream));
+    // runs of 2 kRunPairs steps, then pairs; each returns to the same buffer parity
+    for (int kind = 1; kind >= 0 && h->graphs_ok; --kind) {
+        const int len = kind ? 2 * kRunPairs : 2;
+        if (left < len) continue;
+        if (build_step_graph(h, kind, parity) != POND_OK) {
+            h->graphs_ok = false;
+            break;
+        }
+        for (; left >= len; left -= len) HIP_TRY(h, hipGraphLaunch(h->step_exec[kind][parity], h->stream));
     }
     for (; left > 0; --left) {
         int rc = enqueue_step(h, h->stream, parity);

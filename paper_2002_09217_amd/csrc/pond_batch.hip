@@ -7,8 +7,8 @@
 // step is one launch of each step kernel per group over the concatenated tiles of
 // its members.  Two descriptor arrays per batch: array 0 holds, for every member,
 // the descriptor reading the state that was current when the arrays were built, and
-// array 1 the other one; a step alternates between them, so pairs of steps replay
-// one captured HIP graph.
+// array 1 the other one; a step alternates between them, so runs of an even number
+// of steps replay one captured HIP graph.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -52,7 +52,8 @@ struct pond_batch {
     std::vector<int> flags_h;
     int cap = 0;                         // slots the device arrays hold
     int phase = 0;                       // descriptor array reading the current states
-    hipGraphExec_t pair_exec[2] = {nullptr, nullptr};
+    // [0]: two steps, [1]: 2 kRunPairs steps; each starting from array 0 / 1
+    hipGraphExec_t step_exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     bool graphs_ok = true;
 };
 
@@ -60,11 +61,12 @@ namespace {
 
 void drop_graphs(pond_batch *b)
 {
-    for (auto &g : b->pair_exec)
-        if (g) {
-            (void)hipGraphExecDestroy(g);
-            g = nullptr;
-        }
+    for (auto &kind : b->step_exec)
+        for (auto &g : kind)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
 }
 
 // regroup the members and upload both descriptor arrays
@@ -137,22 +139,27 @@ hipError_t enqueue_step(pond_batch *b, hipStream_t st, int arr)
     return hipSuccess;
 }
 
-bool build_pair_graph(pond_batch *b, int arr)
+// record two steps (kind 0) or 2 kRunPairs steps (kind 1) from descriptor array `arr`
+bool build_step_graph(pond_batch *b, int kind, int arr)
 {
-    if (b->pair_exec[arr]) return true;
+    hipGraphExec_t &exec = b->step_exec[kind][arr];
+    if (exec) return true;
     hipGraph_t g = nullptr;
     if (hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
-    hipError_t e = enqueue_step(b, b->capture_stream, arr);
-    if (e == hipSuccess) e = enqueue_step(b, b->capture_stream, 1 - arr);
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < (kind ? kRunPairs : 1) && e == hipSuccess; ++k) {
+        e = enqueue_step(b, b->capture_stream, arr);
+        if (e == hipSuccess) e = enqueue_step(b, b->capture_stream, 1 - arr);
+    }
     const hipError_t ec = hipStreamEndCapture(b->capture_stream, &g);
     if (e != hipSuccess || ec != hipSuccess || !g) {
         if (g) (void)hipGraphDestroy(g);
         return false;
     }
-    e = hipGraphInstantiate(&b->pair_exec[arr], g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
-        b->pair_exec[arr] = nullptr;
+        exec = nullptr;
         return false;
     }
     return true;
@@ -243,10 +250,17 @@ int pond_batch_step(pond_batch *b, int nsteps)
     if (launch_reset_slot_flags(b->stream, b->desc_d, M) != hipSuccess) return POND_E_DEVICE;
     int arr = b->phase;
     int left = nsteps;
-    if (b->graphs_ok && left >= 2 && !build_pair_graph(b, arr)) b->graphs_ok = false;
-    if (b->graphs_ok)
-        for (; left >= 2; left -= 2)
-            if (hipGraphLaunch(b->pair_exec[arr], b->stream) != hipSuccess) return POND_E_DEVICE;
+    // runs of 2 kRunPairs steps, then pairs; each returns to the same descriptor array
+    for (int kind = 1; kind >= 0 && b->graphs_ok; --kind) {
+        const int len = kind ? 2 * kRunPairs : 2;
+        if (left < len) continue;
+        if (!build_step_graph(b, kind, arr)) {
+            b->graphs_ok = false;
+            break;
+        }
+        for (; left >= len; left -= len)
+            if (hipGraphLaunch(b->step_exec[kind][arr], b->stream) != hipSuccess) return POND_E_DEVICE;
+    }
     for (; left > 0; --left) {
         if (enqueue_step(b, b->stream, arr) != hipSuccess) return POND_E_DEVICE;
         arr = 1 - arr;

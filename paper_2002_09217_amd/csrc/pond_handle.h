@@ -15,7 +15,8 @@ struct pond_handle {
     hipStream_t stream = nullptr;       // where work runs (caller's or owned)
     bool own_stream = false;
     hipStream_t capture_stream = nullptr; // used only to record graphs; created on first use
-    hipGraphExec_t pair_exec[2] = {nullptr, nullptr}; // two steps starting from state 0 / 1
+    // [0]: two steps, [1]: 2 kRunPairs steps; each starting from state 0 / 1
+    hipGraphExec_t step_exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     bool graphs_ok = true;
     bool tuned = false;                 // streaming tile shape fixed
     int cur = 0;                        // state buffer holding the current state

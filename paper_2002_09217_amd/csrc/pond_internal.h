@@ -6,6 +6,11 @@
 
 namespace pond {
 
+// Steps are replayed from captured HIP graphs: runs of 2 kRunPairs steps, and pairs
+// for what is left.  Every graph has an even step count, so it ends on the buffer
+// parity it starts from.  A graph launch costs a few microseconds more than a kernel
+// boundary inside a graph, which longer runs amortise.
+constexpr int kRunPairs = 8;
 enum { kPeriodic = 0, kOutflow = 1, kInflow = 2 };
 
 // error bits written by the kernels into flags[0]
