@@ -5,7 +5,7 @@ admits them in arrival order while the device memory they need (pond_footprint)
 fits the budget and a slot is free, keeps each admitted job's state resident in HBM,
 and advances all admitted jobs together through one libpond batch: each batch step
 is one launch of each step kernel over the tiles of every active lattice, replayed
-in pairs from a captured HIP graph.  Between chunks of steps, finished jobs are read
+in runs of steps from captured HIP graphs.  Between chunks of steps, finished jobs are read
 back and released and newly arrived jobs are admitted, so jobs that arrive while
 others run join the work already on the device.
 
