@@ -233,7 +233,7 @@ __global__ void __launch_bounds__(2 * TX *TY, 2 * TX *TY <= 256 ? 3 : 2)
     // leave the state alone after an earlier failure
     if (abort_block != 0) return;
 
-    // both lanes of a split receiver leave together, so the exchanges below always pair up
+    // both lanes of a receiver leave together, so the exchanges below always pair up
     if (!inside) return;
     const int wbase = (DIM == 2 ? threadIdx.y * LX : 0) + lxr; // window (gx-2, gy-2)
     const double dt = P.dt;
