@@ -439,10 +439,10 @@ static hipError_t launch_stream_t(const LaunchCtx &c, const SlotDesc *slots, int
 
 // Tile shapes of the streaming kernel (receivers per block, x by y); the library picks
 // one per lattice, by measurement or as requested (pond_config.tile).
-static const int kTiles2D[][2] = {{32, 8}, {32, 4}, {16, 8}, {64, 4}, {16, 4}};
+static const int kTiles2D[][2] = {{32, 8}, {32, 4}, {16, 8}, {64, 4}, {16, 4}, {16, 16}};
 static const int kTiles1D[][2] = {{128, 1}, {64, 1}};
 
-int stream_variants(int dim) { return dim == 3 ? 1 : dim == 2 ? 5 : 2; }
+int stream_variants(int dim) { return dim == 3 ? 1 : dim == 2 ? 6 : 2; }
 void stream_tile_shape(int dim, int v, int *tx, int *ty)
 {
     if (dim == 3) {
@@ -462,6 +462,7 @@ static hipError_t launch_stream_v(const LaunchCtx &c, const SlotDesc *slots, int
         case 2: return launch_stream_t<2, PopT, LdsT, 16, 8>(c, slots, nslots, tiles);
         case 3: return launch_stream_t<2, PopT, LdsT, 64, 4>(c, slots, nslots, tiles);
         case 4: return launch_stream_t<2, PopT, LdsT, 16, 4>(c, slots, nslots, tiles);
+        case 5: return launch_stream_t<2, PopT, LdsT, 16, 16>(c, slots, nslots, tiles);
         default: return launch_stream_t<2, PopT, LdsT, 32, 8>(c, slots, nslots, tiles);
         }
     }

@@ -99,14 +99,14 @@ def test_fp32_storage_with_fp64_arithmetic_within_1e6(which):
     _check(case, 100, tol=1e-6, precision=pond.FP32_STORE_FP64_MATH, fields=fields)
 
 
-@pytest.mark.parametrize("tile", range(5))
+@pytest.mark.parametrize("tile", range(6))
 def test_every_stream_tile_shape_2d(tile):
     case = W.perturbed(70, 45, seed=30 + tile, kappa=0.0176, u0=(0.1, -0.2))
     _check(case, 30, tile=tile)
 
 
 @pytest.mark.parametrize("precision,tol", [(pond.FP32_STORE, 1e-4), (pond.FP32_STORE_FP64_MATH, 1e-6)])
-@pytest.mark.parametrize("tile", range(5))
+@pytest.mark.parametrize("tile", range(6))
 def test_every_stream_tile_shape_2d_fp32_storage(tile, precision, tol):
     """Each tile shape's FP32-storage windows (FP32 rows summed in FP32, or FP64 rows added
     straight into the accumulators), including the 256-lane shapes compiled for three
