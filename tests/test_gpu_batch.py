@@ -46,7 +46,8 @@ def _mix():
 
 def test_batch_members_bitwise_equal_to_alone():
     mix = _mix()
-    schedule = (1, 6, 7, 2)               # odd and even chunks: both graph phases
+    # odd and even chunks, one past a 16-step graph: both graph phases and lengths
+    schedule = (1, 6, 19, 2)
     total = sum(schedule)
     alone = []
     for case, tile, prec in mix:
