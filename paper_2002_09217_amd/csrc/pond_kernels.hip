@@ -81,6 +81,53 @@ __device__ __forceinline__ void raise_error(int *flags, int bits, int parity)
 // ---------------------------------------------------------------------------
 // streaming with the predictor-corrector
 // ---------------------------------------------------------------------------
+// The 2D window of one FP64 set without its zero taps: acc[3k+l] += sum_n B_ln sum_r
+// wy_l[r] sum_m A_km sum_c wx_k[c] M_mn[r][c], for a wave in which every lane's departure
+// stencils of k = 0 and l = 0 start at window column/row 1 and those of k = 2 and l = 2
+// end at column/row 3 (the usual case: |u| < sqrt(theta)).  Same group order, one-ahead
+// LDS reads and row accumulation as the general window in k_stream.
+template <int LN, int LX>
+__device__ __forceinline__ void window2_no_zero_taps(const double *sbase, const double (&wx)[3][5],
+                                                     const double (&wy)[3][5], const double (&A)[3][3],
+                                                     const double (&Bd)[3][3], double (&acc)[9])
+{
+    constexpr int CS = 2;
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+        auto load_group = [&](int g, double v[5]) {
+            const double *row = sbase + ((3 * (g % 3) + n) * LN + (g / 3) * LX) * CS;
+#pragma unroll
+            for (int c = 0; c < 5; ++c) v[c] = row[c * CS];
+        };
+        double Z[3], cur[5], nxt[5];
+        load_group(0, cur);
+#pragma unroll
+        for (int g = 0; g < 15; ++g) {
+            const int r = g / 3, m = g % 3;
+            if (g + 1 < 15) load_group(g + 1, nxt);
+            const double x0 = wx[0][1] * cur[1] + wx[0][2] * cur[2] + wx[0][3] * cur[3] + wx[0][4] * cur[4];
+            const double x1 =
+                wx[1][0] * cur[0] + wx[1][1] * cur[1] + wx[1][2] * cur[2] + wx[1][3] * cur[3] + wx[1][4] * cur[4];
+            const double x2 = wx[2][0] * cur[0] + wx[2][1] * cur[1] + wx[2][2] * cur[2] + wx[2][3] * cur[3];
+            Z[0] = m == 0 ? A[0][0] * x0 : Z[0] + A[0][m] * x0;
+            Z[1] = m == 0 ? A[1][0] * x1 : Z[1] + A[1][m] * x1;
+            Z[2] = m == 0 ? A[2][0] * x2 : Z[2] + A[2][m] * x2;
+            if (m == 2) {
+#pragma unroll
+                for (int l = 0; l < 3; ++l) {
+                    if ((l == 0 && r == 0) || (l == 2 && r == 4)) continue;
+                    const double C = Bd[l][n] * wy[l][r];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) acc[3 * k + l] += C * Z[k];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 5; ++c) cur[c] = nxt[c];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 // Two lanes per receiver: lane 2 i + set works on population set `set` (0 = f, 1 = g)
 // of receiver i; the pass moments are exchanged between the two lanes.  Blocks of at
 // most 256 lanes are compiled for three waves per SIMD, larger ones for two.
@@ -285,7 +332,16 @@ __global__ void __launch_bounds__(2 * TX *TY, 2 * TX *TY <= 256 ? 3 : 2)
 #pragma unroll
             for (int q = 0; q < Q; ++q) acc[q] = 0.0;
         }
-        if (DIM == 2) {
+        // FP64 windows in eight-wave workgroups (two waves per SIMD, registers to spare)
+        // also carry the variant without zero taps, taken by every wave that can
+        bool no_zero_taps = false;
+        if constexpr (DIM == 2 && NT == 512 && sizeof(LdsT) == 8) {
+            if (__all(wx[0][0] == 0.0 && wx[2][4] == 0.0 && wy[0][0] == 0.0 && wy[2][4] == 0.0)) {
+                window2_no_zero_taps<LN, LX>(sbase, wx, wy, A, Bd, acc);
+                no_zero_taps = true;
+            }
+        }
+        if (DIM == 2 && !no_zero_taps) {
 #pragma unroll
             for (int n = 0; n < 3; ++n) {
                 // Row r of field (m, n) is group g = 3 r + m of five window values; each
@@ -340,7 +396,7 @@ __global__ void __launch_bounds__(2 * TX *TY, 2 * TX *TY <= 256 ? 3 : 2)
                 // loads of all of them and run out of registers
                 __builtin_amdgcn_sched_barrier(0);
             }
-        } else {
+        } else if (DIM == 1) {
 #pragma unroll
             for (int m = 0; m < 3; ++m) {
                 const LdsT *row = sbase + m * LN * CS;
