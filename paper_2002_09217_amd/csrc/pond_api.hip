@@ -389,6 +389,7 @@ int pond_create(const pond_config *cfg, pond_handle **out)
     P.k_scale = c.k_scale;
     P.dt = c.dt;
     P.Cv = c.R / c.delta;
+    P.inv_Cv = c.delta / c.R;
     P.Cp_ig = c.R * (1.0 + c.delta) / c.delta;
     P.eos = c.eos;
     P.isothermal = c.isothermal ? 1 : 0;

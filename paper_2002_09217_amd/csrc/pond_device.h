@@ -62,7 +62,7 @@ __device__ __forceinline__ double eos_p(const PT &P, double rho, double T)
 template <bool GEN = true, typename PT>
 __device__ __forceinline__ double eos_T_of_e(const PT &P, double rho, double e)
 {
-    return GEN && P.isothermal ? P.T0 : P.delta * (e + P.a * rho) / P.R;
+    return GEN && P.isothermal ? P.T0 : (e + P.a * rho) * P.inv_Cv;
 }
 // temperature of an initial or inflow state given T
 template <typename PT>

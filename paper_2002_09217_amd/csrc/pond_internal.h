@@ -31,6 +31,7 @@ struct DevParams {
     int n_pass, nz;
     double a, b, R, delta, omega, kappa, k_scale, dt;
     double Cv, Cp_ig;      // R/delta and R(1 + delta)/delta
+    double inv_Cv;         // delta/R: T = (e + a rho) / C_v as a product
     int eos, isothermal;   // pond_config: equation of state, T = T0 switch
     double T0, eos_c[4];
     GhostFace ghost[4];    // face 2 axis + side
