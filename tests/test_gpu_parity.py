@@ -40,6 +40,17 @@ def test_perturbed_2d_one_step_large_velocity():
     _check(case, 20)
 
 
+@pytest.mark.parametrize("tile", [0, 3, 5])
+def test_shear_flow_both_fp64_window_variants(tile):
+    """A shear flow faster than sqrt(theta) in some rows and slower in others, on the
+    512-lane tile shapes: waves whose stencils all allow it take the FP64 window without
+    zero taps, the others the general window."""
+    case = W.perturbed(48, 40, seed=12 + tile, rho0=1.0, t_over_tcr=1.4)
+    y = np.arange(40, dtype=float).repeat(48)
+    case.u[0] = case.u[0] - case.u[0].mean() + 1.2 * np.sin(2.0 * np.pi * y / 40.0)
+    _check(case, 20, tile=tile)
+
+
 def test_droplet_64_100_steps():
     case = W.static_droplet(n=64, radius=14.0, steps=100)
     _check(case, 100)
