@@ -897,8 +897,8 @@ __global__ void __launch_bounds__(kMonThreads) k3_monitor_partials(const DevPara
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-// streaming tile: 16 x 8 receivers with FP32 streaming, 8 x 8 with FP64 (LDS of the
-// 54 staged fields of one donor plane within 64 KB)
+// streaming tile: 16 x 8 receivers in every precision; the 54 staged fields of one donor
+// plane take 52 KB of LDS in FP32 and 104 KB in FP64
 void stream3_tile(int fp32, int *tx, int *ty)
 {
     (void)fp32;
