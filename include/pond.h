@@ -112,8 +112,12 @@ int pond_create(const pond_config *cfg, pond_handle **out);
  * of N) and temperature T (N), host arrays.  The force F0 = -div K(rho) follows from
  * rho; the gauge velocity is u - F0 dt/(2 rho); the stored populations are the
  * collision of the equilibrium populations f = rho W, g = g^eq (eqs. 7, 16-22).
+ * Before returning, the call records the HIP graphs that pond_step replays (runs of
+ * 16 and of 2 steps from either state buffer), so that stepping itself captures and
+ * instantiates nothing.
  * Errors: POND_E_INVALID (NULL pointer), POND_E_PRESSURE / POND_E_NONFINITE when a
- * node is outside the EoS domain (state then undefined, handle not initialised). */
+ * node is outside the EoS domain or a field holds NaN or Inf (state then undefined,
+ * handle not initialised). */
 int pond_init_fields(pond_handle *h, const double *rho, const double *u, const double *T);
 
 /* Advance nsteps >= 0 time steps, then synchronise the stream.  Returns the first
@@ -157,7 +161,8 @@ int pond_destroy(pond_handle *h);
  *   buf of at least that many bytes.  Errors: POND_E_INVALID (NULL, buffer too small),
  *   POND_E_STATE (not initialised).
  * pond_load: make the state of buf current in h, as if h had just completed the saved
- *   number of steps; clears the error state.  Errors: POND_E_INVALID (NULL, buffer too
+ *   number of steps; clears the error state and records the step graphs as
+ *   pond_init_fields does.  Errors: POND_E_INVALID (NULL, buffer too
  *   small, not a checkpoint, or saved from another lattice shape, precision or set of
  *   parameters), POND_E_STATE (h is a member of a batch). */
 int pond_checkpoint_size(const pond_handle *h, unsigned long long *bytes);

@@ -1,9 +1,15 @@
 """Algorithmic cost model of one time step (per lattice node), used to express measured
 throughput against the MI355X rooflines.
 
-Bytes: the compulsory HBM traffic of a step is reading and writing the post-collision
-populations f, g (2 Q values) and the five side fields (gauge u_x, u_y, theta and the
-force F_x, F_y); neighbour reuse through LDS or caches is not counted.
+Bytes (compulsory HBM traffic; neighbour reuse through LDS or caches is not counted).
+A step is two kernels:
+  streaming  reads one state (2 Q populations and the five side fields: gauge u_x, u_y,
+             theta and the force F_x, F_y) and writes the streamed state as gauge-free
+             moment planes (rho, u and the central moments: 18 planes in 2D, 6 in 1D);
+  collision  reads those moment planes and writes the next state.
+bytes_per_node_step is that two-kernel traffic (656 B in FP64 D2Q9, 544 B with FP32
+population storage).  fused_bytes_per_node_step is the floor of a step that kept the
+streamed state on chip, i.e. one state read and one state written (368 B and 256 B).
 
 FLOPs of the streaming kernel (the dominant one), per receiver and pass, for the
 moment-first reconstruction: every set (f, g) has NF moment fields; each field is
@@ -21,22 +27,42 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 
-def bytes_per_node_step(dim: int, fp32_store: bool) -> int:
-    """Read and write of one state: 2Q populations (FP32 storage: 2Q FP32 deviations
-    and the two FP64 set sums) and the five FP64 side fields."""
+def state_bytes_per_node(dim: int, fp32_store: bool) -> int:
+    """One state of a node: 2Q populations (FP32 storage: 2Q FP32 deviations and the
+    two FP64 set sums) and the five FP64 side fields."""
     q = 9 if dim == 2 else 3
     pops = 2 * q * 4 + 2 * 8 if fp32_store else 2 * q * 8
-    return 2 * (pops + 5 * 8)
+    return pops + 5 * 8
+
+
+def moment_bytes_per_node(dim: int) -> int:
+    """The streamed-state moment planes the streaming kernel hands to the collision
+    kernel (FP64): rho, u and the central moments, 18 planes in 2D and 6 in 1D."""
+    return (18 if dim == 2 else 6) * 8
+
+
+def bytes_per_node_step(dim: int, fp32_store: bool) -> int:
+    """Compulsory traffic of the two-kernel step as built: each kernel reads and writes
+    one state or the moment planes once."""
+    return 2 * (state_bytes_per_node(dim, fp32_store) + moment_bytes_per_node(dim))
+
+
+def fused_bytes_per_node_step(dim: int, fp32_store: bool) -> int:
+    """Floor of a step whose streamed state never leaves the chip: one state read, one
+    written."""
+    return 2 * state_bytes_per_node(dim, fp32_store)
 
 
 def stream_bytes_per_node(dim: int, fp32_store: bool) -> int:
     """Compulsory HBM bytes of the streaming kernel alone per receiver: it reads the
-    populations and the five side fields and writes the streamed-state moment planes
-    (rho, u and the central moments: 18 planes in 2D, 6 in 1D) for the collision kernel."""
-    q = 9 if dim == 2 else 3
-    pops = 2 * q * 4 + 2 * 8 if fp32_store else 2 * q * 8
-    mom_planes = 18 if dim == 2 else 6
-    return pops + 5 * 8 + mom_planes * 8
+    populations and the five side fields and writes the streamed-state moment planes."""
+    return state_bytes_per_node(dim, fp32_store) + moment_bytes_per_node(dim)
+
+
+def collide_bytes_per_node(dim: int, fp32_store: bool) -> int:
+    """Compulsory HBM bytes of the collision kernel per node: the moment planes in, the
+    next state out (the halo re-reads of its stencils are not counted)."""
+    return moment_bytes_per_node(dim) + state_bytes_per_node(dim, fp32_store)
 
 
 def stream_flops_per_node(dim: int, n_pass: int) -> int:

@@ -84,8 +84,8 @@ const char *err_name(int bits)
     return "unknown";
 }
 
-// move the handle to the last completed state of a batch of steps, given its flags
-int handle_finish_batch(pond_handle *h, const int *fl)
+// completed steps of a batch of steps that started on state buffer `cur`, given its flags
+int completed_steps(const int *fl, int cur)
 {
     int done = fl[kFlagSteps];
     if (fl[kFlagErr]) {
@@ -95,9 +95,16 @@ int handle_finish_batch(pond_handle *h, const int *fl)
         const int p = fl[kFlagErrParity] - 1;
         if (p < 0)
             done -= 1; // not raised by a step kernel: the counter includes the failing step
-        else if ((done & 1) != ((p - h->cur) & 1))
+        else if ((done & 1) != ((p - cur) & 1))
             done -= 1;
     }
+    return done;
+}
+
+// move the handle to the last completed state of a batch of steps, given its flags
+int handle_finish_batch(pond_handle *h, const int *fl)
+{
+    const int done = completed_steps(fl, h->cur);
     h->cur = (h->cur + done) % 2;
     h->steps += done;
     if (fl[kFlagErr]) {
@@ -227,7 +234,7 @@ int build_step_graph(pond_handle *h, int kind, int from)
 {
     hipGraphExec_t &exec = h->step_exec[kind][from];
     if (exec) return POND_OK;
-    // created on first use: handles stepped only inside batches never need one
+    // the capture stream is created with the first graph
     if (!h->capture_stream)
         HIP_TRY(h, hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking));
     hipGraph_t g = nullptr;
@@ -250,6 +257,16 @@ int build_step_graph(pond_handle *h, int kind, int from)
         return handle_fail(h, POND_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
     }
     return POND_OK;
+}
+
+// Record every step graph pond_step can use (both run lengths, both buffer parities)
+// now, so that no capture or instantiation happens inside a caller's stepping.  A
+// failure leaves the handle on direct launches, as a failed capture in pond_step does.
+void build_all_graphs(pond_handle *h)
+{
+    for (int kind = 1; kind >= 0 && h->graphs_ok; --kind)
+        for (int from = 0; from < 2 && h->graphs_ok; ++from)
+            if (build_step_graph(h, kind, from) != POND_OK) h->graphs_ok = false;
 }
 
 int read_flags(pond_handle *h, int out[kFlagWords])
@@ -336,6 +353,49 @@ int tune_stream_tile(pond_handle *h, int reps)
 
 } // namespace
 
+namespace pond {
+
+int config_valid(const pond_config *cfg) { return validate(cfg); }
+
+size_t state_pop_bytes(int dim, long long N, int fp32) { return pop_bytes(dim, N, fp32); }
+
+// device parameter block of a validated configuration; POND_E_INVALID when an inflow
+// face's state is outside the EoS domain
+int make_params(const pond_config &c, DevParams &P)
+{
+    const int nx = c.n[0], ny = c.dim >= 2 ? c.n[1] : 1, nz = c.dim == 3 ? c.n[2] : 1;
+    std::memset(&P, 0, sizeof P);
+    P.dim = c.dim;
+    P.nx = nx;
+    P.ny = ny;
+    P.N = nx * ny * nz;
+    for (int a = 0; a < 2; ++a)
+        for (int s = 0; s < 2; ++s) P.bc[a][s] = a < c.dim ? c.bc[a][s] : kPeriodic;
+    P.n_pass = c.n_pass;
+    P.nz = nz;
+    P.a = c.a;
+    P.b = c.b;
+    P.R = c.R;
+    P.delta = c.delta;
+    P.omega = c.omega;
+    P.kappa = c.kappa;
+    P.k_scale = c.k_scale;
+    P.dt = c.dt;
+    P.Cv = c.R / c.delta;
+    P.inv_Cv = c.delta / c.R;
+    P.Cp_ig = c.R * (1.0 + c.delta) / c.delta;
+    P.eos = c.eos;
+    P.isothermal = c.isothermal ? 1 : 0;
+    P.T0 = c.T0;
+    for (int i = 0; i < 4; ++i) P.eos_c[i] = c.eos_c[i];
+    for (int a = 0; a < c.dim; ++a)
+        for (int s = 0; s < 2; ++s)
+            if (c.bc[a][s] == kInflow && !make_ghost(c, c.inflow[a][s], P.ghost[2 * a + s])) return POND_E_INVALID;
+    return POND_OK;
+}
+
+} // namespace pond
+
 extern "C" {
 
 int pond_footprint(const pond_config *cfg, unsigned long long *bytes)
@@ -371,36 +431,10 @@ int pond_create(const pond_config *cfg, pond_handle **out)
     h->tuned = c.tile >= 0 || c.dim == 3;
 
     DevParams P;
-    std::memset(&P, 0, sizeof P);
-    P.dim = c.dim;
-    P.nx = nx;
-    P.ny = ny;
-    P.N = N;
-    for (int a = 0; a < 2; ++a)
-        for (int s = 0; s < 2; ++s) P.bc[a][s] = a < c.dim ? c.bc[a][s] : kPeriodic;
-    P.n_pass = c.n_pass;
-    P.nz = nz;
-    P.a = c.a;
-    P.b = c.b;
-    P.R = c.R;
-    P.delta = c.delta;
-    P.omega = c.omega;
-    P.kappa = c.kappa;
-    P.k_scale = c.k_scale;
-    P.dt = c.dt;
-    P.Cv = c.R / c.delta;
-    P.inv_Cv = c.delta / c.R;
-    P.Cp_ig = c.R * (1.0 + c.delta) / c.delta;
-    P.eos = c.eos;
-    P.isothermal = c.isothermal ? 1 : 0;
-    P.T0 = c.T0;
-    for (int i = 0; i < 4; ++i) P.eos_c[i] = c.eos_c[i];
-    for (int a = 0; a < c.dim; ++a)
-        for (int s = 0; s < 2; ++s)
-            if (c.bc[a][s] == kInflow && !make_ghost(c, c.inflow[a][s], P.ghost[2 * a + s])) {
-                delete h;
-                return POND_E_INVALID;
-            }
+    if (make_params(c, P) != POND_OK) {
+        delete h;
+        return POND_E_INVALID;
+    }
 
     const size_t popb = pop_bytes(c.dim, N, h->lc.fp32);
     auto alloc = [&](void **p, size_t bytes) {
@@ -484,6 +518,7 @@ int pond_init_fields(pond_handle *h, const double *rho, const double *u, const d
     // the tuning launches count as started steps: clear the counters again
     HIP_TRY(h, launch_reset_flags(h->lc, h->ds.flags));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
+    build_all_graphs(h);
     h->initialised = true;
     std::snprintf(h->msg, sizeof h->msg, "ok");
     return POND_OK;
@@ -696,6 +731,7 @@ int pond_load(pond_handle *h, const void *buf, unsigned long long bytes)
     h->initialised = true;
     HIP_TRY(h, launch_reset_flags(h->lc, h->ds.flags));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
+    build_all_graphs(h);
     std::snprintf(h->msg, sizeof h->msg, "ok");
     return POND_OK;
 }

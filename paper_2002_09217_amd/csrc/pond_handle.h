@@ -38,6 +38,16 @@ namespace pond {
 int handle_fail(pond_handle *h, int code, const char *fmt, ...);
 int handle_update_desc(pond_handle *h);
 int handle_finish_batch(pond_handle *h, const int *flags);
+// completed steps of a run of steps that started on state buffer `cur`, given its flags
+int completed_steps(const int *flags, int cur);
+// pond_create's checks of a configuration (POND_OK or POND_E_INVALID)
+int config_valid(const pond_config *cfg);
+// bytes of the population part of one state buffer (the side planes follow it)
+size_t state_pop_bytes(int dim, long long N, int fp32);
+// device parameter block of a valid configuration (POND_E_INVALID: bad inflow state)
+int make_params(const pond_config &c, DevParams &P);
+int err_code(int bits);
+const char *err_name(int bits);
 } // namespace pond
 
 

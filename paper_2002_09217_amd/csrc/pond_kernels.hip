@@ -165,7 +165,7 @@ __global__ void __launch_bounds__(2 * TX *TY, 2 * TX *TY <= 256 ? 3 : 2)
     if (tid == 0) err_before = flags[kFlagErr];
     const POND_GLOBAL DevParams &P = *(const POND_GLOBAL DevParams *)S.P;
     const Geo geo = make_geo(P);
-    const int N = P.N;
+    const size_t N = P.N; // plane offsets reach 5 N (side) and 2 Q N (populations)
     const int bx0 = (tile % S.st_tiles_x) * TX;
     const int by0 = DIM == 2 ? (tile / S.st_tiles_x) * TY : 0;
 
@@ -549,7 +549,7 @@ __global__ void k_korteweg(const DevParams *__restrict__ Pp, const double *__res
     const int y = DIM == 2 ? blockIdx.y * blockDim.y + threadIdx.y : 0;
     if (x >= P.nx || y >= (DIM == 2 ? P.ny : 1)) return;
     const int node = x + P.nx * y;
-    const int N = P.N;
+    const size_t N = P.N;
     const double r0 = rho[node];
     double gx = 0.0, gy = 0.0, lap = 0.0;
     constexpr int Q = Layout<DIM>::Q;

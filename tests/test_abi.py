@@ -98,3 +98,19 @@ def test_create_rejects_three_dimensional_limits_without_device():
                 c.bc[a][s] = bc
         h = ctypes.c_void_p()
         assert lib.pond_create(ctypes.byref(c), ctypes.byref(h)) == -1
+
+
+def test_node_count_limits_without_device():
+    """1D and 2D lattices up to 2^30 nodes are accepted (the kernels index planes with
+    64-bit offsets), one node more is refused; pond_footprint validates like pond_create."""
+    lib = pond.load()
+    v = ctypes.c_ulonglong()
+    for dim, ok, too_big in ((2, (32768, 32768), (32768, 32769)), (1, (1 << 30,), ((1 << 30) + 1,))):
+        c = pond.Config(dim=dim, n=ok).to_c()
+        assert lib.pond_footprint(ctypes.byref(c), ctypes.byref(v)) == 0
+        assert v.value > (1 << 30) * (2 * 5 * 8)       # at least the side planes of both states
+        c = pond.Config(dim=dim, n=too_big).to_c()
+        assert lib.pond_footprint(ctypes.byref(c), ctypes.byref(v)) == -1
+        h = ctypes.c_void_p()
+        assert lib.pond_create(ctypes.byref(c), ctypes.byref(h)) == -1
+

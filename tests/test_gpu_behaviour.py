@@ -79,6 +79,29 @@ def test_init_outside_eos_domain_is_rejected():
     lat.close()
 
 
+@pytest.mark.parametrize("bad", [np.nan, np.inf])
+@pytest.mark.parametrize("field", ["rho", "ux", "uy", "T"])
+def test_init_with_nonfinite_input_is_rejected(field, bad):
+    """A NaN or Inf in any input field ends pond_init_fields with POND_E_NONFINITE."""
+    case = W.perturbed(20, 18, seed=4)
+    rho, u, T = case.rho.copy(), case.u.copy(), case.T.copy()
+    target = {"rho": rho, "ux": u[0], "uy": u[1], "T": T}[field]
+    target[57] = bad
+    print(f"non-finite input: {field}[57] = {bad}", flush=True)
+    lat = pond.Lattice(pond_config(case, tile=0))
+    with pytest.raises(pond.PondError) as err:
+        lat.init_fields(rho, u, T)
+    assert err.value.code == -5, err.value
+    with pytest.raises(pond.PondError) as err:
+        lat.step(1)
+    assert err.value.code == -7
+    # the same handle accepts a finite state afterwards
+    lat.init_fields(case.rho, case.u, case.T)
+    lat.step(2)
+    assert np.all(np.isfinite(lat.moments()["rho"]))
+    lat.close()
+
+
 def test_halo_violation_keeps_last_state():
     # |u| + sqrt(theta) > 1/dt: the departure stencil would leave the +-2 window
     case = W.perturbed(24, 24, seed=2, rho0=1.0, t_over_tcr=1.5, u0=(0.7, 0.0), dt=1.0, amp=0.0)
