@@ -51,7 +51,9 @@ typedef enum {
     POND_E_NONFINITE = -5, /* NaN or Inf in the state                                 */
     POND_E_HALO = -6,      /* a departure stencil leaves the +-2 node window:
                               |u| + sqrt(theta) times dt reached 1                    */
-    POND_E_STATE = -7      /* handle not initialised, or in the error state           */
+    POND_E_STATE = -7,     /* handle not initialised, or in the error state           */
+    POND_E_SCRATCH = -8    /* pond_step_noalloc: the lattice needs more scratch than
+                              POND_NOALLOC_SCRATCH_BYTES                              */
 } pond_status;
 
 enum { POND_BC_PERIODIC = 0, POND_BC_OUTFLOW = 1, POND_BC_INFLOW = 2 };
@@ -231,6 +233,43 @@ int pond_batch_size(const pond_batch *b, int *out);
 
 /* Remove all members and release the batch.  NULL is accepted. */
 int pond_batch_destroy(pond_batch *b);
+
+/* ---------------------------------------------------------------------------
+ * Stepping without device allocation.  For callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the caller owns the two state buffers, and every other buffer a step
+ * needs lives in a static device array of POND_NOALLOC_SCRATCH_BYTES that the
+ * library holds on each GPU it runs on until the process ends.
+ * --------------------------------------------------------------------------- */
+#define POND_NOALLOC_SCRATCH_BYTES (64ull * 1024ull * 1024ull)
+
+/* Advance a 1D or 2D lattice nsteps >= 0 time steps with the kernels of pond_step, on
+ * the current device and cfg->stream, then synchronise that stream.  Allocates no
+ * device memory and records no graph.
+ *   state0, state1  device buffers of one state each (caller-owned, read and written):
+ *                   the population planes, then the five FP64 side planes u_x, u_y,
+ *                   theta, F_x, F_y of N values each.  Populations: FP64, the 2Q planes
+ *                   f_0..f_{Q-1}, g_0..g_{Q-1}; FP32 forms, the 2Q FP32 deviation planes
+ *                   f_q - W_q sum f, g_q - W_q sum g, then the two FP64 sum planes.  A
+ *                   checkpoint of the same configuration (pond_save) holds one such
+ *                   buffer after its header, whose size is pond_checkpoint_size minus
+ *                   the bytes of a state buffer.  8-byte alignment is required.  1D
+ *                   lattices neither read nor write the planes u_y and F_y.
+ *   *cur            in: 0 or 1, the buffer holding the current state; out: the buffer
+ *                   holding the last completed state.
+ *   *done           out (may be NULL): the number of completed steps.
+ * cfg->tile selects the streaming tile shape (-1: shape 0, nothing is measured); the
+ * results are bitwise those of pond_step on a handle of the same configuration and
+ * tile shape.  The scratch holds 4096 bytes plus the streamed-state moment planes,
+ * 18 (2D) or 6 (1D) FP64 values per node, so 2D lattices of up to 466 005 nodes fit.
+ * All calls on one GPU share its scratch array: calls that overlap in time on the
+ * same GPU (other threads, or other streams before this call's synchronisation) race
+ * and give undefined results.  Each call sets up its scratch contents itself.
+ * Errors: POND_E_INVALID (cfg as for pond_create, dim 3, NULL buffers, *cur not 0 or 1,
+ * nsteps < 0), POND_E_SCRATCH (the lattice needs more than the scratch array; nothing
+ * is launched), POND_E_DEVICE, and the step errors of pond_step (POND_E_PRESSURE,
+ * POND_E_NONFINITE, POND_E_HALO), after which *cur is the last completed state. */
+int pond_step_noalloc(const pond_config *cfg, void *state0, void *state1, int *cur, int nsteps, int *done);
 
 #ifdef __cplusplus
 }

@@ -12,7 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpond.so")
-SOURCES = ["pond_kernels.hip", "pond_kernels3.hip", "pond_api.hip", "pond_batch.hip"]
+SOURCES = ["pond_kernels.hip", "pond_kernels3.hip", "pond_api.hip", "pond_batch.hip", "pond_noalloc.hip"]
 HEADERS = ["pond_device.h", "pond_internal.h"]
 
 HIPCC_FLAGS = [

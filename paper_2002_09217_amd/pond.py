@@ -19,6 +19,7 @@ POND_OK = 0
 STATUS = {
     0: "POND_OK", -1: "POND_E_INVALID", -2: "POND_E_NOMEM", -3: "POND_E_DEVICE",
     -4: "POND_E_PRESSURE", -5: "POND_E_NONFINITE", -6: "POND_E_HALO", -7: "POND_E_STATE",
+    -8: "POND_E_SCRATCH",
 }
 BC_PERIODIC, BC_OUTFLOW, BC_INFLOW = 0, 1, 2
 FP64, FP32_STORE, FP32_STORE_FP64_MATH = 0, 1, 2
@@ -32,7 +33,7 @@ EXPORTED = ["pond_create", "pond_init_fields", "pond_step", "pond_moments", "pon
             "pond_steps_done", "pond_last_error", "pond_destroy", "pond_time_kernel",
             "pond_step_timed", "pond_tile_info", "pond_footprint", "pond_batch_create",
             "pond_batch_add", "pond_batch_remove", "pond_batch_step", "pond_batch_size",
-            "pond_batch_destroy", "pond_checkpoint_size", "pond_save", "pond_load"]
+            "pond_batch_destroy", "pond_checkpoint_size", "pond_save", "pond_load", "pond_step_noalloc"]
 
 
 class pond_config(ctypes.Structure):
@@ -105,6 +106,8 @@ def load(path: str = LIB_PATH):
     L.pond_checkpoint_size.argtypes = [hp, ctypes.POINTER(ctypes.c_ulonglong)]
     L.pond_save.argtypes = [hp, ctypes.c_void_p, ctypes.c_ulonglong]
     L.pond_load.argtypes = [hp, ctypes.c_void_p, ctypes.c_ulonglong]
+    L.pond_step_noalloc.argtypes = [ctypes.POINTER(pond_config), ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     for name in EXPORTED:
         getattr(L, name).restype = getattr(L, name).restype or ctypes.c_int
     L.pond_last_error.restype = ctypes.c_char_p
@@ -176,6 +179,16 @@ def footprint(cfg: Config) -> int:
     if rc != POND_OK:
         raise PondError(rc, "pond_footprint")
     return int(v.value)
+
+
+def step_noalloc(cfg: Config, state0: int, state1: int, cur: int, nsteps: int):
+    """pond_step_noalloc on two caller-owned device state buffers (device addresses as
+    integers).  Returns (status, buffer holding the last completed state, steps done)."""
+    c = cfg.to_c()
+    cc, done = ctypes.c_int(cur), ctypes.c_int()
+    rc = load().pond_step_noalloc(ctypes.byref(c), state0, state1, ctypes.byref(cc), int(nsteps),
+                                  ctypes.byref(done))
+    return rc, cc.value, done.value
 
 
 @dataclass(eq=False)
