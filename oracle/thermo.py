@@ -15,6 +15,8 @@ Everything follows Reyhanian, Dorschner & Karlin (arXiv:2002.09217):
   * the simplified (double-well) free energy near the critical point,
     with the printed saturated sound speeds                            (Supplement, speed of sound)
   * Maxwell's rule for any isotherm with one loop
+  * the planar interface of the interface energy kappa/2 |grad rho|^2 (eq. 18): surface
+    tension and width of the equilibrium profile                      (Supplement, surface tension)
 All arithmetic is FP64.
 """
 from __future__ import annotations
@@ -147,6 +149,41 @@ class VdW:
         rho_l = brentq(lambda r: self.p(r, T) - ps, r_sl, (1.0 - 1e-14) / b, xtol=1e-15, rtol=1e-15)
         rho_v = brentq(lambda r: self.p(r, T) - ps, 1e-12, r_sv, xtol=1e-15, rtol=1e-15)
         return rho_v, rho_l, ps
+
+    # ------------------------------------------------------------------
+    # Planar interface of the interface energy kappa/2 |grad rho|^2 (eq. 18)
+    # ------------------------------------------------------------------
+    def free_energy(self, rho, T):
+        """Helmholtz free energy per volume, up to terms linear in rho (which drop out of
+        every quantity below): rho R T ln(rho/(1 - b rho)) - a rho^2."""
+        return rho * self.R * T * np.log(rho / (1.0 - self.b * rho)) - self.a * rho * rho
+
+    def chem_potential(self, rho, T):
+        """mu = d f/d rho (same linear terms dropped); rho mu - f is the pressure."""
+        return self.R * T * (np.log(rho / (1.0 - self.b * rho)) + 1.0 / (1.0 - self.b * rho)) - 2.0 * self.a * rho
+
+    def grand_excess(self, rho, T, rho_v=None):
+        """omega(rho) = f(rho) - f(rho_v) - mu_sat (rho - rho_v): the excess grand potential
+        density against the coexisting bulk phases, zero at both coexistence densities."""
+        if rho_v is None:
+            rho_v = self.maxwell(T)[0]
+        return (self.free_energy(rho, T) - self.free_energy(rho_v, T)
+                - self.chem_potential(rho_v, T) * (rho - rho_v))
+
+    def surface_tension(self, T, kappa):
+        """Tension of the planar interface at T < T_cr: sigma = int_{rho_v}^{rho_l}
+        sqrt(2 kappa omega(rho)) d rho (the equilibrium profile has kappa rho'^2 / 2 = omega)."""
+        rv, rl, _ = self.maxwell(T)
+        return quad(lambda r: math.sqrt(max(2.0 * kappa * float(self.grand_excess(r, T, rv)), 0.0)), rv, rl,
+                    epsabs=0.0, epsrel=1e-12, limit=200)[0]
+
+    def interface_width(self, T, kappa, lo=0.1, hi=0.9):
+        """Distance between the points of the equilibrium profile at the fractions lo and hi
+        of the density jump: x(rho) = int sqrt(kappa / (2 omega)) d rho."""
+        rv, rl, _ = self.maxwell(T)
+        a, b = rv + lo * (rl - rv), rv + hi * (rl - rv)
+        return quad(lambda r: math.sqrt(kappa / (2.0 * float(self.grand_excess(r, T, rv)))), a, b,
+                    epsabs=0.0, epsrel=1e-12, limit=200)[0]
 
     # ------------------------------------------------------------------
     # Rankine-Hugoniot (App. E)
