@@ -45,13 +45,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def gpu_run(case, precision, steps, warmup, stream, timed_steps=500):
+def gpu_run(case, precision, steps, warmup, stream, timed_steps=500, two_kernel=0):
     import torch
 
     from paper_2002_09217_amd import pond
     from paper_2002_09217_amd.serve import lattice_config
 
-    lat = pond.Lattice(lattice_config(case, precision, -1, stream))
+    lat = pond.Lattice(lattice_config(case, precision, -1, stream, two_kernel=two_kernel))
     ti = time.perf_counter()
     lat.init_fields(case.rho, case.u, case.T)
     log(f"bench: {case.name} init (fields, tile measurement, step graphs) {1e3 * (time.perf_counter() - ti):.1f} ms")
@@ -69,25 +69,38 @@ def gpu_run(case, precision, steps, warmup, stream, timed_steps=500):
     return (t1 - t0), kern, mon
 
 
-def traffic_from_profile(kernel_prefix):
-    """HBM bytes per launch of a kernel from the committed rocprofv3 counter summary,
-    or None when the summary was taken on other kernel sources than the current ones."""
-    import glob
+def sources_digest():
+    """SHA-256 of the 2D kernel sources the committed profile summaries record."""
     import hashlib
 
     h = hashlib.sha256()
     for f in ("pond_kernels.hip", "pond_device.h", "pond_internal.h"):
         with open(os.path.join(ROOT, "paper_2002_09217_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    digest = h.hexdigest()
+    return h.hexdigest()
+
+
+def profile_record(kind, kernel_prefix):
+    """A machine-readable line `<kind>: kernel=... key=value ...` of a committed rocprofv3
+    summary for a kernel, or (None, None) when the summary was taken on other kernel
+    sources than the current ones."""
+    import glob
+
+    digest = sources_digest()
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         for line in open(path):
-            if not line.startswith("traffic:"):
+            if not line.startswith(kind + ":"):
                 continue
             kv = dict(item.split("=", 1) for item in line.split()[1:])
             if kv.get("kernel", "").startswith(kernel_prefix.replace(" ", "")) and kv.get("sources_sha256") == digest:
-                return int(float(kv["bytes_per_launch"])), os.path.relpath(path, ROOT)
+                return kv, os.path.relpath(path, ROOT)
     return None, None
+
+
+def traffic_from_profile(kernel_prefix):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter summary."""
+    kv, src = profile_record("traffic", kernel_prefix)
+    return (int(float(kv["bytes_per_launch"])), src) if kv else (None, None)
 
 
 def serving(precision, stream, jobs_n, log_prefix, budget_mib=None):
@@ -259,32 +272,44 @@ def main():
         log(f"bench: copy calibration, 5 copies of {args.copy_calibration_mib} MiB")
         del src, dst
 
-    log(f"bench: {case.name} FP64, warmup {args.warmup}, timed {args.steps} steps")
-    t64, kern64, mon64 = gpu_run(case, pond.FP64, args.steps, args.warmup, stream.cuda_stream)
-    mlups64 = N * args.steps / t64 / 1e6
-    log(f"bench: FP64 {mlups64:.1f} MLUPS, kernels (us): {kern64}")
-    log(f"bench: FP32-store, warmup {args.warmup}, timed {args.steps} steps")
-    t32, kern32, mon32 = gpu_run(case, pond.FP32_STORE, args.steps, args.warmup, stream.cuda_stream)
-    t32m, kern32m, _ = gpu_run(case, pond.FP32_STORE_FP64_MATH, args.steps, args.warmup, stream.cuda_stream)
-    mlups32m = N * args.steps / t32m / 1e6
-    log(f"bench: FP32-store with FP64 arithmetic {mlups32m:.1f} MLUPS, kernels (us): {kern32m}")
-    mlups32 = N * args.steps / t32 / 1e6
-    log(f"bench: FP32-store {mlups32:.1f} MLUPS, kernels (us): {kern32}")
+    # The 2048^2 runs come first: besides their own figures they bring the device to its
+    # sustained clocks, so that a short timed run of the 256^2 workload (a few hundred
+    # microseconds) measures the steady state rather than the clock ramp of an idle GPU.
+    # the two forms of the step: one fused kernel (default), or two kernels with stored
+    # populations; bytes per node-step of each
+    forms = (("", 0), ("_two_kernel", 1))
+
+    def node_bytes(prec, two):
+        fp32 = prec != pond.FP64
+        return cost.bytes_per_node_step(2, fp32) if two else cost.fused_step_bytes_per_node(2, fp32)
 
     large = None
     if not args.no_large:
         big = W.static_droplet(n=2048, radius=320.0)
         large = {"workload": "2D static droplet D2Q9 2048x2048 periodic, T=0.9 T_cr, R=320"}
-        for name, prec in (("fp64", pond.FP64), ("fp32_store", pond.FP32_STORE)):
-            tb, kb, _ = gpu_run(big, prec, 200, 20, stream.cuda_stream, timed_steps=50)
-            ml = big.N * 200 / tb / 1e6
-            bpn = cost.bytes_per_node_step(2, prec == pond.FP32_STORE)
-            large[name] = {"mlups": round(ml, 1), "bytes_per_node_step": bpn,
-                           "fused_bytes_per_node_step": cost.fused_bytes_per_node_step(2, prec == pond.FP32_STORE),
-                           "hbm_GBs": round(bpn * ml * 1e6 / 1e9, 1),
-                           "hbm_frac": round(bpn * ml * 1e6 / 1e9 / cost.HBM_PEAK_GBS, 4),
-                           "kernels_us": {k: (round(v, 2) if isinstance(v, float) else v) for k, v in kb.items()}}
-            log(f"bench: 2048^2 {name} {ml:.1f} MLUPS, kernels (us): {kb}")
+        for suffix, two in forms:
+            for name, prec in (("fp64", pond.FP64), ("fp32_store", pond.FP32_STORE)):
+                tb, kb, _ = gpu_run(big, prec, 200, 20, stream.cuda_stream, timed_steps=50, two_kernel=two)
+                ml = big.N * 200 / tb / 1e6
+                bpn = node_bytes(prec, two)
+                large[name + suffix] = {"mlups": round(ml, 1), "bytes_per_node_step": bpn,
+                                        "hbm_GBs": round(bpn * ml * 1e6 / 1e9, 1),
+                                        "hbm_frac": round(bpn * ml * 1e6 / 1e9 / cost.HBM_PEAK_GBS, 4),
+                                        "kernels_us": {k: (round(v, 2) if isinstance(v, float) else v)
+                                                       for k, v in kb.items()}}
+                log(f"bench: 2048^2 {name}{suffix} {ml:.1f} MLUPS, kernels (us): {kb}")
+
+    runs = {}
+    for suffix, two in forms:
+        for name, prec in (("fp64", pond.FP64), ("fp32_store", pond.FP32_STORE),
+                           ("fp32_store_fp64_math", pond.FP32_STORE_FP64_MATH)):
+            log(f"bench: {case.name} {name}{suffix}, warmup {args.warmup}, timed {args.steps} steps")
+            t, kern, mon = gpu_run(case, prec, args.steps, args.warmup, stream.cuda_stream, two_kernel=two)
+            runs[name + suffix] = dict(t=t, kern=kern, mon=mon, mlups=N * args.steps / t / 1e6,
+                                       bytes=node_bytes(prec, two))
+            log(f"bench: {name}{suffix} {runs[name + suffix]['mlups']:.1f} MLUPS, kernels (us): {kern}")
+    t64, kern64, mon64 = runs["fp64"]["t"], runs["fp64"]["kern"], runs["fp64"]["mon"]
+    mlups64 = runs["fp64"]["mlups"]
 
     configs = None if args.no_configs else config_runs(stream.cuda_stream)
     config5 = None if args.no_3d else config5_sample(stream.cuda_stream)
@@ -297,13 +322,17 @@ def main():
                                            budget_mib=512),
                      "fp64": serving(pond.FP64, stream.cuda_stream, args.serving_jobs, "fp64")}
 
-    flops = cost.stream_flops_per_node(2, n_pass) * N
-    t_stream = kern64["k_stream"] * 1e-6
-    achieved = flops / t_stream / 1e12
-    k_name = "k_stream<2, double, double, {tx}, {ty}".format(**kern64["tile"])
+    # the dominant kernel: the fused step (streaming with the collision recomputed on each
+    # tile's halo); algorithmic flops = the streaming passes plus one collision per node
+    flops_per_node = cost.stream_flops_per_node(2, n_pass) + cost.collide_flops_per_node(2)
+    flops = flops_per_node * N
+    t_step = kern64["k_step"] * 1e-6
+    achieved = flops / t_step / 1e12
+    k_name = "k_step<2, false, double, {tx}, {ty}".format(**kern64["tile"])
     traffic, traffic_src = traffic_from_profile(k_name)
-    b64 = cost.bytes_per_node_step(2, False)
-    b32 = cost.bytes_per_node_step(2, True)
+    # the same kernel's mean duration in the committed rocprofv3 kernel trace (same sources)
+    dur, dur_src = profile_record("duration", k_name)
+    prof_us = float(dur["avg_us"]) if dur else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -330,24 +359,28 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(achieved, 3),
                      "peak": round(cost.VALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
                      "frac": round(achieved / cost.VALU_PEAK_TFLOPS, 4), "traffic": traffic,
-                     "kernel": k_name + ">", "avg_launch_us": round(kern64["k_stream"], 3),
-                     "flops_per_node": cost.stream_flops_per_node(2, n_pass),
-                     "algorithmic_bytes_per_launch": cost.stream_bytes_per_node(2, False) * N,
-                     "traffic_source": traffic_src},
-        "hbm": {"bytes_per_node_step": b64, "achieved_GBs": round(b64 * mlups64 * 1e6 / 1e9, 1),
-                "frac": round(b64 * mlups64 * 1e6 / 1e9 / cost.HBM_PEAK_GBS, 4),
-                "fused_bytes_per_node_step": cost.fused_bytes_per_node_step(2, False),
-                "note": "bytes_per_node_step: the two-kernel step as built (state in, moment planes "
-                        "out, moment planes in, state out); fused_bytes_per_node_step: the floor of "
-                        "a step that kept the streamed state on chip"},
-        "fp32_store_fp64_math": {"value": round(mlups32m, 2), "unit": "MLUPS",
-                                 "ratio_vs_fp64": round(mlups32m / mlups64, 3), "bytes_per_node_step": b32},
-        "fp32_store": {"value": round(mlups32, 2), "unit": "MLUPS", "ratio_vs_fp64": round(mlups32 / mlups64, 3),
-                       "bytes_per_node_step": b32, "k_stream_us": round(kern32["k_stream"], 3)},
-        "kernels_us": {"fp64": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in kern64.items()},
-                       "fp32_store": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in kern32.items()},
-                       "fp32_store_fp64_math": {k: (round(v, 3) if isinstance(v, float) else v)
-                                                for k, v in kern32m.items()}},
+                     "kernel": k_name + ">", "avg_launch_us": round(kern64["k_step"], 3),
+                     "flops_per_node": flops_per_node,
+                     "algorithmic_bytes_per_launch": cost.fused_step_bytes_per_node(2, False) * N,
+                     "traffic_source": traffic_src,
+                     "timing_source": "HIP start/stop events the runtime records around each launch of "
+                                      "a second, individually launched run of steps (pond_step_timed)",
+                     "profile_avg_us": prof_us, "profile_source": dur_src,
+                     "frac_from_profile": round(flops / (prof_us * 1e-6) / 1e12 / cost.VALU_PEAK_TFLOPS, 4)
+                     if prof_us else None},
+        "hbm": {"bytes_per_node_step": runs["fp64"]["bytes"],
+                "achieved_GBs": round(runs["fp64"]["bytes"] * mlups64 * 1e6 / 1e9, 1),
+                "frac": round(runs["fp64"]["bytes"] * mlups64 * 1e6 / 1e9 / cost.HBM_PEAK_GBS, 4),
+                "note": "fused step: the 18 streamed-moment planes read and written once per step (the "
+                        "collided populations never reach HBM); two_kernel: populations and side fields "
+                        "in, moment planes out, moment planes in, populations and side fields out"},
+        "fp32_store": {"value": round(runs["fp32_store"]["mlups"], 2), "unit": "MLUPS",
+                       "ratio_vs_fp64": round(runs["fp32_store"]["mlups"] / mlups64, 3),
+                       "bytes_per_node_step": runs["fp32_store"]["bytes"]},
+        "forms": {key: {"value": round(r["mlups"], 2), "unit": "MLUPS", "ratio_vs_fp64": round(r["mlups"] / mlups64, 3),
+                        "ms_per_step": round(1e3 * r["t"] / args.steps, 5), "bytes_per_node_step": r["bytes"],
+                        "kernels_us": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in r["kern"].items()}}
+                  for key, r in runs.items()},
         "monitors_after": {"mass": mon64["mass"], "min_p": mon64["min_p"], "max_v_dt": mon64["max_v_dt"]},
         "large": large,
         "configs": configs,

@@ -99,12 +99,25 @@ typedef struct {
                                  compiled shapes on the first pond_init_fields and keep
                                  the fastest; k >= 0 = shape k (see pond_tile_info).
                                  Results depend on the shape at round-off level only. */
+    int two_kernel;           /* 1D and 2D lattices.  0 (default): each step is one kernel
+                                 that recomputes the collision of the previous step on its
+                                 tile and a 2-node halo and streams; the state kept between
+                                 steps is the streamed moments (18 planes in 2D, 6 in 1D;
+                                 in the FP32 storage precisions rho, u and 2 rho E in FP64,
+                                 the other moments in FP32), so the collided populations
+                                 never reach device memory.  1: two kernels per step, with
+                                 the collided populations and side fields stored (the FP32
+                                 precisions store the populations in FP32).  D3Q27
+                                 lattices always store populations.  Both give the same
+                                 results up to round-off (FP32 precisions: within their
+                                 FP32 rounding).                                         */
     void *stream;             /* hipStream_t or NULL                                    */
 } pond_config;
 
 /* Validate cfg and allocate the device state.  *out receives the handle (NULL on
  * error).  Errors: POND_E_INVALID (dim, sizes: N <= 2^30 nodes, 2^29 in 3D;
- * 0 < delta <= 2/3, 0 < omega < 2, n_pass >= 1, dt > 0, tile in range, inflow state
+ * 0 < delta <= 2/3, 0 < omega < 2, n_pass >= 1, dt > 0, tile in range, two_kernel
+ * not 0 or 1, inflow state
  * with p <= 0, a non-periodic face in 3D; eos out of range, a non-van-der-Waals eos
  * without isothermal, T0 <= 0 when isothermal, double-well constants other than
  * beta > 0, rho_l > rho_v > 0, p0 > 0), POND_E_NOMEM, POND_E_DEVICE. */
@@ -243,9 +256,10 @@ int pond_batch_destroy(pond_batch *b);
  * --------------------------------------------------------------------------- */
 #define POND_NOALLOC_SCRATCH_BYTES (64ull * 1024ull * 1024ull)
 
-/* Advance a 1D or 2D lattice nsteps >= 0 time steps with the kernels of pond_step, on
- * the current device and cfg->stream, then synchronise that stream.  Allocates no
- * device memory and records no graph.
+/* Advance a 1D or 2D lattice nsteps >= 0 time steps with the two-kernel step of pond_step
+ * (cfg->two_kernel must be 1: the state is stored populations), on the current device
+ * and cfg->stream, then synchronise that stream.  Allocates no device memory and records
+ * no graph.
  *   state0, state1  device buffers of one state each (caller-owned, read and written):
  *                   the population planes, then the five FP64 side planes u_x, u_y,
  *                   theta, F_x, F_y of N values each.  Populations: FP64, the 2Q planes
@@ -265,8 +279,8 @@ int pond_batch_destroy(pond_batch *b);
  * All calls on one GPU share its scratch array: calls that overlap in time on the
  * same GPU (other threads, or other streams before this call's synchronisation) race
  * and give undefined results.  Each call sets up its scratch contents itself.
- * Errors: POND_E_INVALID (cfg as for pond_create, dim 3, NULL buffers, *cur not 0 or 1,
- * nsteps < 0), POND_E_SCRATCH (the lattice needs more than the scratch array; nothing
+ * Errors: POND_E_INVALID (cfg as for pond_create, dim 3, two_kernel 0, NULL buffers, *cur
+ * not 0 or 1, nsteps < 0), POND_E_SCRATCH (the lattice needs more than the scratch array; nothing
  * is launched), POND_E_DEVICE, and the step errors of pond_step (POND_E_PRESSURE,
  * POND_E_NONFINITE, POND_E_HALO), after which *cur is the last completed state. */
 int pond_step_noalloc(const pond_config *cfg, void *state0, void *state1, int *cur, int nsteps, int *done);

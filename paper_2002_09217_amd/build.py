@@ -12,8 +12,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpond.so")
-SOURCES = ["pond_kernels.hip", "pond_kernels3.hip", "pond_api.hip", "pond_batch.hip", "pond_noalloc.hip"]
-HEADERS = ["pond_device.h", "pond_internal.h"]
+SOURCES = ["pond_kernels.hip", "pond_step.hip", "pond_kernels3.hip", "pond_api.hip", "pond_batch.hip", "pond_noalloc.hip"]
+HEADERS = ["pond_device.h", "pond_internal.h", "pond_collide.h", "pond_stream.h"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

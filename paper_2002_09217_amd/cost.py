@@ -65,6 +65,29 @@ def collide_bytes_per_node(dim: int, fp32_store: bool) -> int:
     return moment_bytes_per_node(dim) + state_bytes_per_node(dim, fp32_store)
 
 
+def fused_state_bytes_per_node(dim: int, fp32_store: bool) -> int:
+    """One state of the fused step: the streamed moment planes (FP64, or in the FP32
+    storage precisions rho, u and 2 rho E in FP64 and the other moments in FP32)."""
+    planes = 18 if dim == 2 else 6
+    dbl = dim + 2 if fp32_store else planes
+    return dbl * 8 + (planes - dbl) * 4
+
+
+def fused_step_bytes_per_node(dim: int, fp32_store: bool) -> int:
+    """Compulsory traffic of the fused step as built: one state read, one written (288 B in
+    FP64 D2Q9, 176 B in the FP32 storage precisions); halo re-reads are not counted."""
+    return 2 * fused_state_bytes_per_node(dim, fp32_store)
+
+
+def collide_flops_per_node(dim: int) -> int:
+    """Closure and collision of one node (my count, FMA = 2 flops): Korteweg stress and
+    its divergence (~80), thermodynamic state (~30), both sets rebuilt from their central
+    moments (2 x 108), f collision with the force source (~70), g collision with M0 and
+    the force-extended equilibrium (~280), and the donor moments about the tile velocity
+    (2 x 60)."""
+    return 800 if dim == 2 else 200
+
+
 def stream_flops_per_node(dim: int, n_pass: int) -> int:
     if dim == 3:
         # per z-window plane and z power: the D2Q9 x-y contraction of 9 fields (972 FMA

@@ -35,21 +35,18 @@ int handle_fail(pond_handle *h, int code, const char *fmt, ...)
     return code;
 }
 
-// rebuild the two step descriptors of a lattice (after allocation or a tile change)
+// rebuild the step descriptors of a lattice (after allocation or a tile change)
 int handle_update_desc(pond_handle *h)
 {
     int stx, stc, fcx, fcc;
     tile_counts(h->lc, &stx, &stc, &fcx, &fcc);
     h->st_tiles = stc;
     h->fc_tiles = fcc;
-    for (int p = 0; p < 2; ++p) {
+    const int R = h->states();
+    for (int p = 0; p < R; ++p) {
         SlotDesc &d = h->desc_h[p];
+        std::memset(&d, 0, sizeof d);
         d.P = h->ds.params;
-        d.pop_src = h->ds.pop[p];
-        d.side_src = h->ds.side[p];
-        d.pop_dst = h->ds.pop[1 - p];
-        d.side_dst = h->ds.side[1 - p];
-        d.mom = h->ds.mom;
         d.flags = h->ds.flags;
         d.st_tiles_x = stx;
         d.st_begin = 0;
@@ -61,10 +58,25 @@ int handle_update_desc(pond_handle *h)
         d.dmom = h->ds.dmom;
         d.kor = h->ds.kor;
         d.aux = h->ds.aux;
+        if (h->lc.fused) {
+            // the step reads slot p and writes slot p + 1; the collision kernel (check and
+            // read-back) reads slot p and writes the read-back state
+            d.smom_src = h->ds.ring[p];
+            d.smom_dst = h->ds.ring[(p + 1) % R];
+            d.mom = (double *)h->ds.ring[p];
+            d.pop_dst = h->ds.pop[0];
+            d.side_dst = h->ds.side[0];
+        } else {
+            d.pop_src = h->ds.pop[p];
+            d.side_src = h->ds.side[p];
+            d.pop_dst = h->ds.pop[1 - p];
+            d.side_dst = h->ds.side[1 - p];
+            d.mom = h->ds.mom;
+        }
     }
     // synchronous: the descriptors are read by work already queued on the stream
     HIP_TRY(h, hipStreamSynchronize(h->stream));
-    HIP_TRY(h, hipMemcpy(h->desc_d, h->desc_h, sizeof h->desc_h, hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(h->desc_d, h->desc_h, sizeof(SlotDesc) * R, hipMemcpyHostToDevice));
     return POND_OK;
 }
 
@@ -84,28 +96,37 @@ const char *err_name(int bits)
     return "unknown";
 }
 
-// completed steps of a batch of steps that started on state buffer `cur`, given its flags
-int completed_steps(const int *fl, int cur)
+// Completed steps of a run of nsteps steps that started on state buffer or ring slot `cur`
+// of `states`, given its flags.  The launch that raised the first error (launch k reads
+// the state of slot (cur + k) mod states) is known from the slot it recorded and from the
+// launch counter, which is k or k + 1 (whether that launch's first tile started before
+// the error was raised).  Two-kernel steps: the state k launches on is the last good one.
+// Fused steps: launch k first recomputes the collision of the state it reads (an error
+// there, kErrCollideStage, makes that state bad and the one before it the last good one),
+// and the run ends with a check of its last state's closure, counted as launch nsteps.
+int completed_steps(const int *fl, int cur, int states, int nsteps)
 {
-    int done = fl[kFlagSteps];
-    if (fl[kFlagErr]) {
-        // The failing step k read the state of parity (cur + k) % 2, recorded with the
-        // error; the counter is k or k + 1 (whether the failing step's first tile ran
-        // before the error was raised), and the parity tells which.
-        const int p = fl[kFlagErrParity] - 1;
-        if (p < 0)
-            done -= 1; // not raised by a step kernel: the counter includes the failing step
-        else if ((done & 1) != ((p - cur) & 1))
-            done -= 1;
-    }
-    return done;
+    if (!fl[kFlagErr]) return nsteps;
+    const int count = fl[kFlagSteps];
+    const int slot = fl[kFlagErrParity] - 1;
+    if (slot < 0) return count > 0 ? count - 1 : 0; // not raised by a step kernel
+    const int want = ((slot - cur) % states + states) % states;
+    const int k = ((count - want) % states + states) % states == 0 ? count : count - 1;
+    if (states == kFusedRing && (fl[kFlagErr] & kErrCollideStage)) return k - 1;
+    return k;
 }
 
-// move the handle to the last completed state of a batch of steps, given its flags
-int handle_finish_batch(pond_handle *h, const int *fl)
+int run_length(const pond_handle *h, int kind)
 {
-    const int done = completed_steps(fl, h->cur);
-    h->cur = (h->cur + done) % 2;
+    if (h->lc.fused) return kind ? kFusedRun : kFusedRing;
+    return kind ? 2 * kRunPairs : 2;
+}
+
+// move the handle to the last completed state of a run of nsteps steps, given its flags
+int handle_finish_batch(pond_handle *h, const int *fl, int nsteps)
+{
+    const int done = completed_steps(fl, h->cur, h->states(), nsteps);
+    h->cur = (h->cur + done) % h->states();
     h->steps += done;
     if (fl[kFlagErr]) {
         h->failed = true;
@@ -177,13 +198,27 @@ size_t dmom_bytes(int dim, long long N, int fp32)
     return dim == 3 ? (size_t)N * 54 * (fp32 == 1 ? sizeof(float) : sizeof(double)) : 0;
 }
 
+// bytes of one streamed state of the fused step: the moment planes, FP64 or mixed
+size_t ring_bytes(int dim, long long N, int fp32)
+{
+    const int planes = mom_planes(dim), dbl = fp32 ? dim + 2 : planes;
+    return (size_t)N * (dbl * sizeof(double) + (planes - dbl) * sizeof(float));
+}
+
+// the fused step serves D1Q3 and D2Q9 lattices that do not ask for two kernels
+bool fused_step(const pond_config &c) { return c.dim != 3 && !c.two_kernel; }
+
 // device bytes of one lattice of the given shape (all buffers of pond_create)
-size_t footprint(int dim, long long N, int fp32)
+size_t footprint(int dim, long long N, int fp32, bool fused)
 {
     const size_t mon = sizeof(double) * 8 * ((N + 255) / 256) + sizeof(double) * 8;
-    return 2 * pop_bytes(dim, N, fp32) +
-           (size_t)N * sizeof(double) * (2 * side_planes(dim) + mom_planes(dim) + kor_planes(dim) + aux_planes(dim)) +
-           dmom_bytes(dim, N, fp32) + sizeof(int) * kFlagWords + sizeof(DevParams) + 2 * sizeof(SlotDesc) + mon;
+    const size_t common = (size_t)N * sizeof(double) * (kor_planes(dim) + aux_planes(dim)) + sizeof(int) * kFlagWords +
+                          sizeof(DevParams) + kFusedRing * sizeof(SlotDesc) + mon;
+    if (fused) // the ring, and one population buffer with its side planes for read-back
+        return kFusedRing * ring_bytes(dim, N, fp32) + pop_bytes(dim, N, fp32) +
+               (size_t)N * sizeof(double) * side_planes(dim) + common;
+    return 2 * pop_bytes(dim, N, fp32) + (size_t)N * sizeof(double) * (2 * side_planes(dim) + mom_planes(dim)) +
+           dmom_bytes(dim, N, fp32) + common;
 }
 
 int validate(const pond_config *cfg)
@@ -213,23 +248,36 @@ int validate(const pond_config *cfg)
         !(c.eos_c[0] > 0.0 && c.eos_c[1] > c.eos_c[2] && c.eos_c[2] > 0.0 && c.eos_c[3] > 0.0))
         return POND_E_INVALID;
     if (c.tile < -1 || c.tile >= stream_variants(c.dim)) return POND_E_INVALID;
+    if (c.two_kernel != 0 && c.two_kernel != 1) return POND_E_INVALID;
     for (int a = 0; a < c.dim && a < 2; ++a)
         for (int s = 0; s < 2; ++s)
             if (c.bc[a][s] < 0 || c.bc[a][s] > 2) return POND_E_INVALID;
     return POND_OK;
 }
 
+// one step from state buffer or ring slot `from`
 int enqueue_step(pond_handle *h, hipStream_t st, int from)
 {
     LaunchCtx c = h->lc;
     c.st = st;
+    if (h->lc.fused) {
+        HIP_TRY(h, launch_step_fused(c, h->desc_d + from, 1, h->st_tiles));
+        return POND_OK;
+    }
     HIP_TRY(h, launch_stream(c, h->desc_d + from, 1, h->st_tiles));
     HIP_TRY(h, launch_force_collide(c, h->desc_d + from, 1, h->fc_tiles));
     return POND_OK;
 }
 
-// record a run of steps starting from state `from` into an executable graph: two steps
-// (kind 0) or 2 kRunPairs steps (kind 1)
+// fused step: the closure check of the state in ring slot `slot` (ends every run of steps)
+int enqueue_check(pond_handle *h, int slot)
+{
+    HIP_TRY(h, launch_collide_check(h->lc, h->desc_d + slot, 1, h->fc_tiles));
+    return POND_OK;
+}
+
+// record a run of run_length(h, kind) steps starting from state buffer or ring slot
+// `from` into an executable graph; the run ends on the slot it starts from
 int build_step_graph(pond_handle *h, int kind, int from)
 {
     hipGraphExec_t &exec = h->step_exec[kind][from];
@@ -240,10 +288,8 @@ int build_step_graph(pond_handle *h, int kind, int from)
     hipGraph_t g = nullptr;
     HIP_TRY(h, hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal));
     int rc = POND_OK;
-    for (int k = 0; k < (kind ? kRunPairs : 1) && rc == POND_OK; ++k) {
-        rc = enqueue_step(h, h->capture_stream, from);
-        if (rc == POND_OK) rc = enqueue_step(h, h->capture_stream, 1 - from);
-    }
+    const int R = h->states();
+    for (int k = 0; k < run_length(h, kind) && rc == POND_OK; ++k) rc = enqueue_step(h, h->capture_stream, (from + k) % R);
     hipError_t e = hipStreamEndCapture(h->capture_stream, &g);
     if (rc != POND_OK) {
         if (g) (void)hipGraphDestroy(g);
@@ -265,24 +311,27 @@ int build_step_graph(pond_handle *h, int kind, int from)
 void build_all_graphs(pond_handle *h)
 {
     for (int kind = 1; kind >= 0 && h->graphs_ok; --kind)
-        for (int from = 0; from < 2 && h->graphs_ok; ++from)
+        for (int from = 0; from < h->states() && h->graphs_ok; ++from)
             if (build_step_graph(h, kind, from) != POND_OK) h->graphs_ok = false;
 }
 
+// copy the flags into pinned host memory (a plain DMA, no staging through a bounce
+// buffer: this read-back ends every pond_step) and wait for it
 int read_flags(pond_handle *h, int out[kFlagWords])
 {
-    HIP_TRY(h, hipMemcpyAsync(out, h->ds.flags, sizeof(int) * kFlagWords, hipMemcpyDeviceToHost,
+    HIP_TRY(h, hipMemcpyAsync(h->flags_host, h->ds.flags, sizeof(int) * kFlagWords, hipMemcpyDeviceToHost,
                               h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
+    std::memcpy(out, h->flags_host, sizeof(int) * kFlagWords);
     return POND_OK;
 }
 
-int finish_batch(pond_handle *h)
+int finish_batch(pond_handle *h, int nsteps)
 {
     int fl[kFlagWords];
     int rc = read_flags(h, fl);
     if (rc != POND_OK) return rc;
-    return handle_finish_batch(h, fl);
+    return handle_finish_batch(h, fl, nsteps);
 }
 
 void drop_graphs(pond_handle *h)
@@ -306,17 +355,28 @@ void free_all(pond_handle *h)
     if (h->ds.kor) (void)hipFree(h->ds.kor);
     if (h->ds.aux) (void)hipFree(h->ds.aux);
     if (h->ds.dmom) (void)hipFree(h->ds.dmom);
+    for (void *r : h->ds.ring)
+        if (r) (void)hipFree(r);
     if (h->ds.flags) (void)hipFree(h->ds.flags);
     if (h->ds.params) (void)hipFree(h->ds.params);
     if (h->desc_d) (void)hipFree(h->desc_d);
     if (h->mon_partials) (void)hipFree(h->mon_partials);
     if (h->mon_out) (void)hipFree(h->mon_out);
+    if (h->flags_host) (void)hipHostFree(h->flags_host);
     if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
 }
 
-// Time every compiled tile shape of the streaming kernel on the current state (one
-// warm-up launch, then `reps` launches between HIP events) and keep the fastest.
+// the kernel whose tile shape is tuned, on the current state: the fused step, or the
+// streaming kernel of the two-kernel step; neither changes the current state
+hipError_t launch_streaming(const pond_handle *h, const LaunchCtx &c)
+{
+    return h->lc.fused ? launch_step_fused(c, h->desc_d + h->cur, 1, h->st_tiles)
+                       : launch_stream(c, h->desc_d + h->cur, 1, h->st_tiles);
+}
+
+// Time every compiled tile shape of the streaming (or fused step) kernel on the current
+// state (one warm-up launch, then `reps` launches between HIP events) and keep the fastest.
 int tune_stream_tile(pond_handle *h, int reps)
 {
     const int nv = stream_variants(h->lc.dim);
@@ -330,9 +390,9 @@ int tune_stream_tile(pond_handle *h, int reps)
         h->lc.stream_tile = v;
         rc = handle_update_desc(h);
         if (rc != POND_OK) break;
-        HIP_TRY(h, launch_stream(h->lc, h->desc_d + h->cur, 1, h->st_tiles));
+        HIP_TRY(h, launch_streaming(h, h->lc));
         HIP_TRY(h, hipEventRecord(e0, h->stream));
-        for (int r = 0; r < reps; ++r) HIP_TRY(h, launch_stream(h->lc, h->desc_d + h->cur, 1, h->st_tiles));
+        for (int r = 0; r < reps; ++r) HIP_TRY(h, launch_streaming(h, h->lc));
         HIP_TRY(h, hipEventRecord(e1, h->stream));
         HIP_TRY(h, hipEventSynchronize(e1));
         float ms = 0.0f;
@@ -405,7 +465,7 @@ int pond_footprint(const pond_config *cfg, unsigned long long *bytes)
     if (rc != POND_OK) return rc;
     const long long N = (long long)cfg->n[0] * (cfg->dim >= 2 ? cfg->n[1] : 1) * (cfg->dim == 3 ? cfg->n[2] : 1);
     const int fp32 = cfg->precision == POND_FP64 ? 0 : (cfg->precision == POND_FP32_STORE ? 1 : 2);
-    *bytes = footprint(cfg->dim, N, fp32);
+    *bytes = footprint(cfg->dim, N, fp32, fused_step(*cfg));
     return POND_OK;
 }
 
@@ -428,6 +488,7 @@ int pond_create(const pond_config *cfg, pond_handle **out)
                       c.tile < 0 ? 0 : c.tile};
     h->lc.nz = nz;
     h->lc.gen_eos = c.eos != POND_EOS_VDW || c.isothermal;
+    h->lc.fused = fused_step(c);
     h->tuned = c.tile >= 0 || c.dim == 3;
 
     DevParams P;
@@ -444,20 +505,31 @@ int pond_create(const pond_config *cfg, pond_handle **out)
             rc = handle_fail(h, POND_E_NOMEM, "hipMalloc of %zu bytes failed", bytes);
         }
     };
-    for (int i = 0; i < 2; ++i) {
-        alloc(&h->ds.pop[i], popb);
-        alloc((void **)&h->ds.side[i], sizeof(double) * side_planes(c.dim) * N);
+    if (h->lc.fused) {
+        // the ring of streamed states, and one collided state for read-back
+        for (int i = 0; i < kFusedRing; ++i) alloc(&h->ds.ring[i], ring_bytes(c.dim, N, h->lc.fp32));
+        alloc(&h->ds.pop[0], popb);
+        alloc((void **)&h->ds.side[0], sizeof(double) * side_planes(c.dim) * N);
+    } else {
+        for (int i = 0; i < 2; ++i) {
+            alloc(&h->ds.pop[i], popb);
+            alloc((void **)&h->ds.side[i], sizeof(double) * side_planes(c.dim) * N);
+        }
+        alloc((void **)&h->ds.mom, sizeof(double) * mom_planes(c.dim) * N);
     }
-    alloc((void **)&h->ds.mom, sizeof(double) * mom_planes(c.dim) * N);
     alloc((void **)&h->ds.kor, sizeof(double) * kor_planes(c.dim) * N);
     alloc((void **)&h->ds.aux, sizeof(double) * aux_planes(c.dim) * N);
     if (c.dim == 3) alloc(&h->ds.dmom, dmom_bytes(3, N, h->lc.fp32));
     alloc((void **)&h->ds.flags, sizeof(int) * kFlagWords);
     alloc((void **)&h->ds.params, sizeof(DevParams));
-    alloc((void **)&h->desc_d, 2 * sizeof(SlotDesc));
+    alloc((void **)&h->desc_d, kFusedRing * sizeof(SlotDesc));
     h->mon_blocks = monitor_blocks(h->lc);
     alloc((void **)&h->mon_partials, sizeof(double) * 8 * h->mon_blocks);
     alloc((void **)&h->mon_out, sizeof(double) * 8);
+    if (rc == POND_OK && hipHostMalloc((void **)&h->flags_host, sizeof(int) * kFlagWords, hipHostMallocDefault) != hipSuccess) {
+        h->flags_host = nullptr;
+        rc = handle_fail(h, POND_E_NOMEM, "hipHostMalloc of the flag read-back buffer failed");
+    }
     if (rc == POND_OK) {
         if (c.stream) {
             h->stream = (hipStream_t)c.stream;
@@ -501,10 +573,16 @@ int pond_init_fields(pond_handle *h, const double *rho, const double *u, const d
         HIP_TRY(h, launch_init3(h->lc, h->ds, h->desc_d + 1));
     } else {
         if (h->cfg.kappa != 0.0) HIP_TRY(h, launch_korteweg(h->lc, h->ds, d_rho));
-        HIP_TRY(h, launch_init_equilibrium(h->lc, h->ds, d_rho, d_u, d_T));
+        HIP_TRY(h, launch_init_equilibrium(h->lc, h->ds, d_rho, d_u, d_T, h->lc.fused ? h->ds.ring[0] : h->ds.mom));
     }
-    // the descriptor of parity 1 writes state 0
-    HIP_TRY(h, launch_force_collide(h->lc, h->desc_d + 1, 1, h->fc_tiles));
+    if (h->lc.fused) {
+        // the state is ring slot 0; its closure must be admissible
+        int rc = enqueue_check(h, 0);
+        if (rc != POND_OK) return rc;
+    } else {
+        // the descriptor of parity 1 writes state 0
+        HIP_TRY(h, launch_force_collide(h->lc, h->desc_d + 1, 1, h->fc_tiles));
+    }
     int fl[kFlagWords];
     int rc = read_flags(h, fl);
     if (rc != POND_OK) return rc;
@@ -532,24 +610,42 @@ int pond_step(pond_handle *h, int nsteps)
     if (h->batch) return handle_fail(h, POND_E_STATE, "handle is a member of a batch");
     if (nsteps == 0) return POND_OK;
     HIP_TRY(h, launch_reset_flags(h->lc, h->ds.flags));
-    int parity = h->cur;
+    int slot = h->cur;
     int left = nsteps;
-    // runs of 2 kRunPairs steps, then pairs; each returns to the same buffer parity
+    // long runs, then short runs; each returns to the slot it starts from
     for (int kind = 1; kind >= 0 && h->graphs_ok; --kind) {
-        const int len = kind ? 2 * kRunPairs : 2;
+        const int len = run_length(h, kind);
         if (left < len) continue;
-        if (build_step_graph(h, kind, parity) != POND_OK) {
+        if (build_step_graph(h, kind, slot) != POND_OK) {
             h->graphs_ok = false;
             break;
         }
-        for (; left >= len; left -= len) HIP_TRY(h, hipGraphLaunch(h->step_exec[kind][parity], h->stream));
+        for (; left >= len; left -= len) HIP_TRY(h, hipGraphLaunch(h->step_exec[kind][slot], h->stream));
     }
     for (; left > 0; --left) {
-        int rc = enqueue_step(h, h->stream, parity);
+        int rc = enqueue_step(h, h->stream, slot);
         if (rc != POND_OK) return rc;
-        parity = 1 - parity;
+        slot = (slot + 1) % h->states();
     }
-    return finish_batch(h);
+    if (h->lc.fused) {
+        // the last state's closure runs in the next step: check it now
+        int rc = enqueue_check(h, slot);
+        if (rc != POND_OK) return rc;
+    }
+    return finish_batch(h, nsteps);
+}
+
+// the state buffer holding the collided current state: a fused-step lattice recomputes
+// the collision of its ring slot into buffer 0 first
+static int readback_state(pond_handle *h, int *buf)
+{
+    *buf = h->cur;
+    if (!h->lc.fused) return POND_OK;
+    // flags of an earlier failure would make the collision kernel leave the state alone
+    HIP_TRY(h, launch_reset_flags(h->lc, h->ds.flags));
+    HIP_TRY(h, launch_force_collide(h->lc, h->desc_d + h->cur, 1, h->fc_tiles));
+    *buf = 0;
+    return POND_OK;
 }
 
 int pond_moments(pond_handle *h, double *rho, double *u, double *T, double *p, double *E)
@@ -558,7 +654,10 @@ int pond_moments(pond_handle *h, double *rho, double *u, double *T, double *p, d
     if (!h->initialised) return handle_fail(h, POND_E_STATE, "not initialised");
     const size_t N = h->lc.N;
     const int dim = h->lc.dim;
-    HIP_TRY(h, launch_macro(h->lc, h->ds, h->cur, h->ds.aux));
+    int buf = 0;
+    int rc = readback_state(h, &buf);
+    if (rc != POND_OK) return rc;
+    HIP_TRY(h, launch_macro(h->lc, h->ds, buf, h->ds.aux));
     const double *base = h->ds.aux;
     struct {
         double *dst;
@@ -577,7 +676,10 @@ int pond_monitors(pond_handle *h, double *out)
 {
     if (!h || !out) return POND_E_INVALID;
     if (!h->initialised) return handle_fail(h, POND_E_STATE, "not initialised");
-    HIP_TRY(h, launch_monitors(h->lc, h->ds, h->cur, h->mon_partials, h->mon_blocks, h->mon_out));
+    int buf = 0;
+    int rc = readback_state(h, &buf);
+    if (rc != POND_OK) return rc;
+    HIP_TRY(h, launch_monitors(h->lc, h->ds, buf, h->mon_partials, h->mon_blocks, h->mon_out));
     double tmp[8];
     HIP_TRY(h, hipMemcpyAsync(tmp, h->mon_out, sizeof tmp, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
@@ -617,14 +719,16 @@ int pond_destroy(pond_handle *h)
 }
 
 namespace {
-// checkpoint layout: header, then the population buffer, then the kSidePlanes side planes
+// checkpoint layout: header, then the state: the population buffer and the side planes
+// (two-kernel step, D3Q27), or the streamed-state moment planes of the current ring slot
+// (fused step; side_bytes is then 0)
 struct CheckpointHeader {
-    char magic[8];          // "PONDCKP2"
+    char magic[8];          // "PONDCKP3"
     int dim, n[3], precision, tile, n_pass, eos;
     int bc[3][2];
     long long steps;
     double a, b, R, delta, omega, kappa, k_scale, dt;
-    int isothermal, pad_;
+    int isothermal, fused;
     double T0, eos_c[4];
     double inflow[3][2][5];
     unsigned long long pop_bytes, side_bytes;
@@ -634,7 +738,7 @@ CheckpointHeader make_header(const pond_handle *h)
 {
     CheckpointHeader H;
     std::memset(&H, 0, sizeof H);
-    std::memcpy(H.magic, "PONDCKP2", 8);
+    std::memcpy(H.magic, "PONDCKP3", 8);
     const pond_config &c = h->cfg;
     H.dim = c.dim;
     for (int a = 0; a < 3; ++a) H.n[a] = c.n[a];
@@ -656,8 +760,9 @@ CheckpointHeader make_header(const pond_handle *h)
     H.T0 = c.T0;
     for (int i = 0; i < 4; ++i) H.eos_c[i] = c.eos_c[i];
     std::memcpy(H.inflow, c.inflow, sizeof H.inflow);
-    H.pop_bytes = pop_bytes(c.dim, h->lc.N, h->lc.fp32);
-    H.side_bytes = sizeof(double) * side_planes(h->lc.dim) * (size_t)h->lc.N;
+    H.fused = h->lc.fused ? 1 : 0;
+    H.pop_bytes = h->lc.fused ? ring_bytes(c.dim, h->lc.N, h->lc.fp32) : pop_bytes(c.dim, h->lc.N, h->lc.fp32);
+    H.side_bytes = h->lc.fused ? 0 : sizeof(double) * side_planes(h->lc.dim) * (size_t)h->lc.N;
     return H;
 }
 
@@ -668,7 +773,8 @@ bool same_config(const CheckpointHeader &x, const CheckpointHeader &y)
            x.precision == y.precision && x.n_pass == y.n_pass && std::memcmp(x.bc, y.bc, sizeof x.bc) == 0 &&
            x.a == y.a && x.b == y.b && x.R == y.R && x.delta == y.delta && x.omega == y.omega &&
            x.kappa == y.kappa && x.k_scale == y.k_scale && x.dt == y.dt && x.eos == y.eos &&
-           x.isothermal == y.isothermal && x.T0 == y.T0 && std::memcmp(x.eos_c, y.eos_c, sizeof x.eos_c) == 0 &&
+           x.isothermal == y.isothermal && x.fused == y.fused && x.T0 == y.T0 &&
+           std::memcmp(x.eos_c, y.eos_c, sizeof x.eos_c) == 0 &&
            std::memcmp(x.inflow, y.inflow, sizeof x.inflow) == 0 && x.pop_bytes == y.pop_bytes &&
            x.side_bytes == y.side_bytes;
 }
@@ -693,9 +799,11 @@ int pond_save(pond_handle *h, void *buf, unsigned long long bytes)
                            (unsigned long long)(sizeof H + H.pop_bytes + H.side_bytes));
     char *p = (char *)buf;
     std::memcpy(p, &H, sizeof H);
-    HIP_TRY(h, hipMemcpyAsync(p + sizeof H, h->ds.pop[h->cur], H.pop_bytes, hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(h, hipMemcpyAsync(p + sizeof H + H.pop_bytes, h->ds.side[h->cur], H.side_bytes, hipMemcpyDeviceToHost,
-                              h->stream));
+    const void *state = h->lc.fused ? h->ds.ring[h->cur] : h->ds.pop[h->cur];
+    HIP_TRY(h, hipMemcpyAsync(p + sizeof H, state, H.pop_bytes, hipMemcpyDeviceToHost, h->stream));
+    if (H.side_bytes)
+        HIP_TRY(h, hipMemcpyAsync(p + sizeof H + H.pop_bytes, h->ds.side[h->cur], H.side_bytes, hipMemcpyDeviceToHost,
+                                  h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     return POND_OK;
 }
@@ -716,8 +824,9 @@ int pond_load(pond_handle *h, const void *buf, unsigned long long bytes)
         return handle_fail(h, POND_E_INVALID, "checkpoint tile shape out of range");
     const char *p = (const char *)buf;
     HIP_TRY(h, hipStreamSynchronize(h->stream));
-    HIP_TRY(h, hipMemcpy(h->ds.pop[0], p + sizeof S, S.pop_bytes, hipMemcpyHostToDevice));
-    HIP_TRY(h, hipMemcpy(h->ds.side[0], p + sizeof S + S.pop_bytes, S.side_bytes, hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(h->lc.fused ? h->ds.ring[0] : h->ds.pop[0], p + sizeof S, S.pop_bytes, hipMemcpyHostToDevice));
+    if (S.side_bytes)
+        HIP_TRY(h, hipMemcpy(h->ds.side[0], p + sizeof S + S.pop_bytes, S.side_bytes, hipMemcpyHostToDevice));
     if (S.tile != h->lc.stream_tile) {
         drop_graphs(h);
         h->lc.stream_tile = S.tile;
@@ -744,14 +853,16 @@ int pond_time_kernel(pond_handle *h, int which, int reps, double *avg_us)
     const LaunchCtx &c = h->lc;
     const SlotDesc *d = h->desc_d + h->cur;
     HIP_TRY(h, launch_reset_flags(c, h->ds.flags));
-    // bring the scratch planes to the current step's values first
-    HIP_TRY(h, launch_stream(c, d, 1, h->st_tiles));
+    // two-kernel step: bring the scratch planes to the current step's values first
+    if (!c.fused) HIP_TRY(h, launch_stream(c, d, 1, h->st_tiles));
     hipEvent_t e0, e1;
     HIP_TRY(h, hipEventCreate(&e0));
     HIP_TRY(h, hipEventCreate(&e1));
     HIP_TRY(h, hipEventRecord(e0, h->stream));
     for (int r = 0; r < reps; ++r) {
-        hipError_t e = which == 0 ? launch_stream(c, d, 1, h->st_tiles) : launch_force_collide(c, d, 1, h->fc_tiles);
+        hipError_t e = which == 0 ? launch_streaming(h, c)
+                                  : (c.fused ? launch_collide_check(c, d, 1, h->fc_tiles)
+                                             : launch_force_collide(c, d, 1, h->fc_tiles));
         if (e != hipSuccess) return handle_fail(h, POND_E_DEVICE, "timing launch: %s", hipGetErrorString(e));
     }
     HIP_TRY(h, hipEventRecord(e1, h->stream));
@@ -784,7 +895,8 @@ int pond_step_timed(pond_handle *h, int nsteps, double *kernel_us)
             rc = handle_fail(h, POND_E_DEVICE, "hipEventCreate");
             break;
         }
-    int parity = h->cur;
+    int slot = h->cur;
+    const bool fused = h->lc.fused;
     for (int i = 0; rc == POND_OK && i < nsteps; ++i) {
         hipEvent_t *e = ev + 4 * i;
         LaunchCtx c1 = h->lc, c2 = h->lc;
@@ -792,17 +904,20 @@ int pond_step_timed(pond_handle *h, int nsteps, double *kernel_us)
         c1.ev_stop = e[1];
         c2.ev_start = e[2];
         c2.ev_stop = e[3];
-        if (launch_stream(c1, h->desc_d + parity, 1, h->st_tiles) != hipSuccess ||
-            launch_force_collide(c2, h->desc_d + parity, 1, h->fc_tiles) != hipSuccess)
-            rc = handle_fail(h, POND_E_DEVICE, "timed step launch");
-        parity = 1 - parity;
+        const hipError_t err = fused ? launch_step_fused(c1, h->desc_d + slot, 1, h->st_tiles)
+                                     : (launch_stream(c1, h->desc_d + slot, 1, h->st_tiles) != hipSuccess
+                                            ? hipErrorUnknown
+                                            : launch_force_collide(c2, h->desc_d + slot, 1, h->fc_tiles));
+        if (err != hipSuccess) rc = handle_fail(h, POND_E_DEVICE, "timed step launch");
+        slot = (slot + 1) % h->states();
     }
+    if (rc == POND_OK && fused) rc = enqueue_check(h, slot);
     if (rc == POND_OK && hipStreamSynchronize(h->stream) != hipSuccess) rc = handle_fail(h, POND_E_DEVICE, "sync");
     double acc[2] = {0.0, 0.0};
     for (int i = 0; rc == POND_OK && i < nsteps; ++i) {
         float a = 0.0f, b = 0.0f;
         if (hipEventElapsedTime(&a, ev[4 * i], ev[4 * i + 1]) != hipSuccess ||
-            hipEventElapsedTime(&b, ev[4 * i + 2], ev[4 * i + 3]) != hipSuccess)
+            (!fused && hipEventElapsedTime(&b, ev[4 * i + 2], ev[4 * i + 3]) != hipSuccess))
             rc = handle_fail(h, POND_E_DEVICE, "hipEventElapsedTime");
         acc[0] += a;
         acc[1] += b;
@@ -812,7 +927,7 @@ int pond_step_timed(pond_handle *h, int nsteps, double *kernel_us)
     if (rc != POND_OK) return rc;
     kernel_us[0] = 1000.0 * acc[0] / nsteps;
     kernel_us[1] = 1000.0 * acc[1] / nsteps;
-    return finish_batch(h);
+    return finish_batch(h, nsteps);
 }
 
 } // extern "C"

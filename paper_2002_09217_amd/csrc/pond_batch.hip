@@ -5,10 +5,12 @@
 //
 // Members that share (dim, precision, streaming tile shape) form a group; a batch
 // step is one launch of each step kernel per group over the concatenated tiles of
-// its members.  Two descriptor arrays per batch: array 0 holds, for every member,
-// the descriptor reading the state that was current when the arrays were built, and
-// array 1 the other one; a step alternates between them, so runs of an even number
-// of steps replay one captured HIP graph.
+// its members.  The members of a batch share the form of the step (fused, or two
+// kernels), which fixes the number of state buffers or ring slots R (3 or 2) they cycle
+// through.  R descriptor arrays per batch: array a holds, for every member, the
+// descriptor reading the state a steps after the one current when the arrays were built;
+// steps cycle through them, so runs of a multiple of R steps replay one captured HIP
+// graph.  A run of fused steps ends with the closure check of every member's last state.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -52,9 +54,13 @@ struct pond_batch {
     std::vector<int> flags_h;
     int cap = 0;                         // slots the device arrays hold
     int phase = 0;                       // descriptor array reading the current states
-    // [0]: two steps, [1]: 2 kRunPairs steps; each starting from array 0 / 1
-    hipGraphExec_t step_exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    bool fused = false;                  // form of the step of every member
+    // [0]: the short run, [1]: the long run of steps (run_length); each starting from
+    // descriptor array a
+    hipGraphExec_t step_exec[2][kFusedRing] = {};
     bool graphs_ok = true;
+    int states() const { return fused ? kFusedRing : 2; }
+    int run(int kind) const { return fused ? (kind ? kFusedRun : kFusedRing) : (kind ? 2 * kRunPairs : 2); }
 };
 
 namespace {
@@ -91,12 +97,13 @@ int rebuild(pond_batch *b)
         b->desc_d = nullptr;
         b->flags_d = nullptr;
         b->cap = 0;
-        if (hipMalloc((void **)&b->desc_d, sizeof(SlotDesc) * 2 * cap) != hipSuccess ||
+        if (hipMalloc((void **)&b->desc_d, sizeof(SlotDesc) * kFusedRing * cap) != hipSuccess ||
             hipMalloc((void **)&b->flags_d, sizeof(int) * kFlagWords * cap) != hipSuccess)
             return POND_E_NOMEM;
         b->cap = cap;
     }
-    b->desc_h.assign((size_t)2 * std::max(M, 1), SlotDesc{});
+    const int R = b->states();
+    b->desc_h.assign((size_t)R * std::max(M, 1), SlotDesc{});
     b->flags_h.assign((size_t)kFlagWords * std::max(M, 1), 0);
     int gkey = -1;
     for (int s = 0; s < M; ++s) {
@@ -108,8 +115,8 @@ int rebuild(pond_batch *b)
         }
         Group &g = b->groups.back();
         b->slot_of[i] = s;
-        for (int a = 0; a < 2; ++a) {
-            SlotDesc d = h->desc_h[(h->cur + a) % 2];
+        for (int a = 0; a < R; ++a) {
+            SlotDesc d = h->desc_h[(h->cur + a) % R];
             d.st_begin = g.st_tiles;
             d.fc_begin = g.fc_tiles;
             b->desc_h[(size_t)a * M + s] = d;
@@ -118,7 +125,7 @@ int rebuild(pond_batch *b)
         g.st_tiles += h->st_tiles;
         g.fc_tiles += h->fc_tiles;
     }
-    if (M > 0 && hipMemcpy(b->desc_d, b->desc_h.data(), sizeof(SlotDesc) * 2 * M, hipMemcpyHostToDevice) != hipSuccess)
+    if (M > 0 && hipMemcpy(b->desc_d, b->desc_h.data(), sizeof(SlotDesc) * R * M, hipMemcpyHostToDevice) != hipSuccess)
         return POND_E_DEVICE;
     b->phase = 0;
     b->dirty = false;
@@ -131,15 +138,34 @@ hipError_t enqueue_step(pond_batch *b, hipStream_t st, int arr)
     for (const Group &g : b->groups) {
         LaunchCtx c{g.dim, 0, 0, 0, g.fp32, st, g.tile};
         c.gen_eos = g.gen_eos;
+        c.fused = b->fused;
         const SlotDesc *d = b->desc_d + (size_t)arr * M + g.first;
-        hipError_t e = launch_stream(c, d, g.count, g.st_tiles);
-        if (e == hipSuccess) e = launch_force_collide(c, d, g.count, g.fc_tiles);
+        hipError_t e;
+        if (b->fused) {
+            e = launch_step_fused(c, d, g.count, g.st_tiles);
+        } else {
+            e = launch_stream(c, d, g.count, g.st_tiles);
+            if (e == hipSuccess) e = launch_force_collide(c, d, g.count, g.fc_tiles);
+        }
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-// record two steps (kind 0) or 2 kRunPairs steps (kind 1) from descriptor array `arr`
+// fused steps: the closure check of every member's state read by descriptor array `arr`
+hipError_t enqueue_check(pond_batch *b, hipStream_t st, int arr)
+{
+    const int M = (int)b->members.size();
+    for (const Group &g : b->groups) {
+        LaunchCtx c{g.dim, 0, 0, 0, g.fp32, st, g.tile};
+        c.fused = true;
+        hipError_t e = launch_collide_check(c, b->desc_d + (size_t)arr * M + g.first, g.count, g.fc_tiles);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// record a run of b->run(kind) steps from descriptor array `arr`
 bool build_step_graph(pond_batch *b, int kind, int arr)
 {
     hipGraphExec_t &exec = b->step_exec[kind][arr];
@@ -147,10 +173,7 @@ bool build_step_graph(pond_batch *b, int kind, int arr)
     hipGraph_t g = nullptr;
     if (hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
     hipError_t e = hipSuccess;
-    for (int k = 0; k < (kind ? kRunPairs : 1) && e == hipSuccess; ++k) {
-        e = enqueue_step(b, b->capture_stream, arr);
-        if (e == hipSuccess) e = enqueue_step(b, b->capture_stream, 1 - arr);
-    }
+    for (int k = 0; k < b->run(kind) && e == hipSuccess; ++k) e = enqueue_step(b, b->capture_stream, (arr + k) % b->states());
     const hipError_t ec = hipStreamEndCapture(b->capture_stream, &g);
     if (e != hipSuccess || ec != hipSuccess || !g) {
         if (g) (void)hipGraphDestroy(g);
@@ -207,6 +230,8 @@ int pond_batch_add(pond_batch *b, pond_handle *h)
     if (h->lc.dim == 3) return handle_fail(h, POND_E_INVALID, "D3Q27 lattices are stepped alone");
     if (!h->initialised || h->failed)
         return handle_fail(h, POND_E_STATE, h->failed ? "handle in error state" : "not initialised");
+    if (!b->members.empty() && h->lc.fused != b->fused)
+        return handle_fail(h, POND_E_INVALID, "the members of a batch share the form of the step (two_kernel)");
     long long st = h->st_tiles, fc = h->fc_tiles;
     for (const pond_handle *m : b->members)
         if (m->lc.dim == h->lc.dim && m->lc.fp32 == h->lc.fp32 && m->lc.stream_tile == h->lc.stream_tile) {
@@ -222,6 +247,10 @@ int pond_batch_add(pond_batch *b, pond_handle *h)
         return POND_E_NOMEM;
     }
     h->batch = b;
+    if (b->members.size() == 1 && b->fused != h->lc.fused) {
+        drop_graphs(b);
+        b->fused = h->lc.fused;
+    }
     b->dirty = true;
     return POND_OK;
 }
@@ -250,9 +279,9 @@ int pond_batch_step(pond_batch *b, int nsteps)
     if (launch_reset_slot_flags(b->stream, b->desc_d, M) != hipSuccess) return POND_E_DEVICE;
     int arr = b->phase;
     int left = nsteps;
-    // runs of 2 kRunPairs steps, then pairs; each returns to the same descriptor array
+    // long runs, then short runs; each returns to the descriptor array it starts from
     for (int kind = 1; kind >= 0 && b->graphs_ok; --kind) {
-        const int len = kind ? 2 * kRunPairs : 2;
+        const int len = b->run(kind);
         if (left < len) continue;
         if (!build_step_graph(b, kind, arr)) {
             b->graphs_ok = false;
@@ -263,8 +292,9 @@ int pond_batch_step(pond_batch *b, int nsteps)
     }
     for (; left > 0; --left) {
         if (enqueue_step(b, b->stream, arr) != hipSuccess) return POND_E_DEVICE;
-        arr = 1 - arr;
+        arr = (arr + 1) % b->states();
     }
+    if (b->fused && enqueue_check(b, b->stream, arr) != hipSuccess) return POND_E_DEVICE;
     if (launch_gather_slot_flags(b->stream, b->desc_d, M, b->flags_d) != hipSuccess) return POND_E_DEVICE;
     if (hipMemcpyAsync(b->flags_h.data(), b->flags_d, sizeof(int) * kFlagWords * M, hipMemcpyDeviceToHost,
                        b->stream) != hipSuccess ||
@@ -277,7 +307,7 @@ int pond_batch_step(pond_batch *b, int nsteps)
     keep.reserve(M);
     for (int i = 0; i < M; ++i) {
         pond_handle *h = b->members[i];
-        const int rc = handle_finish_batch(h, &b->flags_h[(size_t)kFlagWords * b->slot_of[i]]);
+        const int rc = handle_finish_batch(h, &b->flags_h[(size_t)kFlagWords * b->slot_of[i]], nsteps);
         if (rc == POND_OK) {
             keep.push_back(h);
         } else {

@@ -178,6 +178,53 @@ __device__ __forceinline__ int map_node(const Geo &g, int x, int y)
 }
 
 // ---------------------------------------------------------------------------
+// How a derived field is read at lattice position (x, y) (same rule as map_node):
+//   kSelf   the position is a node, or wraps onto one (periodic): evaluate there;
+//   kCopy   an outflow face clamps it: take the value of the clamped node (cx, cy);
+//   kGhost  an inflow face: the ghost state's value (face in *face).
+// ---------------------------------------------------------------------------
+enum { kSelf = 0, kCopy = 1, kGhost = 2 };
+template <int DIM>
+__device__ __forceinline__ int classify(const Geo &g, int x, int y, int &cx, int &cy, int &face)
+{
+    int cls = kSelf;
+    cx = x;
+    cy = y;
+    if (x < 0 || x >= g.nx) {
+        const int side = x < 0 ? 0 : 1;
+        const int bc = g.bc(0, side);
+        if (bc == kInflow) {
+            face = side;
+            return kGhost;
+        }
+        if (bc == kOutflow) {
+            cx = x < 0 ? 0 : g.nx - 1;
+            cls = kCopy;
+        }
+    }
+    if (DIM == 2 && (y < 0 || y >= g.ny)) {
+        const int side = y < 0 ? 0 : 1;
+        const int bc = g.bc(1, side);
+        if (bc == kInflow) {
+            face = 2 + side;
+            return kGhost;
+        }
+        if (bc == kOutflow) {
+            cy = y < 0 ? 0 : g.ny - 1;
+            cls = kCopy;
+        }
+    }
+    return cls;
+}
+
+// error bits of a step, with the parity of the state it read if it is the first error
+__device__ __forceinline__ void raise_error(int *flags, int bits, int parity)
+{
+    atomicOr(&flags[kFlagErr], bits);
+    atomicCAS(&flags[kFlagErrParity], 0, parity + 1);
+}
+
+// ---------------------------------------------------------------------------
 // moments of one population set about a reference velocity (rx, ry):
 // out[3m+n] = sum_{a,b} f_ab (ux - rx + s (a-1))^m (uy - ry + s (b-1))^n  (2D)
 // out[m]    = sum_a f_a (ux - rx + s (a-1))^m                              (1D)

@@ -13,8 +13,17 @@ namespace pond {
 constexpr int kRunPairs = 8;
 enum { kPeriodic = 0, kOutflow = 1, kInflow = 2 };
 
-// error bits written by the kernels into flags[0]
-enum { kErrPressure = 1, kErrNonfinite = 2, kErrHalo = 4 };
+// error bits written by the kernels into flags[0]; kErrCollideStage marks an error of
+// the closure that precedes a state's collision (fused step and its check), which makes
+// that state, not the next one, the first bad one
+enum { kErrPressure = 1, kErrNonfinite = 2, kErrHalo = 4, kErrCollideStage = 8 };
+
+// The fused step keeps the streamed states of three consecutive steps (a ring), so that
+// after an error found in the closure of a state the state before it is still intact.
+// Its graphs replay runs of kFusedRun and of kFusedRing steps, which return to the ring
+// slot they start from.
+constexpr int kFusedRing = 3;
+constexpr int kFusedRun = 15;
 
 // Inflow ghost state of one face: the equilibrium of (rho, u, T) with F = 0, as
 // populations in its own gauge plus the scalar fields the gradient stencils read.
@@ -102,6 +111,10 @@ struct SlotDesc {
     // 3D only: donor moments, Korteweg stress and thermodynamic scratch
     void *dmom;
     double *kor, *aux;
+    // fused step: streamed state read (the collision recomputed on the fly) and written;
+    // `parity` is then the ring slot of smom_src
+    const void *smom_src;
+    void *smom_dst;
 };
 
 // device buffers of one lattice
@@ -114,6 +127,9 @@ struct DevState {
     int *flags;         // kFlagWords ints
     DevParams *params;  // device copy
     void *dmom;         // 3D: donor moments, 54 planes (float with FP32 streaming)
+    // fused step: the streamed states of three consecutive steps; pop[0] and side[0]
+    // then receive the collided state for read-back (pop[1], side[1] and mom unused)
+    void *ring[kFusedRing];
 };
 
 // ---------------------------------------------------------------------------
@@ -132,6 +148,10 @@ struct LaunchCtx {
     // streaming kernels with the general equation of state (isothermal runs or a
     // non-van-der-Waals pressure); false: the van der Waals fluid with its energy
     bool gen_eos = false;
+    // fused step (one kernel per step, the state between steps is the streamed moment
+    // planes, mixed FP64/FP32 in the FP32 storage precisions); false: two kernels per
+    // step with stored populations
+    bool fused = false;
 };
 
 int stream_variants(int dim);
@@ -145,12 +165,22 @@ hipError_t launch_gather_slot_flags(hipStream_t st, const SlotDesc *slots, int n
 // step kernels over the tiles of `nslots` lattices (device descriptor array); every
 // lattice must share dim and precision with c; `tiles` is the total tile count
 hipError_t launch_stream(const LaunchCtx &c, const SlotDesc *slots, int nslots, int tiles);
+// closure and collision of the moment planes `mom` into pop_dst/side_dst (the second
+// kernel of the two-kernel step; for a fused-step lattice, the read-back of its state)
 hipError_t launch_force_collide(const LaunchCtx &c, const SlotDesc *slots, int nslots, int tiles);
+// fused step: collision of smom_src recomputed on each tile and its halo, then the
+// streaming into smom_dst; `tiles` as for launch_stream
+hipError_t launch_step_fused(const LaunchCtx &c, const SlotDesc *slots, int nslots, int tiles);
+// fused step: closure of the state in `mom` (every node), raising its errors with
+// kErrCollideStage and counting as a launch; `tiles` as for launch_force_collide
+hipError_t launch_collide_check(const LaunchCtx &c, const SlotDesc *slots, int nslots, int tiles);
 // tile counts of one lattice for the current tile shapes
 void tile_counts(const LaunchCtx &c, int *st_tiles_x, int *st_count, int *fc_tiles_x, int *fc_count);
 hipError_t launch_korteweg(const LaunchCtx &c, const DevState &s, const double *rho);
+// the streamed-state planes of the equilibrium of (rho, u_hat, T) into `mom` (FP64, or
+// mixed for a fused-step lattice in an FP32 storage precision)
 hipError_t launch_init_equilibrium(const LaunchCtx &c, const DevState &s, const double *rho,
-                                   const double *u, const double *T);
+                                   const double *u, const double *T, void *mom);
 hipError_t launch_macro(const LaunchCtx &c, const DevState &s, int cur, double *out);
 hipError_t launch_monitors(const LaunchCtx &c, const DevState &s, int cur, double *partials,
                            int nblocks, double *out);

@@ -24,8 +24,10 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include "pond_collide.h"
 #include "pond_device.h"
 #include "pond_internal.h"
+#include "pond_stream.h"
 
 namespace pond {
 
@@ -71,63 +73,10 @@ hipError_t launch_gather_slot_flags(hipStream_t st, const SlotDesc *slots, int n
     return hipGetLastError();
 }
 
-// error bits of a step, with the parity of the state it read if it is the first error
-__device__ __forceinline__ void raise_error(int *flags, int bits, int parity)
-{
-    atomicOr(&flags[kFlagErr], bits);
-    atomicCAS(&flags[kFlagErrParity], 0, parity + 1);
-}
 
 // ---------------------------------------------------------------------------
 // streaming with the predictor-corrector
 // ---------------------------------------------------------------------------
-// The 2D window of one FP64 set without its zero taps: acc[3k+l] += sum_n B_ln sum_r
-// wy_l[r] sum_m A_km sum_c wx_k[c] M_mn[r][c], for a wave in which every lane's departure
-// stencils of k = 0 and l = 0 start at window column/row 1 and those of k = 2 and l = 2
-// end at column/row 3 (the usual case: |u| < sqrt(theta)).  Same group order, one-ahead
-// LDS reads and row accumulation as the general window in k_stream.
-template <int LN, int LX>
-__device__ __forceinline__ void window2_no_zero_taps(const double *sbase, const double (&wx)[3][5],
-                                                     const double (&wy)[3][5], const double (&A)[3][3],
-                                                     const double (&Bd)[3][3], double (&acc)[9])
-{
-    constexpr int CS = 2;
-#pragma unroll
-    for (int n = 0; n < 3; ++n) {
-        auto load_group = [&](int g, double v[5]) {
-            const double *row = sbase + ((3 * (g % 3) + n) * LN + (g / 3) * LX) * CS;
-#pragma unroll
-            for (int c = 0; c < 5; ++c) v[c] = row[c * CS];
-        };
-        double Z[3], cur[5], nxt[5];
-        load_group(0, cur);
-#pragma unroll
-        for (int g = 0; g < 15; ++g) {
-            const int r = g / 3, m = g % 3;
-            if (g + 1 < 15) load_group(g + 1, nxt);
-            const double x0 = wx[0][1] * cur[1] + wx[0][2] * cur[2] + wx[0][3] * cur[3] + wx[0][4] * cur[4];
-            const double x1 =
-                wx[1][0] * cur[0] + wx[1][1] * cur[1] + wx[1][2] * cur[2] + wx[1][3] * cur[3] + wx[1][4] * cur[4];
-            const double x2 = wx[2][0] * cur[0] + wx[2][1] * cur[1] + wx[2][2] * cur[2] + wx[2][3] * cur[3];
-            Z[0] = m == 0 ? A[0][0] * x0 : Z[0] + A[0][m] * x0;
-            Z[1] = m == 0 ? A[1][0] * x1 : Z[1] + A[1][m] * x1;
-            Z[2] = m == 0 ? A[2][0] * x2 : Z[2] + A[2][m] * x2;
-            if (m == 2) {
-#pragma unroll
-                for (int l = 0; l < 3; ++l) {
-                    if ((l == 0 && r == 0) || (l == 2 && r == 4)) continue;
-                    const double C = Bd[l][n] * wy[l][r];
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) acc[3 * k + l] += C * Z[k];
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < 5; ++c) cur[c] = nxt[c];
-        }
-        __builtin_amdgcn_sched_barrier(0);
-    }
-}
-
 // Two lanes per receiver: lane 2 i + set works on population set `set` (0 = f, 1 = g)
 // of receiver i; the pass moments are exchanged between the two lanes.  Blocks of at
 // most 256 lanes are compiled for three waves per SIMD, larger ones for two.
@@ -291,186 +240,10 @@ __global__ void __launch_bounds__(2 * TX *TY, 2 * TX *TY <= 256 ? 3 : 2)
     double rho = 0.0;
     int err = 0;
     const LdsT *sbase = &lds[wbase * 2 + myset];
-    // When the grid is one workgroup per CU (512 lanes, two waves per SIMD), the SIMD
-    // issues for the older wave first, the younger one falls behind and finishes its
-    // last pass alone, with nothing to hide its latencies.  Favouring the younger wave
-    // in the first pass lets both finish at about the same time.
-    const int young = __builtin_amdgcn_readfirstlane((tid >> 6) >= NT / 128 && NT == 512 && gridDim.x <= kCUs ? 1 : 0);
-    for (int pass = 0; pass < P.n_pass; ++pass) {
-        if (pass == 0 && young) __builtin_amdgcn_s_setprio(1);
-        else __builtin_amdgcn_s_setprio(0);
-        const double s = sqrt(th);
-        LdsT wx[3][5], wy[3][5];
-        err |= window_weights<LdsT>(Ux, s, dt, wx);
-        if (DIM == 2) err |= window_weights<LdsT>(Uy, s, dt, wy);
-        double Ad[3][3], Bd[3][3];
-        lagrange_coeffs(Ux - rx, s, Ad);
-        if (DIM == 2) lagrange_coeffs(Uy - ry, s, Bd);
-        LdsT A[3][3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int m = 0; m < 3; ++m) A[k][m] = (LdsT)Ad[k][m];
+    err |= stream_passes<DIM, LdsT, LN, LX, NT, GEN>(P, sbase, tid, myset, rx, ry, refR0, refR1, refT, Ux, Uy, th,
+                                                     Fpx, Fpy, pq, rho, sUx, sUy, sS);
 
-        // populations of this set in the receiver gauge, one per direction:
-        //   f_kl = sum_n B_ln sum_r wy_l[r] sum_m A_km sum_c wx_k[c] M_mn[r][c]
-        double acc[Q];
-        if constexpr (kDevI) {
-            // the reference part (see the fill); the window adds the deviations
-            const double R = myset == 0 ? refR0 : refR1;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const double ak = R * (Ad[k][0] + refT * Ad[k][2]);
-                if (DIM == 2) {
-#pragma unroll
-                    for (int l = 0; l < 3; ++l) acc[3 * k + l] = ak * (Bd[l][0] + refT * Bd[l][2]);
-                } else {
-                    acc[k] = ak;
-                }
-            }
-        } else {
-#pragma unroll
-            for (int q = 0; q < Q; ++q) acc[q] = 0.0;
-        }
-        // FP64 windows in eight-wave workgroups (two waves per SIMD, registers to spare)
-        // also carry the variant without zero taps, taken by every wave that can
-        bool no_zero_taps = false;
-        if constexpr (DIM == 2 && NT == 512 && sizeof(LdsT) == 8) {
-            if (__all(wx[0][0] == 0.0 && wx[2][4] == 0.0 && wy[0][0] == 0.0 && wy[2][4] == 0.0)) {
-                window2_no_zero_taps<LN, LX>(sbase, wx, wy, A, Bd, acc);
-                no_zero_taps = true;
-            }
-        }
-        if (DIM == 2 && !no_zero_taps) {
-#pragma unroll
-            for (int n = 0; n < 3; ++n) {
-                // Row r of field (m, n) is group g = 3 r + m of five window values; each
-                // group is read from LDS one group ahead of its use, so that the read
-                // latency overlaps the arithmetic of the group before.
-                auto load_group = [&](int g, LdsT v[5]) {
-                    const LdsT *row = sbase + ((3 * (g % 3) + n) * LN + (g / 3) * LX) * CS;
-#pragma unroll
-                    for (int c = 0; c < 5; ++c) v[c] = row[c * CS];
-                };
-                // FP64 windows add each row straight into acc with the weights
-                // B_ln wy_l[r] (no I registers); FP32 windows sum the rows in FP32 first
-                constexpr bool kRowsToAcc = sizeof(LdsT) == 8;
-                LdsT I[3][3]; // sum_r wy_l[r] Z_k[r]
-                LdsT Z[3];    // sum_m A_km (x-interpolated M_mn) of the current row
-                LdsT cur[5], nxt[5];
-                load_group(0, cur);
-#pragma unroll
-                for (int g = 0; g < 15; ++g) {
-                    const int r = g / 3, m = g % 3;
-                    if (g + 1 < 15) load_group(g + 1, nxt);
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        const LdsT xk = wx[k][0] * cur[0] + wx[k][1] * cur[1] + wx[k][2] * cur[2] +
-                                        wx[k][3] * cur[3] + wx[k][4] * cur[4];
-                        Z[k] = m == 0 ? A[k][m] * xk : Z[k] + A[k][m] * xk;
-                    }
-                    if (m == 2 && kRowsToAcc) {
-                        double C[3];
-#pragma unroll
-                        for (int l = 0; l < 3; ++l) C[l] = Bd[l][n] * (double)wy[l][r];
-#pragma unroll
-                        for (int k = 0; k < 3; ++k)
-#pragma unroll
-                            for (int l = 0; l < 3; ++l) acc[3 * k + l] += C[l] * (double)Z[k];
-                    } else if (m == 2) {
-#pragma unroll
-                        for (int k = 0; k < 3; ++k)
-#pragma unroll
-                            for (int l = 0; l < 3; ++l) I[k][l] = r == 0 ? wy[l][r] * Z[k] : I[k][l] + wy[l][r] * Z[k];
-                    }
-#pragma unroll
-                    for (int c = 0; c < 5; ++c) cur[c] = nxt[c];
-                }
-                if (!kRowsToAcc) {
-#pragma unroll
-                    for (int k = 0; k < 3; ++k)
-#pragma unroll
-                        for (int l = 0; l < 3; ++l) acc[3 * k + l] += Bd[l][n] * (double)I[k][l];
-                }
-                // keep the three n-blocks apart: the scheduler would otherwise hoist the
-                // loads of all of them and run out of registers
-                __builtin_amdgcn_sched_barrier(0);
-            }
-        } else if (DIM == 1) {
-#pragma unroll
-            for (int m = 0; m < 3; ++m) {
-                const LdsT *row = sbase + m * LN * CS;
-                const LdsT v0 = row[0], v1 = row[CS], v2 = row[2 * CS], v3 = row[3 * CS], v4 = row[4 * CS];
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    const LdsT xk = wx[k][0] * v0 + wx[k][1] * v1 + wx[k][2] * v2 + wx[k][3] * v3 + wx[k][4] * v4;
-                    acc[k] += Ad[k][m] * (double)xk;
-                }
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < Q; ++q) pq[q] = acc[q];
-
-        // moments of the streamed populations (eq. 2) and the EoS closure: each lane sums
-        // its own set; the partner lane supplies the other sums
-        double s0 = 0.0, sx = 0.0, sy = 0.0;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const double cx = DIM == 2 ? (double)(q / 3 - 1) : (double)(q - 1);
-            const double cy = DIM == 2 ? (double)(q % 3 - 1) : 0.0;
-            s0 += pq[q];
-            sx += pq[q] * (Ux + s * cx);
-            if (DIM == 2) sy += pq[q] * (Uy + s * cy);
-        }
-        const double o0 = __shfl_xor(s0, 1, 64);
-        const double ox = __shfl_xor(sx, 1, 64);
-        const double oy = DIM == 2 ? __shfl_xor(sy, 1, 64) : 0.0;
-        const double r0 = myset == 0 ? s0 : o0;
-        const double jx = myset == 0 ? sx : ox;
-        const double jy = myset == 0 ? sy : oy;
-        const double G2 = myset == 0 ? o0 : s0;
-        rho = r0;
-        // one reciprocal of rho serves every quotient by it (FP64 division is a
-        // long dependent sequence on this hardware)
-        const double i_rho = 1.0 / rho;
-        const double E = 0.5 * G2 * i_rho;
-        const double ux = jx * i_rho;
-        const double uy = DIM == 2 ? jy * i_rho : 0.0;
-        const double uhx = ux + 0.5 * Fpx * dt * i_rho;
-        const double uhy = DIM == 2 ? uy + 0.5 * Fpy * dt * i_rho : 0.0;
-        const double e = E - 0.5 * (uhx * uhx + uhy * uhy);
-        const double T = eos_T_of_e<GEN>(P, rho, e);
-        const double p = eos_p<GEN>(P, rho, T);
-        err |= eos_bad<GEN>(P, rho, p);
-        sUx = Ux;
-        sUy = Uy;
-        sS = s;
-        Ux = ux;
-        Uy = uy;
-        th = p * i_rho * kInvTL;
-    }
-
-    // streamed state for the collision: rho, u and central moments about u
-    double mq[NF];
-    moments_about<DIM>(pq, sUx - Ux, sUy - Uy, sS, mq);
-    if (myset == 0) {
-        mom[(size_t)L::kRho * N + node] = rho;
-        mom[(size_t)L::kUx * N + node] = Ux;
-        if constexpr (DIM == 2) {
-            mom[(size_t)L::kUy * N + node] = Uy;
-            mom[(size_t)(L::kF + 0) * N + node] = mq[4]; // (1,1)
-            mom[(size_t)(L::kF + 1) * N + node] = mq[6]; // (2,0)
-            mom[(size_t)(L::kF + 2) * N + node] = mq[2]; // (0,2)
-            mom[(size_t)(L::kF + 3) * N + node] = mq[7]; // (2,1)
-            mom[(size_t)(L::kF + 4) * N + node] = mq[5]; // (1,2)
-            mom[(size_t)(L::kF + 5) * N + node] = mq[8]; // (2,2)
-        } else {
-            mom[(size_t)L::kF * N + node] = mq[2];
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < NF; ++i) mom[(size_t)(L::kG + i) * N + node] = mq[i];
-    }
+    store_streamed<DIM, false>(S.mom, N, node, myset, pq, rho, Ux, Uy, sUx, sUy, sS);
     if (err) raise_error(flags, err, S.parity);
 }
 
@@ -628,45 +401,6 @@ __device__ __forceinline__ void korteweg_force_at(const PT &P, const double *__r
     Fy = DIM == 2 ? -dvy / kTL : 0.0;
 }
 
-// ---------------------------------------------------------------------------
-// How a derived field is read at lattice position (x, y) (same rule as map_node):
-//   kSelf   the position is a node, or wraps onto one (periodic): evaluate there;
-//   kCopy   an outflow face clamps it: take the value of the clamped node (cx, cy);
-//   kGhost  an inflow face: the ghost state's value (face in *face).
-// ---------------------------------------------------------------------------
-enum { kSelf = 0, kCopy = 1, kGhost = 2 };
-template <int DIM>
-__device__ __forceinline__ int classify(const Geo &g, int x, int y, int &cx, int &cy, int &face)
-{
-    int cls = kSelf;
-    cx = x;
-    cy = y;
-    if (x < 0 || x >= g.nx) {
-        const int side = x < 0 ? 0 : 1;
-        const int bc = g.bc(0, side);
-        if (bc == kInflow) {
-            face = side;
-            return kGhost;
-        }
-        if (bc == kOutflow) {
-            cx = x < 0 ? 0 : g.nx - 1;
-            cls = kCopy;
-        }
-    }
-    if (DIM == 2 && (y < 0 || y >= g.ny)) {
-        const int side = y < 0 ? 0 : 1;
-        const int bc = g.bc(1, side);
-        if (bc == kInflow) {
-            face = 2 + side;
-            return kGhost;
-        }
-        if (bc == kOutflow) {
-            cy = y < 0 ? 0 : g.ny - 1;
-            cls = kCopy;
-        }
-    }
-    return cls;
-}
 
 // ---------------------------------------------------------------------------
 // Fused non-local closure and collision of one tile (eqs. 9, 16-22; App. F):
@@ -684,23 +418,29 @@ template <int DIM> struct CollideTile;
 template <> struct CollideTile<2> { static constexpr int TX = 16, TY = 8; };
 template <> struct CollideTile<1> { static constexpr int TX = 256, TY = 1; };
 
-enum { kThFx = 0, kThFy, kThT, kThH, kThMu, kThKc, kThP, kThFields };
+// MODE of the closure-and-collision kernel: store the collided state (the second kernel of
+// the two-kernel step, or the read-back of a fused-step state), or only evaluate the
+// thermodynamic closure of every node and raise its admissibility errors (the check of the
+// last state of a run of fused steps)
+enum { kCollideStore = 0, kCollideCheck = 1 };
 
-template <int DIM, typename PopT, int TX, int TY>
+template <int DIM, typename PopT, bool MIXED, int MODE, int TX, int TY>
 __global__ void __launch_bounds__(2 * TX *TY)
     k_force_collide(const SlotDesc *__restrict__ slots, int nslots)
 {
     using L = Layout<DIM>;
+    using MIO = MomIO<DIM, MIXED>;
     constexpr int Q = L::Q, NF = L::NF;
     constexpr int RX = TX + 6, RY = DIM == 2 ? TY + 6 : 1; // rho region (halo 3)
     constexpr int KX = TX + 4, KY = DIM == 2 ? TY + 4 : 1; // K region (halo 2)
     constexpr int HX = TX + 2, HY = DIM == 2 ? TY + 2 : 1; // thermo region (halo 1)
+    constexpr int HS = HX * HY;                            // field stride of s_th
     constexpr int NN = TX * TY;                            // nodes of the tile
     constexpr int NT = 2 * NN;
     static_assert(NN % 64 == 0, "each population set must fill whole waves");
     __shared__ double s_rho[RX * RY];
     __shared__ double s_K[3][KX * KY];
-    __shared__ double s_th[kThFields][HX * HY];
+    __shared__ double s_th[kThFields * HS];
     __shared__ int abort_block;
 
     // lattice and tile of this workgroup
@@ -708,7 +448,7 @@ __global__ void __launch_bounds__(2 * TX *TY)
     const SlotDesc &S = slots[find_slot<false>(slots, nslots, gtile)];
     const int tile = gtile - S.fc_begin;
     int *__restrict__ flags = S.flags;
-    const POND_GLOBAL double *__restrict__ mom = (const POND_GLOBAL double *)S.mom;
+    const void *mom = S.mom;
     POND_GLOBAL PopT *__restrict__ fout = (POND_GLOBAL PopT *)S.pop_dst;
     POND_GLOBAL double *__restrict__ side_out = (POND_GLOBAL double *)S.side_dst;
 
@@ -747,14 +487,14 @@ __global__ void __launch_bounds__(2 * TX *TY)
     // and the velocity and energy of its thermo-stage positions (used in stage 3).
     constexpr int NOWN = DIM == 2 ? 3 : 2;           // rho, u
     double own[NOWN], oset[NF];
-    if (inside) {
+    if (MODE == kCollideStore && inside) {
 #pragma unroll
-        for (int i = 0; i < NOWN; ++i) own[i] = mom[i * N + node];
+        for (int i = 0; i < NOWN; ++i) own[i] = MIO::load(mom, N, node, i);
         // NF consecutive planes from the set's first one (the f lanes read the stored f
         // moments and a few g planes they ignore): no branch, so no wait between the sets
         const int base = set == 0 ? L::kF : L::kG;
 #pragma unroll
-        for (int i = 0; i < NF; ++i) oset[i] = mom[(base + i) * N + node];
+        for (int i = 0; i < NF; ++i) oset[i] = MIO::load(mom, N, node, base + i);
     }
     constexpr int HITEMS = (HX * HY + NT - 1) / NT;
     double pre_u[HITEMS][3];
@@ -769,9 +509,9 @@ __global__ void __launch_bounds__(2 * TX *TY)
             if (classify<DIM>(geo, gx, gy, cx, cy, face) == kSelf) {
                 const int nb = map_node<DIM>(geo, gx, DIM == 2 ? gy : 0);
                 pre_nb[j] = nb;
-                pre_u[j][0] = mom[L::kUx * N + nb];
-                pre_u[j][1] = DIM == 2 ? mom[L::kUy * N + nb] : 0.0;
-                pre_u[j][2] = mom[L::kG * N + nb];
+                pre_u[j][0] = MIO::load(mom, N, nb, L::kUx);
+                pre_u[j][1] = DIM == 2 ? MIO::load(mom, N, nb, L::kUy) : 0.0;
+                pre_u[j][2] = MIO::load(mom, N, nb, L::kG);
             }
         }
     }
@@ -787,7 +527,7 @@ __global__ void __launch_bounds__(2 * TX *TY)
             if (li < RX * RY) {
                 const int gx = x0 - 3 + li % RX, gy = y0 - 3 + li / RX;
                 const int nb = map_node<DIM>(geo, gx, DIM == 2 ? gy : 0);
-                pre_rho[j] = nb >= 0 ? mom[L::kRho * N + nb] : P.ghost[-nb - 1].rho;
+                pre_rho[j] = nb >= 0 ? MIO::load(mom, N, nb, L::kRho) : P.ghost[-nb - 1].rho;
             }
         }
     }
@@ -804,32 +544,17 @@ __global__ void __launch_bounds__(2 * TX *TY)
         if (tid == 0) abort_block = err_before;
         __syncthreads();
         if (abort_block != 0) return;
-        // stage 2: K = -kappa (rho lap rho + |grad rho|^2/2) I + kappa grad rho grad rho
+        // stage 2: Korteweg stress on the K region
         for (int li = tid; li < KX * KY; li += NT) {
             const int kx = li % KX, ky = li / KX;
             int cx, cy, face;
             const int cls = classify<DIM>(geo, x0 - 2 + kx, y0 - 2 + ky, cx, cy, face);
             if (cls == kSelf) {
-                const int rb = (DIM == 2 ? (ky + 1) * RX : 0) + kx + 1;
-                const double r0 = s_rho[rb];
-                double gx = 0.0, gy = 0.0, lap = 0.0;
-#pragma unroll
-                for (int q = 0; q < Q; ++q) {
-                    const int ex = DIM == 2 ? q / 3 - 1 : q - 1;
-                    const int ey = DIM == 2 ? q % 3 - 1 : 0;
-                    const double w = DIM == 2 ? kW1[q / 3] * kW1[q % 3] : kW1[q];
-                    const double rq = s_rho[rb + ex + ey * RX];
-                    gx += w * (double)ex * rq;
-                    gy += w * (double)ey * rq;
-                    lap += w * (rq - r0);
-                }
-                gx *= kInvTL;
-                gy *= kInvTL;
-                lap *= 2.0 * kInvTL;
-                const double iso = -P.kappa * (r0 * lap + 0.5 * (gx * gx + gy * gy));
-                s_K[0][li] = iso + P.kappa * gx * gx;
-                s_K[1][li] = P.kappa * gx * gy;
-                s_K[2][li] = DIM == 2 ? iso + P.kappa * gy * gy : 0.0;
+                double K[3];
+                korteweg_stress<DIM>(s_rho, (DIM == 2 ? (ky + 1) * RX : 0) + kx + 1, RX, P.kappa, K);
+                s_K[0][li] = K[0];
+                s_K[1][li] = K[1];
+                s_K[2][li] = K[2];
             } else if (cls == kGhost) {
                 s_K[0][li] = s_K[1][li] = s_K[2][li] = 0.0; // uniform inflow state
             }
@@ -862,46 +587,27 @@ __global__ void __launch_bounds__(2 * TX *TY)
         const int cls = classify<DIM>(geo, gx, gy, cx, cy, face);
         if (cls == kSelf) {
             double Fx = 0.0, Fy = 0.0;
-            if (force) {
-                const int kb = (DIM == 2 ? (hy + 1) * KX : 0) + hx + 1;
-                double dvx = 0.0, dvy = 0.0;
-#pragma unroll
-                for (int q = 0; q < Q; ++q) {
-                    const int ex = DIM == 2 ? q / 3 - 1 : q - 1;
-                    const int ey = DIM == 2 ? q % 3 - 1 : 0;
-                    const double w = DIM == 2 ? kW1[q / 3] * kW1[q % 3] : kW1[q];
-                    const int k = kb + ex + ey * KX;
-                    dvx += w * (s_K[0][k] * (double)ex + s_K[1][k] * (double)ey);
-                    dvy += w * (s_K[1][k] * (double)ex + s_K[2][k] * (double)ey);
-                }
-                Fx = -dvx * kInvTL;
-                Fy = DIM == 2 ? -dvy * kInvTL : 0.0;
-            }
+            if (force)
+                korteweg_force<DIM>(s_K[0], s_K[1], s_K[2], (DIM == 2 ? (hy + 1) * KX : 0) + hx + 1, KX, Fx, Fy);
             const int nb = pre_nb[j];
-            const double rho = force ? s_rho[(DIM == 2 ? (hy + 2) * RX : 0) + hx + 2] : mom[L::kRho * N + nb];
-            const double h_r = 0.5 / rho;
-            const double E = pre_u[j][2] * h_r;
-            const double uhx = pre_u[j][0] + Fx * dt * h_r;
-            const double uhy = DIM == 2 ? pre_u[j][1] + Fy * dt * h_r : 0.0;
-            const double e = E - 0.5 * (uhx * uhx + uhy * uhy);
-            const double T = eos_T_of_e(P, rho, e);
-            const double p = eos_p(P, rho, T);
-            err |= eos_bad(P, rho, p);
-            const double mu = visc * p;
-            s_th[kThFx][li] = Fx;
-            s_th[kThFy][li] = Fy;
-            s_th[kThT][li] = T;
-            s_th[kThH][li] = e + 2.0 * p * h_r;
-            s_th[kThMu][li] = mu;
-            s_th[kThKc][li] = P.k_scale * mu * P.Cp_ig;
-            s_th[kThP][li] = p;
+            const double rho = force ? s_rho[(DIM == 2 ? (hy + 2) * RX : 0) + hx + 2] : MIO::load(mom, N, nb, L::kRho);
+            err |= thermo_state<DIM>(P, rho, pre_u[j][0], pre_u[j][1], pre_u[j][2], Fx, Fy, visc, s_th, HS, li);
         } else if (cls == kGhost) {
             const POND_GLOBAL GhostFace &G = P.ghost[face];
-            s_th[kThT][li] = G.T;
-            s_th[kThH][li] = G.h;
-            s_th[kThMu][li] = G.mu;
-            s_th[kThKc][li] = G.kc;
+            s_th[kThT * HS + li] = G.T;
+            s_th[kThH * HS + li] = G.h;
+            s_th[kThMu * HS + li] = G.mu;
+            s_th[kThKc * HS + li] = G.kc;
         }
+    }
+    if (MODE == kCollideCheck) {
+        // the closure of the state is the check: count the launch, report the errors
+        if (!force && tid == 0) abort_block = err_before;
+        if (!force) __syncthreads();
+        if (abort_block != 0) return;
+        if (tid == 0 && tile == 0 && err_before == 0) atomicAdd(&flags[kFlagSteps], 1);
+        if (err) raise_error(flags, err | kErrCollideStage, S.parity);
+        return;
     }
     if (!force && tid == 0) abort_block = err_before;
     __syncthreads();
@@ -913,7 +619,7 @@ __global__ void __launch_bounds__(2 * TX *TY)
             if (classify<DIM>(geo, x0 - 1 + hx, y0 - 1 + hy, cx, cy, face) == kCopy) {
                 const int src = (cx - (x0 - 1)) + (DIM == 2 ? (cy - (y0 - 1)) * HX : 0);
 #pragma unroll
-                for (int f = 0; f < kThFields; ++f) s_th[f][li] = s_th[f][src];
+                for (int f = 0; f < kThFields; ++f) s_th[f * HS + li] = s_th[f * HS + src];
             }
         }
         __syncthreads();
@@ -926,71 +632,16 @@ __global__ void __launch_bounds__(2 * TX *TY)
     const double rho = own[L::kRho];
     const double i_rho = 1.0 / rho;
     const double u[2] = {own[L::kUx], DIM == 2 ? own[L::kUy] : 0.0};
-    const double F[2] = {s_th[kThFx][hb], DIM == 2 ? s_th[kThFy][hb] : 0.0};
-    const double p = s_th[kThP][hb];
+    const double F[2] = {s_th[kThFx * HS + hb], DIM == 2 ? s_th[kThFy * HS + hb] : 0.0};
+    const double p = s_th[kThP * HS + hb];
     const double theta = p * i_rho * kInvTL;
     const double s = sqrt(theta);
 
-    // this set's streamed populations in the collision gauge (u, theta) from their
-    // central moments
-    double mc[NF];
+    // this set's streamed populations in the collision gauge (u, theta)
+    double pop[Q], post[Q];
+    pops_from_central<DIM>(set, rho, oset, s, pop);
     if (set == 0) {
-        if (DIM == 2) {
-            mc[0] = rho;
-            mc[1] = 0.0; // (0,1): zero about u
-            mc[3] = 0.0; // (1,0)
-            mc[4] = oset[0];
-            mc[6] = oset[1];
-            mc[2] = oset[2];
-            mc[7] = oset[3];
-            mc[5] = oset[4];
-            mc[8] = oset[5];
-        } else {
-            mc[0] = rho;
-            mc[1] = 0.0;
-            mc[2] = oset[0];
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < NF; ++i) mc[i] = oset[i];
-    }
-    double A[3][3];
-    lagrange_coeffs(0.0, s, A);
-    double pop[Q];
-    if (DIM == 2) {
-        // separable: first along y (index n -> l), then along x (m -> k)
-        double tt[3][3];
-#pragma unroll
-        for (int m = 0; m < 3; ++m)
-#pragma unroll
-            for (int l = 0; l < 3; ++l)
-                tt[m][l] = A[l][0] * mc[3 * m] + A[l][1] * mc[3 * m + 1] + A[l][2] * mc[3 * m + 2];
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int l = 0; l < 3; ++l) pop[3 * k + l] = A[k][0] * tt[0][l] + A[k][1] * tt[1][l] + A[k][2] * tt[2][l];
-    } else {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) pop[k] = A[k][0] * mc[0] + A[k][1] * mc[1] + A[k][2] * mc[2];
-    }
-
-    if (set == 0) {
-        // f: BGK towards rho W plus the force source (eqs. 16-17)
-        const double i_theta = 1.0 / theta;
-        const double i_s = s * i_theta;
-        double sx[3], sy[3] = {0.0, 0.0, 0.0};
-        source_axis(F[0] * dt * i_rho, i_theta, i_s, sx);
-        if (DIM == 2) source_axis(F[1] * dt * i_rho, i_theta, i_s, sy);
-        double post[Q];
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int k = DIM == 2 ? q / 3 : q;
-            const int l = DIM == 2 ? q % 3 : 1;
-            const double wk = kW1[k], wl = DIM == 2 ? kW1[l] : 1.0;
-            const double Sq = DIM == 2 ? rho * (wk * sy[l] + sx[k] * wl + sx[k] * sy[l]) : rho * sx[k];
-            const double feq = rho * (wk * wl);
-            post[q] = pop[q] + P.omega * (feq - pop[q]) + Sq;
-        }
+        collide_f<DIM>(P, rho, i_rho, F, theta, s, pop, post);
         store_set<DIM, PopT>(fout, N, node, 0, post);
         side_out[kSideUx * N + node] = u[0];
         side_out[kSideTh * N + node] = theta;
@@ -1001,102 +652,52 @@ __global__ void __launch_bounds__(2 * TX *TY)
         }
         return;
     }
-
-    // heat-flux correction M0 = 2 div(-mu grad h + k grad T), flux form (eq. 9)
-    double M0 = 0.0;
-    if (P.k_scale >= 0.0) {
-        const double T0 = s_th[kThT][hb], h0 = s_th[kThH][hb];
-        const double m0 = s_th[kThMu][hb], k0 = s_th[kThKc][hb];
-        double acc = 0.0;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int ex = DIM == 2 ? q / 3 - 1 : q - 1;
-            const int ey = DIM == 2 ? q % 3 - 1 : 0;
-            const double w = DIM == 2 ? kW1[q / 3] * kW1[q % 3] : kW1[q];
-            const int k = hb + ex + ey * HX;
-            const double kmid = 0.5 * (s_th[kThKc][k] + k0);
-            const double mmid = 0.5 * (s_th[kThMu][k] + m0);
-            acc += w * (kmid * (s_th[kThT][k] - T0) - mmid * (s_th[kThH][k] - h0));
-        }
-        M0 = 2.0 * (2.0 * kInvTL) * acc;
-    }
-
-    // g: BGK towards the force-extended equilibrium plus (g~ + phi) dt (eqs. 19-22)
-    const double i_p = 1.0 / p;
-    const double E = 0.5 * oset[0] * i_rho;
-    const double uh[2] = {u[0] + 0.5 * F[0] * dt * i_rho, DIM == 2 ? u[1] + 0.5 * F[1] * dt * i_rho : 0.0};
-    const double Pr = p * i_rho;
-    const double H = E + Pr;
-    const double dt_Pr = dt * rho * i_p;                   // dt / Pr
-    double X[2][2], M[2], Nm[2][2];
-#pragma unroll
-    for (int a = 0; a < DIM; ++a)
-#pragma unroll
-        for (int b = 0; b < DIM; ++b)
-            X[a][b] = uh[a] * F[b] + F[a] * uh[b] + 0.5 * dt * F[a] * F[b] * E * i_p;
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        double xu = 0.0;
-#pragma unroll
-        for (int b = 0; b < DIM; ++b) xu += X[a][b] * u[b];
-        M[a] = dt_Pr * (F[a] * H - xu);
-    }
-#pragma unroll
-    for (int a = 0; a < DIM; ++a)
-#pragma unroll
-        for (int b = 0; b < DIM; ++b) Nm[a][b] = (a == b ? rho : 0.0) + 0.5 * dt_Pr * X[a][b];
-    double work = 0.0;
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) work += 2.0 * uh[a] * F[a];
-    const double c_uc = 0.5 * kInvTL * rho * i_p;          // rho / (2 p T_L)
-    const double c_v2 = 0.5 * rho * i_p;                   // rho / (2 p)
-    double post[Q];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const double c[2] = {DIM == 2 ? (double)(q / 3 - 1) : (double)(q - 1),
-                             DIM == 2 ? (double)(q % 3 - 1) : 0.0};
-        const double wq = DIM == 2 ? kW1[q / 3] * kW1[q % 3] : kW1[q];
-        double v[2], t1 = 0.0, t2 = 0.0, uc = 0.0, v2 = 0.0;
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            v[a] = u[a] + s * c[a];
-            uc += u[a] * c[a];
-            v2 += v[a] * v[a];
-        }
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) t1 += M[a] * (v[a] - u[a]);
-#pragma unroll
-        for (int a = 0; a < DIM; ++a)
-#pragma unroll
-            for (int b = 0; b < DIM; ++b) t2 += Nm[a][b] * (v[a] * v[b] - (a == b ? Pr : 0.0) - u[a] * u[b]);
-        const double geq = wq * (2.0 * rho * E + t1 + t2);
-        const double psi = wq * (1.0 + c_uc * uc * uc - c_v2 * v2 + 0.5 * (double)DIM);
-        post[q] = pop[q] + P.omega * (geq - pop[q]) + (M0 + work) * psi * dt;
-    }
+    const double M0 = heat_correction<DIM>(P, s_th, HS, hb, HX);
+    collide_g<DIM>(P, rho, i_rho, u, F, p, s, oset[0], M0, pop, post);
     store_set<DIM, PopT>(fout, N, node, 1, post);
 }
 
-template <int DIM, typename PopT>
+template <int DIM, typename PopT, bool MIXED, int MODE>
 static hipError_t launch_force_collide_t(const LaunchCtx &c, const SlotDesc *slots, int nslots, int tiles)
 {
     constexpr int TX = CollideTile<DIM>::TX, TY = CollideTile<DIM>::TY;
     if (c.ev_start)
-        hipExtLaunchKernelGGL((k_force_collide<DIM, PopT, TX, TY>), dim3(tiles), dim3(2 * TX * TY), 0, c.st,
-                              c.ev_start, c.ev_stop, 0, slots, nslots);
+        hipExtLaunchKernelGGL((k_force_collide<DIM, PopT, MIXED, MODE, TX, TY>), dim3(tiles), dim3(2 * TX * TY), 0,
+                              c.st, c.ev_start, c.ev_stop, 0, slots, nslots);
     else
-        hipLaunchKernelGGL((k_force_collide<DIM, PopT, TX, TY>), dim3(tiles), dim3(2 * TX * TY), 0, c.st, slots,
-                           nslots);
+        hipLaunchKernelGGL((k_force_collide<DIM, PopT, MIXED, MODE, TX, TY>), dim3(tiles), dim3(2 * TX * TY), 0,
+                           c.st, slots, nslots);
     return hipGetLastError();
 }
 
+template <int DIM, bool MIXED, int MODE>
+static hipError_t launch_force_collide_d(const LaunchCtx &c, const SlotDesc *slots, int nslots, int tiles)
+{
+    return c.fp32 ? launch_force_collide_t<DIM, float, MIXED, MODE>(c, slots, nslots, tiles)
+                  : launch_force_collide_t<DIM, double, MIXED, MODE>(c, slots, nslots, tiles);
+}
+
+// The two-kernel step reads FP64 moment planes; the fused step's states are read back
+// (and checked) from its moment planes, mixed in the FP32 storage precisions.
 hipError_t launch_force_collide(const LaunchCtx &c, const SlotDesc *slots, int nslots, int tiles)
 {
     if (c.dim == 3) return launch_collide3(c, slots);
+    const bool mixed = c.fused && c.fp32;
     if (c.dim == 2)
-        return c.fp32 ? launch_force_collide_t<2, float>(c, slots, nslots, tiles)
-                      : launch_force_collide_t<2, double>(c, slots, nslots, tiles);
-    return c.fp32 ? launch_force_collide_t<1, float>(c, slots, nslots, tiles)
-                  : launch_force_collide_t<1, double>(c, slots, nslots, tiles);
+        return mixed ? launch_force_collide_d<2, true, kCollideStore>(c, slots, nslots, tiles)
+                     : launch_force_collide_d<2, false, kCollideStore>(c, slots, nslots, tiles);
+    return mixed ? launch_force_collide_d<1, true, kCollideStore>(c, slots, nslots, tiles)
+                 : launch_force_collide_d<1, false, kCollideStore>(c, slots, nslots, tiles);
+}
+
+hipError_t launch_collide_check(const LaunchCtx &c, const SlotDesc *slots, int nslots, int tiles)
+{
+    const bool mixed = c.fp32 != 0;
+    if (c.dim == 2)
+        return mixed ? launch_force_collide_t<2, float, true, kCollideCheck>(c, slots, nslots, tiles)
+                     : launch_force_collide_t<2, double, false, kCollideCheck>(c, slots, nslots, tiles);
+    return mixed ? launch_force_collide_t<1, float, true, kCollideCheck>(c, slots, nslots, tiles)
+                 : launch_force_collide_t<1, double, false, kCollideCheck>(c, slots, nslots, tiles);
 }
 
 void tile_counts(const LaunchCtx &c, int *st_tiles_x, int *st_count, int *fc_tiles_x, int *fc_count)
@@ -1120,13 +721,14 @@ void tile_counts(const LaunchCtx &c, int *st_tiles_x, int *st_count, int *fc_til
 // written as the streamed-state moments so that the regular closure and collision
 // kernels turn it into the stored populations
 // ---------------------------------------------------------------------------
-template <int DIM>
+template <int DIM, bool MIXED>
 __global__ void k_init_equilibrium(const DevParams *__restrict__ Pp, const double *__restrict__ rho_in,
                                    const double *__restrict__ u_in, const double *__restrict__ T_in,
-                                   const double *__restrict__ kor, double *__restrict__ mom,
+                                   const double *__restrict__ kor, void *__restrict__ mom,
                                    int *__restrict__ flags)
 {
     using L = Layout<DIM>;
+    using MIO = MomIO<DIM, MIXED>;
     constexpr int Q = L::Q, NF = L::NF;
     const DevParams &P = *Pp;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1177,33 +779,44 @@ __global__ void k_init_equilibrium(const DevParams *__restrict__ Pp, const doubl
     double mf[NF], mg[NF];
     moments_about<DIM>(f, 0.0, 0.0, s, mf);
     moments_about<DIM>(g, 0.0, 0.0, s, mg);
-    mom[L::kRho * N + node] = r;
-    mom[L::kUx * N + node] = u[0];
+    MIO::store(mom, N, node, L::kRho, r);
+    MIO::store(mom, N, node, L::kUx, u[0]);
     if (DIM == 2) {
-        mom[L::kUy * N + node] = u[1];
-        mom[(L::kF + 0) * N + node] = mf[4];
-        mom[(L::kF + 1) * N + node] = mf[6];
-        mom[(L::kF + 2) * N + node] = mf[2];
-        mom[(L::kF + 3) * N + node] = mf[7];
-        mom[(L::kF + 4) * N + node] = mf[5];
-        mom[(L::kF + 5) * N + node] = mf[8];
+        MIO::store(mom, N, node, L::kUy, u[1]);
+        MIO::store(mom, N, node, L::kF + 0, mf[4]);
+        MIO::store(mom, N, node, L::kF + 1, mf[6]);
+        MIO::store(mom, N, node, L::kF + 2, mf[2]);
+        MIO::store(mom, N, node, L::kF + 3, mf[7]);
+        MIO::store(mom, N, node, L::kF + 4, mf[5]);
+        MIO::store(mom, N, node, L::kF + 5, mf[8]);
     } else {
-        mom[L::kF * N + node] = mf[2];
+        MIO::store(mom, N, node, L::kF, mf[2]);
     }
-    for (int i = 0; i < NF; ++i) mom[(L::kG + i) * N + node] = mg[i];
+    for (int i = 0; i < NF; ++i) MIO::store(mom, N, node, L::kG + i, mg[i]);
 }
 
 hipError_t launch_init_equilibrium(const LaunchCtx &c, const DevState &s, const double *rho,
-                                   const double *u, const double *T)
+                                   const double *u, const double *T, void *mom)
 {
     dim3 grid, block;
     grid2(c, grid, block);
-    if (c.dim == 2)
-        hipLaunchKernelGGL(k_init_equilibrium<2>, grid, block, 0, c.st, s.params, rho, u, T, s.kor,
-                           s.mom, s.flags);
-    else
-        hipLaunchKernelGGL(k_init_equilibrium<1>, grid, block, 0, c.st, s.params, rho, u, T, s.kor,
-                           s.mom, s.flags);
+    // the fused step keeps its streamed states mixed FP64/FP32 in the FP32 precisions
+    const bool mixed = c.fused && c.fp32;
+    if (c.dim == 2) {
+        if (mixed)
+            hipLaunchKernelGGL((k_init_equilibrium<2, true>), grid, block, 0, c.st, s.params, rho, u, T, s.kor, mom,
+                               s.flags);
+        else
+            hipLaunchKernelGGL((k_init_equilibrium<2, false>), grid, block, 0, c.st, s.params, rho, u, T, s.kor, mom,
+                               s.flags);
+    } else {
+        if (mixed)
+            hipLaunchKernelGGL((k_init_equilibrium<1, true>), grid, block, 0, c.st, s.params, rho, u, T, s.kor, mom,
+                               s.flags);
+        else
+            hipLaunchKernelGGL((k_init_equilibrium<1, false>), grid, block, 0, c.st, s.params, rho, u, T, s.kor, mom,
+                               s.flags);
+    }
     return hipGetLastError();
 }
 

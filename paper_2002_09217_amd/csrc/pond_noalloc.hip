@@ -73,7 +73,7 @@ extern "C" int pond_step_noalloc(const pond_config *cfg, void *state0, void *sta
     if (config_valid(cfg) != POND_OK || !state0 || !state1 || !cur || (*cur != 0 && *cur != 1) || nsteps < 0)
         return POND_E_INVALID;
     const pond_config &c = *cfg;
-    if (c.dim == 3) return POND_E_INVALID;
+    if (c.dim == 3 || !c.two_kernel) return POND_E_INVALID; // the two-kernel step on stored populations
     const int nx = c.n[0], ny = c.dim == 2 ? c.n[1] : 1;
     const long long N = (long long)nx * ny;
     const size_t need = kMomOffset + (size_t)N * mom_planes(c.dim) * sizeof(double);
@@ -128,7 +128,7 @@ extern "C" int pond_step_noalloc(const pond_config *cfg, void *state0, void *sta
     if (hipMemcpyAsync(fl, flags, sizeof fl, hipMemcpyDeviceToHost, lc.st) != hipSuccess ||
         hipStreamSynchronize(lc.st) != hipSuccess)
         return POND_E_DEVICE;
-    const int n = completed_steps(fl, *cur);
+    const int n = completed_steps(fl, *cur, 2, nsteps);
     *cur = (*cur + n) % 2;
     if (done) *done = n;
     return fl[kFlagErr] ? err_code(fl[kFlagErr]) : POND_OK;

@@ -57,6 +57,7 @@ class pond_config(ctypes.Structure):
         ("n_pass", ctypes.c_int),
         ("precision", ctypes.c_int),
         ("tile", ctypes.c_int),
+        ("two_kernel", ctypes.c_int),
         ("stream", ctypes.c_void_p),
     ]
 
@@ -141,6 +142,7 @@ class Config:
     eos_c: tuple = (0.0, 0.0, 0.0, 0.0)   # EOS_DOUBLE_WELL: beta, rho_l, rho_v, p0
     precision: int = FP64
     tile: int = -1              # streaming tile shape; -1: measured at the first init
+    two_kernel: int = 0         # 1D/2D: 0 = fused one-kernel step, 1 = two kernels, stored populations
     stream: int | None = None   # hipStream_t as an integer (e.g. torch's cuda_stream)
 
     def to_c(self) -> pond_config:
@@ -163,6 +165,7 @@ class Config:
             c.eos_c[i] = float(self.eos_c[i])
         c.omega, c.kappa, c.k_scale, c.dt = self.omega, self.kappa, self.k_scale, self.dt
         c.n_pass, c.precision, c.tile = self.n_pass, self.precision, self.tile
+        c.two_kernel = int(self.two_kernel)
         c.stream = self.stream
         return c
 
@@ -253,11 +256,18 @@ class Lattice:
                     "pond_time_kernel")
         return us.value
 
+    @property
+    def fused(self) -> bool:
+        """One fused kernel per step (1D/2D lattices without two_kernel)."""
+        return self.cfg.dim != 3 and not self.cfg.two_kernel
+
     def step_timed(self, n: int) -> dict:
         """Advance n steps with HIP events around every kernel launch; mean microseconds
-        per launch of each kernel inside the step pipeline."""
+        per launch of each kernel inside the step pipeline (k_step for the fused step)."""
         out = np.zeros(2)
         self._check(load().pond_step_timed(self._h, int(n), _dp(out)), "pond_step_timed")
+        if self.fused:
+            return {"k_step": float(out[0])}
         return {KERNEL_NAMES[K_STREAM]: float(out[0]), KERNEL_NAMES[K_FORCE_COLLIDE]: float(out[1])}
 
     def tile_info(self) -> dict:

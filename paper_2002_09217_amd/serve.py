@@ -65,13 +65,14 @@ def make_jobs(count=64, seed=0, steps=5000, rate=20.0, sides=(64, 128, 256, 512)
             enumerate(W.serving_jobs(count=count, seed=seed, steps=steps, rate=rate, sides=sides))]
 
 
-def lattice_config(case: W.Case, precision: int, tile: int, stream=None) -> pond.Config:
+def lattice_config(case: W.Case, precision: int, tile: int, stream=None, two_kernel: int = 0) -> pond.Config:
     p = case.params
     return pond.Config(dim=case.dim, n=tuple(case.n), bc=case.bc, inflow=case.inflow, a=p["a"], b=p["b"],
                        R=p["R"], delta=p["delta"], omega=p["omega"], kappa=p["kappa"],
                        k_scale=p["k_scale"], dt=p["dt"], n_pass=p["n_pass"], eos=p.get("eos", 0),
                        isothermal=p.get("isothermal", 0), T0=p.get("T0", 0.0),
-                       eos_c=p.get("eos_c", (0.0,) * 4), precision=precision, tile=tile, stream=stream)
+                       eos_c=p.get("eos_c", (0.0,) * 4), precision=precision, tile=tile, stream=stream,
+                       two_kernel=two_kernel)
 
 
 def tune_tiles(sides, precision: int, stream=None) -> dict:

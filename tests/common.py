@@ -28,12 +28,12 @@ def oracle_config(case) -> core.Config:
                        k_scale=p["k_scale"], dt=p["dt"], n_pass=p["n_pass"], **_eos_kw(p))
 
 
-def pond_config(case, precision=pond.FP64, stream=None, tile=-1) -> pond.Config:
+def pond_config(case, precision=pond.FP64, stream=None, tile=-1, two_kernel=0) -> pond.Config:
     p = case.params
     return pond.Config(dim=case.dim, n=tuple(case.n), bc=case.bc, inflow=case.inflow,
                        a=p["a"], b=p["b"], R=p["R"], delta=p["delta"], omega=p["omega"],
                        kappa=p["kappa"], k_scale=p["k_scale"], dt=p["dt"], n_pass=p["n_pass"],
-                       precision=precision, tile=tile, stream=stream, **_eos_kw(p))
+                       precision=precision, tile=tile, stream=stream, two_kernel=two_kernel, **_eos_kw(p))
 
 
 def run_oracle(case, steps):
@@ -59,8 +59,8 @@ def run_oracle3(case, steps):
     return sim.moments()
 
 
-def run_gpu(case, steps, precision=pond.FP64, tile=-1):
-    lat = pond.Lattice(pond_config(case, precision, tile=tile))
+def run_gpu(case, steps, precision=pond.FP64, tile=-1, two_kernel=0):
+    lat = pond.Lattice(pond_config(case, precision, tile=tile, two_kernel=two_kernel))
     try:
         lat.init_fields(case.rho, case.u, case.T)
         if steps:

@@ -120,12 +120,14 @@ def test_noalloc_entry_point_validates_without_device():
     it touches a device."""
     lib = pond.load()
     cur, done = ctypes.c_int(0), ctypes.c_int(-1)
-    c = pond.Config(dim=2, n=(700, 700), tile=0).to_c()     # 4096 + 144 * 490000 B > 64 MiB
+    c = pond.Config(dim=2, n=(700, 700), tile=0, two_kernel=1).to_c()  # 4096 + 144 * 490000 B > 64 MiB
     assert lib.pond_step_noalloc(ctypes.byref(c), 64, 64, ctypes.byref(cur), 1, ctypes.byref(done)) == -8
     assert cur.value == 0 and done.value == 0
-    c = pond.Config(dim=3, n=(8, 8, 8), tile=0).to_c()
+    c = pond.Config(dim=3, n=(8, 8, 8), tile=0, two_kernel=1).to_c()
     assert lib.pond_step_noalloc(ctypes.byref(c), 64, 64, ctypes.byref(cur), 1, None) == -1
-    c = pond.Config(dim=2, n=(16, 16), tile=0).to_c()
+    c = pond.Config(dim=2, n=(16, 16), tile=0).to_c()                 # the fused step: refused
+    assert lib.pond_step_noalloc(ctypes.byref(c), 64, 64, ctypes.byref(cur), 1, None) == -1
+    c = pond.Config(dim=2, n=(16, 16), tile=0, two_kernel=1).to_c()
     assert lib.pond_step_noalloc(ctypes.byref(c), None, 64, ctypes.byref(cur), 1, None) == -1
     assert lib.pond_step_noalloc(ctypes.byref(c), 64, 64, ctypes.byref(cur), -1, None) == -1
     assert lib.pond_step_noalloc(None, 64, 64, ctypes.byref(cur), 1, None) == -1

@@ -1,6 +1,7 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle on identical seeded
 inputs.  Bar: 1e-12 relative L-infinity on rho, u, E (and T, p) for the FP64 form;
-1e-4 for the FP32-storage form on smooth cases.
+1e-4 for the FP32-storage form on smooth cases.  Both forms of the 1D/2D step run: the
+fused one-kernel step (the default) and the two-kernel step with stored populations.
 
 Sizes span several 32 x 8 streaming tiles with ragged tails; the full 256 x 256
 droplet of the benchmark is compared after a few steps, where the oracle finishes in
@@ -16,9 +17,12 @@ pytestmark = pytest.mark.gpu
 TOL64 = 1e-12
 
 
-def _check(case, steps, tol=TOL64, precision=pond.FP64, fields=("rho", "ux", "uy", "E", "T", "p"), tile=-1):
+def _check(case, steps, tol=TOL64, precision=pond.FP64, fields=("rho", "ux", "uy", "E", "T", "p"), tile=-1,
+           two_kernel=0):
     ref = run_oracle(case, steps)
-    got = run_gpu(case, steps, precision, tile=tile)
+    print(f"parity: {case.name} n={case.n} steps={steps} precision={precision} tile={tile} two_kernel={two_kernel}",
+          flush=True)
+    got = run_gpu(case, steps, precision, tile=tile, two_kernel=two_kernel)
     errs = compare(got, ref, fields)
     print(case.name, steps, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
     bad = {k: v for k, v in errs.items() if not v <= tol}
@@ -26,12 +30,13 @@ def _check(case, steps, tol=TOL64, precision=pond.FP64, fields=("rho", "ux", "uy
     return errs
 
 
+@pytest.mark.parametrize("two_kernel", [0, 1])
 @pytest.mark.parametrize("n_pass", [1, 2, 3])
 @pytest.mark.parametrize("kappa", [0.0, 0.0176])
-def test_perturbed_2d_100_steps(n_pass, kappa):
+def test_perturbed_2d_100_steps(n_pass, kappa, two_kernel):
     case = W.perturbed(40, 36, seed=11 + n_pass, rho0=2.0, t_over_tcr=1.05, u0=(0.05, -0.03),
                        n_pass=n_pass, kappa=kappa)
-    _check(case, 100)
+    _check(case, 100, two_kernel=two_kernel)
 
 
 def test_perturbed_2d_one_step_large_velocity():
@@ -51,14 +56,24 @@ def test_shear_flow_both_fp64_window_variants(tile):
     _check(case, 20, tile=tile)
 
 
-def test_droplet_64_100_steps():
+@pytest.mark.parametrize("two_kernel", [0, 1])
+def test_droplet_64_100_steps(two_kernel):
     case = W.static_droplet(n=64, radius=14.0, steps=100)
-    _check(case, 100)
+    _check(case, 100, two_kernel=two_kernel)
 
 
-def test_shock_tube_1d_100_steps():
+@pytest.mark.parametrize("two_kernel", [0, 1])
+def test_droplet_near_the_spinodal_085(two_kernel):
+    """The coldest serving temperature, 0.85 T_cr (0.7 % above the temperature where the
+    van der Waals loop reaches p < 0): a 64^2 droplet for 100 steps."""
+    case = W.static_droplet(n=64, t_over_tcr=0.85, radius=14.0, steps=100)
+    _check(case, 100, two_kernel=two_kernel)
+
+
+@pytest.mark.parametrize("two_kernel", [0, 1])
+def test_shock_tube_1d_100_steps(two_kernel):
     case = W.shock_tube(n=1000)
-    _check(case, 100, fields=("rho", "ux", "E", "T", "p"))
+    _check(case, 100, fields=("rho", "ux", "E", "T", "p"), two_kernel=two_kernel)
 
 
 def test_perturbed_1d_ragged():
@@ -66,9 +81,19 @@ def test_perturbed_1d_ragged():
     _check(case, 100, fields=("rho", "ux", "E", "T", "p"))
 
 
-def test_inflow_outflow_2d():
+@pytest.mark.parametrize("two_kernel", [0, 1])
+def test_inflow_outflow_2d(two_kernel):
     case = W.droplet_shock(nx=96, ny=40, radius=8.0, x_drop=50.0, x_shock=20.0)
-    _check(case, 50)
+    _check(case, 50, two_kernel=two_kernel)
+
+
+@pytest.mark.parametrize("tile", [0, 2, 5])
+def test_outflow_on_every_face_2d(tile):
+    """Outflow faces on all four sides (corners clamp in both axes), a lattice narrower
+    than some halos: the copy stages of the fused step's closure and donor regions."""
+    case = W.perturbed(37, 21, seed=71 + tile, kappa=0.0176, u0=(0.2, -0.1))
+    case.bc = ((W.OUTFLOW, W.OUTFLOW), (W.OUTFLOW, W.OUTFLOW))
+    _check(case, 30, tile=tile)
 
 
 def test_tiny_periodic_lattices():
@@ -89,17 +114,19 @@ def test_full_size_droplet_shock_1024x512_few_steps():
     _check(case, 2)
 
 
+@pytest.mark.parametrize("two_kernel", [0, 1])
 @pytest.mark.parametrize("which", ["perturbed", "droplet"])
-def test_fp32_storage_within_1e4(which):
+def test_fp32_storage_within_1e4(which, two_kernel):
     if which == "perturbed":
         case = W.perturbed(40, 36, seed=21, kappa=0.0176)
     else:
         case = W.static_droplet(n=64, radius=14.0)
-    _check(case, 100, tol=1e-4, precision=pond.FP32_STORE)
+    _check(case, 100, tol=1e-4, precision=pond.FP32_STORE, two_kernel=two_kernel)
 
 
+@pytest.mark.parametrize("two_kernel", [0, 1])
 @pytest.mark.parametrize("which", ["perturbed", "droplet", "shock_tube"])
-def test_fp32_storage_with_fp64_arithmetic_within_1e6(which):
+def test_fp32_storage_with_fp64_arithmetic_within_1e6(which, two_kernel):
     if which == "perturbed":
         case = W.perturbed(40, 36, seed=22, kappa=0.0176, u0=(0.1, -0.05))
     elif which == "droplet":
@@ -107,13 +134,14 @@ def test_fp32_storage_with_fp64_arithmetic_within_1e6(which):
     else:
         case = W.shock_tube(n=1000)
     fields = ("rho", "ux", "E", "T", "p") if case.dim == 1 else ("rho", "ux", "uy", "E", "T", "p")
-    _check(case, 100, tol=1e-6, precision=pond.FP32_STORE_FP64_MATH, fields=fields)
+    _check(case, 100, tol=1e-6, precision=pond.FP32_STORE_FP64_MATH, fields=fields, two_kernel=two_kernel)
 
 
+@pytest.mark.parametrize("two_kernel", [0, 1])
 @pytest.mark.parametrize("tile", range(6))
-def test_every_stream_tile_shape_2d(tile):
+def test_every_stream_tile_shape_2d(tile, two_kernel):
     case = W.perturbed(70, 45, seed=30 + tile, kappa=0.0176, u0=(0.1, -0.2))
-    _check(case, 30, tile=tile)
+    _check(case, 30, tile=tile, two_kernel=two_kernel)
 
 
 @pytest.mark.parametrize("precision,tol", [(pond.FP32_STORE, 1e-4), (pond.FP32_STORE_FP64_MATH, 1e-6)])
@@ -126,7 +154,8 @@ def test_every_stream_tile_shape_2d_fp32_storage(tile, precision, tol):
     _check(case, 30, tol=tol, precision=precision, tile=tile)
 
 
+@pytest.mark.parametrize("two_kernel", [0, 1])
 @pytest.mark.parametrize("tile", range(2))
-def test_every_stream_tile_shape_1d(tile):
+def test_every_stream_tile_shape_1d(tile, two_kernel):
     case = W.perturbed(333, 1, seed=40 + tile, dim=1, kappa=0.0176, u0=(0.2, 0.0))
-    _check(case, 30, tile=tile, fields=("rho", "ux", "E", "T", "p"))
+    _check(case, 30, tile=tile, fields=("rho", "ux", "E", "T", "p"), two_kernel=two_kernel)

@@ -24,6 +24,7 @@ def run_both(torch, case, precision, steps, tile):
     """Step one state with pond_step and with pond_step_noalloc; return both states."""
     print(f"no-alloc case {case.name} n={case.n} precision={precision} tile={tile} steps={steps}", flush=True)
     cfg = pond_config(case, precision, stream=torch.cuda.current_stream().cuda_stream, tile=tile)
+    cfg.two_kernel = 1   # the form with stored populations, which pond_step_noalloc runs
     lat = pond.Lattice(cfg)
     try:
         lat.init_fields(case.rho, case.u, case.T)
@@ -74,9 +75,9 @@ def test_noalloc_rejects_a_lattice_beyond_the_scratch():
     torch = pytest.importorskip("torch")
     # 700 x 700 nodes need 4096 + 18 * 8 * 490000 bytes > 64 MiB
     buf = torch.zeros(64, dtype=torch.uint8, device="cuda")
-    cfg = pond.Config(dim=2, n=(700, 700), tile=0)
+    cfg = pond.Config(dim=2, n=(700, 700), tile=0, two_kernel=1)
     rc, cur, done = pond.step_noalloc(cfg, buf.data_ptr(), buf.data_ptr(), 0, 1)  # rejected before any launch
     assert rc == -8 and cur == 0 and done == 0
-    cfg = pond.Config(dim=2, n=(16, 16), tile=0)
+    cfg = pond.Config(dim=2, n=(16, 16), tile=0, two_kernel=1)
     assert pond.step_noalloc(cfg, 0, buf.data_ptr(), 0, 1)[0] == -1   # NULL buffer
     assert pond.step_noalloc(cfg, buf.data_ptr(), buf.data_ptr(), 2, 1)[0] == -1   # cur not 0 or 1
