@@ -273,4 +273,169 @@ __device__ __forceinline__ void collide_g(const PT &P, double rho, double i_rho,
     }
 }
 
+// ---------------------------------------------------------------------------
+// The collision in moment space.  The populations of a set in the collision gauge
+// (u, theta = s^2) sit on the velocities u + xi, xi = s c, and are fixed by their nine
+// central moments about u (the transfer of App. C is exact for them).  The collision is
+// linear in the populations, and its equilibria and sources are given in closed form, so
+// the central moments of the collided populations follow directly from the streamed
+// ones: with the lattice moments of the weights per axis, sum_c W_c xi^k = 1, 0, theta/3,
+// 0, theta^2/3 for k = 0..4,
+//   f: BGK towards rho W, whose central moments are rho a_m a_n (a = 1, 0, theta/3), plus
+//      the force source S = G^{u}_{u+du}[rho W] - rho W, whose moments are
+//      rho (e_m(du_x) e_n(du_y) - a_m a_n), e = 1, du, du^2 + theta/3 (eqs. 16-17);
+//   g: BGK towards the force-extended equilibrium w_q P(xi) and the source (M0 + 2 u^.F)
+//      dt Psi_q, Psi_q = w_q Q(xi), both quadratic polynomials in xi (eqs. 9, 19-22), whose
+//      moments are sums of products of the per-axis lattice moments.
+// The result is returned as the moments about a reference velocity r (shift d = u - r),
+// out[3 m + n] = sum_q f*_q (d_x + xi_x)^m (d_y + xi_y)^n, as moments_about would take
+// them from the collided populations.  `oset` holds the streamed central moments of the
+// set as stored (f: (1,1), (2,0), (0,2), (2,1), (1,2), (2,2); g: all nine).
+// ---------------------------------------------------------------------------
+template <int DIM, typename PT>
+__device__ __forceinline__ void collide_moments(const PT &P, int set, double rho, double i_rho, const double *u,
+                                                const double *F, double p, double theta, double G0, double M0,
+                                                const double *oset, double dx, double dy, double *out)
+{
+    constexpr int NF = Layout<DIM>::NF;
+    const double dt = P.dt, om = P.omega;
+    const double t3 = theta * kTL;                         // theta / 3 = p / rho
+    const double mu[5] = {1.0, 0.0, t3, 0.0, theta * t3}; // per-axis lattice moments of xi
+    double c[NF];                                          // collided central moments
+    if (set == 0) {
+        double mc[NF];
+        if (DIM == 2) {
+            mc[0] = rho;
+            mc[1] = 0.0;
+            mc[3] = 0.0;
+            mc[4] = oset[0];
+            mc[6] = oset[1];
+            mc[2] = oset[2];
+            mc[7] = oset[3];
+            mc[5] = oset[4];
+            mc[8] = oset[5];
+        } else {
+            mc[0] = rho;
+            mc[1] = 0.0;
+            mc[2] = oset[0];
+        }
+        const double dux = F[0] * dt * i_rho, duy = DIM == 2 ? F[1] * dt * i_rho : 0.0;
+        const double a[3] = {1.0, 0.0, t3};
+        const double ex[3] = {1.0, dux, dux * dux + t3};
+        const double ey[3] = {1.0, duy, duy * duy + t3};
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            if (DIM == 2) {
+#pragma unroll
+                for (int n = 0; n < 3; ++n) {
+                    const double eq = rho * (a[m] * a[n]);
+                    const double src = rho * (ex[m] * ey[n] - a[m] * a[n]);
+                    c[3 * m + n] = mc[3 * m + n] + om * (eq - mc[3 * m + n]) + src;
+                }
+            } else {
+                const double eq = rho * a[m];
+                c[m] = mc[m] + om * (eq - mc[m]) + rho * (ex[m] - a[m]);
+            }
+        }
+    } else {
+        const double i_p = 1.0 / p;
+        const double E = 0.5 * G0 * i_rho;
+        const double uh[2] = {u[0] + 0.5 * F[0] * dt * i_rho, DIM == 2 ? u[1] + 0.5 * F[1] * dt * i_rho : 0.0};
+        const double Pr = p * i_rho;
+        const double H = E + Pr;
+        const double dt_Pr = dt * rho * i_p;
+        double X[2][2], M[2], Nm[2][2];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+#pragma unroll
+            for (int b = 0; b < DIM; ++b)
+                X[a][b] = uh[a] * F[b] + F[a] * uh[b] + 0.5 * dt * F[a] * F[b] * E * i_p;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            double xu = 0.0;
+#pragma unroll
+            for (int b = 0; b < DIM; ++b) xu += X[a][b] * u[b];
+            M[a] = dt_Pr * (F[a] * H - xu);
+        }
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+#pragma unroll
+            for (int b = 0; b < DIM; ++b) Nm[a][b] = (a == b ? rho : 0.0) + 0.5 * dt_Pr * X[a][b];
+        double work = 0.0;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) work += 2.0 * uh[a] * F[a];
+        const double c_uc = 0.5 * kInvTL * rho * i_p;      // rho / (2 p T_L)
+        const double c_v2 = 0.5 * rho * i_p;               // rho / (2 p)
+        const double i_th = 1.0 / theta;
+        const double src = (M0 + work) * dt;
+        // equilibrium 2 rho E + M.xi + sum_ab N_ab (xi_a xi_b + u_a xi_b + xi_a u_b - d_ab Pr)
+        // and kernel 1 + D/2 + c_uc (u.xi)^2 / theta - c_v2 |u + xi|^2, as coefficients of
+        // 1, xi_x, xi_y, xi_x^2, xi_y^2, xi_x xi_y
+        double q[6], k[6];
+        if (DIM == 2) {
+            q[0] = 2.0 * rho * E - Pr * (Nm[0][0] + Nm[1][1]);
+            q[1] = M[0] + 2.0 * (Nm[0][0] * u[0] + Nm[0][1] * u[1]);
+            q[2] = M[1] + 2.0 * (Nm[1][1] * u[1] + Nm[0][1] * u[0]);
+            q[3] = Nm[0][0];
+            q[4] = Nm[1][1];
+            q[5] = 2.0 * Nm[0][1];
+            k[0] = 1.0 + 0.5 * (double)DIM - c_v2 * (u[0] * u[0] + u[1] * u[1]);
+            k[1] = -2.0 * c_v2 * u[0];
+            k[2] = -2.0 * c_v2 * u[1];
+            k[3] = c_uc * u[0] * u[0] * i_th - c_v2;
+            k[4] = c_uc * u[1] * u[1] * i_th - c_v2;
+            k[5] = 2.0 * c_uc * u[0] * u[1] * i_th;
+        } else {
+            q[0] = 2.0 * rho * E - Pr * Nm[0][0];
+            q[1] = M[0] + 2.0 * Nm[0][0] * u[0];
+            q[3] = Nm[0][0];
+            q[2] = q[4] = q[5] = 0.0;
+            k[0] = 1.0 + 0.5 * (double)DIM - c_v2 * u[0] * u[0];
+            k[1] = -2.0 * c_v2 * u[0];
+            k[3] = c_uc * u[0] * u[0] * i_th - c_v2;
+            k[2] = k[4] = k[5] = 0.0;
+        }
+        // moments of w_q (combined polynomial): the equilibrium weighted by omega plus the
+        // source kernel weighted by src
+        double w[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) w[i] = om * q[i] + src * k[i];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            if (DIM == 2) {
+#pragma unroll
+                for (int n = 0; n < 3; ++n) {
+                    const double pm = w[0] * mu[m] * mu[n] + w[1] * mu[m + 1] * mu[n] + w[2] * mu[m] * mu[n + 1] +
+                                      w[3] * mu[m + 2] * mu[n] + w[4] * mu[m] * mu[n + 2] +
+                                      w[5] * mu[m + 1] * mu[n + 1];
+                    c[3 * m + n] = (1.0 - om) * oset[3 * m + n] + pm;
+                }
+            } else {
+                const double pm = w[0] * mu[m] + w[1] * mu[m + 1] + w[3] * mu[m + 2];
+                c[m] = (1.0 - om) * oset[m] + pm;
+            }
+        }
+    }
+    // central moments about u -> moments about r: binomial shift by d per axis
+    if (DIM == 2) {
+        double t[3][3];
+#pragma unroll
+        for (int n = 0; n < 3; ++n) {
+            t[0][n] = c[n];
+            t[1][n] = c[3 + n] + dx * c[n];
+            t[2][n] = c[6 + n] + 2.0 * dx * c[3 + n] + dx * dx * c[n];
+        }
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            out[3 * m] = t[m][0];
+            out[3 * m + 1] = t[m][1] + dy * t[m][0];
+            out[3 * m + 2] = t[m][2] + 2.0 * dy * t[m][1] + dy * dy * t[m][0];
+        }
+    } else {
+        out[0] = c[0];
+        out[1] = c[1] + dx * c[0];
+        out[2] = c[2] + 2.0 * dx * c[1] + dx * dx * c[0];
+    }
+}
+
 } // namespace pond

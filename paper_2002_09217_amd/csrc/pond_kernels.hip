@@ -125,11 +125,12 @@ __global__ void __launch_bounds__(2 * TX *TY, 2 * TX *TY <= 256 ? 3 : 2)
 
     // FP32 streaming: the LDS holds every donor moment minus a reference moment vector of
     // the tile, and the FP32 window arithmetic carries only that variation.  The reference
-    // is the equilibrium-shaped vector of the tile's centre node, R (1, theta, theta,
-    // theta^2) at the moments (0,0), (0,2), (2,0), (2,2) and zero elsewhere, with R its FP64
-    // set sum (rho for f, 2 rho E for g).  Each axis's Lagrange weights reproduce a
-    // constant, so the reference streams to sum_mn A_km B_ln Mref_mn = R a_k b_l with
-    // a_k = A_k0 + theta A_k2, b_l = B_l0 + theta B_l2, added in FP64.
+    // is the equilibrium-shaped vector of the tile's centre node, R (1, v, v, v^2) at the
+    // moments (0,0), (0,2), (2,0), (2,2) and zero elsewhere, with R its FP64 set sum (rho
+    // for f, 2 rho E for g) and v = theta T_L the per-axis second moment of the weights in
+    // the centre's gauge.  Each axis's Lagrange weights reproduce a constant, so the
+    // reference streams to sum_mn A_km B_ln Mref_mn = R a_k b_l with a_k = A_k0 + v A_k2,
+    // b_l = B_l0 + v B_l2, added in FP64.
     constexpr bool kDevI = sizeof(LdsT) == 4;
     static_assert(!kDevI || kDeviationStore<PopT>, "FP32 streaming comes with the FP32 store");
     const POND_GLOBAL double *__restrict__ fsum = (const POND_GLOBAL double *)(fpop + (size_t)2 * Q * N);
@@ -137,7 +138,7 @@ __global__ void __launch_bounds__(2 * TX *TY, 2 * TX *TY <= 256 ? 3 : 2)
     if constexpr (kDevI) {
         refR0 = fsum[cnode];
         refR1 = fsum[(size_t)N + cnode];
-        refT = side[kSideTh * N + cnode];
+        refT = side[kSideTh * N + cnode] * kTL;
     }
 
     // the receiver's own gauge and force, loaded now so that the latency overlaps the fill

@@ -239,10 +239,10 @@ __global__ void __launch_bounds__(2 * TX *TY, 2 * TX *TY <= 256 ? 3 : 2)
     // an error here makes the state this launch read the first bad one
     if (err_c) raise_error(flags, err_c | kErrCollideStage, S.parity);
 
-    // FP32 windows hold deviations from R (1, theta, theta, theta^2) of the tile centre,
-    // with theta of the centre's collision gauge
+    // FP32 windows hold deviations from R (1, v, v, v^2) of the tile centre, with v = p /
+    // rho = theta T_L the per-axis second moment of the centre's collision gauge
     const int cb = (DIM == 2 ? (cnode / P.nx - by0 + 3) * HX : 0) + (cnode % P.nx - bx0 + 3);
-    const double refT = kDevI ? s_th[kThP * HN + cb] * (1.0 / rho_c) * kInvTL : 0.0;
+    const double refT = kDevI ? s_th[kThP * HN + cb] * (1.0 / rho_c) : 0.0;
 
     // --- stage 4: collision of the donors, reduced to moments about (rx, ry) --------
 #pragma unroll
@@ -253,8 +253,9 @@ __global__ void __launch_bounds__(2 * TX *TY, 2 * TX *TY <= 256 ? 3 : 2)
         int cx, cy, face;
         const int cls = it < 2 * LN ? classify<DIM>(geo, bx0 - 2 + wx, by0 - 2 + wy, cx, cy, face) : kCopy;
         if (cls != kCopy) {
-            double post[Q], gux, guy, gth;
+            double m[NF];
             if (cls == kSelf) {
+                // collision in moment space, straight to the moments about (rx, ry)
                 const double rho = pre_d[j][L::kRho];
                 const double i_rho = 1.0 / rho;
                 const double u[2] = {pre_d[j][L::kUx], DIM == 2 ? pre_d[j][L::kUy] : 0.0};
@@ -262,32 +263,20 @@ __global__ void __launch_bounds__(2 * TX *TY, 2 * TX *TY <= 256 ? 3 : 2)
                 const double F[2] = {s_th[kThFx * HN + hb], DIM == 2 ? s_th[kThFy * HN + hb] : 0.0};
                 const double p = s_th[kThP * HN + hb];
                 const double theta = p * i_rho * kInvTL;
-                const double s = sqrt(theta);
-                double oset[NF], pop[Q];
+                double oset[NF];
 #pragma unroll
                 for (int i = 0; i < NF; ++i) oset[i] = pre_d[j][NOWN + i];
-                pops_from_central<DIM>(set, rho, oset, s, pop);
-                if (set == 0) {
-                    collide_f<DIM>(P, rho, i_rho, F, theta, s, pop, post);
-                } else {
-                    const double M0 = heat_correction<DIM>(P, s_th, HN, hb, HX);
-                    collide_g<DIM>(P, rho, i_rho, u, F, p, s, oset[0], M0, pop, post);
-                }
-                gux = u[0];
-                guy = u[1];
-                gth = theta;
+                const double M0 = set == 0 ? 0.0 : heat_correction<DIM>(P, s_th, HN, hb, HX);
+                collide_moments<DIM>(P, set, rho, i_rho, u, F, p, theta, oset[0], M0, oset, u[0] - rx, u[1] - ry, m);
             } else {
                 // inflow ghost: the equilibrium of the face state in its own gauge
                 const POND_GLOBAL GhostFace &G = P.ghost[face];
                 const POND_GLOBAL double *src = set == 0 ? G.f : G.g;
+                double post[Q];
 #pragma unroll
                 for (int q = 0; q < Q; ++q) post[q] = src[q];
-                gux = G.ux;
-                guy = G.uy;
-                gth = G.theta;
+                moments_about<DIM>(post, G.ux - rx, G.uy - ry, sqrt(G.theta), m);
             }
-            double m[NF];
-            moments_about<DIM>(post, gux - rx, guy - ry, sqrt(gth), m);
             if constexpr (kDevI) {
                 const double R = set == 0 ? refR0 : refR1;
                 m[0] -= R;

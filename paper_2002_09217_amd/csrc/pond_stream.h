@@ -61,8 +61,8 @@ __device__ __forceinline__ void window2_no_zero_taps(const double *sbase, const 
 // moment fields at the departure points of the receiver's gauge (Ux, Uy, th), contract
 // them into populations in that gauge, take the moments with the partner lane and close
 // them through the EoS for the next gauge, n_pass times.  FP32 windows (LdsT = float) hold
-// deviations from the tile's reference moment vector R (1, theta, theta, theta^2) (refR0,
-// refR1 and refT).  On return pq holds this set's populations in the gauge (sUx, sUy, sS)
+// deviations from the tile's reference moment vector R (1, v, v, v^2) (refR0, refR1 and
+// refT = v, the per-axis second moment theta T_L of the centre's gauge).  On return pq holds this set's populations in the gauge (sUx, sUy, sS)
 // of the last pass, and (Ux, Uy, th) the gauge it produced; returns the error bits.
 template <int DIM, typename LdsT, int LN, int LX, int NT, bool GEN>
 __device__ __forceinline__ int stream_passes(const POND_GLOBAL DevParams &P, const LdsT *sbase, int tid, int myset, double rx, double ry,
