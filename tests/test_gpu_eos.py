@@ -143,5 +143,6 @@ def test_isothermal_sound_speeds(precision):
         times = (round(60.0 / c_ref), round(120.0 / c_ref))
         c = pulse_speed(factory, rho0, 1.0, times=times)
         print(f"eos {kind} rho {rho0:.4f}: pulse {c:.5f} theory {c_ref:.5f} ({c / c_ref - 1:+.2e})", flush=True)
-        # FP32 streaming rounds the 1e-3 pulse at the 1e-3 level of its own amplitude
-        assert c == pytest.approx(c_ref, rel=5e-3 if precision == pond.FP32_STORE else 3e-3)
+        # FP32 windows hold deviations from the tile's equilibrium-shaped reference, so the
+        # 1e-3 pulse keeps FP64's accuracy in every precision
+        assert c == pytest.approx(c_ref, rel=3e-3)
