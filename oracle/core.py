@@ -123,6 +123,15 @@ def lib():
         L.orc3_moments.argtypes = [p3] + [dp] * 9
         L.orc3_korteweg_force.argtypes = [p3, dp, dp]
         L.orc3_heat_correction.argtypes = [p3] + [dp] * 5
+        pe = ctypes.POINTER(Eos)
+        d = ctypes.c_double
+        for name in ("orc_eos_e", "orc_eos_cv", "orc_eos_T_of_e"):
+            getattr(L, name).argtypes = [pe, d, d, d, d, d, d]
+            getattr(L, name).restype = d
+        L.orc_eos_T_of_p.argtypes = [pe, d, d, d, d, d]
+        L.orc_eos_T_of_p.restype = d
+        L.orc_eos_p.argtypes = [pe, d, d, d, d, d]
+        L.orc_eos_p.restype = d
         _lib = L
     return _lib
 
@@ -156,7 +165,7 @@ class Config:
     k_scale: float = 1.0
     dt: float = 1.0
     n_pass: int = 2
-    eos: int = EOS_VDW          # EOS_VDW, EOS_DIETERICI (isothermal), EOS_WELL (isothermal)
+    eos: int = EOS_VDW          # EOS_VDW, EOS_DIETERICI, EOS_WELL (isothermal)
     isothermal: int = 0         # nonzero: T = T0 everywhere
     T0: float = 0.0
     eos_c: tuple = (0.0, 0.0, 0.0, 0.0)   # EOS_WELL: beta, rho_l, rho_v, p0
@@ -186,6 +195,36 @@ class Config:
 
 class OracleError(RuntimeError):
     pass
+
+
+def _eos_call(name, cfg: Config, *args) -> float:
+    E = _eos(cfg.eos, cfg.isothermal, cfg.T0, cfg.eos_c)
+    return getattr(lib(), name)(ctypes.byref(E), *[float(x) for x in args])
+
+
+def eos_p(cfg: Config, rho, T) -> float:
+    """Pressure p(rho, T) of the run's equation of state (orc_eos_p)."""
+    return _eos_call("orc_eos_p", cfg, cfg.a, cfg.b, cfg.R, rho, T)
+
+
+def eos_e(cfg: Config, rho, T) -> float:
+    """Internal energy e(rho, T) (orc_eos_e; Dieterici by quadrature)."""
+    return _eos_call("orc_eos_e", cfg, cfg.a, cfg.b, cfg.R, cfg.R / cfg.delta, rho, T)
+
+
+def eos_cv(cfg: Config, rho, T) -> float:
+    """(de/dT)_rho of a state (orc_eos_cv)."""
+    return _eos_call("orc_eos_cv", cfg, cfg.a, cfg.b, cfg.R, cfg.R / cfg.delta, rho, T)
+
+
+def eos_T_of_e(cfg: Config, rho, e) -> float:
+    """Temperature of a state from its internal energy (orc_eos_T_of_e)."""
+    return _eos_call("orc_eos_T_of_e", cfg, cfg.a, cfg.b, cfg.R, cfg.R / cfg.delta, rho, e)
+
+
+def eos_T_of_p(cfg: Config, rho, p) -> float:
+    """Temperature of a state from its pressure (orc_eos_T_of_p)."""
+    return _eos_call("orc_eos_T_of_p", cfg, cfg.a, cfg.b, cfg.R, rho, p)
 
 
 @dataclass

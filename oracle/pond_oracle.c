@@ -17,6 +17,8 @@
  *     gauge with the transfer matrix G = M_{lambda'}^{-1} M_lambda             (App. C)
  *     and then interpolated with cubic Lagrange polynomials                    (App. D)
  *   - van der Waals EoS, e = C_v T - a rho, C_v = R/delta                       (main text; App. A)
+ *   - Dieterici EoS with the energy equation, e = C_v T + the integral of
+ *     T (dp/dT)_v - p over v from the ideal-gas limit                           (Supplement)
  *   - isothermal runs with the van der Waals, Dieterici or double-well
  *     (simplified free energy) pressure                                         (Supplement)
  *   - BGK collision of f with the forcing term S_i                             (eqs. 16-17)
@@ -55,10 +57,16 @@
  *   R11 isothermal runs (the Supplement's coexistence and speed-of-sound cases):
  *       T = T0 wherever the step needs a temperature (passes, closure, initial
  *       and inflow states, read-back); the energy population is then passive and
- *       carries e = C_v T (- a rho for van der Waals).  The simplified free
+ *       carries e(rho, T0) of its law (C_v T for the double well).  The simplified free
  *       energy is read with squares, E0 = beta (rho - rho_l)^2 (rho - rho_v)^2,
  *       and a background pressure p0 > 0 is added so that theta stays positive:
  *       p = p0 + rho dE0/drho - E0.
+ *   R12 Dieterici fluid with the energy equation: C_v = R/delta is the constant
+ *       (ideal-gas, v -> infinity) heat capacity of the polytropic assumption, and
+ *       the volume part of de is integrated along the isotherm from that limit, so
+ *       e = C_v T + e_dep(rho, T); (de/dT)_rho = C_v + de_dep/dT is the heat capacity
+ *       of the state.  T follows from e (and, for the read-back, from p) by Newton's
+ *       method.  The conductivity keeps k = k_scale mu C_p^ig (R5).
  *
  * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no FMA contraction).
  */
@@ -125,35 +133,141 @@ double orc_eos_p(const orc_eos *E, double a, double b, double R, double rho, dou
     }
     return rho * R * T / (1.0 - b * rho) - a * rho * rho;
 }
-/* internal energy: van der Waals e = C_v T - a rho (App. A); the other kinds are only
- * run isothermally, where the energy population is passive, and carry e = C_v T */
-double orc_eos_e(const orc_eos *E, double a, double Cv, double rho, double T)
+/* Gauss-Legendre rule of ORC_GL points on [-1, 1]: the nodes are the roots of P_n,
+ * found by Newton's method from the estimates cos(pi (i - 1/4)/(n + 1/2)) with P_n and
+ * P_n' from the three-term recurrence; w_i = 2 / ((1 - x_i^2) P_n'(x_i)^2). */
+#define ORC_GL 32
+static double gl_x[ORC_GL], gl_w[ORC_GL];
+/* computed once when the library is loaded, before any parallel region reads it */
+__attribute__((constructor)) static void gl_rule(void)
 {
+    const int n = ORC_GL;
+    for (int i = 0; i < n; ++i) {
+        double x = cos(3.14159265358979323846 * (i + 0.75) / (n + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = x;
+            for (int j = 2; j <= n; ++j) {
+                double p2 = ((2.0 * j - 1.0) * x * p1 - (j - 1.0) * p0) / j;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (x * p1 - p0) / (x * x - 1.0);
+            double dx = p1 / dp;
+            x -= dx;
+            if (fabs(dx) < 1e-16) break;
+        }
+        gl_x[i] = x;
+        gl_w[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+    }
+}
+
+/* Dieterici internal energy (Supplement, thermodynamics: de = C_v dT + [T (dp/dT)_v - p]
+ * dv with C_v constant).  Integrated from the ideal-gas limit v -> infinity along the
+ * isotherm, where e = C_v T:
+ *   e(rho, T) = C_v T + int_inf^v [T (dp/dT)_v - p] dv' = C_v T - int_0^rho [T (dp/dT) - p](r) / r^2 dr.
+ * For this pressure T (dp/dT)_rho - p = p x with x = a r / (R T), and d(p x)/dT = p x^2 / T
+ * gives (de/dT)_rho under the integral.  Quadrature: the Gauss-Legendre rule in
+ * t = -ln(1 - b r), dr = (1 - b r) dt / b, which maps [0, rho) onto [0, -ln(1 - b rho))
+ * and takes out the growth of p as b r -> 1.  Returns e; *dedT receives (de/dT)_rho. */
+static double diet_e(double a, double b, double R, double Cv, double rho, double T, double *dedT)
+{
+    const double tmax = -log1p(-b * rho);
+    double dep = 0.0, ddep = 0.0;
+    for (int i = 0; i < ORC_GL; ++i) {
+        const double t = 0.5 * tmax * (gl_x[i] + 1.0);
+        const double r = -expm1(-t) / b;
+        const double jac = 0.5 * tmax * gl_w[i] * (1.0 - b * r) / b;
+        const double p = r * R * T / (1.0 - b * r) * exp(-a * r / (R * T));
+        const double x = a * r / (R * T);
+        dep += jac * p * x / (r * r);
+        ddep += jac * p * x * x / (T * r * r);
+    }
+    if (dedT) *dedT = Cv - ddep;
+    return Cv * T - dep;
+}
+
+/* internal energy: van der Waals e = C_v T - a rho (App. A), Dieterici C_v T plus the
+ * departure above; the double well is only run isothermally, where the energy population
+ * is passive, and carries e = C_v T */
+double orc_eos_e(const orc_eos *E, double a, double b, double R, double Cv, double rho, double T)
+{
+    if (E->kind == ORC_EOS_DIETERICI) return diet_e(a, b, R, Cv, rho, T, NULL);
     return Cv * T - (E->kind == ORC_EOS_VDW ? a * rho : 0.0);
 }
-/* temperature of a streamed state: T0 when isothermal, else the van der Waals
- * inversion of e = C_v T - a rho */
-double orc_eos_T_of_e(const orc_eos *E, double a, double Cv, double rho, double e)
+/* (de/dT)_rho, the heat capacity at constant volume of the state */
+double orc_eos_cv(const orc_eos *E, double a, double b, double R, double Cv, double rho, double T)
 {
-    return E->isothermal ? E->T0 : (e + a * rho) / Cv;
+    double c = Cv;
+    if (E->kind == ORC_EOS_DIETERICI) diet_e(a, b, R, Cv, rho, T, &c);
+    return c;
 }
-/* temperature from the pressure (read-back): T0 when isothermal, else the inversion
- * of the van der Waals pressure */
+/* Newton's method for g(T) = 0 with g increasing, kept inside a bracket [lo, hi] with
+ * g(lo) < 0 < g(hi) that each iterate narrows; a step that leaves it is replaced by
+ * bisection.  `val` returns g and g'.  The bracket starts at [0, T1] with T1 doubled
+ * until g(T1) > 0.  Stops when the step is below 1e-15 T (or the bracket is that narrow). */
+typedef double (*orc_gfun)(const void *ctx, double T, double *dg);
+static double newton_T(orc_gfun val, const void *ctx, double T)
+{
+    double lo = 0.0, hi = T > 0.0 ? T : 1.0, dg;
+    for (int k = 0; k < 200 && val(ctx, hi, &dg) <= 0.0; ++k) hi *= 2.0;
+    if (!(T > lo && T < hi)) T = 0.5 * (lo + hi);
+    for (int it = 0; it < 200; ++it) {
+        const double g = val(ctx, T, &dg);
+        if (g > 0.0) hi = T; else lo = T;
+        double Tn = T - g / dg;
+        if (!(Tn > lo && Tn < hi)) Tn = 0.5 * (lo + hi);
+        const double step = fabs(Tn - T);
+        T = Tn;
+        if (step <= 1e-15 * T || hi - lo <= 1e-15 * T) break;
+    }
+    return T;
+}
+typedef struct { double a, b, R, Cv, rho, target; } diet_ctx;
+static double diet_g_e(const void *c, double T, double *dg)
+{
+    const diet_ctx *d = (const diet_ctx *)c;
+    return diet_e(d->a, d->b, d->R, d->Cv, d->rho, T, dg) - d->target;
+}
+static double diet_g_p(const void *c, double T, double *dg)
+{
+    /* ln p(rho, T) - ln p_target, increasing in T: d/dT = 1/T + a rho/(R T^2) */
+    const diet_ctx *d = (const diet_ctx *)c;
+    *dg = 1.0 / T + d->a * d->rho / (d->R * T * T);
+    return log(d->rho * d->R * T / (1.0 - d->b * d->rho)) - d->a * d->rho / (d->R * T) - log(d->target);
+}
+/* temperature of a streamed state: T0 when isothermal, else the inversion of e(rho, T):
+ * van der Waals in closed form, Dieterici by Newton's method */
+double orc_eos_T_of_e(const orc_eos *E, double a, double b, double R, double Cv, double rho, double e)
+{
+    if (E->isothermal) return E->T0;
+    if (E->kind == ORC_EOS_DIETERICI) {
+        diet_ctx d = {a, b, R, Cv, rho, e};
+        return newton_T(diet_g_e, &d, (e + a * rho) / Cv);
+    }
+    return (e + a * rho) / Cv;
+}
+/* temperature from the pressure (read-back): T0 when isothermal, else the inversion of
+ * the pressure: van der Waals in closed form, Dieterici by Newton's method on ln p */
 double orc_eos_T_of_p(const orc_eos *E, double a, double b, double R, double rho, double p)
 {
-    return E->isothermal ? E->T0 : (p + a * rho * rho) * (1.0 - b * rho) / (rho * R);
+    if (E->isothermal) return E->T0;
+    if (E->kind == ORC_EOS_DIETERICI) {
+        diet_ctx d = {a, b, R, 0.0, rho, p};
+        return newton_T(diet_g_p, &d, p * (1.0 - b * rho) / (rho * R));
+    }
+    return (p + a * rho * rho) * (1.0 - b * rho) / (rho * R);
 }
 /* domain of the pressure law: 1 - b rho > 0 for van der Waals and Dieterici */
 int orc_eos_in_domain(const orc_eos *E, double b, double rho)
 {
     return E->kind == ORC_EOS_WELL || 1.0 - b * rho > 0.0;
 }
-/* admissible constants: the non-van-der-Waals kinds are isothermal; T0 > 0; the
- * double well has beta > 0, rho_l > rho_v > 0 and p0 > 0 */
+/* admissible constants: the double well is isothermal; T0 > 0; the double well has
+ * beta > 0, rho_l > rho_v > 0 and p0 > 0 */
 int orc_eos_valid(const orc_eos *E)
 {
     if (E->kind < ORC_EOS_VDW || E->kind > ORC_EOS_WELL) return 0;
-    if (E->kind != ORC_EOS_VDW && !E->isothermal) return 0;
+    if (E->kind == ORC_EOS_WELL && !E->isothermal) return 0;
     if (E->isothermal && !(E->T0 > 0.0)) return 0;
     if (E->kind == ORC_EOS_WELL &&
         !(E->c[0] > 0.0 && E->c[1] > E->c[2] && E->c[2] > 0.0 && E->c[3] > 0.0))
@@ -167,11 +281,11 @@ static double eos_p(const orc_params *P, double rho, double T)
 }
 static double eos_e(const orc_params *P, double rho, double T)
 {
-    return orc_eos_e(&P->eos, P->a, P->R / P->delta, rho, T);
+    return orc_eos_e(&P->eos, P->a, P->b, P->R, P->R / P->delta, rho, T);
 }
 static double eos_T_of_e(const orc_params *P, double rho, double e)
 {
-    return orc_eos_T_of_e(&P->eos, P->a, P->R / P->delta, rho, e);
+    return orc_eos_T_of_e(&P->eos, P->a, P->b, P->R, P->R / P->delta, rho, e);
 }
 /* temperature of an initial or inflow state: T0 when isothermal */
 static double state_T(const orc_params *P, double T) { return P->eos.isothermal ? P->eos.T0 : T; }
@@ -625,7 +739,7 @@ static void korteweg(const orc_params *P, const double *rho, const double ghost_
                      double *Kxx, double *Kxy, double *Kyy)
 {
     int D = P->dim, Q = nq(P);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for collapse(2) schedule(static)
     for (int y = 0; y < P->ny; ++y) {
         for (int x = 0; x < P->nx; ++x) {
             int node = x + P->nx * y;
@@ -655,7 +769,7 @@ static void korteweg_force(const orc_params *P, const double *Kxx, const double 
 {
     int D = P->dim, Q = nq(P);
     const double zero[4] = {0.0, 0.0, 0.0, 0.0}; /* uniform inflow state: K = 0 */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for collapse(2) schedule(static)
     for (int y = 0; y < P->ny; ++y) {
         for (int x = 0; x < P->nx; ++x) {
             int node = x + P->nx * y;
@@ -681,7 +795,7 @@ static void heat_correction(const orc_params *P, const double *T, const double *
                             double *M0)
 {
     int Q = nq(P);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for collapse(2) schedule(static)
     for (int y = 0; y < P->ny; ++y) {
         for (int x = 0; x < P->nx; ++x) {
             int node = x + P->nx * y;
@@ -742,7 +856,8 @@ static int close_and_collide(const orc_params *P, const ghost_state gh[4], const
     double *Fny = malloc(sizeof(double) * N), *T = malloc(sizeof(double) * N);
     double *h = malloc(sizeof(double) * N), *mu = malloc(sizeof(double) * N);
     double *kc = malloc(sizeof(double) * N), *M0 = malloc(sizeof(double) * N);
-    if (!Kxx || !Kxy || !Kyy || !Fnx || !Fny || !T || !h || !mu || !kc || !M0) {
+    int *bad = calloc((size_t)N, sizeof(int));
+    if (!Kxx || !Kxy || !Kyy || !Fnx || !Fny || !T || !h || !mu || !kc || !M0 || !bad) {
         err = ORC_E_NOMEM;
         goto done;
     }
@@ -756,22 +871,26 @@ static int close_and_collide(const orc_params *P, const ghost_state gh[4], const
     }
     korteweg(P, rho, grho, Kxx, Kxy, Kyy);
     korteweg_force(P, Kxx, Kxy, Kyy, Fnx, Fny);
+    /* node by node (in parallel); the first failing node in node order decides the error */
+#pragma omp parallel for schedule(static)
     for (int n = 0; n < N; ++n) {
         double j[2] = {jx[n], D == 2 ? jy[n] : 0.0};
         double F[2] = {Fnx[n], Fny[n]};
         node_thermo t;
         close_node(P, rho[n], j, E[n], F, &t);
-        int bad = thermo_bad(P, rho[n], t.p);
-        if (bad) {
-            err = bad;
-            goto done;
-        }
+        bad[n] = thermo_bad(P, rho[n], t.p);
         T[n] = t.T;
         h[n] = t.h;
         mu[n] = t.mu;
         kc[n] = t.kc;
     }
+    for (int n = 0; n < N; ++n)
+        if (bad[n]) {
+            err = bad[n];
+            goto done;
+        }
     heat_correction(P, T, h, mu, kc, gT, gh_, gmu, gkc, M0);
+#pragma omp parallel for schedule(static)
     for (int n = 0; n < N; ++n) {
         double ls[3] = {lsx[n], D == 2 ? lsy[n] : 0.0, lst[n]};
         double fs[9], gs[9], fo[9], go[9], lo[3];
@@ -780,11 +899,8 @@ static int close_and_collide(const orc_params *P, const ghost_state gh[4], const
             gs[q] = gstr[(size_t)q * N + n];
         }
         double F[2] = {Fnx[n], Fny[n]};
-        int bad = orc_collide(P, ls, fs, gs, F, M0[n], fo, go, lo);
-        if (bad) {
-            err = bad;
-            goto done;
-        }
+        bad[n] = orc_collide(P, ls, fs, gs, F, M0[n], fo, go, lo);
+        if (bad[n]) continue;
         for (int q = 0; q < Q; ++q) {
             f[(size_t)q * N + n] = fo[q];
             g[(size_t)q * N + n] = go[q];
@@ -795,9 +911,14 @@ static int close_and_collide(const orc_params *P, const ghost_state gh[4], const
         Fx[n] = Fnx[n];
         if (D == 2) Fy[n] = Fny[n];
     }
+    for (int n = 0; n < N; ++n)
+        if (bad[n]) {
+            err = bad[n];
+            goto done;
+        }
 done:
     free(Kxx); free(Kxy); free(Kyy); free(Fnx); free(Fny);
-    free(T); free(h); free(mu); free(kc); free(M0);
+    free(T); free(h); free(mu); free(kc); free(M0); free(bad);
     return err;
 }
 
@@ -896,7 +1017,7 @@ int orc_step(const orc_params *P, int nsteps, double *f, double *g, double *ux, 
     }
     for (step = 0; step < nsteps; ++step) {
         cstate S = {f, g, ux, D == 2 ? uy : zy, th, Fx, D == 2 ? Fy : zy};
-#pragma omp parallel for schedule(dynamic, 1)
+#pragma omp parallel for collapse(2) schedule(dynamic, 8)
         for (int y = 0; y < P->ny; ++y) {
             for (int x = 0; x < P->nx; ++x) {
                 int n = x + P->nx * y;

@@ -40,8 +40,8 @@ typedef struct {
     double c[4];
 } orc_eos;
 double orc_eos_p(const orc_eos *E, double a, double b, double R, double rho, double T);
-double orc_eos_e(const orc_eos *E, double a, double Cv, double rho, double T);
-double orc_eos_T_of_e(const orc_eos *E, double a, double Cv, double rho, double e);
+double orc_eos_e(const orc_eos *E, double a, double b, double R, double Cv, double rho, double T);
+double orc_eos_T_of_e(const orc_eos *E, double a, double b, double R, double Cv, double rho, double e);
 double orc_eos_T_of_p(const orc_eos *E, double a, double b, double R, double rho, double p);
 int orc_eos_in_domain(const orc_eos *E, double b, double rho);
 int orc_eos_valid(const orc_eos *E);
@@ -63,11 +63,11 @@ static double wq(int q) { return W1[q / 9] * W1[(q / 3) % 3] * W1[q % 3]; }
 static double eos_p(const orc3_params *P, double rho, double T) { return orc_eos_p(&P->eos, P->a, P->b, P->R, rho, T); }
 static double eos_e(const orc3_params *P, double rho, double T)
 {
-    return orc_eos_e(&P->eos, P->a, P->R / P->delta, rho, T);
+    return orc_eos_e(&P->eos, P->a, P->b, P->R, P->R / P->delta, rho, T);
 }
 static double eos_T_of_e(const orc3_params *P, double rho, double e)
 {
-    return orc_eos_T_of_e(&P->eos, P->a, P->R / P->delta, rho, e);
+    return orc_eos_T_of_e(&P->eos, P->a, P->b, P->R, P->R / P->delta, rho, e);
 }
 /* temperature of an initial state: T0 when isothermal */
 static double state_T(const orc3_params *P, double T) { return P->eos.isothermal ? P->eos.T0 : T; }

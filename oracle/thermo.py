@@ -12,6 +12,8 @@ Everything follows Reyhanian, Dorschner & Karlin (arXiv:2002.09217):
   * Rankine-Hugoniot post-shock state                                  (App. E)
   * Maxwell's equal-area rule for the coexistence densities            (main text, Fig. 2)
   * the Dieterici pressure and its printed critical values             (Supplement, coexistence)
+  * the Dieterici internal energy e = C_v T + int [T (dp/dT)_v - p] dv, its heat
+    capacity, isentropes and isentropic sound speed                    (Supplement, thermodynamics)
   * the simplified (double-well) free energy near the critical point,
     with the printed saturated sound speeds                            (Supplement, speed of sound)
   * Maxwell's rule for any isotherm with one loop
@@ -280,10 +282,12 @@ A_DIET = 4.0 * R_SIM * B_DIET * 8.0 / 63.0
 
 @dataclass(frozen=True)
 class Dieterici:
-    """p = rho R T/(1 - b rho) exp(-a rho/(R T)) (Supplement, coexistence curve)."""
+    """p = rho R T/(1 - b rho) exp(-a rho/(R T)) (Supplement, coexistence curve), with the
+    caloric relation of the Supplement's thermodynamics."""
     a: float = A_DIET
     b: float = B_DIET
     R: float = R_SIM
+    delta: float = 1.0 / 3.0
 
     # critical values as printed (Supplement)
     @property
@@ -309,6 +313,52 @@ class Dieterici:
             raise ValueError("Maxwell construction needs T < T_cr")
         return maxwell_isotherm(lambda r: self.p(r, T), lambda r: self.dp_drho_T(r, T),
                                 1e-9, (1.0 - 1e-12) / self.b)
+
+    # caloric relation (Supplement, thermodynamics): de = C_v dT + [T (dp/dT)_v - p] dv with
+    # the constant (ideal-gas) C_v = R/delta, integrated along the isotherm from v -> oo
+    @property
+    def Cv(self) -> float:
+        return self.R / self.delta
+
+    def dp_dT_rho(self, rho, T):
+        return self.p(rho, T) / T * (1.0 + self.a * rho / (self.R * T))
+
+    def _dep(self, rho, T, power):
+        # int_0^rho [T dp/dT - p](r) / r^2 * (a r / (R T))^power dr; T dp/dT - p = p a r/(R T)
+        def f(r):   # p x / r^2 = a exp(-x) / (1 - b r), x = a r / (R T)
+            x = self.a * r / (self.R * T)
+            return self.a * math.exp(-x) / (1.0 - self.b * r) * x ** power
+        return quad(f, 0.0, float(rho), epsabs=0.0, epsrel=1e-13, limit=200)[0]
+
+    def e(self, rho, T):
+        return self.Cv * T - self._dep(rho, T, 0)
+
+    def cv(self, rho, T):
+        """(de/dT)_rho = C_v - int_0^rho T d^2p/dT^2 / r^2 dr, T d2p/dT2 = p x^2 / T."""
+        return self.Cv - self._dep(rho, T, 1) / T
+
+    def sound(self, rho, T):
+        """Isentropic speed of sound (App. A): (dp/drho)_T + T (dp/dT)_rho^2 / (rho^2 c_v),
+        with c_v = (de/dT)_rho of the state."""
+        return math.sqrt(self.dp_drho_T(rho, T) + T / (rho * rho * self.cv(rho, T)) * self.dp_dT_rho(rho, T) ** 2)
+
+    def T_isentrope(self, rho, rho0, T0):
+        """T along the isentrope through (rho0, T0): T ds = de - p/rho^2 drho = 0 gives
+        dT/drho = T (dp/dT)_rho / (rho^2 c_v), integrated from rho0 (accepts arrays)."""
+        from scipy.integrate import solve_ivp
+        rho = np.asarray(rho, dtype=np.float64)
+        out = np.empty_like(rho)
+        rhs = lambda r, T: [T[0] * self.dp_dT_rho(r, T[0]) / (r * r * self.cv(r, T[0]))]
+        for side in (rho >= rho0, rho < rho0):
+            if not np.any(side):
+                continue
+            end = rho[side].max() if rho[side].max() >= rho0 else rho[side].min()
+            if end == rho0:
+                out[side] = T0
+                continue
+            sol = solve_ivp(rhs, (rho0, float(end)), [T0], rtol=1e-12, atol=0.0, dense_output=True)
+            out[side] = sol.sol(rho[side])[0]
+        return out if out.ndim else float(out)
 
 
 @dataclass(frozen=True)

@@ -82,14 +82,16 @@ def compare(gpu, ref, fields=("rho", "ux", "uy", "E", "T", "p")):
     return {f: rel_err(gpu[f], ref[f], f) for f in fields}
 
 
-def pulse_speed(sim_factory, rho0, Tr, n=800, sigma=8.0, amp=1e-3, dt=0.2, times=(150.0, 300.0)):
+def pulse_speed(sim_factory, rho0, Tr, n=800, sigma=8.0, amp=1e-3, dt=0.2, times=(150.0, 300.0), isentrope=None):
     """Speed of the right-moving half of a Gaussian isentropic density pulse: the
     displacement of its centroid (a window of +-3 sigma around its peak) between two
-    times.  sim_factory(rho, T, dt) returns an object with step(n) and moments()."""
+    times.  sim_factory(rho, T, dt) returns an object with step(n) and moments().
+    isentrope(rho) gives T along the pulse (default: the van der Waals isentrope through
+    rho0 at Tr T_cr)."""
     x = np.arange(n, dtype=float)
     x0 = n / 2
     rho = rho0 * (1.0 + amp * np.exp(-0.5 * ((x - x0) / sigma) ** 2))
-    T = VdW().T_isentrope(rho, rho0, Tr * VdW().T_cr)
+    T = VdW().T_isentrope(rho, rho0, Tr * VdW().T_cr) if isentrope is None else isentrope(rho)
     sim = sim_factory(rho, T, dt)
     pos, done = [], 0
     for t in times:
