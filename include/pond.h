@@ -72,15 +72,19 @@ typedef struct {
     double a, b, R;           /* van der Waals p = rho R T/(1 - b rho) - a rho^2, or
                                  Dieterici p = rho R T/(1 - b rho) exp(-a rho/(R T))  */
     double delta;             /* C_v = R/delta, 0 < delta <= 2/3 (main text)            */
-    int eos;                  /* POND_EOS_VDW (with the energy equation, or isothermal);
-                                 POND_EOS_DIETERICI and POND_EOS_DOUBLE_WELL need
+    int eos;                  /* POND_EOS_VDW (e = C_v T - a rho) and POND_EOS_DIETERICI
+                                 (e = C_v T + the integral of T (dp/dT)_v - p over v
+                                 from the ideal-gas limit; T from e by Newton's method;
+                                 Supplement, thermodynamics) run with the energy
+                                 equation or isothermally; POND_EOS_DOUBLE_WELL needs
                                  isothermal.  Double well: p = p0 + rho dE0/drho - E0
-                                 with E0 = beta (rho - rho_l)^2 (rho - rho_v)^2        */
+                                 with E0 = beta (rho - rho_l)^2 (rho - rho_v)^2.  The
+                                 Dieterici energy is evaluated for T > a/(150 R b).     */
     int isothermal;           /* nonzero: T = T0 wherever the step needs a temperature
                                  (passes, closure, initial and inflow states, read-back;
                                  the T given to pond_init_fields is not used).  The
                                  energy population is then passive and carries
-                                 e = C_v T (- a rho for van der Waals).                */
+                                 e(rho, T0) of the law (C_v T for the double well).    */
     double T0;                /* isothermal temperature, > 0                            */
     double eos_c[4];          /* POND_EOS_DOUBLE_WELL: beta > 0, rho_l > rho_v > 0, p0 > 0 */
     double omega;             /* BGK relaxation, 0 < omega < 2; mu = (1/omega - 1/2) p dt */
@@ -118,7 +122,7 @@ typedef struct {
  * error).  Errors: POND_E_INVALID (dim, sizes: N <= 2^30 nodes, 2^29 in 3D;
  * 0 < delta <= 2/3, 0 < omega < 2, n_pass >= 1, dt > 0, tile in range, two_kernel
  * not 0 or 1, inflow state
- * with p <= 0, a non-periodic face in 3D; eos out of range, a non-van-der-Waals eos
+ * with p <= 0, a non-periodic face in 3D; eos out of range, the double well
  * without isothermal, T0 <= 0 when isothermal, double-well constants other than
  * beta > 0, rho_l > rho_v > 0, p0 > 0), POND_E_NOMEM, POND_E_DEVICE. */
 int pond_create(const pond_config *cfg, pond_handle **out);

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpond.so")
 SOURCES = ["pond_kernels.hip", "pond_step.hip", "pond_kernels3.hip", "pond_api.hip", "pond_batch.hip", "pond_noalloc.hip"]
-HEADERS = ["pond_device.h", "pond_internal.h", "pond_collide.h", "pond_stream.h"]
+HEADERS = ["pond_device.h", "pond_internal.h", "pond_collide.h", "pond_stream.h", "pond_eos.h"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

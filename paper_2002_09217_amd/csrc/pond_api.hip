@@ -10,6 +10,7 @@
 #include <new>
 
 #include "pond.h"
+#include "pond_eos.h"
 #include "pond_handle.h"
 #include "pond_internal.h"
 
@@ -161,7 +162,9 @@ bool make_ghost(const pond_config &c, const double st[5], GhostFace &G)
     const double p = host_p(c, rho, T);
     const bool domain = c.eos == POND_EOS_DOUBLE_WELL || 1.0 - c.b * rho > 0.0;
     if (!(rho > 0.0) || !(p > 0.0) || !domain || !std::isfinite(p)) return false;
-    const double e = (c.R / c.delta) * T - (c.eos == POND_EOS_VDW ? c.a * rho : 0.0);
+    const double Cv = c.R / c.delta;
+    const double e = c.eos == POND_EOS_DIETERICI ? diet_energy(c.a, c.b, c.R, Cv, rho, T, nullptr)
+                                                 : Cv * T - (c.eos == POND_EOS_VDW ? c.a * rho : 0.0);
     const double theta = p / (rho * (1.0 / 3.0));
     const double s = std::sqrt(theta);
     const int Q = c.dim == 2 ? 9 : 3;
@@ -240,9 +243,9 @@ int validate(const pond_config *cfg)
     if (c.n_pass < 1 || c.n_pass > 64 || !(c.dt > 0.0) || !(c.R > 0.0)) return POND_E_INVALID;
     if (c.precision != POND_FP64 && c.precision != POND_FP32_STORE && c.precision != POND_FP32_STORE_FP64_MATH)
         return POND_E_INVALID;
-    // equation of state: the Dieterici and double-well pressures only isothermally
+    // equation of state: the double-well pressure only isothermally
     if (c.eos < POND_EOS_VDW || c.eos > POND_EOS_DOUBLE_WELL) return POND_E_INVALID;
-    if (c.eos != POND_EOS_VDW && !c.isothermal) return POND_E_INVALID;
+    if (c.eos == POND_EOS_DOUBLE_WELL && !c.isothermal) return POND_E_INVALID;
     if (c.isothermal && !(c.T0 > 0.0 && std::isfinite(c.T0))) return POND_E_INVALID;
     if (c.eos == POND_EOS_DOUBLE_WELL &&
         !(c.eos_c[0] > 0.0 && c.eos_c[1] > c.eos_c[2] && c.eos_c[2] > 0.0 && c.eos_c[3] > 0.0))

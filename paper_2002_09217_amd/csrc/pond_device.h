@@ -9,6 +9,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "pond_eos.h"
 #include "pond_internal.h"
 
 namespace pond {
@@ -36,11 +37,12 @@ constexpr bool kDeviationStore = sizeof(PopT) == 4;
 #define POND_GLOBAL __attribute__((address_space(1)))
 
 // ---------------------------------------------------------------------------
-// Equations of state (main text; App. A; Supplement).  The van der Waals fluid runs
-// with the energy equation (T from e = C_v T - a rho) or isothermally; the Dieterici
-// and double-well pressures run isothermally: T = T0 wherever a temperature is
-// needed, and the energy population is passive, carrying e = C_v T (- a rho for van
-// der Waals).  The kind is uniform over a launch, so the branches are scalar.  GEN =
+// Equations of state (main text; App. A; Supplement).  The van der Waals fluid (e =
+// C_v T - a rho) and the Dieterici fluid (e = C_v T plus its departure integral, see
+// pond_eos.h) run with the energy equation or isothermally; the double-well pressure
+// runs isothermally.  Isothermal runs take T = T0 wherever a temperature is needed, and
+// the energy population is passive, carrying e(rho, T0) of the law (C_v T for the
+// double well).  The kind is uniform over a launch, so the branches are scalar.  GEN =
 // false compiles the van der Waals fluid with the energy equation only: the streaming
 // kernels are instantiated both ways, so that the common case carries none of the
 // other laws' code and registers.
@@ -62,7 +64,9 @@ __device__ __forceinline__ double eos_p(const PT &P, double rho, double T)
 template <bool GEN = true, typename PT>
 __device__ __forceinline__ double eos_T_of_e(const PT &P, double rho, double e)
 {
-    return GEN && P.isothermal ? P.T0 : (e + P.a * rho) * P.inv_Cv;
+    if (GEN && P.isothermal) return P.T0;
+    if (GEN && P.eos == kEosDieterici) return diet_T_of_e(P.a, P.b, P.R, P.Cv, rho, e);
+    return (e + P.a * rho) * P.inv_Cv;
 }
 // temperature of an initial or inflow state given T
 template <typename PT>
@@ -70,15 +74,18 @@ __device__ __forceinline__ double eos_state_T(const PT &P, double T)
 {
     return P.isothermal ? P.T0 : T;
 }
-// temperature from the pressure (read-back): the van der Waals inversion, or T0
+// temperature from the pressure (read-back): the inversion of the law's pressure, or T0
 template <typename PT>
 __device__ __forceinline__ double eos_T_of_p(const PT &P, double rho, double p)
 {
-    return P.isothermal ? P.T0 : (p + P.a * rho * rho) * (1.0 - P.b * rho) / (rho * P.R);
+    if (P.isothermal) return P.T0;
+    if (P.eos == kEosDieterici) return diet_T_of_p(P.a, P.b, P.R, rho, p);
+    return (p + P.a * rho * rho) * (1.0 - P.b * rho) / (rho * P.R);
 }
 template <typename PT>
 __device__ __forceinline__ double eos_e(const PT &P, double rho, double T)
 {
+    if (P.eos == kEosDieterici) return diet_energy(P.a, P.b, P.R, P.Cv, rho, T, nullptr);
     return P.Cv * T - (P.eos == kEosVdw ? P.a * rho : 0.0);
 }
 // bit set of the admissibility violations of a state (pressure domain, finiteness)

@@ -74,7 +74,6 @@ def test_null_arguments():
 
 @pytest.mark.parametrize("kw", [
     dict(eos=3, isothermal=1, T0=0.1),                                       # unknown law
-    dict(eos=pond.EOS_DIETERICI),                                            # needs isothermal
     dict(eos=pond.EOS_DOUBLE_WELL, T0=0.1),                                  # needs isothermal
     dict(eos=pond.EOS_VDW, isothermal=1, T0=0.0),                            # T0 <= 0
     dict(eos=pond.EOS_DOUBLE_WELL, isothermal=1, T0=0.1, eos_c=(0.0, 5.0, 0.5, 0.1)),   # beta

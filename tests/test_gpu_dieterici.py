@@ -1,0 +1,90 @@
+"""The Dieterici fluid with the energy equation on the HIP path through the C ABI
+(Supplement: thermodynamics of a real gas with the Dieterici pressure): parity with the
+oracle on identical seeded inputs in 1D, 2D and 3D, both step forms and the FP32
+storage forms, and an isentropic pulse at the sound speed of App. A with the heat
+capacity (de/dT)_rho of the state."""
+import numpy as np
+import pytest
+
+from oracle.thermo import Dieterici
+from paper_2002_09217_amd import pond, workloads as W
+from tests.common import compare, pulse_speed, run_gpu, run_oracle, run_oracle3
+
+pytestmark = pytest.mark.gpu
+
+DIET = Dieterici()
+KW = dict(eos=pond.EOS_DIETERICI, isothermal=0, a=DIET.a, b=DIET.b, R=DIET.R)
+
+
+def _check(ref, got, fields, tol, name):
+    errs = compare(got, ref, fields)
+    print(name, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    assert not bad, f"{name}: {bad}"
+
+
+@pytest.mark.parametrize("two_kernel", [0, 1])
+@pytest.mark.parametrize("dim", [1, 2])
+def test_parity_supercritical(dim, two_kernel):
+    case = W.perturbed(40, 36, seed=11, dim=dim, rho0=2.5, t_over_tcr=1.05, u0=(0.05, -0.02), kappa=0.0176,
+                       dt=0.2, **KW)
+    fields = ("rho", "ux", "uy", "E", "T", "p") if dim == 2 else ("rho", "ux", "E", "T", "p")
+    print(f"dim {dim} two_kernel {two_kernel}", flush=True)
+    _check(run_oracle(case, 20), run_gpu(case, 20, two_kernel=two_kernel), fields, 1e-12, case.name)
+
+
+@pytest.mark.parametrize("two_kernel", [0, 1])
+def test_parity_subcritical_droplet(two_kernel):
+    """A droplet at 0.9 T_cr between the Dieterici coexistence densities, with the
+    interface energy on: liquid, vapour and interface states in one run."""
+    T = 0.9 * DIET.T_cr
+    rv, rl, _ = DIET.maxwell(T)
+    n = 48
+    rho = W.droplet_field(n, n, rv, rl, [(n / 2, n / 2)], [10.0], 4.0)
+    case = W.Case(name="dieterici_droplet48", dim=2, n=(n, n),
+                  params=W.base_params(omega=1.5, kappa=0.0176, dt=0.1, **KW),
+                  rho=rho, u=np.zeros((2, n * n)), T=np.full(n * n, T), steps=30)
+    print(f"droplet two_kernel {two_kernel}", flush=True)
+    _check(run_oracle(case, 30), run_gpu(case, 30, two_kernel=two_kernel), ("rho", "ux", "uy", "E", "T", "p"),
+           1e-12, case.name)
+
+
+@pytest.mark.parametrize("precision,tol", [(pond.FP32_STORE, 1e-4), (pond.FP32_STORE_FP64_MATH, 1e-6)])
+def test_parity_fp32_storage_forms(precision, tol):
+    case = W.perturbed(33, 29, seed=3, rho0=2.5, t_over_tcr=1.05, u0=(0.02, 0.04), kappa=0.0176, dt=0.2, **KW)
+    print(f"precision {precision}", flush=True)
+    _check(run_oracle(case, 20), run_gpu(case, 20, precision), ("rho", "ux", "uy", "E", "T", "p"), tol, case.name)
+
+
+def test_parity_three_dimensions():
+    case = W.perturbed3(13, 10, 7, seed=2, rho0=2.5, t_over_tcr=1.05, u0=(0.03, -0.02, 0.01), kappa=0.0176,
+                        dt=0.2, **KW)
+    print("3d", flush=True)
+    _check(run_oracle3(case, 8), run_gpu(case, 8), ("rho", "ux", "uy", "uz", "E", "T", "p"), 1e-12, case.name)
+
+
+def _states():
+    T = 0.9 * DIET.T_cr
+    rv, rl, _ = DIET.maxwell(T)
+    return [(rv, 0.9), (rl, 0.9), (3.5, 1.2)]
+
+
+@pytest.mark.parametrize("precision", [pond.FP64, pond.FP32_STORE, pond.FP32_STORE_FP64_MATH])
+def test_pulse_travels_at_the_isentropic_sound_speed(precision):
+    for rho0, tr in _states():
+        T0 = tr * DIET.T_cr
+
+        def factory(rho, T, dt):
+            p = W.base_params(omega=1.5, dt=dt, **KW)
+            cfg = pond.Config(dim=1, n=(rho.size,), bc=((0, 0),), a=p["a"], b=p["b"], R=p["R"], delta=p["delta"],
+                              omega=1.5, kappa=0.0, dt=dt, n_pass=2, eos=pond.EOS_DIETERICI, isothermal=0,
+                              precision=precision, tile=0)
+            lat = pond.Lattice(cfg)
+            lat.init_fields(rho, np.zeros(rho.size), T)
+            return lat
+
+        c_ref = DIET.sound(rho0, T0)
+        times = (round(60.0 / c_ref), round(120.0 / c_ref))
+        c = pulse_speed(factory, rho0, tr, times=times, isentrope=lambda r: DIET.T_isentrope(r, rho0, T0))
+        print(f"rho {rho0:.4f} T/Tcr {tr}: pulse {c:.5f} theory {c_ref:.5f} ({c / c_ref - 1:+.2e})", flush=True)
+        assert c == pytest.approx(c_ref, rel=3e-3)

@@ -64,7 +64,7 @@ def test_parity_three_dimensions(kind, T0, rho0):
 
 def test_admissibility_rules():
     base = W.perturbed(16, 16, seed=1, rho0=1.5)
-    bad = [dict(eos=pond.EOS_DIETERICI),                                     # not isothermal
+    bad = [dict(eos=pond.EOS_DOUBLE_WELL, eos_c=(1e-3, 5.0, 0.5, 0.1)),      # not isothermal
            dict(eos=pond.EOS_VDW, isothermal=1, T0=0.0),                     # T0 <= 0
            dict(eos=pond.EOS_DOUBLE_WELL, isothermal=1, T0=0.1, eos_c=(1e-3, 0.5, 5.0, 0.1)),  # rho_l < rho_v
            dict(eos=pond.EOS_DOUBLE_WELL, isothermal=1, T0=0.1, eos_c=(1e-3, 5.0, 0.5, 0.0)),  # p0 = 0
