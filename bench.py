@@ -74,16 +74,17 @@ def sources_digest():
     import hashlib
 
     h = hashlib.sha256()
-    for f in ("pond_kernels.hip", "pond_device.h", "pond_internal.h"):
+    for f in ("pond_kernels.hip", "pond_step.hip", "pond_device.h", "pond_internal.h", "pond_collide.h",
+              "pond_stream.h", "pond_eos.h"):
         with open(os.path.join(ROOT, "paper_2002_09217_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def profile_record(kind, kernel_prefix):
-    """A machine-readable line `<kind>: kernel=... key=value ...` of a committed rocprofv3
-    summary for a kernel, or (None, None) when the summary was taken on other kernel
-    sources than the current ones."""
+def profile_record(kind, kernel_prefix, nodes):
+    """A machine-readable line `<kind>: kernel=... nodes=... key=value ...` of a committed
+    rocprofv3 summary for a kernel launched over `nodes` lattice nodes, or (None, None)
+    when the summary was taken on other kernel sources than the current ones."""
     import glob
 
     digest = sources_digest()
@@ -92,14 +93,15 @@ def profile_record(kind, kernel_prefix):
             if not line.startswith(kind + ":"):
                 continue
             kv = dict(item.split("=", 1) for item in line.split()[1:])
-            if kv.get("kernel", "").startswith(kernel_prefix.replace(" ", "")) and kv.get("sources_sha256") == digest:
+            if (kv.get("kernel", "").startswith(kernel_prefix.replace(" ", "")) and kv.get("sources_sha256") == digest
+                    and kv.get("nodes") == str(nodes)):
                 return kv, os.path.relpath(path, ROOT)
     return None, None
 
 
-def traffic_from_profile(kernel_prefix):
+def traffic_from_profile(kernel_prefix, nodes):
     """HBM bytes per launch of a kernel from the committed rocprofv3 counter summary."""
-    kv, src = profile_record("traffic", kernel_prefix)
+    kv, src = profile_record("traffic", kernel_prefix, nodes)
     return (int(float(kv["bytes_per_launch"])), src) if kv else (None, None)
 
 
@@ -329,9 +331,9 @@ def main():
     t_step = kern64["k_step"] * 1e-6
     achieved = flops / t_step / 1e12
     k_name = "k_step<2, false, double, {tx}, {ty}".format(**kern64["tile"])
-    traffic, traffic_src = traffic_from_profile(k_name)
+    traffic, traffic_src = traffic_from_profile(k_name, N)
     # the same kernel's mean duration in the committed rocprofv3 kernel trace (same sources)
-    dur, dur_src = profile_record("duration", k_name)
+    dur, dur_src = profile_record("duration", k_name, N)
     prof_us = float(dur["avg_us"]) if dur else None
 
     cpu = None

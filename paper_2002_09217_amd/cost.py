@@ -2,14 +2,18 @@
 throughput against the MI355X rooflines.
 
 Bytes (compulsory HBM traffic; neighbour reuse through LDS or caches is not counted).
-A step is two kernels:
+The fused step is one kernel: it reads the streamed-state moment planes of the previous
+step (rho, u and the central moments: 18 planes in 2D, 6 in 1D), recomputes the collision
+of each tile and its halo on chip, streams, and writes the next streamed state
+(fused_step_bytes_per_node: 288 B in FP64 D2Q9, 176 B with the FP32 moment planes).
+The two-kernel step stores the collided state in between:
   streaming  reads one state (2 Q populations and the five side fields: gauge u_x, u_y,
-             theta and the force F_x, F_y) and writes the streamed state as gauge-free
-             moment planes (rho, u and the central moments: 18 planes in 2D, 6 in 1D);
+             theta and the force F_x, F_y) and writes the moment planes;
   collision  reads those moment planes and writes the next state.
 bytes_per_node_step is that two-kernel traffic (656 B in FP64 D2Q9, 544 B with FP32
 population storage).  fused_bytes_per_node_step is the floor of a step that kept the
-streamed state on chip, i.e. one state read and one state written (368 B and 256 B).
+collided populations with their side fields on chip, i.e. one such state read and one
+written (368 B and 256 B).
 
 FLOPs of the streaming kernel (the dominant one), per receiver and pass, for the
 moment-first reconstruction: every set (f, g) has NF moment fields; each field is
@@ -80,12 +84,13 @@ def fused_step_bytes_per_node(dim: int, fp32_store: bool) -> int:
 
 
 def collide_flops_per_node(dim: int) -> int:
-    """Closure and collision of one node (my count, FMA = 2 flops): Korteweg stress and
-    its divergence (~80), thermodynamic state (~30), both sets rebuilt from their central
-    moments (2 x 108), f collision with the force source (~70), g collision with M0 and
-    the force-extended equilibrium (~280), and the donor moments about the tile velocity
-    (2 x 60)."""
-    return 800 if dim == 2 else 200
+    """Closure and collision of one node in moment space, as the fused step computes it
+    (my count, FMA = 2 flops).  2D: Korteweg stress and its divergence (~90),
+    thermodynamic state (~30), the heat-flux correction M0 (~100), f collision on its
+    nine central moments with the force source (~80), g collision: the force-extended
+    equilibrium and source polynomials (~130) and their nine moments (~190), and both
+    sets shifted to the tile velocity (~55).  1D: the same terms on three moments."""
+    return 680 if dim == 2 else 230
 
 
 def stream_flops_per_node(dim: int, n_pass: int) -> int:
