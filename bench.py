@@ -70,14 +70,18 @@ def gpu_run(case, precision, steps, warmup, stream, timed_steps=500, two_kernel=
 
 
 def sources_digest():
-    """SHA-256 of the 2D kernel sources the committed profile summaries record."""
+    """SHA-256 of the 2D kernel sources the committed profile summaries record: the code
+    with comments and blank lines taken out, so that edits of comments keep a summary."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
     for f in ("pond_kernels.hip", "pond_step.hip", "pond_device.h", "pond_internal.h", "pond_collide.h",
               "pond_stream.h", "pond_eos.h"):
-        with open(os.path.join(ROOT, "paper_2002_09217_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2002_09217_amd", "csrc", f)) as fh:
+            code = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        lines = (re.sub(r"//.*$", "", line).rstrip() for line in code.splitlines())
+        h.update("\n".join(line for line in lines if line).encode())
     return h.hexdigest()
 
 

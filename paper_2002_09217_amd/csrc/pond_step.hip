@@ -7,8 +7,11 @@
 //      2-node halo: density on a 5-node halo, Korteweg stress K on 4 (eq. 18), force
 //      F = -div K and the thermodynamic state on 3 (App. F), the heat-flux correction M0
 //      (eq. 9) and the collisions of f and g on 2 (eqs. 16-22);
-//   2. reduces every collided donor to its nine moments about the tile's reference
-//      velocity in LDS, exactly as the two-kernel step does with stored populations;
+//   2. collides every donor of the tile and its halo on its central moments (the
+//      collision is linear in the populations and its equilibria and sources are
+//      polynomials of the peculiar velocity, pond_collide.h) and shifts them to the
+//      tile's reference velocity in LDS: the moments the two-kernel step takes of its
+//      stored populations;
 //   3. streams (the predictor-corrector passes of k_stream, pond_stream.h) and writes the
 //      new streamed state.
 // So the collided populations never reach HBM: a step reads and writes the 18 moment
