@@ -3,9 +3,9 @@
 // error flags and step counter, and each step kernel reads a member's descriptor
 // exactly as it does for a lattice stepped alone, so results are bitwise identical.
 //
-// Members that share (dim, precision, streaming tile shape) form a group; a batch
-// step is one launch of each step kernel per group over the concatenated tiles of
-// its members.  The members of a batch share the form of the step (fused, or two
+// Members that share (dim, precision, tile shape, equation-of-state variant) form a
+// group; a batch step is one launch of each step kernel per group over the
+// concatenated tiles of its members.  The members of a batch share the form of the step (fused, or two
 // kernels), which fixes the number of state buffers or ring slots R (3 or 2) they cycle
 // through.  R descriptor arrays per batch: array a holds, for every member, the
 // descriptor reading the state a steps after the one current when the arrays were built;
@@ -75,7 +75,7 @@ void drop_graphs(pond_batch *b)
             }
 }
 
-// regroup the members and upload both descriptor arrays
+// regroup the members and upload the descriptor arrays
 int rebuild(pond_batch *b)
 {
     drop_graphs(b);

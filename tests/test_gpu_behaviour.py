@@ -118,6 +118,32 @@ def test_halo_violation_keeps_last_state():
     lat.close()
 
 
+@pytest.mark.parametrize("two_kernel", [0, 1])
+def test_failure_mid_run_keeps_the_last_completed_state(two_kernel):
+    """A run that leaves the EoS domain in step 310 (serving job 1: 128^2, four droplets at
+    0.85 T_cr) ends with POND_E_PRESSURE or POND_E_NONFINITE, whichever the failing state
+    shows first, after 309 completed steps, and the handle holds bitwise the state of a run
+    of exactly 309 steps.  The fused step finds a closure error in the state it reads, one
+    step late, and steps back to the state before."""
+    case = W.serving_jobs()[1][1]
+    print(f"two_kernel {two_kernel}: serving job 1 {case.meta}", flush=True)
+    a = _lattice(case, two_kernel=two_kernel)
+    b = _lattice(case, two_kernel=two_kernel)
+    try:
+        a.step(300)
+        with pytest.raises(pond.PondError) as err:
+            a.step(40)
+        print(f"   {err.value}", flush=True)
+        assert err.value.code in (-4, -5), err.value
+        assert "step 310" in str(err.value)
+        assert a.steps_done() == 309
+        b.step(309)
+        assert np.array_equal(_fields(a.moments()), _fields(b.moments()))
+    finally:
+        a.close()
+        b.close()
+
+
 def test_autotuned_tile_is_valid_and_results_agree_to_roundoff():
     case = W.perturbed(64, 48, seed=12, kappa=0.0176)
     auto = _lattice(case, tile=-1)

@@ -1,6 +1,9 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle on identical seeded
 inputs.  Bar: 1e-12 relative L-infinity on rho, u, E (and T, p) for the FP64 form;
-1e-4 for the FP32-storage form on smooth cases.  Both forms of the 1D/2D step run: the
+1e-5 for the FP32-storage form over 100 steps (FP32 rounding, 6e-8 of the deviations from
+the tile reference per step, accumulating like a random walk over 100 steps and amplified
+a few times at droplet interfaces: 1e-7 to 3e-6 observed) and 1e-6 for FP32 storage with
+FP64 arithmetic.  Both forms of the 1D/2D step run: the
 fused one-kernel step (the default) and the two-kernel step with stored populations.
 
 Sizes span several 32 x 8 streaming tiles with ragged tails; the full 256 x 256
@@ -116,12 +119,12 @@ def test_full_size_droplet_shock_1024x512_few_steps():
 
 @pytest.mark.parametrize("two_kernel", [0, 1])
 @pytest.mark.parametrize("which", ["perturbed", "droplet"])
-def test_fp32_storage_within_1e4(which, two_kernel):
+def test_fp32_storage_within_1e5(which, two_kernel):
     if which == "perturbed":
         case = W.perturbed(40, 36, seed=21, kappa=0.0176)
     else:
         case = W.static_droplet(n=64, radius=14.0)
-    _check(case, 100, tol=1e-4, precision=pond.FP32_STORE, two_kernel=two_kernel)
+    _check(case, 100, tol=1e-5, precision=pond.FP32_STORE, two_kernel=two_kernel)
 
 
 @pytest.mark.parametrize("two_kernel", [0, 1])
@@ -144,7 +147,7 @@ def test_every_stream_tile_shape_2d(tile, two_kernel):
     _check(case, 30, tile=tile, two_kernel=two_kernel)
 
 
-@pytest.mark.parametrize("precision,tol", [(pond.FP32_STORE, 1e-4), (pond.FP32_STORE_FP64_MATH, 1e-6)])
+@pytest.mark.parametrize("precision,tol", [(pond.FP32_STORE, 1e-5), (pond.FP32_STORE_FP64_MATH, 1e-6)])
 @pytest.mark.parametrize("tile", range(6))
 def test_every_stream_tile_shape_2d_fp32_storage(tile, precision, tol):
     """Each tile shape's FP32-storage windows (FP32 rows summed in FP32, or FP64 rows added
