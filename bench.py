@@ -233,7 +233,7 @@ def cpu_baseline(case, budget_s):
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return dict(value=case.N * n / dt / 1e6, unit="MLUPS", cores=cores, kind="oracle",
                 sample=f"{case.name}: {n} steps of the full lattice after 1 untimed step "
-                       f"({dt:.1f} s, FP64, OpenMP over rows)")
+                       f"({dt:.1f} s, FP64, OpenMP over nodes)")
 
 
 def main():
