@@ -99,6 +99,37 @@ def test_outflow_on_every_face_2d(tile):
     _check(case, 30, tile=tile)
 
 
+@pytest.mark.parametrize("two_kernel", [0, 1])
+def test_inflow_outflow_1d(two_kernel):
+    """D1Q3 with an inflow face at x = 0 (the fused step's ghost donors and closure cells in
+    1D) and an outflow face at the other end."""
+    case = W.perturbed(150, 1, seed=81, dim=1, kappa=0.0176, u0=(0.08, 0.0))
+    case.bc = ((W.INFLOW, W.OUTFLOW), (W.PERIODIC, W.PERIODIC))
+    case.inflow = ((0, 0, (2.0, 0.08, 0.0, 1.05 * W.T_CR)),)
+    _check(case, 50, fields=("rho", "ux", "E", "T", "p"), two_kernel=two_kernel)
+
+
+@pytest.mark.parametrize("two_kernel", [0, 1])
+def test_inflow_on_a_y_face(two_kernel):
+    """Inflow through the low y face, outflow through the high one, periodic in x."""
+    case = W.perturbed(30, 41, seed=82, kappa=0.0176, u0=(0.0, 0.06))
+    case.bc = ((W.PERIODIC, W.PERIODIC), (W.INFLOW, W.OUTFLOW))
+    case.inflow = ((1, 0, (2.0, 0.0, 0.06, 1.05 * W.T_CR)),)
+    _check(case, 40, two_kernel=two_kernel)
+
+
+@pytest.mark.parametrize("two_kernel", [0, 1])
+def test_tiny_lattices_with_outflow_faces(two_kernel):
+    """Lattices smaller than every halo, outflow on all faces: the copy rules clamp across
+    the whole lattice."""
+    for nx, ny, dim in ((3, 5, 2), (2, 2, 2), (4, 1, 1)):
+        case = W.perturbed(nx, ny, seed=90 + nx * 10 + ny, dim=dim, kappa=0.0176, u0=(0.05, 0.02))
+        case.bc = ((W.OUTFLOW, W.OUTFLOW), (W.OUTFLOW, W.OUTFLOW) if dim == 2 else (W.PERIODIC, W.PERIODIC))
+        fields = ("rho", "ux", "uy", "E", "T", "p") if dim == 2 else ("rho", "ux", "E", "T", "p")
+        print(f"tiny outflow lattice {nx}x{ny} dim {dim}", flush=True)
+        _check(case, 10, fields=fields, two_kernel=two_kernel)
+
+
 def test_tiny_periodic_lattices():
     for nx, ny in ((3, 5), (1, 9), (7, 1)):
         case = W.perturbed(nx, ny, seed=nx * 10 + ny, kappa=0.0176)
