@@ -88,3 +88,43 @@ def test_pulse_travels_at_the_isentropic_sound_speed(precision):
         c = pulse_speed(factory, rho0, tr, times=times, isentrope=lambda r: DIET.T_isentrope(r, rho0, T0))
         print(f"rho {rho0:.4f} T/Tcr {tr}: pulse {c:.5f} theory {c_ref:.5f} ({c / c_ref - 1:+.2e})", flush=True)
         assert c == pytest.approx(c_ref, rel=3e-3)
+
+
+@pytest.mark.parametrize("precision", [pond.FP64, pond.FP32_STORE])
+def test_slab_with_the_energy_equation_reaches_maxwell_coexistence(precision):
+    """Supplement, coexistence curve, with the energy equation on: a liquid slab in its
+    vapour at 0.8, 0.9 and 0.95 T_cr relaxes to a uniform temperature, and the densities at
+    the phase centres (averaged over 8000 steps after 4000) are Maxwell's at that
+    temperature (measured within 0.06%)."""
+    N = 400
+    x = np.arange(N)
+    prof = 0.5 * (np.tanh((x - N / 4) / 3.0) - np.tanh((x - 3 * N / 4) / 3.0))
+    for tr in (0.8, 0.9, 0.95):
+        T0 = tr * DIET.T_cr
+        rv, rl, _ = DIET.maxwell(T0)
+        p = W.base_params(omega=1.0, kappa=0.0176, dt=0.1, **KW)
+        cfg = pond.Config(dim=1, n=(N,), bc=((0, 0),), a=p["a"], b=p["b"], R=p["R"], delta=p["delta"], omega=1.0,
+                          kappa=0.0176, k_scale=p["k_scale"], dt=0.1, n_pass=2, eos=pond.EOS_DIETERICI, isothermal=0,
+                          precision=precision, tile=0)
+        lat = pond.Lattice(cfg)
+        try:
+            lat.init_fields(rv + (rl - rv) * prof, np.zeros(N), np.full(N, T0))
+            lat.step(4000)
+            vap, liq, tv, tl = [], [], [], []
+            for _ in range(40):
+                lat.step(200)
+                m = lat.moments()
+                r, T = m["rho"], m["T"]
+                vap.append(0.5 * (r[:20].mean() + r[-20:].mean()))
+                liq.append(r[N // 2 - 10:N // 2 + 10].mean())
+                tv.append(0.5 * (T[:20].mean() + T[-20:].mean()))
+                tl.append(T[N // 2 - 10:N // 2 + 10].mean())
+        finally:
+            lat.close()
+        Tv, Tl = np.mean(tv), np.mean(tl)
+        rv_b, rl_b, _ = DIET.maxwell(0.5 * (Tv + Tl))
+        ev, el = np.mean(vap) / rv_b - 1.0, np.mean(liq) / rl_b - 1.0
+        print(f"T/T_cr {tr}: bulk T {Tv / DIET.T_cr:.5f} / {Tl / DIET.T_cr:.5f}, vapour {ev:+.2e} liquid {el:+.2e}",
+              flush=True)
+        assert abs(Tv / Tl - 1.0) < 1e-3
+        assert abs(ev) < 5e-3 and abs(el) < 5e-3
