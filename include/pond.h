@@ -169,8 +169,9 @@ int pond_tile_info(const pond_handle *h, int *out);
 /* Release everything owned by h.  NULL is accepted. */
 int pond_destroy(pond_handle *h);
 
-/* Checkpoint / resume.  A checkpoint holds the current state (the stored populations and
- * side fields of the last completed step, in the handle's precision), the step count,
+/* Checkpoint / resume.  A checkpoint holds the current state of the last completed step
+ * (fused step: the streamed-state moment planes; two kernels and D3Q27: the stored
+ * populations and side fields; in the handle's precision), the step count, the step form,
  * the streaming tile shape in use and the configuration it belongs to.  Loading it into a
  * handle of the same configuration and stepping on gives bitwise the results the saving
  * handle gets (the handle adopts the checkpoint's tile shape for that).
@@ -182,8 +183,8 @@ int pond_destroy(pond_handle *h);
  * pond_load: make the state of buf current in h, as if h had just completed the saved
  *   number of steps; clears the error state and records the step graphs as
  *   pond_init_fields does.  Errors: POND_E_INVALID (NULL, buffer too
- *   small, not a checkpoint, or saved from another lattice shape, precision or set of
- *   parameters), POND_E_STATE (h is a member of a batch). */
+ *   small, not a checkpoint, or saved from another lattice shape, precision, step form or
+ *   set of parameters), POND_E_STATE (h is a member of a batch). */
 int pond_checkpoint_size(const pond_handle *h, unsigned long long *bytes);
 int pond_save(pond_handle *h, void *buf, unsigned long long bytes);
 int pond_load(pond_handle *h, const void *buf, unsigned long long bytes);
