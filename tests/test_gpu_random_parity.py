@@ -62,3 +62,20 @@ def test_random_configuration(k):
     errs = compare(got, ref, fields)
     print("   ", {f: f"{v:.2e}" for f, v in errs.items()}, flush=True)
     assert max(errs.values()) <= 1e-12, errs
+
+
+@pytest.mark.parametrize("k", range(0, NCASES, 2))
+def test_random_configuration_fp32_storage(k):
+    """The same cases in the two FP32-storage precisions (bars 1e-5 and 1e-6, as for the
+    fixed FP32 parity cases)."""
+    case, tile, two_kernel, steps = _case(k)
+    precision = pond.FP32_STORE if k % 4 == 0 else pond.FP32_STORE_FP64_MATH
+    tol = 1e-5 if precision == pond.FP32_STORE else 1e-6
+    print(f"case {k}: precision {precision} dim {case.dim} n {case.n} bc {case.bc} tile {tile} "
+          f"two_kernel {two_kernel} steps {steps}", flush=True)
+    ref = run_oracle(case, steps)
+    got = run_gpu(case, steps, precision, tile=tile, two_kernel=two_kernel)
+    fields = ("rho", "ux", "uy", "E", "T", "p") if case.dim == 2 else ("rho", "ux", "E", "T", "p")
+    errs = compare(got, ref, fields)
+    print("   ", {f: f"{v:.2e}" for f, v in errs.items()}, flush=True)
+    assert max(errs.values()) <= tol, errs
