@@ -93,8 +93,9 @@ __device__ __forceinline__ void korteweg_force(const double *Kxx, const double *
 // (2 rho E) and force: u-hat = u + F dt/(2 rho), e = E - |u-hat|^2/2, T and p from the
 // EoS, h = e + p/rho, mu = (1/omega - 1/2) p dt, k = k_scale mu C_p^ig.  Writes the
 // fields of an LDS thermodynamic region (field stride `stride`) at index li; returns the
-// admissibility bits.
-template <int DIM, typename PT>
+// admissibility bits.  GEN = false: the van der Waals fluid with its energy equation only
+// (the lean variant of the streaming kernels).
+template <int DIM, bool GEN = true, typename PT>
 __device__ __forceinline__ int thermo_state(const PT &P, double rho, double ux, double uy, double G0, double Fx,
                                             double Fy, double visc, double *th, int stride, int li)
 {
@@ -104,9 +105,9 @@ __device__ __forceinline__ int thermo_state(const PT &P, double rho, double ux, 
     const double uhx = ux + Fx * dt * h_r;
     const double uhy = DIM == 2 ? uy + Fy * dt * h_r : 0.0;
     const double e = E - 0.5 * (uhx * uhx + uhy * uhy);
-    const double T = eos_T_of_e(P, rho, e);
-    const double p = eos_p(P, rho, T);
-    const int err = eos_bad(P, rho, p);
+    const double T = eos_T_of_e<GEN>(P, rho, e);
+    const double p = eos_p<GEN>(P, rho, T);
+    const int err = eos_bad<GEN>(P, rho, p);
     const double mu = visc * p;
     th[kThFx * stride + li] = Fx;
     th[kThFy * stride + li] = Fy;

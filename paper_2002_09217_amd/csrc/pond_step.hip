@@ -217,7 +217,7 @@ __global__ void __launch_bounds__(2 * TX *TY, 2 * TX *TY <= 256 ? 3 : 2)
             double Fx = 0.0, Fy = 0.0;
             if (force) korteweg_force<DIM>(s_K, s_K + KN, s_K + 2 * KN, (DIM == 2 ? (hy + 1) * KX : 0) + hx + 1, KX, Fx, Fy);
             const double rho = force ? s_rho[(DIM == 2 ? (hy + 2) * RX : 0) + hx + 2] : pre_c[j][0];
-            err_c |= thermo_state<DIM>(P, rho, pre_c[j][1], pre_c[j][2], pre_c[j][3], Fx, Fy, visc, s_th, HN, li);
+            err_c |= thermo_state<DIM, GEN>(P, rho, pre_c[j][1], pre_c[j][2], pre_c[j][3], Fx, Fy, visc, s_th, HN, li);
         } else if (cls == kGhost) {
             const POND_GLOBAL GhostFace &G = P.ghost[face];
             s_th[kThT * HN + li] = G.T;
