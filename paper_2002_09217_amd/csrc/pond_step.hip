@@ -22,6 +22,8 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "pond_collide.h"
 #include "pond_device.h"
 #include "pond_internal.h"
@@ -48,7 +50,7 @@ __global__ void __launch_bounds__(2 * TX *TY, 2 * TX *TY <= 256 ? 3 : 2)
     constexpr size_t kFieldBytes = (size_t)2 * NF * LN * sizeof(LdsT);
     constexpr size_t kRKBytes = (size_t)(RN + 3 * KN) * sizeof(double);
     constexpr size_t kUnionWords = ((kFieldBytes > kRKBytes ? kFieldBytes : kRKBytes) + 7) / 8;
-    __shared__ double s_union[kUnionWords];
+    __shared__ __align__(16) double s_union[kUnionWords];
     __shared__ double s_th[kThFields * HN];
     __shared__ int abort_block;
     LdsT *lds = (LdsT *)s_union;
@@ -130,27 +132,27 @@ __global__ void __launch_bounds__(2 * TX *TY, 2 * TX *TY <= 256 ? 3 : 2)
             }
         }
     }
-    // donor items: the f sets of the window nodes, then their g sets (one set per wave
-    // but at the boundary, and consecutive lanes on consecutive nodes); the f items read
-    // rho, u and the stored f moments, the g items rho, u and the nine g moments
-    constexpr int DITEMS = (2 * LN + NT - 1) / NT;
+    // donor nodes (the tile and its 2-node halo), one per lane: rho, u, the stored f
+    // moments and the nine g moments; each lane collides both sets of its node
+    constexpr int DNODES = (LN + NT - 1) / NT;
     constexpr int NOWN = DIM == 2 ? 3 : 2;
-    double pre_d[DITEMS][NOWN + NF];
+    constexpr int NFS = L::kFStored;
+    constexpr int NPRE = NOWN + NFS + NF;
+    double pre_d[DNODES][NPRE];
 #pragma unroll
-    for (int j = 0; j < DITEMS; ++j) {
-        const int it = tid + j * NT;
-        if (it < 2 * LN) {
-            const int set = it >= LN ? 1 : 0, li = it - set * LN;
+    for (int j = 0; j < DNODES; ++j) {
+        const int li = tid + j * NT;
+        if (li < LN) {
             const int px = bx0 - 2 + li % LX, py = by0 - 2 + li / LX;
             int cx, cy, face;
             if (classify<DIM>(geo, px, py, cx, cy, face) == kSelf) {
                 const int nb = map_node<DIM>(geo, px, DIM == 2 ? py : 0);
 #pragma unroll
                 for (int i = 0; i < NOWN; ++i) pre_d[j][i] = MIO::load(msrc, N, nb, i);
-                const int base = set == 0 ? L::kF : L::kG;
 #pragma unroll
-                for (int i = 0; i < NF; ++i)
-                    pre_d[j][NOWN + i] = (set == 0 && i >= L::kFStored) ? 0.0 : MIO::load(msrc, N, nb, base + i);
+                for (int i = 0; i < NFS; ++i) pre_d[j][NOWN + i] = MIO::load(msrc, N, nb, L::kF + i);
+#pragma unroll
+                for (int i = 0; i < NF; ++i) pre_d[j][NOWN + NFS + i] = MIO::load(msrc, N, nb, L::kG + i);
             }
         }
     }
@@ -248,15 +250,17 @@ __global__ void __launch_bounds__(2 * TX *TY, 2 * TX *TY <= 256 ? 3 : 2)
     const double refT = kDevI ? s_th[kThP * HN + cb] * (1.0 / rho_c) : 0.0;
 
     // --- stage 4: collision of the donors, reduced to moments about (rx, ry) --------
+    // each lane takes both sets of one donor node: they share its closure fields, and
+    // the pair of moments goes to LDS in one store
+    using LdsT2 = typename std::conditional<sizeof(LdsT) == 4, float2, double2>::type;
 #pragma unroll
-    for (int j = 0; j < DITEMS; ++j) {
-        const int it = tid + j * NT;
-        const int set = it >= LN ? 1 : 0, li = it - set * LN;
+    for (int j = 0; j < DNODES; ++j) {
+        const int li = tid + j * NT;
         const int wx = li % LX, wy = li / LX;
         int cx, cy, face;
-        const int cls = it < 2 * LN ? classify<DIM>(geo, bx0 - 2 + wx, by0 - 2 + wy, cx, cy, face) : kCopy;
+        const int cls = li < LN ? classify<DIM>(geo, bx0 - 2 + wx, by0 - 2 + wy, cx, cy, face) : kCopy;
         if (cls != kCopy) {
-            double m[NF];
+            double mf[NF], mg[NF];
             if (cls == kSelf) {
                 // collision in moment space, straight to the moments about (rx, ry)
                 const double rho = pre_d[j][L::kRho];
@@ -266,31 +270,47 @@ __global__ void __launch_bounds__(2 * TX *TY, 2 * TX *TY <= 256 ? 3 : 2)
                 const double F[2] = {s_th[kThFx * HN + hb], DIM == 2 ? s_th[kThFy * HN + hb] : 0.0};
                 const double p = s_th[kThP * HN + hb];
                 const double theta = p * i_rho * kInvTL;
-                double oset[NF];
+                const double M0 = heat_correction<DIM>(P, s_th, HN, hb, HX);
+                double of[NF], og[NF];
 #pragma unroll
-                for (int i = 0; i < NF; ++i) oset[i] = pre_d[j][NOWN + i];
-                const double M0 = set == 0 ? 0.0 : heat_correction<DIM>(P, s_th, HN, hb, HX);
-                collide_moments<DIM>(P, set, rho, i_rho, u, F, p, theta, oset[0], M0, oset, u[0] - rx, u[1] - ry, m);
+                for (int i = 0; i < NF; ++i) {
+                    of[i] = i < NFS ? pre_d[j][NOWN + i] : 0.0;
+                    og[i] = pre_d[j][NOWN + NFS + i];
+                }
+                collide_moments<DIM>(P, 0, rho, i_rho, u, F, p, theta, og[0], 0.0, of, u[0] - rx, u[1] - ry, mf);
+                collide_moments<DIM>(P, 1, rho, i_rho, u, F, p, theta, og[0], M0, og, u[0] - rx, u[1] - ry, mg);
             } else {
                 // inflow ghost: the equilibrium of the face state in its own gauge
                 const POND_GLOBAL GhostFace &G = P.ghost[face];
-                const POND_GLOBAL double *src = set == 0 ? G.f : G.g;
-                double post[Q];
+                double pf[Q], pg[Q];
 #pragma unroll
-                for (int q = 0; q < Q; ++q) post[q] = src[q];
-                moments_about<DIM>(post, G.ux - rx, G.uy - ry, sqrt(G.theta), m);
+                for (int q = 0; q < Q; ++q) {
+                    pf[q] = G.f[q];
+                    pg[q] = G.g[q];
+                }
+                const double gs = sqrt(G.theta);
+                moments_about<DIM>(pf, G.ux - rx, G.uy - ry, gs, mf);
+                moments_about<DIM>(pg, G.ux - rx, G.uy - ry, gs, mg);
             }
             if constexpr (kDevI) {
-                const double R = set == 0 ? refR0 : refR1;
-                m[0] -= R;
-                m[2] -= R * refT;
+                mf[0] -= refR0;
+                mf[2] -= refR0 * refT;
+                mg[0] -= refR1;
+                mg[2] -= refR1 * refT;
                 if (DIM == 2) {
-                    m[6] -= R * refT;
-                    m[8] -= R * refT * refT;
+                    mf[6] -= refR0 * refT;
+                    mf[8] -= refR0 * refT * refT;
+                    mg[6] -= refR1 * refT;
+                    mg[8] -= refR1 * refT * refT;
                 }
             }
 #pragma unroll
-            for (int i = 0; i < NF; ++i) lds[(i * LN + li) * 2 + set] = (LdsT)m[i];
+            for (int i = 0; i < NF; ++i) {
+                LdsT2 v;
+                v.x = (LdsT)mf[i];
+                v.y = (LdsT)mg[i];
+                *(LdsT2 *)&lds[(i * LN + li) * 2] = v;
+            }
         }
     }
     __syncthreads();
