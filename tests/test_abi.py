@@ -15,7 +15,8 @@ HEADER = os.path.join(ROOT, "include", "pond.h")
 
 
 def declared_symbols():
-    text = open(HEADER).read()
+    with open(HEADER) as fh:
+        text = fh.read()
     return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(pond_\w+)\s*\(", text, re.M)))
 
 
