@@ -253,7 +253,7 @@ def main():
                          "FETCH_SIZE/WRITE_SIZE counters calibrate the HBM-traffic readings")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)",
+        print("bench.py measures one GPU: the library has no multi-GPU path (--gpus must be 1)",
               file=sys.stderr)
         sys.exit(2)
 
