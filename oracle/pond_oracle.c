@@ -68,6 +68,11 @@
  *       of the state.  T follows from e (and, for the read-back, from p) by Newton's
  *       method.  The conductivity keeps k = k_scale mu C_p^ig (R5).
  *
+ * Parity unpinned: R1 (the fixed number of passes and their starting gauge), R3 (the
+ * time level of F inside the passes), the shape of phi in R4 and the outflow rule of R8
+ * are fixed by no value outside this file; the tests reach them only through integral
+ * checks (coexistence, the exact Riemann solution, sound speeds, the Laplace law).
+ *
  * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no FMA contraction).
  */
 #include <math.h>
