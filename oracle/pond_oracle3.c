@@ -4,8 +4,9 @@
  * A plain, slow, FP64 CPU implementation of the D3Q27 time step of the
  * two-population Particles-on-Demand model of Reyhanian, Dorschner & Karlin,
  * "Thermokinetic model of compressible multiphase flows", arXiv:2002.09217, on a
- * periodic box.  Same method and the same readings (R1-R11 of pond_oracle.c) as
- * the one- and two-dimensional oracle, written out for three axes:
+ * periodic box.  Same method and the same readings (R1-R12 of pond_oracle.c, with the
+ * same parity-unpinned ones) as the one- and two-dimensional oracle, written out for
+ * three axes:
  *   - D3Q27 = C1 x C1 x C1, W_ijk = W_i W_j W_k, T_L = 1/3                        (App. B)
  *   - v_i = sqrt(theta) c_i + u, moments rho, rho u, 2 rho E                       (eqs. 1-2)
  *   - every donor of the 4x4x4 stencil is re-expressed in the receiver gauge with
