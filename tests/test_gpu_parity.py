@@ -7,8 +7,8 @@ FP64 arithmetic.  Both forms of the 1D/2D step run: the
 fused one-kernel step (the default) and the two-kernel step with stored populations.
 
 Sizes span several 32 x 8 streaming tiles with ragged tails; the full 256 x 256
-droplet of the benchmark is compared after a few steps, where the oracle finishes in
-seconds."""
+droplet of the benchmark is compared after 3 and 45 steps (the oracle takes about half a
+second per step there on 16 threads)."""
 import numpy as np
 import pytest
 
@@ -139,6 +139,24 @@ def test_tiny_periodic_lattices():
 def test_full_size_droplet_256_few_steps():
     case = W.static_droplet(n=256)
     _check(case, 3)
+
+
+@pytest.fixture(scope="module")
+def droplet256_oracle_45():
+    case = W.static_droplet(n=256)
+    return case, run_oracle(case, 45)
+
+
+@pytest.mark.parametrize("precision,tol", [(pond.FP64, TOL64), (pond.FP32_STORE, 1e-5)])
+def test_full_size_droplet_256_three_long_runs(droplet256_oracle_45, precision, tol):
+    """The benchmark's workload (the 256^2 droplet, autotuned tile) for 45 steps: three
+    replays of the 15-step graph the benchmark times, through every ring slot."""
+    case, ref = droplet256_oracle_45
+    print(f"parity: {case.name} n={case.n} steps=45 precision={precision}", flush=True)
+    got = run_gpu(case, 45, precision)
+    errs = compare(got, ref)
+    print(case.name, 45, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    assert max(errs.values()) <= tol, errs
 
 
 def test_full_size_droplet_shock_1024x512_few_steps():
