@@ -8,8 +8,9 @@
 //                     (zero), gauge free, into a scratch buffer;
 //   k3_stream         one workgroup per x-y tile of one z plane; every predictor-corrector
 //                     pass stages the five donor planes z-2 .. z+2 through LDS one at a
-//                     time and accumulates, per plane, the x-y contraction of the D2Q9
-//                     kernel for each z power followed by the z contraction;
+//                     time (FP64: one z power of a plane at a time) and accumulates, per
+//                     plane, the x-y contraction of the D2Q9 kernel for each z power
+//                     followed by the z contraction;
 //   k3_korteweg, k3_thermo, k3_collide
 //                     Korteweg stress, force and thermodynamics, heat-flux correction and
 //                     the collisions of f and g (separate waves), 27-point stencils.
@@ -214,11 +215,60 @@ __device__ __forceinline__ T taps3(int k, const T w[5], T v0, T v1, T v2, T v3, 
     return w[0] * v0 + w[1] * v1 + w[2] * v2 + w[3] * v3 + w[4] * v4;
 }
 
-template <bool FAST, typename LdsT, typename AccT, int LN, int LX>
+// weight of window column j (0..4) in the cubic stencil of departure velocity v: the
+// column weights of window_weights, one at a time (its halo check is not repeated)
+__device__ __forceinline__ double window_tap(double v, double dt, int j)
+{
+    const double d = -v * dt;
+    const double fl = floor(d);
+    const double t = d - fl + 1.0;
+    int i0 = (int)fl;
+    i0 = i0 < -1 ? -1 : (i0 > 0 ? 0 : i0);
+    const int c = j - (i0 + 1); // stencil node of column j
+    if (c == 0) return -(t - 1.0) * (t - 2.0) * (t - 3.0) * (1.0 / 6.0);
+    if (c == 1) return t * (t - 2.0) * (t - 3.0) * 0.5;
+    if (c == 2) return -t * (t - 1.0) * (t - 3.0) * 0.5;
+    if (c == 3) return t * (t - 1.0) * (t - 2.0) * (1.0 / 6.0);
+    return 0.0;
+}
+
+// SPLIT: the LDS holds only the nine fields of z power o, field (m, n) at slot 3 m + n;
+// otherwise all 27, field (m, n, o) at slot 9 m + 3 n + o
+template <bool FAST, bool SPLIT, typename LdsT, typename AccT, int LN, int LX>
 __device__ __forceinline__ void xy_window(const LdsT *sbase, int o, const LdsT (&wx)[3][5],
                                           const LdsT (&wy)[3][5], const LdsT (&A)[3][3], const AccT (&B)[3][3],
                                           AccT (&Y)[3][3])
 {
+    if constexpr (SPLIT) {
+        // each row is x-contracted and added straight into Y with its y weights (no
+        // five-row buffer: the FP64 window must fit two waves per SIMD)
+#pragma unroll
+        for (int n = 0; n < 3; ++n) {
+#pragma unroll
+            for (int r = 0; r < 5; ++r) {
+                LdsT Zr[3];
+#pragma unroll
+                for (int m = 0; m < 3; ++m) {
+                    const LdsT *row = sbase + ((3 * m + n) * LN + r * LX) * 2;
+                    const LdsT v0 = row[0], v1 = row[2], v2 = row[4], v3 = row[6], v4 = row[8];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const LdsT x = taps3<FAST>(k, wx[k], v0, v1, v2, v3, v4);
+                        Zr[k] = m == 0 ? A[k][m] * x : Zr[k] + A[k][m] * x;
+                    }
+                }
+#pragma unroll
+                for (int l = 0; l < 3; ++l) {
+                    if (FAST && ((l == 0 && r == 0) || (l == 2 && r == 4))) continue; // zero taps
+                    const AccT c = B[l][n] * (AccT)wy[l][r];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) Y[k][l] += c * (AccT)Zr[k];
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        return;
+    }
 #pragma unroll
     for (int n = 0; n < 3; ++n) {
         LdsT Z[3][5];
@@ -259,12 +309,18 @@ __device__ __forceinline__ void xy_window(const LdsT *sbase, int o, const LdsT (
 // the moment itself.
 // ---------------------------------------------------------------------------
 template <typename LdsT, int TX, int TY, bool GEN>
-__global__ void __launch_bounds__(2 * TX *TY, sizeof(LdsT) == 4 ? 2 : 1) k3_stream(const SlotDesc *__restrict__ slot)
+__global__ void __launch_bounds__(2 * TX *TY, 2) k3_stream(const SlotDesc *__restrict__ slot)
 {
     constexpr int LX = TX + 4, LY = TY + 4, LN = LX * LY, NT = 2 * TX * TY;
     constexpr bool kDev = sizeof(LdsT) == 4;
     using AccT = LdsT; // window accumulators: FP64, or FP32 deviations
-    __shared__ __align__(16) LdsT lds[2 * 27 * LN];
+    // FP64 windows stage a donor plane in three rounds, the nine fields of one z power
+    // each (35 KB of LDS instead of 104 KB), so that two workgroups share a CU; FP32
+    // windows stage all 27 fields at once
+    constexpr int NO = kDev ? 1 : 3;  // staging rounds per donor plane
+    constexpr int FPS = 27 / NO;      // fields per set and round
+    constexpr bool kSplit = NO > 1;
+    __shared__ __align__(16) LdsT lds[2 * FPS * LN];
     __shared__ LdsT ref[kDev ? 54 : 1];
     __shared__ int abort_block;
     const SlotDesc &S = *slot;
@@ -343,8 +399,10 @@ __global__ void __launch_bounds__(2 * TX *TY, sizeof(LdsT) == 4 ? 2 : 1) k3_stre
                                 wy[2][4] == (LdsT)0);
 
 #pragma unroll 1
-        for (int sz = 0; sz < 5; ++sz) {
-            // stage the donor plane z + sz - 2 of the tile window: 54 fields
+        for (int szo = 0; szo < 5 * NO; ++szo) {
+            // stage the donor plane z + sz - 2 of the tile window: all 54 fields, or the
+            // 18 of z power so (field 9 m + 3 n + so = 3 j + so at slot j = 3 m + n)
+            const int sz = szo / NO, so = szo - sz * NO;
             __syncthreads();
             const int zz = box.wrap(z + sz - 2, box.nz);
             if (stager) {
@@ -352,15 +410,15 @@ __global__ void __launch_bounds__(2 * TX *TY, sizeof(LdsT) == 4 ? 2 : 1) k3_stre
                 // loads in batches of MB fields per set before their stores, so that
                 // their latencies overlap
                 constexpr int MB = 9;
-                static_assert(27 % MB == 0, "whole batches of fields");
+                static_assert(FPS % MB == 0, "whole batches of fields");
 #pragma unroll
-                for (int m0 = 0; m0 < 27; m0 += MB) {
+                for (int m0 = 0; m0 < FPS; m0 += MB) {
                     LdsT a[MB], b[MB];
 #pragma unroll
                     for (int j = 0; j < MB; ++j) {
-                        a[j] = *(const POND_GLOBAL LdsT *)((const POND_GLOBAL char *)(dmom + (size_t)(m0 + j) * N) + off);
-                        b[j] = *(const POND_GLOBAL LdsT *)((const POND_GLOBAL char *)(dmom + (size_t)(27 + m0 + j) * N) +
-                                                           off);
+                        const int f = kSplit ? 3 * j + so : m0 + j;
+                        a[j] = *(const POND_GLOBAL LdsT *)((const POND_GLOBAL char *)(dmom + (size_t)f * N) + off);
+                        b[j] = *(const POND_GLOBAL LdsT *)((const POND_GLOBAL char *)(dmom + (size_t)(27 + f) * N) + off);
                     }
 #pragma unroll
                     for (int j = 0; j < MB; ++j) {
@@ -376,7 +434,7 @@ __global__ void __launch_bounds__(2 * TX *TY, sizeof(LdsT) == 4 ? 2 : 1) k3_stre
                     }
                 }
             }
-            if (pass == 0 && sz == 0 && tid == 0) {
+            if (pass == 0 && szo == 0 && tid == 0) {
                 abort_block = err_before;
                 // one step more has started without an earlier failure
                 if (blockIdx.x == 0 && err_before == 0) atomicAdd(&flags[kFlagSteps], 1);
@@ -386,20 +444,33 @@ __global__ void __launch_bounds__(2 * TX *TY, sizeof(LdsT) == 4 ? 2 : 1) k3_stre
 
             const LdsT *sbase = &lds[wbase * 2 + myset];
 #pragma unroll 1
-            for (int o = 0; o < 3; ++o) {
+            for (int o = kSplit ? so : 0; o < (kSplit ? so + 1 : 3); ++o) {
                 AccT Y[3][3];
 #pragma unroll
                 for (int k = 0; k < 3; ++k)
 #pragma unroll
                     for (int l = 0; l < 3; ++l) Y[k][l] = (AccT)0;
                 if (fast)
-                    xy_window<true, LdsT, AccT, LN, LX>(sbase, o, wx, wy, A, B, Y);
+                    xy_window<true, kSplit, LdsT, AccT, LN, LX>(sbase, o, wx, wy, A, B, Y);
                 else
-                    xy_window<false, LdsT, AccT, LN, LX>(sbase, o, wx, wy, A, B, Y);
-                // z contraction: departure point m of the receiver takes wz[m][sz] C[m][o]
+                    xy_window<false, kSplit, LdsT, AccT, LN, LX>(sbase, o, wx, wy, A, B, Y);
+                // z contraction: departure point m of the receiver takes wz[m][sz] C[m][o].
+                // The FP64 window recomputes these from u_z and s (an empty asm keeps the
+                // recomputation here) instead of holding wz and C across the loop.
+                AccT czs[3];
+                if constexpr (kSplit) {
+                    double u2 = U[2], su = s;
+                    asm volatile("" : "+v"(u2), "+v"(su));
+                    double Cd[3][3];
+                    lagrange_coeffs(u2, su, Cd);
+#pragma unroll
+                    for (int m = 0; m < 3; ++m)
+                        czs[m] = (AccT)((o == 0 ? Cd[m][0] : o == 1 ? Cd[m][1] : Cd[m][2]) *
+                                        window_tap(u2 + su * (double)(m - 1), dt, sz));
+                }
 #pragma unroll
                 for (int m = 0; m < 3; ++m) {
-                    const AccT cz = C[m][o] * wz[m][sz];
+                    const AccT cz = kSplit ? czs[m] : C[m][o] * wz[m][sz];
 #pragma unroll
                     for (int k = 0; k < 3; ++k)
 #pragma unroll
