@@ -968,8 +968,8 @@ __global__ void __launch_bounds__(kMonThreads) k3_monitor_partials(const DevPara
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-// streaming tile: 16 x 8 receivers in every precision; the 54 staged fields of one donor
-// plane take 52 KB of LDS in FP32 and 104 KB in FP64
+// streaming tile: 16 x 8 receivers in every precision (16 x 16 was slower in both); a
+// staging round takes 52 KB of LDS in FP32 (54 fields) and 35 KB in FP64 (18 fields)
 void stream3_tile(int fp32, int *tx, int *ty)
 {
     (void)fp32;
