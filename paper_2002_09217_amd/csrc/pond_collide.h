@@ -100,13 +100,16 @@ __device__ __forceinline__ int thermo_state(const PT &P, double rho, double ux, 
                                             double Fy, double visc, double *th, int stride, int li)
 {
     const double dt = P.dt;
-    const double h_r = 0.5 / rho;
+    // van der Waals without the generic laws: one division gives 1 / rho and 1 / (1 - b rho)
+    const double q = 1.0 - P.b * rho;
+    const double i_rq = GEN ? 0.0 : 1.0 / (rho * q);
+    const double h_r = GEN ? 0.5 / rho : 0.5 * q * i_rq;
     const double E = G0 * h_r;
     const double uhx = ux + Fx * dt * h_r;
     const double uhy = DIM == 2 ? uy + Fy * dt * h_r : 0.0;
     const double e = E - 0.5 * (uhx * uhx + uhy * uhy);
     const double T = eos_T_of_e<GEN>(P, rho, e);
-    const double p = eos_p<GEN>(P, rho, T);
+    const double p = GEN ? eos_p<GEN>(P, rho, T) : vdw_p_lean(P, rho, T, i_rq);
     const int err = eos_bad<GEN>(P, rho, p);
     const double mu = visc * p;
     th[kThFx * stride + li] = Fx;
@@ -294,9 +297,9 @@ __device__ __forceinline__ void collide_g(const PT &P, double rho, double i_rho,
 // set as stored (f: (1,1), (2,0), (0,2), (2,1), (1,2), (2,2); g: all nine).
 // ---------------------------------------------------------------------------
 template <int DIM, typename PT>
-__device__ __forceinline__ void collide_moments(const PT &P, int set, double rho, double i_rho, const double *u,
-                                                const double *F, double p, double theta, double G0, double M0,
-                                                const double *oset, double dx, double dy, double *out)
+__device__ __forceinline__ void collide_moments(const PT &P, int set, double rho, double i_rho, double i_p,
+                                                const double *u, const double *F, double p, double theta, double G0,
+                                                double M0, const double *oset, double dx, double dy, double *out)
 {
     constexpr int NF = Layout<DIM>::NF;
     const double dt = P.dt, om = P.omega;
@@ -339,7 +342,6 @@ __device__ __forceinline__ void collide_moments(const PT &P, int set, double rho
             }
         }
     } else {
-        const double i_p = 1.0 / p;
         const double E = 0.5 * G0 * i_rho;
         const double uh[2] = {u[0] + 0.5 * F[0] * dt * i_rho, DIM == 2 ? u[1] + 0.5 * F[1] * dt * i_rho : 0.0};
         const double Pr = p * i_rho;
@@ -367,7 +369,7 @@ __device__ __forceinline__ void collide_moments(const PT &P, int set, double rho
         for (int a = 0; a < DIM; ++a) work += 2.0 * uh[a] * F[a];
         const double c_uc = 0.5 * kInvTL * rho * i_p;      // rho / (2 p T_L)
         const double c_v2 = 0.5 * rho * i_p;               // rho / (2 p)
-        const double i_th = 1.0 / theta;
+        const double i_th = rho * kTL * i_p; // 1 / theta = rho T_L / p
         const double src = (M0 + work) * dt;
         // equilibrium 2 rho E + M.xi + sum_ab N_ab (xi_a xi_b + u_a xi_b + xi_a u_b - d_ab Pr)
         // and kernel 1 + D/2 + c_uc (u.xi)^2 / theta - c_v2 |u + xi|^2, as coefficients of

@@ -60,6 +60,13 @@ __device__ __forceinline__ double eos_p(const PT &P, double rho, double T)
     }
     return rho * P.R * T / (1.0 - P.b * rho) - P.a * rho * rho;
 }
+// van der Waals pressure given i_rq = 1 / (rho (1 - b rho)): the lean closures take one
+// division for both 1 / rho and 1 / (1 - b rho)
+template <typename PT>
+__device__ __forceinline__ double vdw_p_lean(const PT &P, double rho, double T, double i_rq)
+{
+    return rho * rho * P.R * T * i_rq - P.a * rho * rho;
+}
 // temperature of a streamed state from its internal energy
 template <bool GEN = true, typename PT>
 __device__ __forceinline__ double eos_T_of_e(const PT &P, double rho, double e)

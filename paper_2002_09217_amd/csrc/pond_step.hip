@@ -264,11 +264,12 @@ __global__ void __launch_bounds__(2 * TX *TY, 2 * TX *TY <= 256 ? 3 : 2)
             if (cls == kSelf) {
                 // collision in moment space, straight to the moments about (rx, ry)
                 const double rho = pre_d[j][L::kRho];
-                const double i_rho = 1.0 / rho;
-                const double u[2] = {pre_d[j][L::kUx], DIM == 2 ? pre_d[j][L::kUy] : 0.0};
                 const int hb = (DIM == 2 ? (wy + 1) * HX : 0) + wx + 1;
-                const double F[2] = {s_th[kThFx * HN + hb], DIM == 2 ? s_th[kThFy * HN + hb] : 0.0};
                 const double p = s_th[kThP * HN + hb];
+                const double i_rp = 1.0 / (rho * p); // one division for 1 / rho and 1 / p
+                const double i_rho = p * i_rp, i_p = rho * i_rp;
+                const double u[2] = {pre_d[j][L::kUx], DIM == 2 ? pre_d[j][L::kUy] : 0.0};
+                const double F[2] = {s_th[kThFx * HN + hb], DIM == 2 ? s_th[kThFy * HN + hb] : 0.0};
                 const double theta = p * i_rho * kInvTL;
                 const double M0 = heat_correction<DIM>(P, s_th, HN, hb, HX);
                 double of[NF], og[NF];
@@ -277,8 +278,8 @@ __global__ void __launch_bounds__(2 * TX *TY, 2 * TX *TY <= 256 ? 3 : 2)
                     of[i] = i < NFS ? pre_d[j][NOWN + i] : 0.0;
                     og[i] = pre_d[j][NOWN + NFS + i];
                 }
-                collide_moments<DIM>(P, 0, rho, i_rho, u, F, p, theta, og[0], 0.0, of, u[0] - rx, u[1] - ry, mf);
-                collide_moments<DIM>(P, 1, rho, i_rho, u, F, p, theta, og[0], M0, og, u[0] - rx, u[1] - ry, mg);
+                collide_moments<DIM>(P, 0, rho, i_rho, i_p, u, F, p, theta, og[0], 0.0, of, u[0] - rx, u[1] - ry, mf);
+                collide_moments<DIM>(P, 1, rho, i_rho, i_p, u, F, p, theta, og[0], M0, og, u[0] - rx, u[1] - ry, mg);
             } else {
                 // inflow ghost: the equilibrium of the face state in its own gauge
                 const POND_GLOBAL GhostFace &G = P.ghost[face];

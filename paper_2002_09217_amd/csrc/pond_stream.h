@@ -215,8 +215,11 @@ __device__ __forceinline__ int stream_passes(const POND_GLOBAL DevParams &P, con
         const double G2 = myset == 0 ? o0 : s0;
         rho = r0;
         // one reciprocal of rho serves every quotient by it (FP64 division is a
-        // long dependent sequence on this hardware)
-        const double i_rho = 1.0 / rho;
+        // long dependent sequence on this hardware); the lean van der Waals closure
+        // takes it and 1 / (1 - b rho) from one division
+        const double q = 1.0 - P.b * rho;
+        const double i_rq = GEN ? 0.0 : 1.0 / (rho * q);
+        const double i_rho = GEN ? 1.0 / rho : q * i_rq;
         const double E = 0.5 * G2 * i_rho;
         const double ux = jx * i_rho;
         const double uy = DIM == 2 ? jy * i_rho : 0.0;
@@ -224,7 +227,7 @@ __device__ __forceinline__ int stream_passes(const POND_GLOBAL DevParams &P, con
         const double uhy = DIM == 2 ? uy + 0.5 * Fpy * dt * i_rho : 0.0;
         const double e = E - 0.5 * (uhx * uhx + uhy * uhy);
         const double T = eos_T_of_e<GEN>(P, rho, e);
-        const double p = eos_p<GEN>(P, rho, T);
+        const double p = GEN ? eos_p<GEN>(P, rho, T) : vdw_p_lean(P, rho, T, i_rq);
         err |= eos_bad<GEN>(P, rho, p);
         sUx = Ux;
         sUy = Uy;
