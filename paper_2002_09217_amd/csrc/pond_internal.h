@@ -23,7 +23,7 @@ enum { kErrPressure = 1, kErrNonfinite = 2, kErrHalo = 4, kErrCollideStage = 8 }
 // Its graphs replay runs of kFusedRun and of kFusedRing steps, which return to the ring
 // slot they start from.
 constexpr int kFusedRing = 3;
-constexpr int kFusedRun = 15;
+constexpr int kFusedRun = 45;
 
 // Inflow ghost state of one face: the equilibrium of (rho, u, T) with F = 0, as
 // populations in its own gauge plus the scalar fields the gradient stencils read.

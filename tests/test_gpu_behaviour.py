@@ -33,7 +33,7 @@ def test_runs_are_bitwise_deterministic(precision):
 
 
 def test_step_schedules_agree_bitwise():
-    """One call, many short calls, and timed steps: replays of the 15- and 3-step graphs
+    """One call, many short calls, and timed steps: replays of the 45- and 3-step graphs
     and single launches, from every ring slot, with the closure checks that end each run,
     all give the same state."""
     case = W.perturbed(45, 19, seed=9, kappa=0.0176)

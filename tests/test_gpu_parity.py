@@ -149,8 +149,8 @@ def droplet256_oracle_45():
 
 @pytest.mark.parametrize("precision,tol", [(pond.FP64, TOL64), (pond.FP32_STORE, 1e-5)])
 def test_full_size_droplet_256_three_long_runs(droplet256_oracle_45, precision, tol):
-    """The benchmark's workload (the 256^2 droplet, autotuned tile) for 45 steps: three
-    replays of the 15-step graph the benchmark times, through every ring slot."""
+    """The benchmark's workload (the 256^2 droplet, autotuned tile) for 45 steps: one
+    replay of the 45-step graph the benchmark times, fifteen times through the ring."""
     case, ref = droplet256_oracle_45
     print(f"parity: {case.name} n={case.n} steps=45 precision={precision}", flush=True)
     got = run_gpu(case, 45, precision)
