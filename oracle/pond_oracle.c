@@ -71,7 +71,10 @@
  * Parity unpinned: R1 (the fixed number of passes and their starting gauge), R3 (the
  * time level of F inside the passes), the shape of phi in R4 and the outflow rule of R8
  * are fixed by no value outside this file; the tests reach them only through integral
- * checks (coexistence, the exact Riemann solution, sound speeds, the Laplace law).
+ * checks (coexistence, the exact Riemann solution, sound speeds, the Laplace law).  Of
+ * R1, that the passes form the fixed-point iteration towards the self-consistent gauge
+ * (each result changes with the pass count, the changes contract, many passes reach a
+ * state one more pass leaves unchanged) is pinned; the count itself stays a reading.
  *
  * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no FMA contraction).
  */
