@@ -17,7 +17,9 @@
  *      and the heat-flux correction M0                                (eq. 9)
  *   3. relaxes f and g to their equilibria with the force source S_i, the
  *      force-extended g equilibrium and the sources g~ + phi          (eqs. 16-22)
- * on the device as two kernels (streaming; force, closure and collision).
+ * on the device: for D1Q3 and D2Q9 one fused kernel per step by default (the step keeps
+ * the streamed state and recomputes each tile's collision on chip), or two kernels
+ * (streaming; force, closure and collision) with two_kernel = 1 and for D3Q27.
  *
  * Conventions for every call below
  *   - All functions return a pond_status (0 = POND_OK, negative = error).
@@ -131,8 +133,9 @@ int pond_create(const pond_config *cfg, pond_handle **out);
  * of N) and temperature T (N), host arrays.  The force F0 = -div K(rho) follows from
  * rho; the gauge velocity is u - F0 dt/(2 rho); the stored populations are the
  * collision of the equilibrium populations f = rho W, g = g^eq (eqs. 7, 16-22).
- * Before returning, the call records the HIP graphs that pond_step replays (runs of
- * 16 and of 2 steps from either state buffer), so that stepping itself captures and
+ * Before returning, the call records the HIP graphs that pond_step replays (fused
+ * step: runs of 45 and of 3 steps from each of the three ring slots; two kernels: runs
+ * of 16 and of 2 steps from either state buffer), so that stepping itself captures and
  * instantiates nothing.
  * Errors: POND_E_INVALID (NULL pointer), POND_E_PRESSURE / POND_E_NONFINITE when a
  * node is outside the EoS domain or a field holds NaN or Inf (state then undefined,
