@@ -1,7 +1,8 @@
-"""Batches through the C ABI: a lattice advanced inside a batch of other lattices
-(several groups, mixed sizes, dimensions and precisions, members joining and
-leaving) gives bitwise the same state as the same lattice advanced alone; a member
-that fails leaves the batch without disturbing the others; admission footprints."""
+"""Batches through the C ABI, in both step forms: a lattice advanced inside a batch of
+other lattices (several groups, mixed sizes, dimensions and precisions, members joining
+and leaving) gives bitwise the same state as the same lattice advanced alone; a member
+that fails leaves the batch without disturbing the others; a batch holds one step form;
+admission footprints."""
 import numpy as np
 import pytest
 
@@ -18,8 +19,8 @@ def _fields(m):
     return np.concatenate([m[k] for k in ("rho", "ux", "uy", "T", "p", "E")])
 
 
-def _lat(case, tile, precision=pond.FP64):
-    lat = pond.Lattice(pond_config(case, precision=precision, tile=tile))
+def _lat(case, tile, precision=pond.FP64, two_kernel=0):
+    lat = pond.Lattice(pond_config(case, precision=precision, tile=tile, two_kernel=two_kernel))
     lat.init_fields(case.rho, case.u, case.T)
     return lat
 
@@ -44,20 +45,22 @@ def _mix():
     ]
 
 
-def test_batch_members_bitwise_equal_to_alone():
+@pytest.mark.parametrize("two_kernel", [0, 1])
+def test_batch_members_bitwise_equal_to_alone(two_kernel):
     mix = _mix()
-    # odd and even chunks, one past a 16-step graph: both graph phases and lengths
-    schedule = (1, 6, 19, 2)
+    # chunks of every remainder and one past the long graph run (45 fused steps, 16 for
+    # two kernels): every ring slot or state buffer and both graph lengths
+    schedule = (1, 6, 50, 2)
     total = sum(schedule)
     alone = []
     for case, tile, prec in mix:
-        lat = _lat(case, tile, prec)
+        lat = _lat(case, tile, prec, two_kernel)
         lat.step(total)
         alone.append(_fields(lat.moments()))
         lat.close()
 
     batch = pond.Batch()
-    lats = [_lat(case, tile, prec) for case, tile, prec in mix]
+    lats = [_lat(case, tile, prec, two_kernel) for case, tile, prec in mix]
     # the last member joins after the first chunk, and is stepped alone before it
     for lat in lats[:-1]:
         batch.add(lat)
@@ -83,17 +86,18 @@ def test_batch_members_bitwise_equal_to_alone():
         lat.close()
 
 
-def test_failed_member_leaves_batch_others_unaffected():
+@pytest.mark.parametrize("two_kernel", [0, 1])
+def test_failed_member_leaves_batch_others_unaffected(two_kernel):
     good = W.perturbed(48, 40, seed=7, kappa=0.0176)
     # |u| + sqrt(theta) > 1/dt: the departure stencil would leave the +-2 window
     bad = W.perturbed(24, 24, seed=2, rho0=1.0, t_over_tcr=1.5, u0=(0.7, 0.0), dt=1.0, amp=0.0)
-    ref_lat = _lat(good, 0)
+    ref_lat = _lat(good, 0, two_kernel=two_kernel)
     ref_lat.step(10)
     ref = _fields(ref_lat.moments())
     ref_lat.close()
 
-    g = _lat(good, 0)
-    b = _lat(bad, 0)
+    g = _lat(good, 0, two_kernel=two_kernel)
+    b = _lat(bad, 0, two_kernel=two_kernel)
     before = _fields(b.moments())
     batch = pond.Batch()
     batch.add(b)
@@ -109,6 +113,21 @@ def test_failed_member_leaves_batch_others_unaffected():
     batch.close()
     g.close()
     b.close()
+
+
+def test_batch_refuses_a_member_of_the_other_step_form():
+    case = W.perturbed(20, 12, seed=11, kappa=0.0176)
+    fused, split = _lat(case, 0), _lat(case, 0, two_kernel=1)
+    batch = pond.Batch()
+    batch.add(fused)
+    with pytest.raises(pond.PondError) as err:
+        batch.add(split)
+    assert err.value.code == -1 and batch.size() == 1
+    split.step(2)                     # the refused lattice is still stepped on its own
+    assert split.steps_done() == 2
+    batch.close()
+    fused.close()
+    split.close()
 
 
 def test_footprint_matches_device_allocation():
