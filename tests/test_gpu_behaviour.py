@@ -52,6 +52,25 @@ def test_step_schedules_agree_bitwise():
         x.close()
 
 
+@pytest.mark.parametrize("two_kernel", [0, 1])
+def test_timing_calls_leave_the_state_alone(two_kernel):
+    """pond_time_kernel on both kernels and pond_step_timed: positive durations, and the
+    state and step count afterwards are those of plain pond_step."""
+    case = W.perturbed(40, 24, seed=12, kappa=0.0176)
+    a = _lattice(case, two_kernel=two_kernel)
+    a.step(12)
+    b = _lattice(case, two_kernel=two_kernel)
+    assert b.time_kernel(0, 3) > 0.0 and b.time_kernel(1, 3) > 0.0
+    b.step(5)
+    assert b.time_kernel(0, 2) > 0.0 and b.time_kernel(1, 2) > 0.0
+    t = b.step_timed(7)
+    assert all(v > 0.0 for v in t.values())
+    assert a.steps_done() == b.steps_done() == 12
+    assert np.array_equal(_fields(a.moments()), _fields(b.moments()))
+    a.close()
+    b.close()
+
+
 def test_monitors_match_oracle_sums():
     case = W.static_droplet(n=48, radius=10.0)
     lat = _lattice(case)
