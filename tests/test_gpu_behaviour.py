@@ -32,20 +32,22 @@ def test_runs_are_bitwise_deterministic(precision):
     assert np.array_equal(out[0], out[1])
 
 
-def test_step_schedules_agree_bitwise():
-    """One call, many short calls, and timed steps: replays of the 45- and 3-step graphs
-    and single launches, from every ring slot, with the closure checks that end each run,
-    all give the same state."""
+@pytest.mark.parametrize("two_kernel", [0, 1])
+def test_step_schedules_agree_bitwise(two_kernel):
+    """One call, many short calls, and timed steps give the same state: replays of the 45-
+    and 3-step graphs and single launches from every ring slot, with the closure checks that
+    end each run (fused step), or of the 16- and 2-step graphs and single steps from either
+    state buffer (two kernels)."""
     case = W.perturbed(45, 19, seed=9, kappa=0.0176)
-    a = _lattice(case)
-    a.step(40)
-    b = _lattice(case)
-    for n in (1, 2, 3, 1, 5, 17, 11):
+    a = _lattice(case, two_kernel=two_kernel)
+    a.step(100)
+    b = _lattice(case, two_kernel=two_kernel)
+    for n in (1, 2, 3, 1, 5, 17, 11, 60):
         b.step(n)
-    c = _lattice(case)
+    c = _lattice(case, two_kernel=two_kernel)
     c.step_timed(5)
-    c.step(35)
-    assert a.steps_done() == b.steps_done() == c.steps_done() == 40
+    c.step(95)
+    assert a.steps_done() == b.steps_done() == c.steps_done() == 100
     fa, fb, fc = (_fields(x.moments()) for x in (a, b, c))
     assert np.array_equal(fa, fb) and np.array_equal(fa, fc)
     for x in (a, b, c):
