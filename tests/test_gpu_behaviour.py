@@ -73,6 +73,15 @@ def test_timing_calls_leave_the_state_alone(two_kernel):
     b.close()
 
 
+def test_lattice_and_batch_close_at_the_end_of_a_with_block():
+    case = W.perturbed(16, 12, seed=13)
+    with pond.Lattice(pond_config(case)) as lat, pond.Batch() as batch:
+        lat.init_fields(case.rho, case.u, case.T)
+        batch.add(lat)
+        assert batch.step(4) == [] and lat.steps_done() == 4
+    assert lat._h is None and batch._h is None
+
+
 def test_monitors_match_oracle_sums():
     case = W.static_droplet(n=48, radius=10.0)
     lat = _lattice(case)
