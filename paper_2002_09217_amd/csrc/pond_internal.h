@@ -171,6 +171,8 @@ hipError_t launch_force_collide(const LaunchCtx &c, const SlotDesc *slots, int n
 // fused step: collision of smom_src recomputed on each tile and its halo, then the
 // streaming into smom_dst; `tiles` as for launch_stream
 hipError_t launch_step_fused(const LaunchCtx &c, const SlotDesc *slots, int nslots, int tiles);
+// the same for the FP64 windows (FP64 and FP32 storage with FP64 arithmetic)
+hipError_t launch_step_double_windows(const LaunchCtx &c, const SlotDesc *slots, int nslots, int tiles);
 // fused step: closure of the state in `mom` (every node), raising its errors with
 // kErrCollideStage and counting as a launch; `tiles` as for launch_force_collide
 hipError_t launch_collide_check(const LaunchCtx &c, const SlotDesc *slots, int nslots, int tiles);

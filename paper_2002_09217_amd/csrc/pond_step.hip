@@ -387,11 +387,21 @@ static hipError_t launch_step_v(const LaunchCtx &c, const SlotDesc *slots, int n
     return launch_step_t<1, MIXED, LdsT, 128, 1>(c, slots, nslots, tiles);
 }
 
+// This file is compiled twice (build.py): once for the FP32 windows and the dispatcher,
+// once with POND_STEP_DOUBLE_WINDOWS for the FP64 windows, which LLVM's max-ilp scheduling
+// makes 1-2.5% faster and the FP32 ones slower.
+#ifndef POND_STEP_DOUBLE_WINDOWS
 hipError_t launch_step_fused(const LaunchCtx &c, const SlotDesc *slots, int nslots, int tiles)
 {
     if (c.fp32 == 1) return launch_step_v<true, float>(c, slots, nslots, tiles);
+    return launch_step_double_windows(c, slots, nslots, tiles);
+}
+#else
+hipError_t launch_step_double_windows(const LaunchCtx &c, const SlotDesc *slots, int nslots, int tiles)
+{
     if (c.fp32 == 2) return launch_step_v<true, double>(c, slots, nslots, tiles);
     return launch_step_v<false, double>(c, slots, nslots, tiles);
 }
+#endif
 
 } // namespace pond
