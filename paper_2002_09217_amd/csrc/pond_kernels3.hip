@@ -7,10 +7,9 @@
 //   k3_donor_moments  each node's 27 + 27 moments about a common reference velocity
 //                     (zero), gauge free, into a scratch buffer;
 //   k3_stream         one workgroup per x-y tile of one z plane; every predictor-corrector
-//                     pass stages the five donor planes z-2 .. z+2 through LDS one at a
-//                     time (FP64: one z power of a plane at a time) and accumulates, per
-//                     plane, the x-y contraction of the D2Q9 kernel for each z power
-//                     followed by the z contraction;
+//                     pass stages the five donor planes z-2 .. z+2 through LDS, one z
+//                     power of one plane at a time, and accumulates for each the x-y
+//                     contraction of the D2Q9 kernel followed by the z contraction;
 //   k3_korteweg, k3_thermo, k3_collide
 //                     Korteweg stress, force and thermodynamics, heat-flux correction and
 //                     the collisions of f and g (separate waves), 27-point stencils.
@@ -232,65 +231,36 @@ __device__ __forceinline__ double window_tap(double v, double dt, int j)
     return 0.0;
 }
 
-// SPLIT: the LDS holds only the nine fields of z power o, field (m, n) at slot 3 m + n;
-// otherwise all 27, field (m, n, o) at slot 9 m + 3 n + o
-template <bool FAST, bool SPLIT, typename LdsT, typename AccT, int LN, int LX>
-__device__ __forceinline__ void xy_window(const LdsT *sbase, int o, const LdsT (&wx)[3][5],
-                                          const LdsT (&wy)[3][5], const LdsT (&A)[3][3], const AccT (&B)[3][3],
-                                          AccT (&Y)[3][3])
+// the LDS holds the nine fields (m, n) of one z power, field (m, n) at slot 3 m + n; each
+// row is x-contracted and added straight into Y with its y weights (no five-row buffer:
+// the FP64 window must fit two waves per SIMD)
+template <bool FAST, typename LdsT, typename AccT, int LN, int LX>
+__device__ __forceinline__ void xy_window(const LdsT *sbase, const LdsT (&wx)[3][5], const LdsT (&wy)[3][5],
+                                          const LdsT (&A)[3][3], const AccT (&B)[3][3], AccT (&Y)[3][3])
 {
-    if constexpr (SPLIT) {
-        // each row is x-contracted and added straight into Y with its y weights (no
-        // five-row buffer: the FP64 window must fit two waves per SIMD)
-#pragma unroll
-        for (int n = 0; n < 3; ++n) {
-#pragma unroll
-            for (int r = 0; r < 5; ++r) {
-                LdsT Zr[3];
-#pragma unroll
-                for (int m = 0; m < 3; ++m) {
-                    const LdsT *row = sbase + ((3 * m + n) * LN + r * LX) * 2;
-                    const LdsT v0 = row[0], v1 = row[2], v2 = row[4], v3 = row[6], v4 = row[8];
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        const LdsT x = taps3<FAST>(k, wx[k], v0, v1, v2, v3, v4);
-                        Zr[k] = m == 0 ? A[k][m] * x : Zr[k] + A[k][m] * x;
-                    }
-                }
-#pragma unroll
-                for (int l = 0; l < 3; ++l) {
-                    if (FAST && ((l == 0 && r == 0) || (l == 2 && r == 4))) continue; // zero taps
-                    const AccT c = B[l][n] * (AccT)wy[l][r];
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) Y[k][l] += c * (AccT)Zr[k];
-                }
-            }
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        return;
-    }
 #pragma unroll
     for (int n = 0; n < 3; ++n) {
-        LdsT Z[3][5];
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int r = 0; r < 5; ++r) Z[k][r] = (LdsT)0;
 #pragma unroll
         for (int r = 0; r < 5; ++r) {
+            LdsT Zr[3];
 #pragma unroll
             for (int m = 0; m < 3; ++m) {
-                const LdsT *row = sbase + ((9 * m + 3 * n + o) * LN + r * LX) * 2;
+                const LdsT *row = sbase + ((3 * m + n) * LN + r * LX) * 2;
                 const LdsT v0 = row[0], v1 = row[2], v2 = row[4], v3 = row[6], v4 = row[8];
 #pragma unroll
-                for (int k = 0; k < 3; ++k) Z[k][r] += A[k][m] * taps3<FAST>(k, wx[k], v0, v1, v2, v3, v4);
+                for (int k = 0; k < 3; ++k) {
+                    const LdsT x = taps3<FAST>(k, wx[k], v0, v1, v2, v3, v4);
+                    Zr[k] = m == 0 ? A[k][m] * x : Zr[k] + A[k][m] * x;
+                }
+            }
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                if (FAST && ((l == 0 && r == 0) || (l == 2 && r == 4))) continue; // zero taps
+                const AccT c = B[l][n] * (AccT)wy[l][r];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) Y[k][l] += c * (AccT)Zr[k];
             }
         }
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int l = 0; l < 3; ++l)
-                Y[k][l] += B[l][n] * (AccT)taps3<FAST>(l, wy[l], Z[k][0], Z[k][1], Z[k][2], Z[k][3], Z[k][4]);
         __builtin_amdgcn_sched_barrier(0);
     }
 }
@@ -309,17 +279,15 @@ __device__ __forceinline__ void xy_window(const LdsT *sbase, int o, const LdsT (
 // the moment itself.
 // ---------------------------------------------------------------------------
 template <typename LdsT, int TX, int TY, bool GEN>
-__global__ void __launch_bounds__(2 * TX *TY, 2) k3_stream(const SlotDesc *__restrict__ slot)
+__global__ void __launch_bounds__(2 * TX *TY, sizeof(LdsT) == 4 ? 3 : 2) k3_stream(const SlotDesc *__restrict__ slot)
 {
     constexpr int LX = TX + 4, LY = TY + 4, LN = LX * LY, NT = 2 * TX * TY;
     constexpr bool kDev = sizeof(LdsT) == 4;
     using AccT = LdsT; // window accumulators: FP64, or FP32 deviations
-    // FP64 windows stage a donor plane in three rounds, the nine fields of one z power
-    // each (35 KB of LDS instead of 104 KB), so that two workgroups share a CU; FP32
-    // windows stage all 27 fields at once
-    constexpr int NO = kDev ? 1 : 3;  // staging rounds per donor plane
-    constexpr int FPS = 27 / NO;      // fields per set and round
-    constexpr bool kSplit = NO > 1;
+    // a donor plane is staged in three rounds, the nine fields of one z power per set
+    // each (35 KB of LDS in FP64, 17 KB in FP32 instead of 104 and 52 KB for the whole
+    // plane), so that two FP64 or three FP32 workgroups share a CU
+    constexpr int FPS = 9; // fields per set and round
     __shared__ __align__(16) LdsT lds[2 * FPS * LN];
     __shared__ LdsT ref[kDev ? 54 : 1];
     __shared__ int abort_block;
@@ -356,8 +324,8 @@ __global__ void __launch_bounds__(2 * TX *TY, 2) k3_stream(const SlotDesc *__res
     const double dt = P.dt;
     const int wbase = (int)threadIdx.y * LX + lxr; // window corner (gx-2, gy-2) in the tile plane
     // staging: lane tid < LN owns window node tid of a plane (its x-y node offset is the
-    // same in every plane) and moves both sets of all 27 moments of that node, each
-    // field read from a uniform plane base plus a 32-bit byte offset
+    // same in every plane) and moves both sets of the nine moments of that node of the
+    // round's z power, each field read from a uniform plane base plus a 32-bit byte offset
     static_assert(LN <= NT, "one staging lane per window node");
     const bool stager = tid < LN;
     const unsigned ndxy = (unsigned)(box.wrap(bx0 - 2 + tid % LX, box.nx) +
@@ -371,24 +339,22 @@ __global__ void __launch_bounds__(2 * TX *TY, 2) k3_stream(const SlotDesc *__res
     for (int pass = 0; pass < P.n_pass; ++pass) {
         const double s = sqrt(th);
         LdsT wx[3][5], wy[3][5];
-        AccT wz[3][5];
+        double wz[3][5]; // only its halo check is kept: the rounds recompute the z taps
         const int werr = window_weights<LdsT>(U[0], s, dt, wx) | window_weights<LdsT>(U[1], s, dt, wy) |
-                         window_weights<AccT>(U[2], s, dt, wz);
+                         window_weights<double>(U[2], s, dt, wz);
         if (inside) err |= werr; // lanes past the lattice edge only pad the tile
         LdsT A[3][3];
-        AccT B[3][3], C[3][3];
+        AccT B[3][3];
         {
-            double Ad[3][3], Bd[3][3], Cd[3][3];
+            double Ad[3][3], Bd[3][3];
             lagrange_coeffs(U[0], s, Ad);
             lagrange_coeffs(U[1], s, Bd);
-            lagrange_coeffs(U[2], s, Cd);
 #pragma unroll
             for (int k = 0; k < 3; ++k)
 #pragma unroll
                 for (int m = 0; m < 3; ++m) {
                     A[k][m] = (LdsT)Ad[k][m];
                     B[k][m] = (AccT)Bd[k][m];
-                    C[k][m] = (AccT)Cd[k][m];
                 }
         }
         AccT av[27];
@@ -399,10 +365,13 @@ __global__ void __launch_bounds__(2 * TX *TY, 2) k3_stream(const SlotDesc *__res
                                 wy[2][4] == (LdsT)0);
 
 #pragma unroll 1
-        for (int szo = 0; szo < 5 * NO; ++szo) {
-            // stage the donor plane z + sz - 2 of the tile window: all 54 fields, or the
-            // 18 of z power so (field 9 m + 3 n + so = 3 j + so at slot j = 3 m + n)
-            const int sz = szo / NO, so = szo - sz * NO;
+        for (int szo = 0; szo < 15; ++szo) {
+            // stage the 18 fields of z power so of the donor plane z + sz - 2 of the tile
+            // window (field 9 m + 3 n + so = 3 j + so at slot j = 3 m + n).  The five planes
+            // of one power come before the next power: the blocks that run together on an
+            // XCD are consecutive z planes, so block z - 1 stages the same plane and power
+            // one round after block z, while it is still in the XCD's L2
+            const int so = szo / 5, sz = szo - 5 * so;
             __syncthreads();
             const int zz = box.wrap(z + sz - 2, box.nz);
             if (stager) {
@@ -416,16 +385,17 @@ __global__ void __launch_bounds__(2 * TX *TY, 2) k3_stream(const SlotDesc *__res
                     LdsT a[MB], b[MB];
 #pragma unroll
                     for (int j = 0; j < MB; ++j) {
-                        const int f = kSplit ? 3 * j + so : m0 + j;
+                        const int f = 3 * (m0 + j) + so;
                         a[j] = *(const POND_GLOBAL LdsT *)((const POND_GLOBAL char *)(dmom + (size_t)f * N) + off);
                         b[j] = *(const POND_GLOBAL LdsT *)((const POND_GLOBAL char *)(dmom + (size_t)(27 + f) * N) + off);
                     }
 #pragma unroll
                     for (int j = 0; j < MB; ++j) {
+                        const int f = 3 * (m0 + j) + so;
                         Pair v;
                         if (kDev) {
-                            v.x = a[j] - ref[m0 + j];
-                            v.y = b[j] - ref[27 + m0 + j];
+                            v.x = a[j] - ref[f];
+                            v.y = b[j] - ref[27 + f];
                         } else {
                             v.x = a[j];
                             v.y = b[j];
@@ -443,34 +413,28 @@ __global__ void __launch_bounds__(2 * TX *TY, 2) k3_stream(const SlotDesc *__res
             if (abort_block != 0) return;
 
             const LdsT *sbase = &lds[wbase * 2 + myset];
-#pragma unroll 1
-            for (int o = kSplit ? so : 0; o < (kSplit ? so + 1 : 3); ++o) {
-                AccT Y[3][3];
+            AccT Y[3][3];
 #pragma unroll
-                for (int k = 0; k < 3; ++k)
+            for (int k = 0; k < 3; ++k)
 #pragma unroll
-                    for (int l = 0; l < 3; ++l) Y[k][l] = (AccT)0;
-                if (fast)
-                    xy_window<true, kSplit, LdsT, AccT, LN, LX>(sbase, o, wx, wy, A, B, Y);
-                else
-                    xy_window<false, kSplit, LdsT, AccT, LN, LX>(sbase, o, wx, wy, A, B, Y);
-                // z contraction: departure point m of the receiver takes wz[m][sz] C[m][o].
-                // The FP64 window recomputes these from u_z and s (an empty asm keeps the
-                // recomputation here) instead of holding wz and C across the loop.
-                AccT czs[3];
-                if constexpr (kSplit) {
-                    double u2 = U[2], su = s;
-                    asm volatile("" : "+v"(u2), "+v"(su));
-                    double Cd[3][3];
-                    lagrange_coeffs(u2, su, Cd);
-#pragma unroll
-                    for (int m = 0; m < 3; ++m)
-                        czs[m] = (AccT)((o == 0 ? Cd[m][0] : o == 1 ? Cd[m][1] : Cd[m][2]) *
-                                        window_tap(u2 + su * (double)(m - 1), dt, sz));
-                }
+                for (int l = 0; l < 3; ++l) Y[k][l] = (AccT)0;
+            if (fast)
+                xy_window<true, LdsT, AccT, LN, LX>(sbase, wx, wy, A, B, Y);
+            else
+                xy_window<false, LdsT, AccT, LN, LX>(sbase, wx, wy, A, B, Y);
+            // z contraction: departure point m of the receiver takes its z tap of plane sz
+            // times its z Lagrange coefficient of power so, both recomputed here from u_z
+            // and s (an empty asm keeps the recomputation here) instead of held across the
+            // loop
+            {
+                double u2 = U[2], su = s;
+                asm volatile("" : "+v"(u2), "+v"(su));
+                double Cd[3][3];
+                lagrange_coeffs(u2, su, Cd);
 #pragma unroll
                 for (int m = 0; m < 3; ++m) {
-                    const AccT cz = kSplit ? czs[m] : C[m][o] * wz[m][sz];
+                    const AccT cz = (AccT)((so == 0 ? Cd[m][0] : so == 1 ? Cd[m][1] : Cd[m][2]) *
+                                           window_tap(u2 + su * (double)(m - 1), dt, sz));
 #pragma unroll
                     for (int k = 0; k < 3; ++k)
 #pragma unroll
@@ -969,7 +933,7 @@ __global__ void __launch_bounds__(kMonThreads) k3_monitor_partials(const DevPara
 // launchers
 // ---------------------------------------------------------------------------
 // streaming tile: 16 x 8 receivers in every precision (16 x 16 was slower in both); a
-// staging round takes 52 KB of LDS in FP32 (54 fields) and 35 KB in FP64 (18 fields)
+// staging round of 18 fields takes 17 KB of LDS in FP32 and 35 KB in FP64
 void stream3_tile(int fp32, int *tx, int *ty)
 {
     (void)fp32;
