@@ -15,11 +15,12 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpond.so")
 SOURCES = ["pond_kernels.hip", "pond_step.hip", "pond_kernels3.hip", "pond_api.hip", "pond_batch.hip", "pond_noalloc.hip"]
-# compilation units: (source, extra flags).  pond_step.hip is compiled a second time for its
-# FP64-window kernels, with LLVM's max-ilp scheduling (faster for those, slower for the FP32
-# windows of the first unit).
-UNITS = [(s, []) for s in SOURCES] + [
-    ("pond_step.hip", ["-DPOND_STEP_DOUBLE_WINDOWS", "-mllvm", "-amdgpu-sched-strategy=max-ilp"])]
+# compilation units: (source, extra flags).  LLVM's max-ilp scheduling is faster for the
+# D3Q27 kernels and for the FP64-window fused-step kernels, slower for the FP32-window ones:
+# pond_step.hip is compiled a second time for its FP64 windows, with that strategy.
+MAX_ILP = ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]
+UNITS = [(s, MAX_ILP if s == "pond_kernels3.hip" else []) for s in SOURCES] + [
+    ("pond_step.hip", ["-DPOND_STEP_DOUBLE_WINDOWS", *MAX_ILP])]
 HEADERS = ["pond_device.h", "pond_internal.h", "pond_collide.h", "pond_stream.h", "pond_eos.h"]
 
 HIPCC_FLAGS = [
