@@ -290,6 +290,12 @@ __global__ void __launch_bounds__(2 * TX *TY, sizeof(LdsT) == 4 ? 3 : 2) k3_stre
     constexpr int FPS = 9; // fields per set and round
     __shared__ __align__(16) LdsT lds[2 * FPS * LN];
     __shared__ LdsT ref[kDev ? 54 : 1];
+    // z coefficients of the pass, per receiver: the FP32 window keeps the 45 products
+    // C_mo wz_m[sz] of its rounds, the FP64 window the nine C_mo and fifteen wz_m[sz] whose
+    // product each round forms (23 and 25 KB of LDS)
+    constexpr int NR = TX * TY;
+    constexpr int kCz = kDev ? 45 : 24;
+    __shared__ AccT s_cz[kCz * NR];
     __shared__ int abort_block;
     const SlotDesc &S = *slot;
     const POND_GLOBAL DevParams &P = *(const POND_GLOBAL DevParams *)S.P;
@@ -309,6 +315,7 @@ __global__ void __launch_bounds__(2 * TX *TY, sizeof(LdsT) == 4 ? 3 : 2) k3_stre
     const int tile = lb / box.nz, z = lb - tile * box.nz;
     const int bx0 = (tile % tiles_x) * TX, by0 = (tile / tiles_x) * TY;
     const int lxr = (int)threadIdx.x >> 1, myset = (int)threadIdx.x & 1;
+    const int rcv = lxr + TX * (int)threadIdx.y; // receiver index in the tile
     const int gx = bx0 + lxr, gy = by0 + (int)threadIdx.y;
     const bool inside = gx < box.nx && gy < box.ny;
     const int node = min(gx, box.nx - 1) + box.nx * (min(gy, box.ny - 1) + box.ny * z);
@@ -339,7 +346,7 @@ __global__ void __launch_bounds__(2 * TX *TY, sizeof(LdsT) == 4 ? 3 : 2) k3_stre
     for (int pass = 0; pass < P.n_pass; ++pass) {
         const double s = sqrt(th);
         LdsT wx[3][5], wy[3][5];
-        double wz[3][5]; // only its halo check is kept: the rounds recompute the z taps
+        double wz[3][5]; // only its halo check is kept: the z taps go to LDS in the first round
         const int werr = window_weights<LdsT>(U[0], s, dt, wx) | window_weights<LdsT>(U[1], s, dt, wy) |
                          window_weights<double>(U[2], s, dt, wz);
         if (inside) err |= werr; // lanes past the lattice edge only pad the tile
@@ -363,6 +370,32 @@ __global__ void __launch_bounds__(2 * TX *TY, sizeof(LdsT) == 4 ? 3 : 2) k3_stre
         // zero-tap-free window variant when every lane of the wave allows it
         const bool fast = __all(wx[0][0] == (LdsT)0 && wx[2][4] == (LdsT)0 && wy[0][0] == (LdsT)0 &&
                                 wy[2][4] == (LdsT)0);
+
+        // the pass's z coefficients, read in the rounds after their second barrier; the
+        // barrier here ends every read of the previous pass's
+        if (pass > 0) __syncthreads();
+        if (myset == 0) {
+            double Cd[3][3];
+            lagrange_coeffs(U[2], s, Cd);
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                const double vz = U[2] + s * (double)(m - 1);
+#pragma unroll
+                for (int j = 0; j < 5; ++j) {
+                    const double tap = window_tap(vz, dt, j);
+                    if (kDev) {
+#pragma unroll
+                        for (int o = 0; o < 3; ++o) s_cz[((5 * o + j) * 3 + m) * NR + rcv] = (AccT)(Cd[m][o] * tap);
+                    } else {
+                        s_cz[(9 + 5 * m + j) * NR + rcv] = (AccT)tap;
+                    }
+                }
+                if (!kDev) {
+#pragma unroll
+                    for (int o = 0; o < 3; ++o) s_cz[(3 * m + o) * NR + rcv] = (AccT)Cd[m][o];
+                }
+            }
+        }
 
 #pragma unroll 1
         for (int szo = 0; szo < 15; ++szo) {
@@ -423,23 +456,15 @@ __global__ void __launch_bounds__(2 * TX *TY, sizeof(LdsT) == 4 ? 3 : 2) k3_stre
             else
                 xy_window<false, LdsT, AccT, LN, LX>(sbase, wx, wy, A, B, Y);
             // z contraction: departure point m of the receiver takes its z tap of plane sz
-            // times its z Lagrange coefficient of power so, both recomputed here from u_z
-            // and s (an empty asm keeps the recomputation here) instead of held across the
-            // loop
-            {
-                double u2 = U[2], su = s;
-                asm volatile("" : "+v"(u2), "+v"(su));
-                double Cd[3][3];
-                lagrange_coeffs(u2, su, Cd);
+            // times its z Lagrange coefficient of power so
 #pragma unroll
-                for (int m = 0; m < 3; ++m) {
-                    const AccT cz = (AccT)((so == 0 ? Cd[m][0] : so == 1 ? Cd[m][1] : Cd[m][2]) *
-                                           window_tap(u2 + su * (double)(m - 1), dt, sz));
+            for (int m = 0; m < 3; ++m) {
+                const AccT cz = kDev ? s_cz[(3 * szo + m) * NR + rcv]
+                                     : s_cz[(3 * m + so) * NR + rcv] * s_cz[(9 + 5 * m + sz) * NR + rcv];
 #pragma unroll
-                    for (int k = 0; k < 3; ++k)
+                for (int k = 0; k < 3; ++k)
 #pragma unroll
-                        for (int l = 0; l < 3; ++l) av[9 * k + 3 * l + m] += cz * Y[k][l];
-                }
+                    for (int l = 0; l < 3; ++l) av[9 * k + 3 * l + m] += cz * Y[k][l];
             }
         }
         if (kDev) {
