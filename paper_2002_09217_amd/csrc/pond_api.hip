@@ -842,6 +842,8 @@ int pond_load(pond_handle *h, const void *buf, unsigned long long bytes)
     h->failed = false;
     h->initialised = true;
     HIP_TRY(h, launch_reset_flags(h->lc, h->ds.flags));
+    // D3Q27: the donor moments of the loaded state (the descriptor of parity 0 reads it)
+    if (h->lc.dim == 3) HIP_TRY(h, launch_donor_moments3(h->lc, h->desc_d));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     build_all_graphs(h);
     std::snprintf(h->msg, sizeof h->msg, "ok");
@@ -869,6 +871,9 @@ int pond_time_kernel(pond_handle *h, int which, int reps, double *avg_us)
         if (e != hipSuccess) return handle_fail(h, POND_E_DEVICE, "timing launch: %s", hipGetErrorString(e));
     }
     HIP_TRY(h, hipEventRecord(e1, h->stream));
+    // D3Q27: the timed collisions overwrote the donor moments; those of the current state
+    // again
+    if (c.dim == 3 && which == 1) HIP_TRY(h, launch_donor_moments3(c, d));
     HIP_TRY(h, hipEventSynchronize(e1));
     float ms = 0.0f;
     HIP_TRY(h, hipEventElapsedTime(&ms, e0, e1));

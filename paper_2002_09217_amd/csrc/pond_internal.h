@@ -190,10 +190,14 @@ int monitor_blocks(const LaunchCtx &c);
 hipError_t launch_monitor_final(const LaunchCtx &c, const double *partials, int nblocks, double *out);
 
 // D3Q27 (pond_kernels3.hip), one lattice per launch, descriptor in device memory:
-// streaming = donor moments + passes; collision = Korteweg stress + thermodynamics +
-// collision.  With start/stop events set, each group is bracketed by them.
+// streaming = passes over the donor moments; collision = Korteweg stress +
+// thermodynamics + collision (which also writes the next state's donor moments).  With
+// start/stop events set, each group is bracketed by them.
 hipError_t launch_stream3(const LaunchCtx &c, const SlotDesc *slot);
 hipError_t launch_collide3(const LaunchCtx &c, const SlotDesc *slot);
+// the donor moments of the state in pop_src/side_src (the collision writes them for the
+// state it stores; this recomputes them after the populations were set otherwise)
+hipError_t launch_donor_moments3(const LaunchCtx &c, const SlotDesc *slot);
 // initial state from rho, u_hat (3 planes), T staged in aux planes 0-4: streamed-state
 // planes of the equilibrium (then launch_collide3 stores the collided populations)
 hipError_t launch_init3(const LaunchCtx &c, const DevState &s, const SlotDesc *slot);

@@ -4,15 +4,18 @@
 // Same method as the 1D/2D kernels (eqs. 1-4, 9, 16-22; App. B-D, F), laid out for the
 // 5 x 5 x 5 donor window of three dimensions, which does not fit in LDS as a tile plus
 // halo:
-//   k3_donor_moments  each node's 27 + 27 moments about a common reference velocity
-//                     (zero), gauge free, into a scratch buffer;
 //   k3_stream         one workgroup per x-y tile of one z plane; every predictor-corrector
 //                     pass stages the five donor planes z-2 .. z+2 through LDS, one z
 //                     power of one plane at a time, and accumulates for each the x-y
 //                     contraction of the D2Q9 kernel followed by the z contraction;
 //   k3_korteweg, k3_thermo, k3_collide
 //                     Korteweg stress, force and thermodynamics, heat-flux correction and
-//                     the collisions of f and g (separate waves), 27-point stencils.
+//                     the collisions of f and g (separate waves), 27-point stencils; the
+//                     collision stores the populations and each node's 27 + 27 moments
+//                     about a common reference velocity (zero), gauge free, into a scratch
+//                     buffer: the donor moments the next step's streaming reads;
+//   k3_donor_moments  the same moments from stored populations (after an initialisation
+//                     or a checkpoint load).
 // Index conventions: direction q = 9 (cx+1) + 3 (cy+1) + (cz+1); moment 9 m + 3 n + o
 // for sum f wx^m wy^n wz^o.
 #include <hip/hip_runtime.h>
@@ -194,6 +197,33 @@ __global__ void __launch_bounds__(256) k3_donor_moments(const SlotDesc *__restri
     const double s = sqrt(side[kSideTh * N + node]);
     double m[27];
     moments27(f, ux, uy, uz, s, m);
+    POND_GLOBAL MomT *out = (POND_GLOBAL MomT *)S.dmom + (size_t)set * 27 * N;
+#pragma unroll
+    for (int i = 0; i < 27; ++i) out[(size_t)i * N + node] = (MomT)m[i];
+}
+
+// The donor moments of a set that the collision has just stored (post in the gauge u, s),
+// as k3_donor_moments computes them from the stored populations: in the FP32 storage
+// forms from the stored deviations and sum, so that both give the same bits
+template <typename PopT, typename MomT>
+__device__ __forceinline__ void store_donor_moments(const SlotDesc &S, size_t N, size_t node, int set,
+                                                    const double *post, const double u[3], double s)
+{
+    double f[27];
+    if constexpr (kDeviationStore<PopT>) {
+        double sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < 27; ++q) sum += post[q];
+#pragma unroll
+        for (int q = 0; q < 27; ++q) f[q] = (double)(PopT)(post[q] - weight_q<3>(q) * sum);
+#pragma unroll
+        for (int q = 0; q < 27; ++q) f[q] += w27(q) * sum;
+    } else {
+#pragma unroll
+        for (int q = 0; q < 27; ++q) f[q] = post[q];
+    }
+    double m[27];
+    moments27(f, u[0], u[1], u[2], s, m);
     POND_GLOBAL MomT *out = (POND_GLOBAL MomT *)S.dmom + (size_t)set * 27 * N;
 #pragma unroll
     for (int i = 0; i < 27; ++i) out[(size_t)i * N + node] = (MomT)m[i];
@@ -673,7 +703,7 @@ __global__ void __launch_bounds__(256) k3_thermo(const SlotDesc *__restrict__ sl
 // ---------------------------------------------------------------------------
 // collision (eqs. 9, 16-22): blockIdx.y = 0 collides f, 1 collides g
 // ---------------------------------------------------------------------------
-template <typename PopT>
+template <typename PopT, typename MomT>
 __global__ void __launch_bounds__(256) k3_collide(const SlotDesc *__restrict__ slot)
 {
     const SlotDesc &S = *slot;
@@ -725,6 +755,7 @@ __global__ void __launch_bounds__(256) k3_collide(const SlotDesc *__restrict__ s
             post[q] = pop[q] + P.omega * (rho * Wq - pop[q]) + Sq;
         }
         store_set<3, PopT>(pout, N, (int)n, 0, post);
+        store_donor_moments<PopT, MomT>(S, N, n, 0, post, u, s);
         POND_GLOBAL double *side = (POND_GLOBAL double *)S.side_dst;
         side[kSideUx * N + n] = u[0];
         side[kSideUy * N + n] = u[1];
@@ -799,6 +830,7 @@ __global__ void __launch_bounds__(256) k3_collide(const SlotDesc *__restrict__ s
         post[q] = pop[q] + P.omega * (geq - pop[q]) + (M0 + work) * psi * dt;
     }
     store_set<3, PopT>(pout, N, (int)n, 1, post);
+    store_donor_moments<PopT, MomT>(S, N, n, 1, post, u, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -981,24 +1013,32 @@ static inline dim3 grid_nodes(const LaunchCtx &c, int per = 1)
     return dim3((unsigned)(((size_t)c.N * per + 255) / 256));
 }
 
+// the donor moments of the state the step reads are those its collision wrote (or, after
+// an initialisation or a checkpoint load, launch_donor_moments3's)
 hipError_t launch_stream3(const LaunchCtx &c, const SlotDesc *slot)
 {
     if (c.ev_start) (void)hipEventRecord(c.ev_start, c.st);
-    if (c.fp32 == 1) {
-        hipLaunchKernelGGL((k3_donor_moments<float, float>), grid_nodes(c, 2), dim3(256), 0, c.st, slot);
+    if (c.fp32 == 1)
         launch_stream3_t<float, 16, 8>(c, slot);
-    } else if (c.fp32 == 2) {
-        hipLaunchKernelGGL((k3_donor_moments<float, double>), grid_nodes(c, 2), dim3(256), 0, c.st, slot);
+    else
         launch_stream3_t<double, 16, 8>(c, slot);
-    } else {
-        hipLaunchKernelGGL((k3_donor_moments<double, double>), grid_nodes(c, 2), dim3(256), 0, c.st, slot);
-        launch_stream3_t<double, 16, 8>(c, slot);
-    }
     if (c.ev_stop) (void)hipEventRecord(c.ev_stop, c.st);
     return hipGetLastError();
 }
 
-// the Korteweg stress of the streamed density (mom plane 0) and the rest of the closure
+hipError_t launch_donor_moments3(const LaunchCtx &c, const SlotDesc *slot)
+{
+    if (c.fp32 == 1)
+        hipLaunchKernelGGL((k3_donor_moments<float, float>), grid_nodes(c, 2), dim3(256), 0, c.st, slot);
+    else if (c.fp32 == 2)
+        hipLaunchKernelGGL((k3_donor_moments<float, double>), grid_nodes(c, 2), dim3(256), 0, c.st, slot);
+    else
+        hipLaunchKernelGGL((k3_donor_moments<double, double>), grid_nodes(c, 2), dim3(256), 0, c.st, slot);
+    return hipGetLastError();
+}
+
+// the Korteweg stress of the streamed density (mom plane 0), the rest of the closure and
+// the collision
 hipError_t launch_collide3(const LaunchCtx &c, const SlotDesc *slot)
 {
     if (c.ev_start) (void)hipEventRecord(c.ev_start, c.st);
@@ -1006,10 +1046,13 @@ hipError_t launch_collide3(const LaunchCtx &c, const SlotDesc *slot)
     hipLaunchKernelGGL(k3_thermo, grid_nodes(c), dim3(256), 0, c.st, slot);
     dim3 g = grid_nodes(c);
     g.y = 2;
-    if (c.fp32)
-        hipLaunchKernelGGL((k3_collide<float>), g, dim3(256), 0, c.st, slot);
+    // the collision also writes the donor moments of the state it stores
+    if (c.fp32 == 1)
+        hipLaunchKernelGGL((k3_collide<float, float>), g, dim3(256), 0, c.st, slot);
+    else if (c.fp32 == 2)
+        hipLaunchKernelGGL((k3_collide<float, double>), g, dim3(256), 0, c.st, slot);
     else
-        hipLaunchKernelGGL((k3_collide<double>), g, dim3(256), 0, c.st, slot);
+        hipLaunchKernelGGL((k3_collide<double, double>), g, dim3(256), 0, c.st, slot);
     if (c.ev_stop) (void)hipEventRecord(c.ev_stop, c.st);
     return hipGetLastError();
 }
