@@ -14,8 +14,8 @@
 //                     collision stores the populations and each node's 27 + 27 moments
 //                     about a common reference velocity (zero), gauge free, into a scratch
 //                     buffer: the donor moments the next step's streaming reads;
-//   k3_donor_moments  the same moments from stored populations (after an initialisation
-//                     or a checkpoint load).
+//   k3_donor_moments  the same moments from stored populations (after a checkpoint load;
+//                     an initialisation ends with a collision).
 // Index conventions: direction q = 9 (cx+1) + 3 (cy+1) + (cz+1); moment 9 m + 3 n + o
 // for sum f wx^m wy^n wz^o.
 #include <hip/hip_runtime.h>
@@ -1013,8 +1013,8 @@ static inline dim3 grid_nodes(const LaunchCtx &c, int per = 1)
     return dim3((unsigned)(((size_t)c.N * per + 255) / 256));
 }
 
-// the donor moments of the state the step reads are those its collision wrote (or, after
-// an initialisation or a checkpoint load, launch_donor_moments3's)
+// the donor moments of the state the step reads are those the collision before it wrote
+// (or, after a checkpoint load, launch_donor_moments3's)
 hipError_t launch_stream3(const LaunchCtx &c, const SlotDesc *slot)
 {
     if (c.ev_start) (void)hipEventRecord(c.ev_start, c.st);
