@@ -54,6 +54,30 @@ def test_resume_is_bitwise(precision):
     b.close()
 
 
+@pytest.mark.parametrize("precision", [pond.FP64, pond.FP32_STORE, pond.FP32_STORE_FP64_MATH])
+def test_schedules_and_timing_calls_agree_bitwise(precision):
+    """The collision writes the donor moments the next step streams: single steps, graph
+    runs, timed steps and kernel timings (which run the collision on their own and then
+    rebuild the donor moments of the current state) all give the state of plain steps."""
+    case = W.perturbed3(14, 11, 9, seed=8, kappa=0.0176, u0=(0.03, -0.02, 0.04), dt=0.2)
+    a = pond.Lattice(pond_config(case, precision=precision))
+    a.init_fields(case.rho, case.u, case.T)
+    a.step(30)
+    b = pond.Lattice(pond_config(case, precision=precision))
+    b.init_fields(case.rho, case.u, case.T)
+    assert b.time_kernel(1, 2) > 0.0 and b.time_kernel(0, 2) > 0.0
+    for n in (1, 3, 2, 5):
+        b.step(n)
+    assert b.time_kernel(1, 3) > 0.0
+    t = b.step_timed(4)
+    assert all(v > 0.0 for v in t.values())
+    b.step(15)
+    assert a.steps_done() == b.steps_done() == 30
+    assert np.array_equal(_fields(a.moments()), _fields(b.moments()))
+    a.close()
+    b.close()
+
+
 class _Column:
     """A periodic box that is long along one axis and two nodes wide across it,
     seen as a one-dimensional line of nodes along that axis."""
