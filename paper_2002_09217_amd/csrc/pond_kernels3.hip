@@ -326,6 +326,7 @@ __global__ void __launch_bounds__(2 * TX *TY, sizeof(LdsT) == 4 ? 3 : 2) k3_stre
     constexpr int NR = TX * TY;
     constexpr int kCz = kDev ? 45 : 24;
     __shared__ AccT s_cz[kCz * NR];
+    __shared__ int s_wfast[NT / 64]; // per wave: its lanes allow the zero-tap-free window
     __shared__ int abort_block;
     const SlotDesc &S = *slot;
     const POND_GLOBAL DevParams &P = *(const POND_GLOBAL DevParams *)S.P;
@@ -401,9 +402,15 @@ __global__ void __launch_bounds__(2 * TX *TY, sizeof(LdsT) == 4 ? 3 : 2) k3_stre
         const bool fast = __all(wx[0][0] == (LdsT)0 && wx[2][4] == (LdsT)0 && wy[0][0] == (LdsT)0 &&
                                 wy[2][4] == (LdsT)0);
 
-        // the pass's z coefficients, read in the rounds after their second barrier; the
-        // barrier here ends every read of the previous pass's
-        if (pass > 0) __syncthreads();
+        // the block takes the zero-tap-free window when every wave allows it (a choice
+        // uniform over the block: the rounds hold barriers).  The pass's z coefficients are
+        // read in the rounds after their second barrier; the barrier here ends every read
+        // of the previous pass's, and of the previous pass's votes
+        if ((tid & 63) == 0) s_wfast[tid >> 6] = fast ? 1 : 0;
+        __syncthreads();
+        bool block_fast = true;
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) block_fast = block_fast && s_wfast[w] != 0;
         if (myset == 0) {
             double Cd[3][3];
             lagrange_coeffs(U[2], s, Cd);
@@ -427,76 +434,78 @@ __global__ void __launch_bounds__(2 * TX *TY, sizeof(LdsT) == 4 ? 3 : 2) k3_stre
             }
         }
 
+        auto rounds = [&](auto fast_tag) -> bool {
+            constexpr bool FAST = decltype(fast_tag)::value;
 #pragma unroll 1
-        for (int szo = 0; szo < 15; ++szo) {
-            // stage the 18 fields of z power so of the donor plane z + sz - 2 of the tile
-            // window (field 9 m + 3 n + so = 3 j + so at slot j = 3 m + n).  The five planes
-            // of one power come before the next power: the blocks that run together on an
-            // XCD are consecutive z planes, so block z - 1 stages the same plane and power
-            // one round after block z, while it is still in the XCD's L2
-            const int so = szo / 5, sz = szo - 5 * so;
-            __syncthreads();
-            const int zz = box.wrap(z + sz - 2, box.nz);
-            if (stager) {
-                const unsigned off = (ndxy + plane * (unsigned)zz) * (unsigned)sizeof(LdsT);
-                // loads in batches of MB fields per set before their stores, so that
-                // their latencies overlap
-                constexpr int MB = 9;
-                static_assert(FPS % MB == 0, "whole batches of fields");
+            for (int szo = 0; szo < 15; ++szo) {
+                // stage the 18 fields of z power so of the donor plane z + sz - 2 of the tile
+                // window (field 9 m + 3 n + so = 3 j + so at slot j = 3 m + n).  The five planes
+                // of one power come before the next power: the blocks that run together on an
+                // XCD are consecutive z planes, so block z - 1 stages the same plane and power
+                // one round after block z, while it is still in the XCD's L2
+                const int so = szo / 5, sz = szo - 5 * so;
+                __syncthreads();
+                const int zz = box.wrap(z + sz - 2, box.nz);
+                if (stager) {
+                    const unsigned off = (ndxy + plane * (unsigned)zz) * (unsigned)sizeof(LdsT);
+                    // loads in batches of MB fields per set before their stores, so that
+                    // their latencies overlap
+                    constexpr int MB = 9;
+                    static_assert(FPS % MB == 0, "whole batches of fields");
 #pragma unroll
-                for (int m0 = 0; m0 < FPS; m0 += MB) {
-                    LdsT a[MB], b[MB];
+                    for (int m0 = 0; m0 < FPS; m0 += MB) {
+                        LdsT a[MB], b[MB];
 #pragma unroll
-                    for (int j = 0; j < MB; ++j) {
-                        const int f = 3 * (m0 + j) + so;
-                        a[j] = *(const POND_GLOBAL LdsT *)((const POND_GLOBAL char *)(dmom + (size_t)f * N) + off);
-                        b[j] = *(const POND_GLOBAL LdsT *)((const POND_GLOBAL char *)(dmom + (size_t)(27 + f) * N) + off);
-                    }
-#pragma unroll
-                    for (int j = 0; j < MB; ++j) {
-                        const int f = 3 * (m0 + j) + so;
-                        Pair v;
-                        if (kDev) {
-                            v.x = a[j] - ref[f];
-                            v.y = b[j] - ref[27 + f];
-                        } else {
-                            v.x = a[j];
-                            v.y = b[j];
+                        for (int j = 0; j < MB; ++j) {
+                            const int f = 3 * (m0 + j) + so;
+                            a[j] = *(const POND_GLOBAL LdsT *)((const POND_GLOBAL char *)(dmom + (size_t)f * N) + off);
+                            b[j] = *(const POND_GLOBAL LdsT *)((const POND_GLOBAL char *)(dmom + (size_t)(27 + f) * N) + off);
                         }
-                        *(Pair *)&lds[((m0 + j) * LN + tid) * 2] = v;
+#pragma unroll
+                        for (int j = 0; j < MB; ++j) {
+                            const int f = 3 * (m0 + j) + so;
+                            Pair v;
+                            if (kDev) {
+                                v.x = a[j] - ref[f];
+                                v.y = b[j] - ref[27 + f];
+                            } else {
+                                v.x = a[j];
+                                v.y = b[j];
+                            }
+                            *(Pair *)&lds[((m0 + j) * LN + tid) * 2] = v;
+                        }
                     }
                 }
-            }
-            if (pass == 0 && szo == 0 && tid == 0) {
-                abort_block = err_before;
-                // one step more has started without an earlier failure
-                if (blockIdx.x == 0 && err_before == 0) atomicAdd(&flags[kFlagSteps], 1);
-            }
-            __syncthreads();
-            if (abort_block != 0) return;
+                if (pass == 0 && szo == 0 && tid == 0) {
+                    abort_block = err_before;
+                    // one step more has started without an earlier failure
+                    if (blockIdx.x == 0 && err_before == 0) atomicAdd(&flags[kFlagSteps], 1);
+                }
+                __syncthreads();
+                if (abort_block != 0) return false;
 
-            const LdsT *sbase = &lds[wbase * 2 + myset];
-            AccT Y[3][3];
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-#pragma unroll
-                for (int l = 0; l < 3; ++l) Y[k][l] = (AccT)0;
-            if (fast)
-                xy_window<true, LdsT, AccT, LN, LX>(sbase, wx, wy, A, B, Y);
-            else
-                xy_window<false, LdsT, AccT, LN, LX>(sbase, wx, wy, A, B, Y);
-            // z contraction: departure point m of the receiver takes its z tap of plane sz
-            // times its z Lagrange coefficient of power so
-#pragma unroll
-            for (int m = 0; m < 3; ++m) {
-                const AccT cz = kDev ? s_cz[(3 * szo + m) * NR + rcv]
-                                     : s_cz[(3 * m + so) * NR + rcv] * s_cz[(9 + 5 * m + sz) * NR + rcv];
+                const LdsT *sbase = &lds[wbase * 2 + myset];
+                AccT Y[3][3];
 #pragma unroll
                 for (int k = 0; k < 3; ++k)
 #pragma unroll
-                    for (int l = 0; l < 3; ++l) av[9 * k + 3 * l + m] += cz * Y[k][l];
+                    for (int l = 0; l < 3; ++l) Y[k][l] = (AccT)0;
+                xy_window<FAST, LdsT, AccT, LN, LX>(sbase, wx, wy, A, B, Y);
+                // z contraction: departure point m of the receiver takes its z tap of plane sz
+                // times its z Lagrange coefficient of power so
+#pragma unroll
+                for (int m = 0; m < 3; ++m) {
+                    const AccT cz = kDev ? s_cz[(3 * szo + m) * NR + rcv]
+                                         : s_cz[(3 * m + so) * NR + rcv] * s_cz[(9 + 5 * m + sz) * NR + rcv];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k)
+#pragma unroll
+                        for (int l = 0; l < 3; ++l) av[9 * k + 3 * l + m] += cz * Y[k][l];
+                }
             }
-        }
+            return true;
+        };
+        if (!(block_fast ? rounds(std::true_type{}) : rounds(std::false_type{}))) return;
         if (kDev) {
             // reference part: sum_mno A_km B_ln C_m'o R_mno in FP64 (the window weights of
             // each axis sum to one).  The inputs pass an empty asm so that the coefficients
